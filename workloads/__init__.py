@@ -1,0 +1,127 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws test matrices; it holds none of the randomized SVD's
+arithmetic (the Gaussian test matrix of the method is generated separately
+by each side from its counter-based definition).  Both the tests (GPU path
+and oracle) and bench.py take their inputs from here.
+
+The paper's own inputs (two SuiteSparse matrices and a 512 x 512 image) are
+not available; these matrices stand in for them with stated shapes, spectra
+and noise.  Recipes:
+
+  dense_lowrank: A = U diag(sigma) V^T + noise_std * N(0, 1), U (m x r) and
+    V (n x r) Haar-distributed orthonormal columns (QR of a Gaussian matrix
+    with the columns multiplied by sign(diag R), Mezzadri 2007).  "N(0, x)"
+    in a recipe is read as standard deviation x.
+
+Named recipes (sizes, spectra, seeds):
+  plain_small    2000 x 1000, sigma_i = exp(-i/50) (i = 1..1000), noise 1e-6,
+                 FP64, seed 1, k = 20, p = 10, q = 2
+  plain_gpu      50000 x 20000, sigma_i = 1/i (i <= 2000), noise 1e-4, FP32,
+                 seed 2, k = 100, p = 20, q = 2, 4096 x 4096 tiles
+  mixed          65536 x 32768, sigma_i = i^-0.5, noise 1e-4, FP32, seed 5,
+                 k = 128, p = 32, q = 3
+  fd             256 x 128, sigma_i = i^-0.5 (i <= 128), noise 1e-4, seeds
+                 100..104, k = 16, p = 112, q = 3
+Scaled-down variants keep the spectrum law and noise and shrink m, n.
+"""
+
+import math
+
+import numpy as np
+import torch
+
+
+def _gen(seed, device):
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def haar_columns(rows, cols, gen, device="cpu", dtype=torch.float64):
+    """rows x cols matrix with Haar-distributed orthonormal columns."""
+    G = torch.randn(rows, cols, generator=gen, device=device, dtype=dtype)
+    Qm, R = torch.linalg.qr(G, mode="reduced")
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1
+    return Qm * d[None, :]
+
+
+def dense_lowrank(m, n, sigma, noise_std, seed, device="cpu", out_dtype=torch.float32,
+                  work_dtype=torch.float64):
+    """A = U diag(sigma) V^T + noise_std * N(0,1) as an (m, n) torch tensor
+    (row-major) of out_dtype on `device`."""
+    sigma = torch.as_tensor(np.asarray(sigma, dtype=np.float64), dtype=work_dtype, device=device)
+    r = int(sigma.numel())
+    if r > min(m, n):
+        raise ValueError("rank exceeds min(m, n)")
+    g = _gen(seed, device)
+    U = haar_columns(m, r, g, device, work_dtype)
+    V = haar_columns(n, r, g, device, work_dtype)
+    A = (U * sigma[None, :]) @ V.T
+    del U, V
+    if noise_std:
+        A.add_(torch.randn(m, n, generator=g, device=device, dtype=work_dtype), alpha=float(noise_std))
+    return A.to(out_dtype)
+
+
+def spectrum_exp(count, scale=50.0):
+    i = np.arange(1, count + 1, dtype=np.float64)
+    return np.exp(-i / scale)
+
+
+def spectrum_pow(count, power):
+    i = np.arange(1, count + 1, dtype=np.float64)
+    return i ** (-float(power))
+
+
+RECIPES = {
+    "plain_small": dict(m=2000, n=1000, spectrum=("exp", 1000, 50.0), noise=1e-6, seed=1,
+                        k=20, p=10, q=2, dtype="f64", tile=(2000, 1000)),
+    "plain_gpu": dict(m=50000, n=20000, spectrum=("pow", 2000, 1.0), noise=1e-4, seed=2,
+                      k=100, p=20, q=2, dtype="f32", tile=(4096, 4096)),
+    "mixed": dict(m=65536, n=32768, spectrum=("pow", 32768, 0.5), noise=1e-4, seed=5,
+                  k=128, p=32, q=3, dtype="f32", tile=(4096, 4096)),
+}
+
+
+def recipe_sigma(spec):
+    kind = spec[0]
+    if kind == "exp":
+        return spectrum_exp(spec[1], spec[2])
+    if kind == "pow":
+        return spectrum_pow(spec[1], spec[2])
+    raise ValueError(kind)
+
+
+def make(name, device="cpu", scale=1.0, out_dtype=None):
+    """Build a named recipe (optionally with m, n and the spectrum length
+    scaled by `scale`).  Returns (A, meta)."""
+    r = dict(RECIPES[name])
+    m = max(8, int(round(r["m"] * scale)))
+    n = max(8, int(round(r["n"] * scale)))
+    spec = r["spectrum"]
+    cnt = min(max(1, int(round(spec[1] * scale))), m, n)
+    sigma = recipe_sigma((spec[0], cnt) + tuple(spec[2:]))
+    if out_dtype is None:
+        out_dtype = torch.float64 if r["dtype"] == "f64" else torch.float32
+    A = dense_lowrank(m, n, sigma, r["noise"], r["seed"], device=device, out_dtype=out_dtype)
+    meta = dict(r, m=m, n=n, sigma=sigma, scale=scale)
+    return A, meta
+
+
+def fd_instance(seed, m=256, n=128, noise=1e-4, device="cpu"):
+    sigma = spectrum_pow(min(m, n), 0.5)
+    return dense_lowrank(m, n, sigma, noise, seed, device=device, out_dtype=torch.float64)
+
+
+def sizes_ok(m, n, k, p):
+    return k >= 1 and p >= 0 and k + p <= min(m, n)
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+__all__ = ["dense_lowrank", "haar_columns", "make", "fd_instance",
+           "RECIPES", "recipe_sigma", "spectrum_exp", "spectrum_pow", "math"]
