@@ -1,0 +1,227 @@
+/*
+ * rsvd.h -- C ABI of the MI355X randomized-SVD library.
+ *
+ * Computes a rank-k approximate SVD  A ~ U diag(S) V^T  of an m x n matrix A
+ * by the randomized SVD of Halko, Martinsson and Tropp as the paper states it
+ * (Section 2.1, steps 1-7): a Gaussian test matrix O (n x l), the sketch
+ * Y = A O, a thin QR of Y, the projection B = Q^T A, an SVD of the small B,
+ * and U = Q U_B.  The sketch is taken of the power matrix (A A^T)^q A
+ * (Section 2.2, Eq. (1)), evaluated right to left (Eq. (2)) and
+ * re-orthonormalised after every product with A or A^T.  The sketch has
+ * l = k + p columns (p = oversampling); the result keeps k.  Products with A
+ * run block by block over the block-cyclic tiles of A (Section 2.3, Eq. (3);
+ * Section 3.1); workspace is sized before anything runs (Section 3.4).
+ *
+ * Conventions
+ *   - All integer sizes are int64_t and counted in elements.
+ *   - A dense A is row-major: element (i, j) at data[i * ld + j], ld >= n.
+ *   - U (m x k) and V (n x k) are column-major: U(i, j) at U[i + j * ldu],
+ *     ldu >= m; V(i, j) at V[i + j * ldv], ldv >= n.  S holds k doubles,
+ *     descending.  Signs: the largest-magnitude entry of every column of V
+ *     (lowest row on ties) is positive.
+ *   - Device pointers are HIP device (or managed) memory on the current
+ *     device; "stream" arguments are hipStream_t handles passed as void*
+ *     (NULL = the default stream).
+ *   - The caller owns every buffer: A, U, S, V, gradients and workspaces.
+ *     The library never allocates device memory in rsvd_factor or
+ *     rsvd_backward; a plan owns only host metadata.
+ *   - Every call returns an rsvd_status; nothing throws across the ABI.
+ *     A text message for the last failure of a plan is available from
+ *     rsvd_last_error(plan) (or rsvd_last_error(NULL) for plan-less calls).
+ *   - Calls on one plan must not overlap; different plans are independent.
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rsvd_status;
+enum {
+  RSVD_OK = 0,
+  RSVD_W_RANK_DEFICIENT = 1, /* results valid; some sketch directions were dropped */
+  RSVD_W_DEGENERATE = 2,     /* results valid; backward met equal singular values  */
+  RSVD_E_INVALID_ARG = -1,
+  RSVD_E_BUDGET = -2,        /* workspace does not fit the HBM budget              */
+  RSVD_E_HIP = -3,           /* a HIP runtime call failed                          */
+  RSVD_E_UNSUPPORTED = -4,   /* legal but not implemented combination              */
+  RSVD_E_NUMERIC = -5        /* NaN/Inf met on the device                          */
+};
+
+enum { RSVD_DENSE = 0, RSVD_CSR = 1 };                               /* formats   */
+enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2, RSVD_FP8E4M3 = 3 }; /* dtypes    */
+enum { RSVD_LOC_DEVICE = 0, RSVD_LOC_HOST_PINNED = 1 };              /* locations */
+enum { RSVD_ORTHO_EACH = 0, RSVD_ORTHO_FINAL_ONLY = 2 };             /* schedules */
+enum {
+  RSVD_FLAG_NO_SIGN_FIX = 1,   /* skip the sign convention                          */
+  RSVD_FLAG_CHOLQR1 = 2        /* one CholeskyQR pass for intermediate bases        */
+};
+
+/* The problem: A is m x n, rank k, oversampling p, q power steps
+ * (Section 2.1; Section 2.2, Eq. (1)), Gaussian test matrix from `seed`. */
+typedef struct {
+  int64_t m, n, k, p, q;
+  int32_t format;   /* RSVD_DENSE (RSVD_CSR reserved)                   */
+  int32_t dtype;    /* storage type of A: RSVD_F32 or RSVD_F64            */
+  int32_t loc;      /* RSVD_LOC_DEVICE                                    */
+  int32_t reserved;
+  uint64_t seed;
+  int64_t nnz;      /* CSR only                                           */
+} rsvd_problem;
+
+/* Options.  prec_* choose the operand type of the products with A in the
+ * sketch, the power steps and the projection (RSVD_F32 or RSVD_BF16); all
+ * products accumulate in FP32, Gram/Cholesky/small SVD run in FP64.
+ * tile_m/tile_n: block-cyclic tile size (0 = chosen by the plan);
+ * grid_p/grid_q: process grid of the block-cyclic map (1 x 1 on one GPU).
+ * hbm_budget_bytes: cap on the device workspace (0 = none). */
+typedef struct {
+  int32_t prec_sketch, prec_power, prec_project;
+  int32_t ortho;
+  int64_t tile_m, tile_n;
+  int64_t grid_p, grid_q;
+  uint64_t hbm_budget_bytes;
+  int32_t flags;
+  int32_t reserved;
+} rsvd_options;
+
+/* Stage timers follow the paper's stage list (Section 4.1): 0 Gaussian O,
+ * 1 sketch A O, 2 orthogonalisation of the sketch, 3 power steps (products
+ * and their orthogonalisation), 4 projection A^T Q, 5 SVD0 preparation
+ * (Gram of B), 6 SVD0, 7 post-processing.  gemm_*_ms sum the device time of
+ * the product kernels alone (HIP events around each launch on the stream). */
+typedef struct {
+  double stage_ms[8];
+  double total_ms;
+  double flops_alg;        /* algorithmic flops of the passes over A        */
+  double bytes_alg;        /* algorithmic HBM bytes of the passes over A    */
+  double gemm_nn_ms;       /* summed time of the A X product kernels        */
+  double gemm_tn_ms;       /* summed time of the A^T X product kernels      */
+  int64_t ws_bytes;        /* device workspace used                         */
+  int32_t gemm_nn_launches;
+  int32_t gemm_tn_launches;
+  int32_t dropped;         /* sketch directions dropped as dependent        */
+  int32_t jacobi_sweeps;   /* sweeps of the small eigensolver               */
+  int32_t nonfinite;       /* NaN/Inf seen on the device                    */
+  int32_t reserved;
+} rsvd_report;
+
+typedef struct rsvd_plan_s* rsvd_plan_t;
+
+/* Validate the problem and options, build the block-cyclic tile maps and size
+ * the device workspace (Section 3.4: sizes are known before running).  Host
+ * only: makes no HIP call.  On success *out holds a new plan and
+ * *device_ws_bytes the workspace rsvd_factor needs (256-byte aligned).
+ * Errors: RSVD_E_INVALID_ARG (k < 1, p < 0, q < 0, k + p > min(m, n),
+ * bad enum, tile sizes), RSVD_E_UNSUPPORTED (format/dtype/location not
+ * implemented), RSVD_E_BUDGET (workspace above hbm_budget_bytes; the message
+ * states the bytes needed).  opt may be NULL (defaults: FP32 everywhere,
+ * ortho EACH, automatic tiles, no budget). */
+rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_plan_t* out,
+                      size_t* device_ws_bytes);
+
+/* Run the randomized SVD (Section 2.1 steps 1-7 on the power matrix of
+ * Section 2.2) on the device stream `stream`.
+ *   A      device pointer, row-major m x n of the plan's dtype, leading
+ *          dimension lda >= n (elements), naturally aligned.  Rows that are
+ *          16-byte aligned (lda % 4 == 0 and A 16-byte aligned for FP32) take
+ *          the vector-load path.
+ *   ws     device workspace of at least device_ws_bytes, 256-byte aligned.
+ *   U, S, V outputs (device): U m x k column-major (ldu >= m), S k doubles,
+ *          V n x k column-major (ldv >= n).
+ *   report optional (may be NULL).  If given, the call waits for the
+ *          stream, fills the report and turns device-side outcomes into the
+ *          status (RSVD_E_NUMERIC, RSVD_W_RANK_DEFICIENT); if NULL the call
+ *          only enqueues work and returns RSVD_OK on successful launch. */
+rsvd_status rsvd_factor(rsvd_plan_t plan, const void* A, int64_t lda, void* ws,
+                        float* U, int64_t ldu, double* S, float* V, int64_t ldv,
+                        void* stream, rsvd_report* report);
+
+/* Free a plan (NULL is ignored). */
+void rsvd_plan_destroy(rsvd_plan_t plan);
+
+/* Static text of a status code. */
+const char* rsvd_status_str(rsvd_status s);
+
+/* Message of the last failing call on `plan` (NULL: last plan-less call or
+ * last rsvd_plan failure).  Valid until the next call on that plan. */
+const char* rsvd_last_error(rsvd_plan_t plan);
+
+/* Library version, e.g. "rsvd-mi355x 0.1". */
+const char* rsvd_version(void);
+
+/* ---- inspection hooks (used by the parity tests) ------------------------ */
+
+/* Tile descriptors of the plan's block-cyclic map over A (Sections 2.3, 3.1),
+ * 12 int64 per tile in I-major order:
+ *   I, J, row0, rows, col0, cols, owner_p, owner_q, local_I, local_J,
+ *   local_row0, local_col0.
+ * Writes min(cap, 12 * tiles) values to out (host memory) and the full count
+ * of values to *n_out.  Host only. */
+rsvd_status rsvd_tile_map(rsvd_plan_t plan, int64_t* out, size_t cap, size_t* n_out);
+
+/* Order in which pass `pass_index` (0 = sketch, then alternating A^T and A
+ * products, 2q+1 = projection) visits the tiles, as linear indices
+ * I * tiles_n + J: even passes row-major forward, odd passes column-major
+ * backward (each pass starts on the tile the previous one ended on).
+ * Host only; semantics of cap/n_out as in rsvd_tile_map. */
+rsvd_status rsvd_visit_order(rsvd_plan_t plan, int64_t pass_index, int64_t* out, size_t cap,
+                             size_t* n_out);
+
+/* Raw Philox-4x32-10 words of the Gaussian test matrix (Section 2.1, step 1):
+ * for rows j in [row0, row0 + rows) and column blocks b in [0, blocks) writes
+ * the four 32-bit words of counter (b, j mod 2^32, j / 2^32, stream) under key
+ * (seed mod 2^32, seed / 2^32) to out[((j - row0) * blocks + b) * 4 + w]
+ * (device memory, rows * blocks * 4 uint32).  Asynchronous on `stream`. */
+rsvd_status rsvd_philox_raw(uint64_t seed, uint32_t stream_id, int64_t row0, int64_t rows,
+                            int64_t blocks, uint32_t* out, void* stream);
+
+/* Gaussian test matrix O (n x l) rows [row0, row0 + rows), entry (j, c) from
+ * Philox words -> uniforms (x + 1/2) 2^-32 -> Box-Muller in FP64, written as
+ * FP64 (dtype RSVD_F64) or FP32 (RSVD_F32) into out[(j - row0) * ldo + c]
+ * (device, row-major, ldo >= l).  Asynchronous on `stream`. */
+rsvd_status rsvd_omega(uint64_t seed, int64_t n, int64_t l, int64_t row0, int64_t rows,
+                       int32_t dtype, void* out, int64_t ldo, void* stream);
+
+
+/* ---- single-step hooks: one step of rsvd_factor in isolation ------------- */
+/* They run the same kernels as rsvd_factor on caller panels, using the plan's
+ * workspace `ws` for staging.  Panels are column-major FP32 (element (i, c) at
+ * P[i + c * ld]) with l = k + p columns.  Asynchronous on `stream`. */
+
+/* Block-wise product with A over the plan's tiles (Section 2.3, Eq. (3)):
+ * op 0: out (m x l, ldo >= m) = A X with X n x l (ldx >= n);
+ * op 1: out (n x l, ldo >= n) = A^T X with X m x l (ldx >= m).
+ * A as in rsvd_factor (dtype of the plan; FP64 is cast to FP32 first). */
+rsvd_status rsvd_step_product(rsvd_plan_t plan, int32_t op, const void* A, int64_t lda,
+                              const float* X, int64_t ldx, float* out, int64_t ldo, void* ws,
+                              void* stream);
+
+/* Orthonormal basis of the columns of Y (Section 2.1, steps 3-4) by
+ * CholeskyQR twice (FP64 Gram and Cholesky), dependent directions dropped as
+ * zero columns.  side 0: Y has m rows, side 1: n rows.  Q may alias Y. */
+rsvd_status rsvd_step_orth(rsvd_plan_t plan, int32_t side, const float* Y, int64_t ldy, float* Q,
+                           int64_t ldq, void* ws, void* stream);
+
+/* Gram matrix G = Y^T Y (l x l, FP64, row-major at G[a * l + c]) of a panel
+ * with m rows (side 0) or n rows (side 1): FP64 products of the FP32
+ * entries summed in FP64 (the CholeskyQR and SVD0-preparation step). */
+rsvd_status rsvd_step_gram(rsvd_plan_t plan, int32_t side, const float* Y, int64_t ldy, double* G,
+                           void* ws, void* stream);
+
+/* SVD of the small B = Bt^T (Section 2.1, step 6) from Bt (n x l, ldb >= n):
+ * C = B B^T in FP64, cyclic Jacobi eigensolver, sorted descending.  Writes
+ * the l singular values to sig (device, FP64) and U_B (l x l, FP64,
+ * row-major: U_B(a, c) at ub[a * l + c], column c belongs to sig[c]). */
+rsvd_status rsvd_step_small_svd(rsvd_plan_t plan, const float* Bt, int64_t ldb, double* sig,
+                                double* ub, void* ws, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H */

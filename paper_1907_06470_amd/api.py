@@ -1,0 +1,183 @@
+"""Python binding of the randomized SVD library (argument marshalling only).
+
+PyTorch supplies device memory and the stream; every step of the computation
+runs in the HIP kernels of librsvd.so.  Panels handed to and from the library
+are column-major: a torch tensor of shape (rows, cols) with strides
+(1, ld), built as ``torch.empty(cols, ld)[:, :rows].T``.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.F32, torch.float64: L.F64}
+_PREC = {"fp32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def col_major(rows, cols, dtype=torch.float32, device="cuda", ld=None):
+    """Empty column-major (rows, cols) tensor with leading dimension ld."""
+    ld = rows if ld is None else ld
+    return torch.empty(cols, ld, dtype=dtype, device=device)[:, :rows].T
+
+
+def _ld_col_major(t):
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("panel must be column-major (stride (1, ld))")
+    return t.stride(1) if t.shape[1] > 1 else max(t.shape[0], 1)
+
+
+def _ld_row_major(A):
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be row-major with unit column stride")
+    return A.stride(0) if A.shape[0] > 1 else A.shape[1]
+
+
+class Plan:
+    """A validated problem with its tile map and workspace size."""
+
+    def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
+                 tile=None, grid=(1, 1), hbm_budget=0, flags=0):
+        prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE, dtype=_DT.get(dtype, -99),
+                         loc=L.LOC_DEVICE, reserved=0, seed=seed, nnz=0)
+        pr = _PREC.get(precision, -99) if isinstance(precision, str) else -99
+        tm, tn = (tile if tile is not None else (0, 0))
+        opt = L.Options(prec_sketch=pr, prec_power=pr, prec_project=pr, ortho=L.ORTHO_EACH,
+                        tile_m=tm, tile_n=tn, grid_p=grid[0], grid_q=grid[1],
+                        hbm_budget_bytes=int(hbm_budget), flags=flags, reserved=0)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        st = L.lib().rsvd_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h),
+                               ctypes.byref(ws))
+        L.check(st, None)
+        self.handle = h
+        self.ws_bytes = ws.value
+        self.m, self.n, self.k, self.p, self.q, self.seed = m, n, k, p, q, seed
+        self.l = k + p
+        self.dtype = dtype
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib().rsvd_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def workspace(self, device="cuda"):
+        return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
+
+    def tile_map(self):
+        n = ctypes.c_size_t()
+        L.check(L.lib().rsvd_tile_map(self.handle, None, 0, ctypes.byref(n)), self.handle)
+        buf = (ctypes.c_int64 * n.value)()
+        L.check(L.lib().rsvd_tile_map(self.handle, buf, n.value, ctypes.byref(n)), self.handle)
+        return torch.tensor(list(buf), dtype=torch.int64).reshape(-1, 12)
+
+    def visit_order(self, pass_index):
+        n = ctypes.c_size_t()
+        L.check(L.lib().rsvd_visit_order(self.handle, pass_index, None, 0, ctypes.byref(n)),
+                self.handle)
+        buf = (ctypes.c_int64 * n.value)()
+        L.check(L.lib().rsvd_visit_order(self.handle, pass_index, buf, n.value, ctypes.byref(n)),
+                self.handle)
+        return torch.tensor(list(buf), dtype=torch.int64)
+
+    # ---- calls that run on the GPU ---------------------------------------
+    def factor(self, A, ws=None, out=None, stream=None, report=True):
+        """Randomized SVD of A (cuda tensor, row-major).  Returns
+        (U (m x k, column-major), S (k, FP64), V (n x k, column-major), info)."""
+        lda = _ld_row_major(A)
+        if A.dtype != self.dtype or tuple(A.shape) != (self.m, self.n) or not A.is_cuda:
+            raise ValueError("A does not match the plan")
+        ws = self.workspace(A.device) if ws is None else ws
+        if out is None:
+            U = col_major(self.m, self.k, device=A.device)
+            S = torch.empty(self.k, dtype=torch.float64, device=A.device)
+            V = col_major(self.n, self.k, device=A.device)
+        else:
+            U, S, V = out
+        rep = L.Report() if report else None
+        st = L.lib().rsvd_factor(self.handle, _ptr(A), lda, _ptr(ws), _ptr(U), _ld_col_major(U),
+                                 _ptr(S), _ptr(V), _ld_col_major(V), _stream_ptr(stream),
+                                 ctypes.byref(rep) if rep is not None else None)
+        L.check(st, self.handle)
+        info = {"status": st}
+        if rep is not None:
+            info.update(stage_ms=list(rep.stage_ms), total_ms=rep.total_ms,
+                        flops_alg=rep.flops_alg, bytes_alg=rep.bytes_alg,
+                        gemm_nn_ms=rep.gemm_nn_ms, gemm_tn_ms=rep.gemm_tn_ms,
+                        gemm_nn_launches=rep.gemm_nn_launches,
+                        gemm_tn_launches=rep.gemm_tn_launches,
+                        ws_bytes=rep.ws_bytes, dropped=rep.dropped,
+                        jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite)
+        return U, S, V, info
+
+    def step_product(self, op, A, X, ws=None, stream=None):
+        rows_out = self.m if op == 0 else self.n
+        out = col_major(rows_out, self.l, device=A.device)
+        ws = self.workspace(A.device) if ws is None else ws
+        st = L.lib().rsvd_step_product(self.handle, op, _ptr(A), _ld_row_major(A), _ptr(X),
+                                       _ld_col_major(X), _ptr(out), _ld_col_major(out), _ptr(ws),
+                                       _stream_ptr(stream))
+        L.check(st, self.handle)
+        return out
+
+    def step_orth(self, side, Y, ws=None, stream=None):
+        rows = self.m if side == 0 else self.n
+        Q = col_major(rows, self.l, device=Y.device)
+        ws = self.workspace(Y.device) if ws is None else ws
+        st = L.lib().rsvd_step_orth(self.handle, side, _ptr(Y), _ld_col_major(Y), _ptr(Q),
+                                    _ld_col_major(Q), _ptr(ws), _stream_ptr(stream))
+        L.check(st, self.handle)
+        return Q
+
+    def step_gram(self, side, Y, ws=None, stream=None):
+        G = torch.empty(self.l, self.l, dtype=torch.float64, device=Y.device)
+        ws = self.workspace(Y.device) if ws is None else ws
+        st = L.lib().rsvd_step_gram(self.handle, side, _ptr(Y), _ld_col_major(Y), _ptr(G),
+                                    _ptr(ws), _stream_ptr(stream))
+        L.check(st, self.handle)
+        return G
+
+    def step_small_svd(self, Bt, ws=None, stream=None):
+        sig = torch.empty(self.l, dtype=torch.float64, device=Bt.device)
+        ub = torch.empty(self.l, self.l, dtype=torch.float64, device=Bt.device)
+        ws = self.workspace(Bt.device) if ws is None else ws
+        st = L.lib().rsvd_step_small_svd(self.handle, _ptr(Bt), _ld_col_major(Bt), _ptr(sig),
+                                         _ptr(ub), _ptr(ws), _stream_ptr(stream))
+        L.check(st, self.handle)
+        return sig, ub
+
+
+def factor(A, k, p, q, seed=0, precision="fp32", tile=None, flags=0, stream=None):
+    """One-call randomized SVD: returns (U, S, V, info)."""
+    plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, dtype=A.dtype, precision=precision,
+                tile=tile, flags=flags)
+    return plan.factor(A, stream=stream)
+
+
+def philox_raw(seed, stream_id, row0, rows, blocks, device="cuda"):
+    out = torch.empty(rows * blocks * 4, dtype=torch.int32, device=device)
+    st = L.lib().rsvd_philox_raw(seed, stream_id, row0, rows, blocks, _ptr(out), _stream_ptr())
+    L.check(st)
+    return out.view(rows, blocks, 4)
+
+
+def omega(seed, n, l, row0=0, rows=None, dtype=torch.float64, device="cuda"):
+    rows = n - row0 if rows is None else rows
+    out = torch.empty(rows, l, dtype=dtype, device=device)
+    st = L.lib().rsvd_omega(seed, n, l, row0, rows, _DT[dtype], _ptr(out), l, _stream_ptr())
+    L.check(st)
+    return out

@@ -1,0 +1,52 @@
+// Device-side helpers shared by the CDNA4 (gfx950) kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsvd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Launch-time description of a column-major panel: element (i, c) at
+// base[c * ld + i], rows valid, lp columns.
+struct PanelF32 {
+  float* p;
+  int64_t ld;
+};
+
+__device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ inline void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+// Load 4 consecutive floats from row-major storage with a per-element bound.
+__device__ inline float4 ld4_masked(const float* row, int64_t k, int64_t kend) {
+  if (k + 4 <= kend) return ld4(row + k);
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (k + 0 < kend) v.x = row[k + 0];
+  if (k + 1 < kend) v.y = row[k + 1];
+  if (k + 2 < kend) v.z = row[k + 2];
+  return v;
+}
+
+// Same, element by element (rows that are not 16-byte aligned).
+__device__ inline float4 ld4_scalar(const float* row, int64_t k, int64_t kend) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (k + 0 < kend) v.x = row[k + 0];
+  if (k + 1 < kend) v.y = row[k + 1];
+  if (k + 2 < kend) v.z = row[k + 2];
+  if (k + 3 < kend) v.w = row[k + 3];
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline int is_finite_d(double x) { return __builtin_isfinite(x); }
+
+}  // namespace rsvd

@@ -1,0 +1,630 @@
+// Small dense steps of the randomized SVD, FP64 where the conditioning needs
+// it:
+//  * Gram matrices P^T P of tall-skinny FP32 panels on the FP64 matrix cores
+//    (v_mfma_f64_16x16x4_f64), split over row chunks and summed in chunk
+//    order (deterministic).  Used by the QR of steps 3-4 (Section 2.1) as
+//    CholeskyQR, and for B B^T of step 6 ("SVD0 preparation", Section 4.1).
+//  * Cholesky G = L L^T (right-looking, one workgroup, packed triangle in
+//    LDS).  A pivot at or below tau times its original diagonal marks the
+//    direction as linearly dependent: its column is dropped (the basis gets a
+//    zero column and the direction is excluded from all later ones).
+//  * X = L^-1 column by column (one workgroup per column) and W = X^T, so that
+//    Q = Y W has orthonormal columns (R = L^T is the triangular QR factor).
+//  * Panel times small matrix on the FP32 matrix cores (Q = Y W, U = Q U_B,
+//    V = B^T U_B S^-1; step 7 of Section 2.1).
+//  * Cyclic Jacobi eigensolver for the symmetric B B^T (step 6), one
+//    workgroup, round-robin ordering of disjoint pairs, rotations logged and
+//    applied to the identity afterwards by a row-parallel kernel.
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int kMaxLp = 192;
+constexpr int kTri = kMaxLp * (kMaxLp + 1) / 2;
+
+__device__ inline int tidx(int i, int c) { return i * (i + 1) / 2 + c; }   // i >= c
+
+__device__ inline void tri_decode(int e, int& i, int& c) {
+  int ii = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+  while (ii * (ii + 1) / 2 > e) --ii;
+  while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+  i = ii;
+  c = e - ii * (ii + 1) / 2;
+}
+
+__device__ inline double nan_low(double x) { return x == x ? x : -__builtin_inf(); }
+
+__device__ inline f64x4 mfma64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- Gram ----
+// gpart[(chunk * npairs + pair) * 64 * 64 + r * 64 + c] =
+//   sum over rows i of the chunk of P(i, 64*ab + r) * P(i, 64*bb + c),
+// pair = ab * (ab + 1) / 2 + bb, ab >= bb.  4 waves in a 2 x 2 grid, each a
+// 32 x 32 block as 2 x 2 MFMA tiles of 16 x 16.
+__global__ __launch_bounds__(256) void k_gram_part(const float* __restrict__ P, int64_t ld,
+                                                   int64_t rows, int64_t lp, int64_t chunk_rows,
+                                                   double* __restrict__ gpart, int npairs) {
+  __shared__ __attribute__((aligned(16))) float Pa[64][68];
+  __shared__ __attribute__((aligned(16))) float Pb[64][68];
+  const int pair = blockIdx.x;
+  const int64_t chunk = blockIdx.y;
+  int ab = 0;
+  while ((ab + 1) * (ab + 2) / 2 <= pair) ++ab;
+  const int bb = pair - ab * (ab + 1) / 2;
+  const int64_t r0 = chunk * chunk_rows;
+  const int64_t r1 = min(rows, r0 + chunk_rows);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wa = wave >> 1, wb = wave & 1, l16 = lane & 15, q = lane >> 4;
+  const int lrow = tid >> 4, lcol = (tid & 15) * 4;
+
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t it = r0; it < r1; it += 64) {
+    const int64_t i = it + lcol;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t ca = (int64_t)ab * 64 + lrow + 16 * s;
+      const int64_t cb = (int64_t)bb * 64 + lrow + 16 * s;
+      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+      if (ca < lp && i < r1) va = ld4_masked(P + ca * ld, i, r1);
+      if (cb < lp && i < r1) vb = ld4_masked(P + cb * ld, i, r1);
+      *reinterpret_cast<float4*>(&Pa[lrow + 16 * s][lcol]) = va;
+      *reinterpret_cast<float4*>(&Pb[lrow + 16 * s][lcol]) = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = *reinterpret_cast<const float4*>(&Pa[wa * 32 + t * 16 + l16][q * 16 + s4 * 4]);
+        bv[t] = *reinterpret_cast<const float4*>(&Pb[wb * 32 + t * 16 + l16][q * 16 + s4 * 4]);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb)
+            acc[ta][tb] = mfma64((double)av[ta][e], (double)bv[tb][e], acc[ta][tb]);
+      }
+    }
+    __syncthreads();
+  }
+  // FP64 16x16 accumulators: lane (l16, q) register r holds row q + 4 r of
+  // column l16 (rows strided by 4, unlike the FP32 layouts where a lane's
+  // registers are consecutive rows).
+  double* out = gpart + ((int64_t)chunk * npairs + pair) * 4096;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wa * 32 + ta * 16 + q + 4 * r;
+        const int col = wb * 32 + tb * 16 + l16;
+        out[row * 64 + col] = acc[ta][tb][r];
+      }
+}
+
+// G (lp x lp, full symmetric) from the chunk partials, summed in chunk order.
+__global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, int npairs,
+                              int64_t lp, double* __restrict__ G) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)npairs * 4096) return;
+  const int pair = (int)(t / 4096), e = (int)(t % 4096);
+  int ab = 0;
+  while ((ab + 1) * (ab + 2) / 2 <= pair) ++ab;
+  const int bb = pair - ab * (ab + 1) / 2;
+  const int64_t row = (int64_t)ab * 64 + e / 64, col = (int64_t)bb * 64 + e % 64;
+  if (row >= lp || col >= lp) return;
+  if (ab == bb && row < col) return;      // diagonal block: lower half writes both
+  double v = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) v += gpart[(c * npairs + pair) * 4096 + e];
+  G[row * lp + col] = v;
+  G[col * lp + row] = v;
+}
+
+// ------------------------------------------------------------ Cholesky ----
+// Lp: packed lower triangle of L (l rows), L(i, c) at i(i+1)/2 + c.
+__global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ G, int64_t lp, int l,
+                                               double* __restrict__ Lp, int32_t* status,
+                                               double tau) {
+  __shared__ double T[kTri];
+  __shared__ double d0[kMaxLp];
+  __shared__ double piv_s;
+  __shared__ int ndrop, nbad;
+  const int tid = threadIdx.x;
+  const int tot = l * (l + 1) / 2;
+  for (int e = tid; e < tot; e += blockDim.x) {
+    int i, c;
+    tri_decode(e, i, c);
+    T[e] = G[(int64_t)i * lp + c];
+  }
+  for (int i = tid; i < l; i += blockDim.x) d0[i] = G[(int64_t)i * lp + i];
+  if (tid == 0) {
+    ndrop = 0;
+    nbad = 0;
+  }
+  __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    if (tid == 0) {
+      const double d = T[tidx(j, j)];
+      double piv = 0.0;
+      if (!is_finite_d(d)) {
+        ++nbad;
+      } else if (!(d0[j] > 0.0) || !(d > tau * d0[j])) {
+        ++ndrop;
+      } else {
+        piv = sqrt(d);
+      }
+      T[tidx(j, j)] = piv;
+      piv_s = piv;
+    }
+    __syncthreads();
+    const double piv = piv_s;
+    const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+    for (int i = j + 1 + tid; i < l; i += blockDim.x) T[tidx(i, j)] *= inv;
+    __syncthreads();
+    if (piv > 0.0) {
+      const int nt = l - j - 1;
+      const int tt = nt * (nt + 1) / 2;
+      for (int e = tid; e < tt; e += blockDim.x) {
+        int ii, cc;
+        tri_decode(e, ii, cc);
+        const int i = j + 1 + ii, c = j + 1 + cc;
+        T[tidx(i, c)] -= T[tidx(i, j)] * T[tidx(c, j)];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < tot; e += blockDim.x) Lp[e] = T[e];
+  if (tid == 0) {
+    status[kStDropped] += ndrop;
+    status[kStNonFinite] += nbad;
+  }
+}
+
+// W row c = column c of X = L^-1 (so W = X^T, upper triangular), FP32.
+// Dropped directions (zero pivot) give zero rows and columns.  One wave per
+// column: the packed triangle is staged in LDS, then forward substitution
+// with a wave-wide dot product per row.
+__global__ __launch_bounds__(64) void k_trtri(const double* __restrict__ Lp, int64_t lp, int l,
+                                              float* __restrict__ W) {
+  __shared__ double T[kTri];
+  __shared__ double x[kMaxLp];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < kMaxLp; i += 64) x[i] = 0.0;
+  const int e0 = c < l ? tidx(c, 0) : 0;
+  const int e1 = l * (l + 1) / 2;
+  for (int e = e0 + lane; e < e1; e += 64) T[e] = Lp[e];
+  __syncthreads();
+  const bool live = c < l && T[tidx(c, c)] > 0.0;
+  if (live) {
+    if (lane == 0) x[c] = 1.0 / T[tidx(c, c)];
+    __syncthreads();
+    for (int i = c + 1; i < l; ++i) {
+      const double lii = T[tidx(i, i)];
+      double part = 0.0;
+      for (int p = c + lane; p < i; p += 64) part += T[tidx(i, p)] * x[p];
+      part = wave_sum(part);
+      if (lane == 0) x[i] = lii > 0.0 ? -part / lii : 0.0;
+      __syncthreads();
+    }
+  }
+  for (int i = lane; i < lp; i += 64) W[(int64_t)c * lp + i] = live ? (float)x[i] : 0.f;
+}
+
+// ------------------------------------------------------ panel x matrix ----
+// out(i, c) = sum_a P(i, a) W(a, c) for c < ncols; rows [rows, out_rows)
+// receive zeros.  One wave per 32 rows, all lp output columns.
+template <int NT, bool TRI>
+__global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int64_t ldp,
+                                               int64_t rows, int kdim, const float* __restrict__ W,
+                                               int64_t ldw, int ncols, float* __restrict__ out,
+                                               int64_t ldo, int64_t out_rows, int vec_ok) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int64_t i = rbase + l32;
+  const bool iok = i < rows;
+  f32x16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+  const int kd2 = (kdim + 1) & ~1;
+  for (int a0 = 0; a0 < kd2; a0 += 16) {
+    float av[8];
+    float bv[NT][8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int a = a0 + 2 * s + half;
+      av[s] = (iok && a < kdim) ? P[(int64_t)a * ldp + i] : 0.f;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bv[t][s] = (a < kdim) ? W[(int64_t)a * ldw + t * 32 + l32] : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (a0 + 2 * s >= kd2) break;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (TRI && a0 + 2 * s >= (t + 1) * 32) continue;
+        acc[t] = mfma32(av[s], bv[t][s], acc[t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = t * 32 + l32;
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t r = rbase + 8 * g + 4 * half;
+      float* dst = out + (int64_t)c * ldo + r;
+      if (vec_ok && r + 3 < out_rows) {
+        st4(dst, make_float4(acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2], acc[t][4 * g + 3]));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (r + e < out_rows) dst[e] = acc[t][4 * g + e];
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- Jacobi ----
+__device__ inline int rr_pos(int x, int t, int le) { return x == 0 ? 0 : 1 + (x - 1 + t) % (le - 1); }
+
+__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, int64_t lp, int l,
+                                                 double* __restrict__ rot, int64_t rot_rounds,
+                                                 double* __restrict__ lam, int32_t* status,
+                                                 double tol, int max_sweeps) {
+  __shared__ double T[kTri];
+  __shared__ double cc_s[kMaxLp / 2 + 1], ss_s[kMaxLp / 2 + 1];
+  __shared__ int pp_s[kMaxLp / 2 + 1], qq_s[kMaxLp / 2 + 1];
+  __shared__ int any_s;
+  const int tid = threadIdx.x;
+  const int le = l + (l & 1), np = le / 2, R = le - 1;
+  const int tot = l * (l + 1) / 2;
+  for (int e = tid; e < tot; e += blockDim.x) {
+    int i, c;
+    tri_decode(e, i, c);
+    T[e] = G[(int64_t)i * lp + c];
+  }
+  __syncthreads();
+  int sweeps = 0;
+  int64_t ridx = 0;
+  for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
+    if (tid == 0) any_s = 0;
+    __syncthreads();
+    for (int t = 0; t < R; ++t) {
+      if (tid < np) {
+        const int a = rr_pos(tid, t, le), b = rr_pos(le - 1 - tid, t, le);
+        const int p = min(a, b), q = max(a, b);
+        double c = 1.0, s = 0.0;
+        if (q < l) {
+          const double app = T[tidx(p, p)], aqq = T[tidx(q, q)], apq = T[tidx(q, p)];
+          if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            any_s = 1;
+          }
+        }
+        pp_s[tid] = p;
+        qq_s[tid] = q;
+        cc_s[tid] = c;
+        ss_s[tid] = s;
+        if (ridx < rot_rounds) {
+          rot[(ridx * np + tid) * 2 + 0] = c;
+          rot[(ridx * np + tid) * 2 + 1] = s;
+        }
+      }
+      __syncthreads();
+      const int nb = np * (np + 1) / 2;
+      for (int e = tid; e < nb; e += blockDim.x) {
+        int P1, P2;
+        tri_decode(e, P1, P2);
+        const int p1 = pp_s[P1], q1 = qq_s[P1], p2 = pp_s[P2], q2 = qq_s[P2];
+        const double c1 = cc_s[P1], s1 = ss_s[P1], c2 = cc_s[P2], s2 = ss_s[P2];
+        if (P1 == P2) {
+          if (q1 < l && s1 != 0.0) {
+            const double app = T[tidx(p1, p1)], aqq = T[tidx(q1, q1)], apq = T[tidx(q1, p1)];
+            const double tt = s1 / c1;
+            T[tidx(p1, p1)] = app - tt * apq;
+            T[tidx(q1, q1)] = aqq + tt * apq;
+            T[tidx(q1, p1)] = 0.0;
+          }
+          continue;
+        }
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        // block rows {p1, q1} x cols {p2, q2} of the symmetric matrix
+        const bool hq1 = q1 < l, hq2 = q2 < l;
+        auto at = [&](int r, int cidx) -> double& { return r >= cidx ? T[tidx(r, cidx)] : T[tidx(cidx, r)]; };
+        const double x = at(p1, p2);
+        const double y = hq2 ? at(p1, q2) : 0.0;
+        const double z = hq1 ? at(q1, p2) : 0.0;
+        const double w = (hq1 && hq2) ? at(q1, q2) : 0.0;
+        const double x1 = c1 * x - s1 * z, y1 = c1 * y - s1 * w;
+        const double z1 = s1 * x + c1 * z, w1 = s1 * y + c1 * w;
+        at(p1, p2) = c2 * x1 - s2 * y1;
+        if (hq2) at(p1, q2) = s2 * x1 + c2 * y1;
+        if (hq1) at(q1, p2) = c2 * z1 - s2 * w1;
+        if (hq1 && hq2) at(q1, q2) = s2 * z1 + c2 * w1;
+      }
+      __syncthreads();
+      ++ridx;
+    }
+    ++sweeps;
+    const int any = any_s;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int i = tid; i < lp; i += blockDim.x) lam[i] = i < l ? T[tidx(i, i)] : 0.0;
+  if (tid == 0) {
+    status[kStSweeps] = sweeps;
+    status[kStRounds] = (int32_t)min(ridx, rot_rounds);
+  }
+}
+
+// Ev = I J_1 J_2 ... (rows independent): 4 rows per workgroup, one wave per
+// row, rotation log staged through LDS in chunks of rounds.
+constexpr int kVecChunk = 16;
+__global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ rot,
+                                                     const int32_t* __restrict__ status,
+                                                     int64_t lp, int l, double* __restrict__ Ev) {
+  __shared__ double rowv[4][kMaxLp + 2];
+  __shared__ double cs[kVecChunk][kMaxLp / 2 + 1][2];
+  const int le = l + (l & 1), np = le / 2, R = le - 1;
+  const int64_t rounds = status[kStRounds];
+  const int rsub = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + rsub;
+  for (int x = lane; x < kMaxLp + 2; x += 64) rowv[rsub][x] = (x == r) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int64_t t0 = 0; t0 < rounds; t0 += kVecChunk) {
+    const int nr = (int)min((int64_t)kVecChunk, rounds - t0);
+    for (int e = threadIdx.x; e < nr * np * 2; e += blockDim.x) {
+      const int tt = e / (np * 2), rem = e % (np * 2);
+      cs[tt][rem / 2][rem % 2] = rot[(t0 + tt) * np * 2 + rem];
+    }
+    __syncthreads();
+    for (int tt = 0; tt < nr; ++tt) {
+      const int tr = (int)((t0 + tt) % R);
+      for (int i = lane; i < np; i += 64) {
+        const double c = cs[tt][i][0], s = cs[tt][i][1];
+        if (s != 0.0) {
+          const int a = rr_pos(i, tr, le), b = rr_pos(le - 1 - i, tr, le);
+          const int p = min(a, b), q = max(a, b);
+          const double vp = rowv[rsub][p], vq = rowv[rsub][q];
+          rowv[rsub][p] = c * vp - s * vq;
+          rowv[rsub][q] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (r < lp)
+    for (int x = lane; x < lp; x += 64) Ev[(int64_t)r * lp + x] = (r < l && x < l) ? rowv[rsub][x] : 0.0;
+}
+
+// Sort eigenvalues descending (ties by index), S = sqrt(lambda) for the first
+// k, Wu(a, c) = Ev(a, order c), Wv(a, c) = Wu(a, c) / sigma_c (0 if sigma_c is
+// negligible), both lp x lp row-major FP32 with zero columns from k on.
+__global__ __launch_bounds__(256) void k_finish_small(const double* __restrict__ lam,
+                                                      const double* __restrict__ Ev, int64_t lp,
+                                                      int l, int k, double* __restrict__ S,
+                                                      float* __restrict__ Wu,
+                                                      float* __restrict__ Wv,
+                                                      int32_t* __restrict__ order_out,
+                                                      int32_t* status) {
+  __shared__ int order[kMaxLp];
+  __shared__ double sig[kMaxLp];
+  __shared__ int nzero;
+  const int tid = threadIdx.x;
+  if (tid == 0) nzero = 0;
+  // Rank by a strict total order: NaN counts as -inf and ties go by index,
+  // so the ranks are a permutation of [0, l) whatever the values are.
+  for (int i = tid; i < l; i += blockDim.x) {
+    const double li = nan_low(lam[i]);
+    int rank = 0;
+    for (int j = 0; j < l; ++j) {
+      const double lj = nan_low(lam[j]);
+      rank += (lj > li) || (lj == li && j < i);
+    }
+    order[rank] = i;
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int j = 0; j < l; ++j) smax = fmax(smax, nan_low(lam[j]));
+  smax = sqrt(fmax(smax, 0.0));
+  for (int c = tid; c < l; c += blockDim.x) {
+    const double s = sqrt(fmax(lam[order[c]], 0.0));
+    sig[c] = s;
+    if (c < k) {
+      S[c] = s;
+      if (!(s > 1e-12 * smax)) atomicAdd(&nzero, 1);
+    }
+    order_out[c] = order[c];
+  }
+  __syncthreads();
+  for (int e = tid; e < lp * lp; e += blockDim.x) {
+    const int a = e / (int)lp, c = e % (int)lp;
+    float u = 0.f, v = 0.f;
+    if (a < l && c < k) {
+      const double ev = Ev[(int64_t)a * lp + order[c]];
+      u = (float)ev;
+      v = sig[c] > 1e-12 * smax ? (float)(ev / sig[c]) : 0.f;
+    }
+    Wu[e] = u;
+    Wv[e] = v;
+  }
+  if (tid == 0) status[kStRankSmall] = nzero;
+}
+
+// Sign convention: in every column c < k of V the entry of largest magnitude
+// (lowest row on ties) becomes positive; U's column flips with it.
+__global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ U, int64_t ldu, int64_t m,
+                                                  float* __restrict__ V, int64_t ldv, int64_t n) {
+  __shared__ float bv[256];
+  __shared__ int64_t bi[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  float best = -1.f;
+  int64_t bidx = 0;
+  for (int64_t j = tid; j < n; j += blockDim.x) {
+    const float a = fabsf(V[(int64_t)c * ldv + j]);
+    if (a > best) {   // strided scan: earlier j of this thread wins ties
+      best = a;
+      bidx = j;
+    }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      const float ob = bv[tid + off];
+      const int64_t oi = bi[tid + off];
+      if (ob > bv[tid] || (ob == bv[tid] && oi < bi[tid])) {
+        bv[tid] = ob;
+        bi[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = V[(int64_t)c * ldv + bi[0]] < 0.f;
+  if (!flip) return;
+  for (int64_t i = tid; i < m; i += blockDim.x) U[(int64_t)c * ldu + i] = -U[(int64_t)c * ldu + i];
+  for (int64_t j = tid; j < n; j += blockDim.x) V[(int64_t)c * ldv + j] = -V[(int64_t)c * ldv + j];
+}
+
+// out(a, c) = Ev(a, order c) for a, c < l (row-major l x l, FP64).
+__global__ void k_gather_cols(const double* __restrict__ Ev, int64_t lp, int l,
+                              const int32_t* __restrict__ order, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)l * l) return;
+  const int a = (int)(t / l), c = (int)(t % l);
+  const int oc = min(max(order[c], 0), l - 1);
+  out[t] = Ev[(int64_t)a * lp + oc];
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+}  // namespace
+
+hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
+                       int64_t chunks, double* gpart, double* G, hipStream_t s) {
+  const int nb = (int)ceil_div_dev(lp, 64);
+  const int npairs = nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(k_gram_part, dim3((unsigned)npairs, (unsigned)chunks), dim3(256), 0, s, P, ld,
+                     rows, lp, chunk_rows, gpart, npairs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div_dev((int64_t)npairs * 4096, 256)),
+                     dim3(256), 0, s, gpart, chunks, npairs, lp, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
+                       double tau, hipStream_t s) {
+  if (lp > kMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, s, G, lp, (int)l, L, status, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_trtri(const double* L, int64_t lp, int64_t l, float* W, hipStream_t s) {
+  if (lp > kMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trtri, dim3((unsigned)lp), dim3(64), 0, s, L, lp, (int)l, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
+                        int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out, int64_t ldo,
+                        int64_t out_rows_total, hipStream_t s) {
+  const int vec_ok = ((ldo % 4) == 0 && (((uintptr_t)out) & 15) == 0) ? 1 : 0;
+  dim3 grid((unsigned)ceil_div_dev(out_rows_total, 128));
+#define AP_CALL(NT)                                                                           \
+  do {                                                                                        \
+    if (tri)                                                                                  \
+      hipLaunchKernelGGL((k_apply<NT, true>), grid, dim3(256), 0, s, P, ldp, rows, (int)kdim, \
+                         W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);               \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_apply<NT, false>), grid, dim3(256), 0, s, P, ldp, rows,           \
+                         (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);    \
+  } while (0)
+  switch (lp / 32) {
+    case 1: AP_CALL(1); break;
+    case 2: AP_CALL(2); break;
+    case 3: AP_CALL(3); break;
+    case 4: AP_CALL(4); break;
+    case 5: AP_CALL(5); break;
+    case 6: AP_CALL(6); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef AP_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
+                         double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s) {
+  if (lp > kMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, G, lp, (int)l, rot, rot_rounds, lam,
+                     status, tol, max_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
+                              double* Ev, hipStream_t s) {
+  if (lp > kMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi_vecs, dim3((unsigned)ceil_div_dev(lp, 4)), dim3(256), 0, s, rot,
+                     status, lp, (int)l, Ev);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, int64_t l,
+                               int64_t k, double* S, float* Wu, float* Wv, int32_t* order,
+                               int32_t* status, hipStream_t s) {
+  if (lp > kMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish_small, dim3(1), dim3(256), 0, s, lam, Ev, lp, (int)l, (int)k, S, Wu,
+                     Wv, order, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, float* V, int64_t ldv, int64_t n,
+                           int64_t k, int32_t* work, hipStream_t s) {
+  (void)work;
+  hipLaunchKernelGGL(k_sign_fix, dim3((unsigned)k), dim3(256), 0, s, U, ldu, m, V, ldv, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double* Ev, int64_t lp, int64_t l, const int32_t* order,
+                              double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div_dev(l * l, 256)), dim3(256), 0, s, Ev,
+                     lp, (int)l, order, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div_dev(count, 256)), dim3(256), 0, s, p,
+                     count, v);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,62 @@
+// Host-side launchers of the gfx950 kernels.  Every launcher checks nothing
+// but the launch itself; shapes are validated by the planner and the driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsvd {
+
+inline int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// --- Gaussian test matrix (k_philox.hip) ---
+hipError_t launch_philox_raw(uint64_t seed, uint32_t stream_id, int64_t row0, int64_t rows,
+                             int64_t blocks, uint32_t* out, hipStream_t s);
+hipError_t launch_omega_rows(uint64_t seed, int64_t l, int64_t row0, int64_t rows, bool f64,
+                             void* out, int64_t ldo, hipStream_t s);
+hipError_t launch_omega_panel(uint64_t seed, int64_t n, int64_t l, int64_t lp, float* X,
+                              int64_t ld, hipStream_t s);
+
+// --- products with A (k_gemm_f32.hip) ---
+// Y(:, 0:lp) (+ partial J at Y + J * part_stride) = A(:, tile J) * X(tile J, 0:lp)
+hipError_t launch_nn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tn, int64_t TJ,
+                         const float* X, int64_t ldx, int64_t lp, float* Y, int64_t ldy,
+                         int64_t part_stride, hipStream_t s);
+// Z(:, 0:lp) (+ partial I) = A(tile I, :)^T * Q(tile I, 0:lp)
+hipError_t launch_tn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tm, int64_t TI,
+                         const float* Q, int64_t ldq, int64_t lp, float* Z, int64_t ldz,
+                         int64_t part_stride, hipStream_t s);
+// out = sum over S partials (fixed order), float4 granularity, count floats
+hipError_t launch_reduce_parts(const float* part, int64_t stride, int64_t S, float* out,
+                               int64_t count, hipStream_t s);
+hipError_t launch_panel_copy(const float* src, int64_t lds, int64_t rows, int64_t cols, float* dst,
+                             int64_t ldd, int64_t dst_rows, int64_t dst_cols, hipStream_t s);
+hipError_t launch_cast_f64_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out,
+                               int64_t ldo, hipStream_t s);
+
+// --- small dense FP64 steps (k_small.hip) ---
+hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
+                       int64_t chunks, double* gpart, double* G, hipStream_t s);
+hipError_t launch_chol(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
+                       double tau, hipStream_t s);
+hipError_t launch_trtri(const double* L, int64_t lp, int64_t l, float* W, hipStream_t s);
+// out(:, 0:ncols) = P(:, 0:kdim) * W(0:kdim, 0:ncols); W row-major with ldw;
+// `tri`: W upper triangular (skip zero blocks).  Rows [rows, ld) written as 0.
+hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
+                        int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out,
+                        int64_t ldo, int64_t out_rows_total, hipStream_t s);
+hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
+                         double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s);
+hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
+                              double* Ev, hipStream_t s);
+// sort eigenvalues, form S (k values), Wu = Ev(:, order(0:k)), Wv = Wu / sigma
+hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, int64_t l,
+                               int64_t k, double* S, float* Wu, float* Wv, int32_t* order,
+                               int32_t* status, hipStream_t s);
+hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, float* V, int64_t ldv, int64_t n,
+                           int64_t k, int32_t* work, hipStream_t s);
+hipError_t launch_gather_cols(const double* Ev, int64_t lp, int64_t l, const int32_t* order,
+                              double* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+
+}  // namespace rsvd

@@ -1,0 +1,157 @@
+// Host-only planner: validation, block-cyclic tiles, splits, workspace layout.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace rsvd {
+
+rsvd_options default_options() {
+  rsvd_options o{};
+  o.prec_sketch = o.prec_power = o.prec_project = RSVD_F32;
+  o.ortho = RSVD_ORTHO_EACH;
+  o.tile_m = o.tile_n = 0;
+  o.grid_p = o.grid_q = 1;
+  o.hbm_budget_bytes = 0;
+  o.flags = 0;
+  return o;
+}
+
+static rsvd_status fail(Plan& p, rsvd_status s, const char* fmt, long long a = 0, long long b = 0,
+                        long long c = 0) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, fmt, a, b, c);
+  p.last_error = buf;
+  return s;
+}
+
+int64_t gram_chunks_for(const Plan& p, int64_t rows) {
+  return std::max<int64_t>(1, ceil_div(rows, p.gram_rows));
+}
+
+// Auto tile size along a dimension of `len` so that `other_blocks` x tiles
+// workgroups fill the device several times, with at most 64 tiles.
+static int64_t auto_tile(int64_t len, int64_t other_blocks) {
+  const int64_t want_wgs = 1024;
+  int64_t tiles = std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(want_wgs, other_blocks)));
+  int64_t t = round_up(ceil_div(len, tiles), 256);
+  return std::max<int64_t>(t, 256);
+}
+
+rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& p) {
+  p.prob = prob;
+  p.opt = optp ? *optp : default_options();
+  const rsvd_options& o = p.opt;
+  const int64_t m = prob.m, n = prob.n, k = prob.k, pp = prob.p, q = prob.q;
+
+  if (m < 1 || n < 1) return fail(p, RSVD_E_INVALID_ARG, "m=%lld and n=%lld must be >= 1", m, n);
+  if (k < 1) return fail(p, RSVD_E_INVALID_ARG, "k=%lld must be >= 1", k);
+  if (pp < 0) return fail(p, RSVD_E_INVALID_ARG, "p=%lld must be >= 0", pp);
+  if (q < 0 || q > 64) return fail(p, RSVD_E_INVALID_ARG, "q=%lld must be in [0, 64]", q);
+  if (k + pp > std::min(m, n))
+    return fail(p, RSVD_E_INVALID_ARG, "k + p = %lld exceeds min(m, n) = %lld", k + pp,
+                std::min(m, n));
+  if (prob.format != RSVD_DENSE) {
+    if (prob.format == RSVD_CSR) return fail(p, RSVD_E_UNSUPPORTED, "CSR input is not implemented");
+    return fail(p, RSVD_E_INVALID_ARG, "unknown format %lld", prob.format);
+  }
+  if (prob.dtype != RSVD_F32 && prob.dtype != RSVD_F64) {
+    if (prob.dtype == RSVD_BF16 || prob.dtype == RSVD_FP8E4M3)
+      return fail(p, RSVD_E_UNSUPPORTED, "A stored as dtype %lld is not implemented", prob.dtype);
+    return fail(p, RSVD_E_INVALID_ARG, "unknown dtype %lld", prob.dtype);
+  }
+  if (prob.loc != RSVD_LOC_DEVICE) {
+    if (prob.loc == RSVD_LOC_HOST_PINNED)
+      return fail(p, RSVD_E_UNSUPPORTED, "host-resident A is not implemented");
+    return fail(p, RSVD_E_INVALID_ARG, "unknown location %lld", prob.loc);
+  }
+  for (int32_t pr : {o.prec_sketch, o.prec_power, o.prec_project}) {
+    if (pr != RSVD_F32 && pr != RSVD_BF16 && pr != RSVD_FP8E4M3)
+      return fail(p, RSVD_E_INVALID_ARG, "unknown product precision %lld", pr);
+    if (pr != RSVD_F32)
+      return fail(p, RSVD_E_UNSUPPORTED, "product precision %lld is not implemented", pr);
+  }
+  if (o.ortho != RSVD_ORTHO_EACH && o.ortho != RSVD_ORTHO_FINAL_ONLY)
+    return fail(p, RSVD_E_INVALID_ARG, "unknown ortho schedule %lld", o.ortho);
+  if (o.ortho == RSVD_ORTHO_FINAL_ONLY)
+    return fail(p, RSVD_E_UNSUPPORTED, "ortho FINAL_ONLY is not implemented");
+  if (o.grid_p < 1 || o.grid_q < 1)
+    return fail(p, RSVD_E_INVALID_ARG, "process grid %lld x %lld must be >= 1", o.grid_p, o.grid_q);
+  if (o.tile_m < 0 || o.tile_n < 0 || o.tile_m % 32 || o.tile_n % 32)
+    return fail(p, RSVD_E_INVALID_ARG, "tile sizes %lld x %lld must be >= 0 and multiples of 32",
+                o.tile_m, o.tile_n);
+  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1))
+    return fail(p, RSVD_E_INVALID_ARG, "unknown flags 0x%llx", o.flags);
+
+  p.l = k + pp;
+  p.lp = round_up(p.l, kColAlign);
+  if (p.lp > 192)
+    return fail(p, RSVD_E_UNSUPPORTED, "k + p = %lld: sketch widths above 192 are not implemented",
+                p.l);
+  p.ldm = round_up(m, kPanelAlign);
+  p.ldn = round_up(n, kPanelAlign);
+
+  // block-cyclic tiles over A; one tile spans the whole dimension at most
+  p.tm = o.tile_m ? std::min<int64_t>(o.tile_m, round_up(m, 32)) : auto_tile(m, ceil_div(n, 128));
+  p.tn = o.tile_n ? std::min<int64_t>(o.tile_n, round_up(n, 32)) : auto_tile(n, ceil_div(m, 128));
+  p.TI = ceil_div(m, p.tm);
+  p.TJ = ceil_div(n, p.tn);
+
+  // Gram chunking: enough chunks that the Gram kernels fill the device
+  {
+    const int64_t pairs = gram_pairs(p);
+    const int64_t want = 512;
+    const int64_t rows = std::max(m, n);
+    int64_t chunks = std::max<int64_t>(1, ceil_div(want, pairs));
+    p.gram_rows = std::max<int64_t>(256, round_up(ceil_div(rows, chunks), 64));
+    p.gram_chunks = gram_chunks_for(p, rows);
+  }
+  // Jacobi rotation log: rounds per sweep = (even width) - 1
+  {
+    int64_t le = p.l + (p.l & 1);
+    p.rot_rounds = (int64_t)kJacobiMaxSweeps * std::max<int64_t>(1, le - 1);
+  }
+
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += (size_t)round_up((int64_t)bytes, 256);
+    return at;
+  };
+  const size_t lp = (size_t)p.lp;
+  Workspace& w = p.ws;
+  w.Xop = take((size_t)p.ldn * lp * 4);
+  w.Mop = take((size_t)p.ldm * lp * 4);
+  w.M0 = take((size_t)p.ldm * lp * 4);
+  w.M1 = take((size_t)p.ldm * lp * 4);
+  w.N0 = take((size_t)p.ldn * lp * 4);
+  w.N1 = take((size_t)p.ldn * lp * 4);
+  {
+    size_t a = p.TJ > 1 ? (size_t)p.TJ * p.ldm * lp * 4 : 0;
+    size_t b = p.TI > 1 ? (size_t)p.TI * p.ldn * lp * 4 : 0;
+    w.part = take(std::max<size_t>(std::max(a, b), 256));
+  }
+  w.gpart = take((size_t)p.gram_chunks * gram_pairs(p) * kGramBlock * kGramBlock * 8);
+  w.G = take(lp * lp * 8);
+  w.L = take(lp * lp * 8);
+  w.W = take(lp * lp * 4);
+  w.W2 = take(lp * lp * 4);
+  w.Ev = take(lp * lp * 8);
+  w.lam = take(lp * 8);
+  w.order = take(lp * 4);
+  w.rot = take((size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8);
+  w.signs = take(lp * 4);
+  w.status = take(kStatusWords * 4);
+  w.Acast = prob.dtype == RSVD_F64 ? take((size_t)m * round_up(n, 64) * 4) : off;
+  p.ldac = round_up(n, 64);
+  w.total = off;
+
+  if (o.hbm_budget_bytes && w.total > o.hbm_budget_bytes)
+    return fail(p, RSVD_E_BUDGET, "workspace needs %lld bytes, budget is %lld", (long long)w.total,
+                (long long)o.hbm_budget_bytes);
+  p.last_error.clear();
+  return RSVD_OK;
+}
+
+}  // namespace rsvd

@@ -1,0 +1,80 @@
+// Host-only planner of the randomized SVD: argument validation, block-cyclic
+// tile maps, kernel splits and the device workspace layout.  No HIP calls:
+// everything here is decided before any device work starts (Section 3.4 of
+// the paper: memory needs of dense products are known exactly beforehand).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/rsvd.h"
+
+namespace rsvd {
+
+constexpr int64_t kPanelAlign = 256;   // panel leading dimensions (elements)
+constexpr int64_t kColAlign = 32;      // sketch width is padded to this
+constexpr int kGramBlock = 64;         // Gram output block edge
+constexpr int kJacobiMaxSweeps = 40;
+constexpr int kStatusWords = 64;
+
+// Device status word indices (int32 array in the workspace).
+enum StatusWord {
+  kStDropped = 0,      // directions dropped by the Cholesky step (sum over calls)
+  kStNonFinite = 1,    // NaN/Inf pivots met
+  kStSweeps = 2,       // Jacobi sweeps of the small eigensolver
+  kStRounds = 3,       // Jacobi rotation rounds logged
+  kStRankSmall = 4,    // zero singular values in the small SVD
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+struct Workspace {
+  // byte offsets into the device workspace
+  size_t Xop, Mop;        // operand panels (n x lp, m x lp)
+  size_t M0, M1;          // FP32 m-side panels (column-major, ld = ldm)
+  size_t N0, N1;          // FP32 n-side panels (ld = ldn)
+  size_t part;            // split-K partial products
+  size_t gpart;           // Gram partial blocks (FP64)
+  size_t G;               // lp x lp FP64 Gram
+  size_t L;               // lp x lp FP64 Cholesky factor
+  size_t W;               // lp x lp FP32 right factor applied to panels
+  size_t W2;              // lp x lp FP32 second right factor
+  size_t Ev;              // lp x lp FP64 eigenvectors
+  size_t lam;             // lp FP64 eigenvalues / singular values
+  size_t order;           // lp int32 sort order
+  size_t rot;             // Jacobi rotation log (FP64 pairs)
+  size_t signs;           // k int32 sign-fix argmax
+  size_t status;          // kStatusWords int32
+  size_t Acast;           // FP32 copy of an FP64 A
+  size_t total;
+};
+
+struct Plan {
+  rsvd_problem prob{};
+  rsvd_options opt{};
+  int64_t l = 0, lp = 0;        // sketch width, padded width
+  int64_t tm = 0, tn = 0;       // tile sizes
+  int64_t TI = 0, TJ = 0;       // tile counts (rows, cols)
+  int64_t ldm = 0, ldn = 0;     // panel leading dimensions
+  int64_t ldac = 0;             // leading dimension of the FP32 cast of A
+  int64_t gram_rows = 0;        // rows per Gram chunk
+  int64_t gram_chunks = 0;      // max chunks over the m- and n-side panels
+  int64_t rot_rounds = 0;       // capacity of the rotation log (rounds)
+  Workspace ws{};
+  std::string last_error;
+  void* hip_events = nullptr;   // created lazily by the driver
+};
+
+// Fill `plan` or return an error status with plan.last_error set.
+rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* opt, Plan& plan);
+
+// Gram chunking of a panel with `rows` rows.
+int64_t gram_chunks_for(const Plan& p, int64_t rows);
+inline int64_t gram_nb(const Plan& p) { return ceil_div(p.lp, kGramBlock); }
+inline int64_t gram_pairs(const Plan& p) { int64_t nb = gram_nb(p); return nb * (nb + 1) / 2; }
+
+rsvd_options default_options();
+
+}  // namespace rsvd

@@ -1,0 +1,549 @@
+// C ABI and pass schedule of the randomized SVD on one MI355X.
+//
+// Schedule (Section 2.1 steps 1-7 on the power matrix of Section 2.2):
+//   O (n x l) Gaussian                         step 1
+//   Y = A O, Q = orth(Y)                        steps 2-4
+//   q times: Z = A^T Q, Z = orth(Z),            Eq. (2), right to left,
+//            Y = A Z,   Q = orth(Y)             re-orthonormalised
+//   B^T = A^T Q                                 step 5 (computed transposed)
+//   C = B B^T (FP64), C = E diag(lambda) E^T    step 6 (Jacobi)
+//   U = Q E_k, S = sqrt(lambda_k), V = B^T E_k S^-1,  sign convention  step 7
+// orth() is CholeskyQR2 with an FP64 Gram and Cholesky.  Everything is
+// enqueued on one stream; the host waits only when a report is requested.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+struct rsvd_plan_s {
+  rsvd::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr double kCholTau = 1e-10;    // pivot / original diagonal below which a direction drops
+constexpr double kJacobiTol = 1e-14;  // relative off-diagonal size that ends a rotation
+constexpr int kNumEvents = 9;
+
+// Stage events plus one start/stop pair per product-kernel launch.
+struct Events {
+  hipEvent_t ev[kNumEvents];
+  std::vector<hipEvent_t> kern;   // 2 per product launch
+  bool made = false;
+};
+
+hipError_t make_events(Events& e, size_t kernel_pairs) {
+  if (!e.made) {
+    for (int i = 0; i < kNumEvents; ++i) {
+      hipError_t err = hipEventCreate(&e.ev[i]);
+      if (err != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(e.ev[j]);
+        return err;
+      }
+    }
+    e.made = true;
+  }
+  while (e.kern.size() < 2 * kernel_pairs) {
+    hipEvent_t x;
+    hipError_t err = hipEventCreate(&x);
+    if (err != hipSuccess) return err;
+    e.kern.push_back(x);
+  }
+  return hipSuccess;
+}
+
+void destroy_events(Events* e) {
+  if (!e) return;
+  if (e->made)
+    for (int i = 0; i < kNumEvents; ++i) (void)hipEventDestroy(e->ev[i]);
+  for (hipEvent_t x : e->kern) (void)hipEventDestroy(x);
+  delete e;
+}
+
+rsvd_status set_err(rsvd_plan_t h, rsvd_status s, const std::string& msg) {
+  if (h)
+    h->p.last_error = msg;
+  else
+    g_last_error = msg;
+  return s;
+}
+
+rsvd_status hip_err(rsvd_plan_t h, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return set_err(h, RSVD_E_HIP, msg);
+}
+
+#define RSVD_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_err(h, e_, #call);  \
+  } while (0)
+
+struct Buffers {
+  float *Xop, *Mop, *M0, *M1, *N0, *N1, *part, *W, *W2, *Acast;
+  double *gpart, *G, *L, *Ev, *lam, *rot;
+  int32_t *order, *signs, *status;
+};
+
+Buffers carve(const rsvd::Plan& P, void* ws) {
+  char* b = static_cast<char*>(ws);
+  const rsvd::Workspace& w = P.ws;
+  Buffers B;
+  B.Xop = (float*)(b + w.Xop);
+  B.Mop = (float*)(b + w.Mop);
+  B.M0 = (float*)(b + w.M0);
+  B.M1 = (float*)(b + w.M1);
+  B.N0 = (float*)(b + w.N0);
+  B.N1 = (float*)(b + w.N1);
+  B.part = (float*)(b + w.part);
+  B.W = (float*)(b + w.W);
+  B.W2 = (float*)(b + w.W2);
+  B.Acast = (float*)(b + w.Acast);
+  B.gpart = (double*)(b + w.gpart);
+  B.G = (double*)(b + w.G);
+  B.L = (double*)(b + w.L);
+  B.Ev = (double*)(b + w.Ev);
+  B.lam = (double*)(b + w.lam);
+  B.rot = (double*)(b + w.rot);
+  B.order = (int32_t*)(b + w.order);
+  B.signs = (int32_t*)(b + w.signs);
+  B.status = (int32_t*)(b + w.status);
+  return B;
+}
+
+// The runner holds everything one call needs.
+struct Runner {
+  rsvd_plan_t h;
+  const rsvd::Plan& P;
+  Buffers B;
+  hipStream_t s;
+  const float* A32 = nullptr;
+  int64_t lda32 = 0;
+  Events* ev = nullptr;        // non-null: time every product kernel
+  int nn_pairs = 0, tn_pairs = 0;
+  std::vector<int> nn_idx, tn_idx;
+  int next_pair = 0;
+
+  hipError_t tick(bool nn, bool start) {
+    if (!ev) return hipSuccess;
+    if (start) {
+      (nn ? nn_idx : tn_idx).push_back(next_pair);
+      return hipEventRecord(ev->kern[2 * next_pair], s);
+    }
+    return hipEventRecord(ev->kern[2 * (next_pair++) + 1], s);
+  }
+
+  Runner(rsvd_plan_t hh, void* ws, hipStream_t ss) : h(hh), P(hh->p), B(carve(hh->p, ws)), s(ss) {}
+
+  // A (row-major FP32 or FP64) -> A32/lda32
+  rsvd_status bind_A(const void* A, int64_t lda) {
+    if (P.prob.dtype == RSVD_F64) {
+      RSVD_HIP(rsvd::launch_cast_f64_f32((const double*)A, lda, P.prob.m, P.prob.n, B.Acast,
+                                         P.ldac, s));
+      A32 = B.Acast;
+      lda32 = P.ldac;
+    } else {
+      A32 = (const float*)A;
+      lda32 = lda;
+    }
+    return RSVD_OK;
+  }
+
+  // out (m-side panel, ld = ldm) = A X   (X: n-side panel, ld = ldn)
+  rsvd_status product_nn(const float* X, float* out) {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    RSVD_HIP(tick(true, true));
+    if (P.TJ == 1) {
+      RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, 1, X, P.ldn, P.lp, out, P.ldm, 0, s));
+      RSVD_HIP(tick(true, false));
+    } else {
+      const int64_t stride = P.ldm * P.lp;
+      RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, P.TJ, X, P.ldn, P.lp, B.part, P.ldm,
+                                   stride, s));
+      RSVD_HIP(tick(true, false));
+      RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TJ, out, stride, s));
+    }
+    return RSVD_OK;
+  }
+
+  // out (n-side panel) = A^T Q   (Q: m-side panel)
+  rsvd_status product_tn(const float* Q, float* out) {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    RSVD_HIP(tick(false, true));
+    if (P.TI == 1) {
+      RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, 1, Q, P.ldm, P.lp, out, P.ldn, 0, s));
+      RSVD_HIP(tick(false, false));
+    } else {
+      const int64_t stride = P.ldn * P.lp;
+      RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, P.TI, Q, P.ldm, P.lp, B.part, P.ldn,
+                                   stride, s));
+      RSVD_HIP(tick(false, false));
+      RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TI, out, stride, s));
+    }
+    return RSVD_OK;
+  }
+
+  rsvd_status gram(const float* Pn, int64_t rows, int64_t ld) {
+    const int64_t chunks = rsvd::gram_chunks_for(P, rows);
+    RSVD_HIP(rsvd::launch_gram(Pn, ld, rows, P.lp, P.gram_rows, chunks, B.gpart, B.G, s));
+    return RSVD_OK;
+  }
+
+  // One CholeskyQR pass: out = in R^-1 with R^T R = in^T in.
+  rsvd_status cholqr_pass(const float* in, float* out, int64_t rows, int64_t ld) {
+    rsvd_status st = gram(in, rows, ld);
+    if (st != RSVD_OK) return st;
+    RSVD_HIP(rsvd::launch_chol(B.G, P.lp, P.l, B.L, B.status, kCholTau, s));
+    RSVD_HIP(rsvd::launch_trtri(B.L, P.lp, P.l, B.W, s));
+    RSVD_HIP(rsvd::launch_apply(in, ld, rows, P.l, B.W, P.lp, P.lp, P.lp, true, out, ld, ld, s));
+    return RSVD_OK;
+  }
+
+  // Orthonormal basis of `in` written to `out` (CholeskyQR2, or one pass).
+  rsvd_status orth(const float* in, float* out, float* tmp, int64_t rows, int64_t ld, bool twice) {
+    if (!twice) return cholqr_pass(in, out, rows, ld);
+    rsvd_status st = cholqr_pass(in, tmp, rows, ld);
+    if (st != RSVD_OK) return st;
+    return cholqr_pass(tmp, out, rows, ld);
+  }
+
+  // Small SVD of B from Bt (n-side panel): leaves sorted S (k), Wu, Wv.
+  rsvd_status small_svd_eig(const float* Bt) {
+    rsvd_status st = gram(Bt, P.prob.n, P.ldn);
+    if (st != RSVD_OK) return st;
+    return RSVD_OK;
+  }
+  rsvd_status small_svd_solve(double* S, int64_t kout) {
+    RSVD_HIP(rsvd::launch_jacobi(B.G, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status, kJacobiTol,
+                                 rsvd::kJacobiMaxSweeps, s));
+    RSVD_HIP(rsvd::launch_jacobi_vecs(B.rot, B.status, P.lp, P.l, B.Ev, s));
+    RSVD_HIP(rsvd::launch_finish_small(B.lam, B.Ev, P.lp, P.l, kout, S, B.W, B.W2, B.order,
+                                       B.status, s));
+    return RSVD_OK;
+  }
+};
+
+rsvd_status check_plan(rsvd_plan_t h) {
+  if (!h) return set_err(nullptr, RSVD_E_INVALID_ARG, "plan is NULL");
+  return RSVD_OK;
+}
+
+rsvd_status check_A(rsvd_plan_t h, const void* A, int64_t lda) {
+  const rsvd::Plan& P = h->p;
+  if (!A) return set_err(h, RSVD_E_INVALID_ARG, "A is NULL");
+  if (lda < P.prob.n) return set_err(h, RSVD_E_INVALID_ARG, "lda < n");
+  if (P.prob.dtype == RSVD_F32 && (((uintptr_t)A) & 3) != 0)
+    return set_err(h, RSVD_E_INVALID_ARG, "FP32 A must be 4-byte aligned");
+  if (P.prob.dtype == RSVD_F64 && (((uintptr_t)A) & 7) != 0)
+    return set_err(h, RSVD_E_INVALID_ARG, "FP64 A must be 8-byte aligned");
+  return RSVD_OK;
+}
+
+rsvd_status check_ws(rsvd_plan_t h, void* ws) {
+  if (!ws) return set_err(h, RSVD_E_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws) & 255) return set_err(h, RSVD_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsvd_version(void) { return "rsvd-mi355x 0.1"; }
+
+const char* rsvd_status_str(rsvd_status s) {
+  switch (s) {
+    case RSVD_OK: return "ok";
+    case RSVD_W_RANK_DEFICIENT: return "warning: rank deficient sketch (directions dropped)";
+    case RSVD_W_DEGENERATE: return "warning: degenerate singular values";
+    case RSVD_E_INVALID_ARG: return "invalid argument";
+    case RSVD_E_BUDGET: return "workspace exceeds the HBM budget";
+    case RSVD_E_HIP: return "HIP runtime error";
+    case RSVD_E_UNSUPPORTED: return "unsupported combination";
+    case RSVD_E_NUMERIC: return "non-finite values met";
+    default: return "unknown status";
+  }
+}
+
+const char* rsvd_last_error(rsvd_plan_t plan) {
+  return plan ? plan->p.last_error.c_str() : g_last_error.c_str();
+}
+
+rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_plan_t* out,
+                      size_t* device_ws_bytes) {
+  if (!prob || !out || !device_ws_bytes)
+    return set_err(nullptr, RSVD_E_INVALID_ARG, "prob, out and device_ws_bytes must be non-NULL");
+  *out = nullptr;
+  *device_ws_bytes = 0;
+  rsvd_plan_s* h = new (std::nothrow) rsvd_plan_s;
+  if (!h) return set_err(nullptr, RSVD_E_INVALID_ARG, "out of host memory");
+  rsvd_status st = rsvd::make_plan(*prob, opt, h->p);
+  if (st < 0) {
+    g_last_error = h->p.last_error;
+    delete h;
+    return st;
+  }
+  *out = h;
+  *device_ws_bytes = h->p.ws.total;
+  return RSVD_OK;
+}
+
+void rsvd_plan_destroy(rsvd_plan_t plan) {
+  if (!plan) return;
+  destroy_events(static_cast<Events*>(plan->p.hip_events));
+  delete plan;
+}
+
+rsvd_status rsvd_tile_map(rsvd_plan_t h, int64_t* out, size_t cap, size_t* n_out) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!n_out || (!out && cap)) return set_err(h, RSVD_E_INVALID_ARG, "bad output arguments");
+  const rsvd::Plan& P = h->p;
+  const int64_t Pg = P.opt.grid_p, Qg = P.opt.grid_q;
+  size_t w = 0;
+  for (int64_t I = 0; I < P.TI; ++I) {
+    const int64_t r0 = I * P.tm, r1 = std::min(P.prob.m, r0 + P.tm);
+    for (int64_t J = 0; J < P.TJ; ++J) {
+      const int64_t c0 = J * P.tn, c1 = std::min(P.prob.n, c0 + P.tn);
+      const int64_t v[12] = {I,      J,      r0,     r1 - r0, c0, c1 - c0, I % Pg, J % Qg, I / Pg,
+                             J / Qg, ((r0 / P.tm) / Pg) * P.tm + r0 % P.tm,
+                             ((c0 / P.tn) / Qg) * P.tn + c0 % P.tn};
+      for (int e = 0; e < 12; ++e, ++w)
+        if (w < cap) out[w] = v[e];
+    }
+  }
+  *n_out = w;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_visit_order(rsvd_plan_t h, int64_t pass_index, int64_t* out, size_t cap,
+                             size_t* n_out) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!n_out || (!out && cap) || pass_index < 0)
+    return set_err(h, RSVD_E_INVALID_ARG, "bad arguments");
+  const rsvd::Plan& P = h->p;
+  size_t w = 0;
+  if (pass_index % 2 == 0) {
+    for (int64_t I = 0; I < P.TI; ++I)
+      for (int64_t J = 0; J < P.TJ; ++J, ++w)
+        if (w < cap) out[w] = I * P.TJ + J;
+  } else {
+    for (int64_t J = P.TJ - 1; J >= 0; --J)
+      for (int64_t I = P.TI - 1; I >= 0; --I, ++w)
+        if (w < cap) out[w] = I * P.TJ + J;
+  }
+  *n_out = w;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_philox_raw(uint64_t seed, uint32_t stream_id, int64_t row0, int64_t rows,
+                            int64_t blocks, uint32_t* out, void* stream) {
+  rsvd_plan_t h = nullptr;
+  if (row0 < 0 || rows < 0 || blocks < 0 || (rows * blocks > 0 && !out))
+    return set_err(nullptr, RSVD_E_INVALID_ARG, "bad philox arguments");
+  if (blocks > 0xFFFFFFFFll) return set_err(nullptr, RSVD_E_INVALID_ARG, "too many column blocks");
+  RSVD_HIP(rsvd::launch_philox_raw(seed, stream_id, row0, rows, blocks, out, (hipStream_t)stream));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_omega(uint64_t seed, int64_t n, int64_t l, int64_t row0, int64_t rows,
+                       int32_t dtype, void* out, int64_t ldo, void* stream) {
+  rsvd_plan_t h = nullptr;
+  if (n < 0 || l < 0 || row0 < 0 || rows < 0 || row0 + rows > n || ldo < l ||
+      (rows > 0 && !out) || (dtype != RSVD_F64 && dtype != RSVD_F32) || l / 4 >= 65535)
+    return set_err(nullptr, RSVD_E_INVALID_ARG, "bad omega arguments");
+  RSVD_HIP(rsvd::launch_omega_rows(seed, l, row0, rows, dtype == RSVD_F64, out, ldo,
+                                   (hipStream_t)stream));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, float* U, int64_t ldu,
+                        double* S, float* V, int64_t ldv, void* stream, rsvd_report* report) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k;
+  if (!U || !S || !V) return set_err(h, RSVD_E_INVALID_ARG, "U, S and V must be non-NULL");
+  if (ldu < m || ldv < n) return set_err(h, RSVD_E_INVALID_ARG, "ldu < m or ldv < n");
+
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  Events* ev = nullptr;
+  if (report) {
+    if (!P.hip_events) {
+      Events* e = new (std::nothrow) Events;
+      if (!e) return set_err(h, RSVD_E_INVALID_ARG, "out of host memory");
+      h->p.hip_events = e;
+    }
+    ev = static_cast<Events*>(P.hip_events);
+    RSVD_HIP(make_events(*ev, (size_t)(2 * P.prob.q + 2)));
+    R.ev = ev;
+  }
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev->ev[i], s) : hipSuccess; };
+  const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
+  rsvd_status st;
+
+  RSVD_HIP(mark(0));
+  RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
+  if ((st = R.bind_A(A, lda))) return st;
+  RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, R.B.Xop, P.ldn, s));   // step 1
+  RSVD_HIP(mark(1));
+  if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;                                // step 2
+  RSVD_HIP(mark(2));
+  if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;  // 3-4
+  RSVD_HIP(mark(3));
+  for (int64_t t = 0; t < P.prob.q; ++t) {                                            // Eq. (2)
+    const bool last = t + 1 == P.prob.q;
+    if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;
+    if ((st = R.orth(R.B.N0, R.B.Xop, R.B.N1, n, P.ldn, !cq1))) return st;
+    if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;
+    if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || last))) return st;
+  }
+  RSVD_HIP(mark(4));
+  if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;                                // step 5
+  RSVD_HIP(mark(5));
+  if ((st = R.small_svd_eig(R.B.N0))) return st;                                      // SVD0 prep
+  RSVD_HIP(mark(6));
+  if ((st = R.small_svd_solve(S, k))) return st;                                      // step 6
+  RSVD_HIP(mark(7));
+  // step 7: U = Q E_k (W), V = B^T E_k S^-1 (W2)
+  RSVD_HIP(rsvd::launch_apply(R.B.Mop, P.ldm, m, P.l, R.B.W, P.lp, P.lp, k, false, U, ldu, m, s));
+  RSVD_HIP(rsvd::launch_apply(R.B.N0, P.ldn, n, P.l, R.B.W2, P.lp, P.lp, k, false, V, ldv, n, s));
+  if (!(P.opt.flags & RSVD_FLAG_NO_SIGN_FIX))
+    RSVD_HIP(rsvd::launch_sign_fix(U, ldu, m, V, ldv, n, k, R.B.signs, s));
+  RSVD_HIP(mark(8));
+
+  if (!report) return RSVD_OK;
+  std::memset(report, 0, sizeof *report);
+  RSVD_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 8; ++i) {
+    float ms = 0.f;
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[i], ev->ev[i + 1]));
+    report->stage_ms[i] = ms;
+  }
+  {
+    float ms = 0.f;
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
+    report->total_ms = ms;
+    for (int i : R.nn_idx) {
+      RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
+      report->gemm_nn_ms += ms;
+    }
+    for (int i : R.tn_idx) {
+      RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
+      report->gemm_tn_ms += ms;
+    }
+    report->gemm_nn_launches = (int32_t)R.nn_idx.size();
+    report->gemm_tn_launches = (int32_t)R.tn_idx.size();
+  }
+  int32_t stw[rsvd::kStatusWords];
+  RSVD_HIP(hipMemcpy(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost));
+  const double passes = 2.0 * (double)P.prob.q + 2.0;
+  report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
+  report->bytes_alg = passes * ((double)m * (double)n * 4.0 + ((double)m + (double)n) * P.l * 4.0);
+  report->ws_bytes = (int64_t)P.ws.total;
+  report->dropped = stw[rsvd::kStDropped];
+  report->jacobi_sweeps = stw[rsvd::kStSweeps];
+  report->nonfinite = stw[rsvd::kStNonFinite];
+  if (stw[rsvd::kStNonFinite] > 0) return set_err(h, RSVD_E_NUMERIC, "NaN or Inf met on the device");
+  if (stw[rsvd::kStDropped] > 0 || stw[rsvd::kStRankSmall] > 0) return RSVD_W_RANK_DEFICIENT;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t lda, const float* X,
+                              int64_t ldx, float* out, int64_t ldo, void* ws, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n;
+  if (op != 0 && op != 1) return set_err(h, RSVD_E_INVALID_ARG, "op must be 0 or 1");
+  const int64_t in_rows = op == 0 ? n : m, out_rows = op == 0 ? m : n;
+  if (!X || !out || ldx < in_rows || ldo < out_rows)
+    return set_err(h, RSVD_E_INVALID_ARG, "bad panel arguments");
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  rsvd_status st;
+  if ((st = R.bind_A(A, lda))) return st;
+  if (op == 0) {
+    RSVD_HIP(rsvd::launch_panel_copy(X, ldx, n, P.l, R.B.Xop, P.ldn, P.ldn, P.lp, s));
+    if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;
+    RSVD_HIP(rsvd::launch_panel_copy(R.B.M0, P.ldm, m, P.l, out, ldo, m, P.l, s));
+  } else {
+    RSVD_HIP(rsvd::launch_panel_copy(X, ldx, m, P.l, R.B.Mop, P.ldm, P.ldm, P.lp, s));
+    if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;
+    RSVD_HIP(rsvd::launch_panel_copy(R.B.N0, P.ldn, n, P.l, out, ldo, n, P.l, s));
+  }
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_step_orth(rsvd_plan_t h, int32_t side, const float* Y, int64_t ldy, float* Q,
+                           int64_t ldq, void* ws, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  if (side != 0 && side != 1) return set_err(h, RSVD_E_INVALID_ARG, "side must be 0 or 1");
+  const int64_t rows = side == 0 ? P.prob.m : P.prob.n;
+  const int64_t ld = side == 0 ? P.ldm : P.ldn;
+  if (!Y || !Q || ldy < rows || ldq < rows) return set_err(h, RSVD_E_INVALID_ARG, "bad panel arguments");
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  float* a = side == 0 ? R.B.M0 : R.B.N0;
+  float* b = side == 0 ? R.B.M1 : R.B.N1;
+  float* c = side == 0 ? R.B.Mop : R.B.Xop;
+  RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
+  RSVD_HIP(rsvd::launch_panel_copy(Y, ldy, rows, P.l, a, ld, ld, P.lp, s));
+  rsvd_status st;
+  if ((st = R.orth(a, c, b, rows, ld, true))) return st;
+  RSVD_HIP(rsvd::launch_panel_copy(c, ld, rows, P.l, Q, ldq, rows, P.l, s));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_step_gram(rsvd_plan_t h, int32_t side, const float* Y, int64_t ldy, double* G,
+                           void* ws, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  if (side != 0 && side != 1) return set_err(h, RSVD_E_INVALID_ARG, "side must be 0 or 1");
+  const int64_t rows = side == 0 ? P.prob.m : P.prob.n;
+  const int64_t ld = side == 0 ? P.ldm : P.ldn;
+  if (!Y || !G || ldy < rows) return set_err(h, RSVD_E_INVALID_ARG, "bad panel arguments");
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  float* a = side == 0 ? R.B.M0 : R.B.N0;
+  RSVD_HIP(rsvd::launch_panel_copy(Y, ldy, rows, P.l, a, ld, ld, P.lp, s));
+  rsvd_status st;
+  if ((st = R.gram(a, rows, ld))) return st;
+  RSVD_HIP(hipMemcpy2DAsync(G, P.l * sizeof(double), R.B.G, P.lp * sizeof(double),
+                            P.l * sizeof(double), P.l, hipMemcpyDeviceToDevice, s));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_step_small_svd(rsvd_plan_t h, const float* Bt, int64_t ldb, double* sig,
+                                double* ub, void* ws, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  if (!Bt || !sig || !ub || ldb < P.prob.n) return set_err(h, RSVD_E_INVALID_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
+  RSVD_HIP(rsvd::launch_panel_copy(Bt, ldb, P.prob.n, P.l, R.B.N0, P.ldn, P.ldn, P.lp, s));
+  rsvd_status st;
+  if ((st = R.small_svd_eig(R.B.N0))) return st;
+  if ((st = R.small_svd_solve(sig, P.l))) return st;
+  // U_B(a, c) = Ev(a, order c) in FP64
+  RSVD_HIP(rsvd::launch_gather_cols(R.B.Ev, P.lp, P.l, R.B.order, ub, s));
+  return RSVD_OK;
+}
+
+}  // extern "C"

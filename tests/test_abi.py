@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/rsvd.h declares; rsvd_plan validates its
+arguments; tile maps and visit orders equal the oracle's bit for bit."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import tilemap
+from paper_1907_06470_amd import _lib as L
+from paper_1907_06470_amd.api import Plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsvd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsvd_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.exported_symbols())
+
+
+def test_version_and_status_strings():
+    lib = L.lib()
+    assert lib.rsvd_version().decode().startswith("rsvd-mi355x")
+    for s in (0, 1, 2, -1, -2, -3, -4, -5):
+        assert lib.rsvd_status_str(s)
+    assert lib.rsvd_status_str(99) == b"unknown status"
+
+
+def make(m=100, n=80, k=5, p=5, q=1, **kw):
+    return Plan(m, n, k, p, q, **kw)
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(k=0), L.E_INVALID_ARG),
+    (dict(p=-1), L.E_INVALID_ARG),
+    (dict(q=-1), L.E_INVALID_ARG),
+    (dict(k=50, p=40), L.E_INVALID_ARG),          # k + p > min(m, n)
+    (dict(tile=(100, 64)), L.E_INVALID_ARG),      # not a multiple of 32
+    (dict(precision="fp16"), L.E_INVALID_ARG),
+])
+def test_plan_rejects_bad_arguments(args, status):
+    with pytest.raises(L.RsvdError) as e:
+        make(**args)
+    assert e.value.status == status
+    assert L.lib().rsvd_last_error(None)
+
+
+def test_plan_budget_error_names_the_bytes():
+    with pytest.raises(L.RsvdError) as e:
+        make(hbm_budget=1024)
+    assert e.value.status == L.E_BUDGET
+    assert "bytes" in str(e.value)
+    p = make()
+    ok = make(hbm_budget=p.ws_bytes)
+    assert ok.ws_bytes == p.ws_bytes
+
+
+def test_plan_unsupported_combinations():
+    prob = L.Problem(m=100, n=80, k=5, p=5, q=1, format=L.CSR, dtype=L.F32, loc=L.LOC_DEVICE,
+                     seed=0)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
+    prob.format = L.DENSE
+    prob.loc = L.LOC_HOST_PINNED
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
+    prob.loc = 7
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
+    assert L.lib().rsvd_plan(None, None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
+
+
+def test_plan_with_null_options_uses_defaults():
+    prob = L.Problem(m=300, n=200, k=10, p=5, q=2, format=L.DENSE, dtype=L.F32,
+                     loc=L.LOC_DEVICE, seed=3)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.OK
+    assert ws.value > 0 and ws.value % 256 == 0
+    L.lib().rsvd_plan_destroy(h)
+    L.lib().rsvd_plan_destroy(None)
+
+
+@pytest.mark.parametrize("m,n,tile,grid", [
+    (50000, 20000, (4096, 4096), (1, 1)),
+    (200000, 100000, (8192, 8192), (1, 1)),
+    (1000, 700, (256, 192), (1, 1)),
+    (1000, 700, (256, 192), (3, 2)),
+    (97, 65, (32, 64), (2, 5)),
+])
+def test_tile_map_matches_oracle(m, n, tile, grid):
+    p = Plan(m, n, 10, 5, 1, tile=tile, grid=grid)
+    got = p.tile_map().numpy()
+    ref = tilemap.tile_descriptors(m, n, tile[0], tile[1], grid[0], grid[1])
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+    TI, TJ = tilemap.num_tiles(m, tile[0]), tilemap.num_tiles(n, tile[1])
+    for t in range(2 * 1 + 2):
+        assert np.array_equal(p.visit_order(t).numpy(), tilemap.visit_order(TI, TJ, t))
+
+
+def test_auto_tiles_cover_the_matrix():
+    p = Plan(50000, 20000, 100, 20, 2)
+    d = p.tile_map().numpy()
+    assert d[:, 3].sum() == 50000 * len(np.unique(d[:, 1]))
+    assert d[:, 5].sum() == 20000 * len(np.unique(d[:, 0]))
+
+
+def test_workspace_prediction_is_deterministic_and_monotone():
+    a = Plan(1000, 500, 10, 10, 1).ws_bytes
+    b = Plan(1000, 500, 10, 10, 1).ws_bytes
+    c = Plan(2000, 500, 10, 10, 1).ws_bytes
+    assert a == b and c > a
+
+
+def test_missing_library_fails_loudly():
+    code = ("import paper_1907_06470_amd._lib as L; L.LIB_PATH = '/nonexistent/librsvd.so'; "
+            "L._lib = None\ntry:\n    L.lib()\nexcept RuntimeError as e:\n    print('LOUD', e)")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
+    assert "LOUD" in out.stdout
