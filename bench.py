@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32")
+    ap.add_argument("--forms", default="fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -143,8 +143,8 @@ def main():
                                "k=100 p=20 q=2, 4096x4096 tiles, resident in HBM",
                    "m": m, "n": n, "k": k, "p": p, "q": q, "tile": list(W["tile"]),
                    "parallelism": "single GPU"},
-        "forms": {kf: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in f.items()}
-                  for kf, f in forms.items()},
+        "forms": {kf: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv)
+                       for kk, vv in f.items()} for kf, f in forms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 
-_DT = {torch.float32: L.F32, torch.float64: L.F64}
+_DT = {torch.float32: L.F32, torch.float64: L.F64, torch.bfloat16: L.BF16}
 _PREC = {"fp32": L.F32, "bf16": L.BF16, "fp8": L.FP8E4M3}
 
 

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["plan.cpp", "k_philox.hip", "k_gemm_f32.hip", "k_small.hip", "rsvd_api.hip"]
+SOURCES = ["plan.cpp", "k_philox.hip", "k_gemm_f32.hip", "k_gemm_bf16.hip", "k_small.hip",
+           "rsvd_api.hip"]
 LIB = os.path.join(PKG, "librsvd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -49,4 +49,12 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline int is_finite_d(double x) { return __builtin_isfinite(x); }
 
+// Workgroup barrier that orders LDS only: global stores issued before it stay
+// in flight (a plain __syncthreads() would wait for them to reach memory).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace rsvd

@@ -1,0 +1,318 @@
+// Products of A with a tall-skinny panel in BF16 on the gfx950 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation): the same passes over A as
+// the FP32 kernels (Section 2.1 steps 2 and 5, Section 2.2 Eq. (2)) with A and
+// the panel stored in BF16, which halves the bytes streamed from HBM.  The
+// paper stores half precision and computes in single (Section 3.2); here the
+// matrix cores multiply BF16 operands exactly and accumulate in FP32.
+//
+// Operands: A16 row-major (leading dimension a multiple of 8, rows 16-byte
+// aligned); panels column-major BF16 (element (i, c) at P[c * ld + i]).
+// Like the FP32 kernels, grid.y runs over the block-cyclic tiles of the
+// reduced dimension and each tile writes its own FP32 partial panel.
+#include "device.h"
+#include "kernels.h"
+
+namespace rsvd {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16;
+
+constexpr int BK = 64;          // reduction slab (elements)
+constexpr int PADK = BK + 8;    // LDS row of a k-contiguous tile: 144 bytes
+
+__device__ inline f32x16 mfma_bf16(const bf16x8& a, const bf16x8& b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// 8 consecutive BF16 of a row from index k, zero past kend.
+__device__ inline uint4 ld8_masked(const u16* row, int64_t k, int64_t kend) {
+  if (k + 8 <= kend) return *reinterpret_cast<const uint4*>(row + k);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (k + e < kend) w[e >> 1] |= (uint32_t)row[k + e] << (16 * (e & 1));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ inline void store_acc16(float* out, int64_t ld, int64_t row_base, int col,
+                                   const f32x16& acc, int half) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t r = row_base + 8 * g + 4 * half;
+    st4(out + (int64_t)col * ld + r,
+        make_float4(acc[4 * g + 0], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]));
+  }
+}
+
+// Y (+ partial J) = A16(:, tile J) X16(tile J, :).  4 waves; wave w owns rows
+// [w*WR, (w+1)*WR) of the BM = 4*WR rows and all NT*32 panel columns.
+// Within a 64-deep slab, lane half h takes reduction indices h*32 + 8s + v at
+// MFMA step s, so every lane reads 16-byte runs of both LDS tiles.
+template <int NT, int MT>
+__global__ __launch_bounds__(256) void k_nn_bf16(const u16* __restrict__ A, int64_t lda, int64_t m,
+                                                 int64_t n, int64_t tn, const u16* __restrict__ X,
+                                                 int64_t ldx, float* __restrict__ Y, int64_t ldy,
+                                                 int64_t part_stride) {
+  constexpr int LP = NT * 32, WR = MT * 32, BM = 4 * WR, AS = BM / 32;
+  __shared__ __attribute__((aligned(16))) u16 As[2][BM][PADK];
+  __shared__ __attribute__((aligned(16))) u16 Xs[2][LP][PADK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tn;
+  const int64_t k1 = min(n, k0 + tn);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int lr = tid >> 3, lc = (tid & 7) * 8;
+
+  uint4 ra[AS];
+  uint4 rx[NT];
+  auto gload = [&](int64_t kt) {
+    const int64_t kk = kt + lc;
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+      const int64_t i = i0 + lr + 32 * s;
+      ra[s] = (i < m && kk < k1) ? ld8_masked(A + i * lda, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const int c = lr + 32 * s;
+      rx[s] = kk < k1 ? ld8_masked(X + (int64_t)c * ldx, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < AS; ++s) *reinterpret_cast<uint4*>(&As[buf][lr + 32 * s][lc]) = ra[s];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) *reinterpret_cast<uint4*>(&Xs[buf][lr + 32 * s][lc]) = rx[s];
+  };
+
+  f32x16 acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[a][t] = f32x16{};
+
+  gload(k0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kt = k0; kt < k1; kt += BK) {
+    const bool more = kt + BK < k1;
+    if (more) gload(kt + BK);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      bf16x8 av[MT], bv[NT];
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+        av[a] = *reinterpret_cast<const bf16x8*>(&As[buf][wave * WR + a * 32 + l32][half * 32 + s * 8]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        bv[t] = *reinterpret_cast<const bf16x8*>(&Xs[buf][t * 32 + l32][half * 32 + s * 8]);
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      store_acc16(Yp, ldy, i0 + wave * WR + a * 32, t * 32 + l32, acc[a][t], half);
+}
+
+// Z (+ partial I) = A16(tile I, :)^T Q16(tile I, :).  The A tile is staged
+// row-major as loaded ([i][j], coalesced 16-byte loads); each lane gathers
+// its A^T fragment (8 consecutive i of one column j) with 16-bit LDS reads,
+// so no transposed copy of A is ever stored.
+constexpr int TBN = 128;
+constexpr int TPAD = TBN + 8;
+template <int NT>
+__global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int64_t lda, int64_t m,
+                                                 int64_t n, int64_t tm, const u16* __restrict__ Q,
+                                                 int64_t ldq, float* __restrict__ Z, int64_t ldz,
+                                                 int64_t part_stride) {
+  constexpr int LP = NT * 32;
+  __shared__ __attribute__((aligned(16))) u16 As[2][BK][TPAD];
+  __shared__ __attribute__((aligned(16))) u16 Qs[2][LP][PADK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int64_t j0 = (int64_t)blockIdx.x * TBN;
+  const int64_t ib0 = (int64_t)blockIdx.y * tm;
+  const int64_t ib1 = min(m, ib0 + tm);
+  float* Zp = Z + (int64_t)blockIdx.y * part_stride;
+  const int ar = tid >> 4, ac = (tid & 15) * 8;      // A tile: 16 chunks of 8 per row
+  const int qr = tid >> 3, qc = (tid & 7) * 8;       // Q tile: 8 chunks of 8 per row
+
+  uint4 ra[4];
+  uint4 rq[NT];
+  auto gload = [&](int64_t it) {
+    const int64_t j = j0 + ac;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t i = it + ar + 16 * s;
+      ra[s] = (i < ib1 && j < n) ? ld8_masked(A + i * lda, j, n) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    const int64_t kk = it + qc;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const int c = qr + 32 * s;
+      rq[s] = kk < ib1 ? ld8_masked(Q + (int64_t)c * ldq, kk, ib1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) *reinterpret_cast<uint4*>(&As[buf][ar + 16 * s][ac]) = ra[s];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) *reinterpret_cast<uint4*>(&Qs[buf][qr + 32 * s][qc]) = rq[s];
+  };
+
+  f32x16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+
+  gload(ib0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  const int jl = wave * 32 + l32;
+  for (int64_t it = ib0; it < ib1; it += BK) {
+    const bool more = it + BK < ib1;
+    if (more) gload(it + BK);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      // reduction indices of this step: 16 s + 8 half + v
+      uint32_t w[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t lo = As[buf][s * 16 + half * 8 + 2 * v][jl];
+        const uint32_t hi = As[buf][s * 16 + half * 8 + 2 * v + 1][jl];
+        w[v] = lo | (hi << 16);
+      }
+      bf16x8 av;
+      __builtin_memcpy(&av, w, 16);
+      bf16x8 bv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        bv[t] = *reinterpret_cast<const bf16x8*>(&Qs[buf][t * 32 + l32][s * 16 + half * 8]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16(av, bv[t], acc[t]);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) store_acc16(Zp, ldz, j0 + wave * 32, t * 32 + l32, acc[t], half);
+}
+
+// A16 (m x ldo, BF16, round to nearest even) = A (m x n FP32 or FP64, lda);
+// columns [n, ldo) zero.  8 elements per thread.
+template <typename T>
+__global__ void k_cast_to_bf16(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                               u16* __restrict__ out, int64_t ldo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_row = ldo / 8;
+  if (t >= m * per_row) return;
+  const int64_t i = t / per_row, j0 = (t % per_row) * 8;
+  uint32_t w[4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const T x0 = j0 + e < n ? A[i * lda + j0 + e] : T(0);
+    const T x1 = j0 + e + 1 < n ? A[i * lda + j0 + e + 1] : T(0);
+    const __bf16 b0 = (__bf16)x0, b1 = (__bf16)x1;
+    uint16_t u0, u1;
+    __builtin_memcpy(&u0, &b0, 2);
+    __builtin_memcpy(&u1, &b1, 2);
+    w[e >> 1] = (uint32_t)u0 | ((uint32_t)u1 << 16);
+  }
+  *reinterpret_cast<uint4*>(out + i * ldo + j0) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// BF16 copy of an FP32 panel (same leading dimension), 4 elements per thread.
+__global__ void k_panel_to_bf16(const float* __restrict__ P, u16* __restrict__ P16, int64_t count4) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count4) return;
+  const float4 v = ld4(P + 4 * t);
+  const __bf16 b[4] = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+  uint2 o;
+  __builtin_memcpy(&o, b, 8);
+  *reinterpret_cast<uint2*>(P16 + 4 * t) = o;
+}
+
+}  // namespace
+
+hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
+                          int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
+                          int64_t ldy, int64_t part_stride, hipStream_t s) {
+  const int nt = (int)(lp / 32);
+  if (nt <= 4) {   // two M tiles per wave: 256 rows per workgroup
+    dim3 grid((unsigned)ceil_div_dev(m, 256), (unsigned)TJ);
+#define NN16(NT) hipLaunchKernelGGL((k_nn_bf16<NT, 2>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y, ldy, part_stride)
+    switch (nt) {
+      case 1: NN16(1); break;
+      case 2: NN16(2); break;
+      case 3: NN16(3); break;
+      case 4: NN16(4); break;
+    }
+#undef NN16
+  } else {
+    dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
+#define NN16(NT) hipLaunchKernelGGL((k_nn_bf16<NT, 1>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y, ldy, part_stride)
+    switch (nt) {
+      case 5: NN16(5); break;
+      case 6: NN16(6); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef NN16
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
+                          int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
+                          int64_t ldz, int64_t part_stride, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div_dev(n, TBN), (unsigned)TI);
+#define TN16(NT) hipLaunchKernelGGL((k_tn_bf16<NT>), grid, dim3(256), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz, part_stride)
+  switch (lp / 32) {
+    case 1: TN16(1); break;
+    case 2: TN16(2); break;
+    case 3: TN16(3); break;
+    case 4: TN16(4); break;
+    case 5: TN16(5); break;
+    case 6: TN16(6); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef TN16
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_to_bf16(const void* A, bool f64, int64_t lda, int64_t m, int64_t n,
+                               uint16_t* out, int64_t ldo, hipStream_t s) {
+  if (ldo % 8) return hipErrorInvalidValue;
+  const int64_t total = m * (ldo / 8);
+  dim3 grid((unsigned)ceil_div_dev(total, 256));
+  if (f64)
+    hipLaunchKernelGGL(k_cast_to_bf16<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n,
+                       out, ldo);
+  else
+    hipLaunchKernelGGL(k_cast_to_bf16<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, n,
+                       out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_to_bf16(const float* P, uint16_t* P16, int64_t count, hipStream_t s) {
+  const int64_t c4 = count / 4;
+  hipLaunchKernelGGL(k_panel_to_bf16, dim3((unsigned)ceil_div_dev(c4, 256)), dim3(256), 0, s, P,
+                     P16, c4);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -140,27 +140,34 @@ __global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, 
 }
 
 // ------------------------------------------------------------ Cholesky ----
-// Lp: packed lower triangle of L (l rows), L(i, c) at i(i+1)/2 + c.
-__global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ G, int64_t lp, int l,
-                                               double* __restrict__ Lp, int32_t* status,
-                                               double tau) {
+// One workgroup: G = L L^T (right-looking, packed lower triangle in LDS),
+// then X = L^-1 in place, row by row, and W = X^T written as FP32.  A pivot
+// at or below tau times its original diagonal (or not finite) drops the
+// direction: its column of L and its row and column of X are zero, so the
+// basis Q = Y W gets a zero column and the direction feeds no other column.
+constexpr int kCholThreads = 256;
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int64_t lp,
+                                                           int l, float* __restrict__ W,
+                                                           int32_t* status, double tau) {
   __shared__ double T[kTri];
   __shared__ double d0[kMaxLp];
+  __shared__ double rowtmp[kMaxLp];
   __shared__ double piv_s;
   __shared__ int ndrop, nbad;
   const int tid = threadIdx.x;
   const int tot = l * (l + 1) / 2;
-  for (int e = tid; e < tot; e += blockDim.x) {
+  for (int e = tid; e < tot; e += kCholThreads) {
     int i, c;
     tri_decode(e, i, c);
     T[e] = G[(int64_t)i * lp + c];
   }
-  for (int i = tid; i < l; i += blockDim.x) d0[i] = G[(int64_t)i * lp + i];
+  for (int i = tid; i < l; i += kCholThreads) d0[i] = G[(int64_t)i * lp + i];
   if (tid == 0) {
     ndrop = 0;
     nbad = 0;
   }
-  __syncthreads();
+  lds_barrier();
+  const int ty = tid >> 4, tx = tid & 15;
   for (int j = 0; j < l; ++j) {
     if (tid == 0) {
       const double d = T[tidx(j, j)];
@@ -175,59 +182,49 @@ __global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ G, int
       T[tidx(j, j)] = piv;
       piv_s = piv;
     }
-    __syncthreads();
+    lds_barrier();
     const double piv = piv_s;
     const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-    for (int i = j + 1 + tid; i < l; i += blockDim.x) T[tidx(i, j)] *= inv;
-    __syncthreads();
+    for (int i = j + 1 + tid; i < l; i += kCholThreads) T[tidx(i, j)] *= inv;
+    lds_barrier();
     if (piv > 0.0) {
-      const int nt = l - j - 1;
-      const int tt = nt * (nt + 1) / 2;
-      for (int e = tid; e < tt; e += blockDim.x) {
-        int ii, cc;
-        tri_decode(e, ii, cc);
-        const int i = j + 1 + ii, c = j + 1 + cc;
-        T[tidx(i, c)] -= T[tidx(i, j)] * T[tidx(c, j)];
+      for (int i = j + 1 + ty; i < l; i += 16) {
+        const double lij = T[tidx(i, j)];
+        const int base = tidx(i, 0);
+        for (int c = j + 1 + tx; c <= i; c += 16) T[base + c] -= lij * T[tidx(c, j)];
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int e = tid; e < tot; e += blockDim.x) Lp[e] = T[e];
+  // X = L^-1 in place: row i of X needs row i of L and rows < i of X.
+  for (int i = 0; i < l; ++i) {
+    const double lii = T[tidx(i, i)];
+    for (int c = tid; c <= i; c += kCholThreads) {
+      double v = 0.0;
+      if (lii > 0.0) {
+        if (c == i) {
+          v = 1.0 / lii;
+        } else if (T[tidx(c, c)] != 0.0) {
+          double acc = 0.0;
+          for (int p = c; p < i; ++p) acc += T[tidx(i, p)] * T[tidx(p, c)];
+          v = -acc / lii;
+        }
+      }
+      rowtmp[c] = v;
+    }
+    lds_barrier();
+    for (int c = tid; c <= i; c += kCholThreads) T[tidx(i, c)] = rowtmp[c];
+    lds_barrier();
+  }
+  // W(a, c) = X(c, a), upper triangular, FP32
+  for (int e = tid; e < lp * lp; e += kCholThreads) {
+    const int a = e / (int)lp, c = e % (int)lp;
+    W[e] = (c < l && a <= c) ? (float)T[tidx(c, a)] : 0.f;
+  }
   if (tid == 0) {
     status[kStDropped] += ndrop;
     status[kStNonFinite] += nbad;
   }
-}
-
-// W row c = column c of X = L^-1 (so W = X^T, upper triangular), FP32.
-// Dropped directions (zero pivot) give zero rows and columns.  One wave per
-// column: the packed triangle is staged in LDS, then forward substitution
-// with a wave-wide dot product per row.
-__global__ __launch_bounds__(64) void k_trtri(const double* __restrict__ Lp, int64_t lp, int l,
-                                              float* __restrict__ W) {
-  __shared__ double T[kTri];
-  __shared__ double x[kMaxLp];
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  for (int i = lane; i < kMaxLp; i += 64) x[i] = 0.0;
-  const int e0 = c < l ? tidx(c, 0) : 0;
-  const int e1 = l * (l + 1) / 2;
-  for (int e = e0 + lane; e < e1; e += 64) T[e] = Lp[e];
-  __syncthreads();
-  const bool live = c < l && T[tidx(c, c)] > 0.0;
-  if (live) {
-    if (lane == 0) x[c] = 1.0 / T[tidx(c, c)];
-    __syncthreads();
-    for (int i = c + 1; i < l; ++i) {
-      const double lii = T[tidx(i, i)];
-      double part = 0.0;
-      for (int p = c + lane; p < i; p += 64) part += T[tidx(i, p)] * x[p];
-      part = wave_sum(part);
-      if (lane == 0) x[i] = lii > 0.0 ? -part / lii : 0.0;
-      __syncthreads();
-    }
-  }
-  for (int i = lane; i < lp; i += 64) W[(int64_t)c * lp + i] = live ? (float)x[i] : 0.f;
 }
 
 // ------------------------------------------------------ panel x matrix ----
@@ -289,10 +286,14 @@ __global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int6
 // --------------------------------------------------------------- Jacobi ----
 __device__ inline int rr_pos(int x, int t, int le) { return x == 0 ? 0 : 1 + (x - 1 + t) % (le - 1); }
 
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, int64_t lp, int l,
-                                                 double* __restrict__ rot, int64_t rot_rounds,
-                                                 double* __restrict__ lam, int32_t* status,
-                                                 double tol, int max_sweeps) {
+constexpr int kJacThreads = 512;
+constexpr int kJacMaxBlocks = (kMaxLp / 2 * (kMaxLp / 2 + 1) / 2 + kJacThreads - 1) / kJacThreads;
+
+__global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int64_t lp,
+                                                        int l, double* __restrict__ rot,
+                                                        int64_t rot_rounds,
+                                                        double* __restrict__ lam, int32_t* status,
+                                                        double tol, int max_sweeps) {
   __shared__ double T[kTri];
   __shared__ double cc_s[kMaxLp / 2 + 1], ss_s[kMaxLp / 2 + 1];
   __shared__ int pp_s[kMaxLp / 2 + 1], qq_s[kMaxLp / 2 + 1];
@@ -300,17 +301,29 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
   const int tid = threadIdx.x;
   const int le = l + (l & 1), np = le / 2, R = le - 1;
   const int tot = l * (l + 1) / 2;
-  for (int e = tid; e < tot; e += blockDim.x) {
+  for (int e = tid; e < tot; e += kJacThreads) {
     int i, c;
     tri_decode(e, i, c);
     T[e] = G[(int64_t)i * lp + c];
   }
-  __syncthreads();
+  // Each thread owns the same 2 x 2 blocks (pair positions P1 >= P2) in every
+  // round; only the indices sitting at those positions change.
+  const int nb = np * (np + 1) / 2;
+  int P1[kJacMaxBlocks], P2[kJacMaxBlocks];
+#pragma unroll
+  for (int u = 0; u < kJacMaxBlocks; ++u) {
+    const int e = tid + u * kJacThreads;
+    int a = 0, b = 0;
+    if (e < nb) tri_decode(e, a, b);
+    P1[u] = a;
+    P2[u] = b;
+  }
+  lds_barrier();
   int sweeps = 0;
   int64_t ridx = 0;
   for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
     if (tid == 0) any_s = 0;
-    __syncthreads();
+    lds_barrier();
     for (int t = 0; t < R; ++t) {
       if (tid < np) {
         const int a = rr_pos(tid, t, le), b = rr_pos(le - 1 - tid, t, le);
@@ -330,19 +343,19 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
         qq_s[tid] = q;
         cc_s[tid] = c;
         ss_s[tid] = s;
-        if (ridx < rot_rounds) {
+        if (ridx < rot_rounds) {   // the log stays in flight: barriers below order LDS only
           rot[(ridx * np + tid) * 2 + 0] = c;
           rot[(ridx * np + tid) * 2 + 1] = s;
         }
       }
-      __syncthreads();
-      const int nb = np * (np + 1) / 2;
-      for (int e = tid; e < nb; e += blockDim.x) {
-        int P1, P2;
-        tri_decode(e, P1, P2);
-        const int p1 = pp_s[P1], q1 = qq_s[P1], p2 = pp_s[P2], q2 = qq_s[P2];
-        const double c1 = cc_s[P1], s1 = ss_s[P1], c2 = cc_s[P2], s2 = ss_s[P2];
-        if (P1 == P2) {
+      lds_barrier();
+#pragma unroll
+      for (int u = 0; u < kJacMaxBlocks; ++u) {
+        if (tid + u * kJacThreads >= nb) break;
+        const int b1 = P1[u], b2 = P2[u];
+        const int p1 = pp_s[b1], q1 = qq_s[b1], p2 = pp_s[b2], q2 = qq_s[b2];
+        const double c1 = cc_s[b1], s1 = ss_s[b1], c2 = cc_s[b2], s2 = ss_s[b2];
+        if (b1 == b2) {
           if (q1 < l && s1 != 0.0) {
             const double app = T[tidx(p1, p1)], aqq = T[tidx(q1, q1)], apq = T[tidx(q1, p1)];
             const double tt = s1 / c1;
@@ -353,9 +366,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
           continue;
         }
         if (s1 == 0.0 && s2 == 0.0) continue;
-        // block rows {p1, q1} x cols {p2, q2} of the symmetric matrix
         const bool hq1 = q1 < l, hq2 = q2 < l;
-        auto at = [&](int r, int cidx) -> double& { return r >= cidx ? T[tidx(r, cidx)] : T[tidx(cidx, r)]; };
+        auto at = [&](int r, int cidx) -> double& {
+          return r >= cidx ? T[tidx(r, cidx)] : T[tidx(cidx, r)];
+        };
         const double x = at(p1, p2);
         const double y = hq2 ? at(p1, q2) : 0.0;
         const double z = hq1 ? at(q1, p2) : 0.0;
@@ -367,59 +381,78 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, i
         if (hq1) at(q1, p2) = c2 * z1 - s2 * w1;
         if (hq1 && hq2) at(q1, q2) = s2 * z1 + c2 * w1;
       }
-      __syncthreads();
+      lds_barrier();
       ++ridx;
     }
     ++sweeps;
     const int any = any_s;
-    __syncthreads();
+    lds_barrier();
     if (!any) break;
   }
-  for (int i = tid; i < lp; i += blockDim.x) lam[i] = i < l ? T[tidx(i, i)] : 0.0;
+  for (int i = tid; i < lp; i += kJacThreads) lam[i] = i < l ? T[tidx(i, i)] : 0.0;
   if (tid == 0) {
     status[kStSweeps] = sweeps;
     status[kStRounds] = (int32_t)min(ridx, rot_rounds);
   }
 }
 
-// Ev = I J_1 J_2 ... (rows independent): 4 rows per workgroup, one wave per
-// row, rotation log staged through LDS in chunks of rounds.
-constexpr int kVecChunk = 16;
-__global__ __launch_bounds__(256) void k_jacobi_vecs(const double* __restrict__ rot,
-                                                     const int32_t* __restrict__ status,
-                                                     int64_t lp, int l, double* __restrict__ Ev) {
-  __shared__ double rowv[4][kMaxLp + 2];
-  __shared__ double cs[kVecChunk][kMaxLp / 2 + 1][2];
+// Ev = I J_1 J_2 ... : rows are independent, one wave per row (16 rows per
+// workgroup).  Within a round the lanes of a wave rotate disjoint pairs of
+// their row, so rounds need no workgroup barrier; the rotation log is staged
+// through LDS in chunks of rounds, the next chunk prefetched into registers.
+constexpr int kVecRows = 16;
+constexpr int kVecChunk = 64;
+constexpr int kVecPer = (kVecChunk * (kMaxLp / 2 + 1) * 2 + kVecRows * 64 - 1) / (kVecRows * 64);
+__global__ __launch_bounds__(kVecRows * 64) void k_jacobi_vecs(const double* __restrict__ rot,
+                                                              const int32_t* __restrict__ status,
+                                                              int64_t lp, int l,
+                                                              double* __restrict__ Ev) {
+  __shared__ double rowv[kVecRows][kMaxLp + 2];
+  __shared__ double cs[kVecChunk * (kMaxLp / 2 + 1) * 2];
   const int le = l + (l & 1), np = le / 2, R = le - 1;
   const int64_t rounds = status[kStRounds];
-  const int rsub = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + rsub;
-  for (int x = lane; x < kMaxLp + 2; x += 64) rowv[rsub][x] = (x == r) ? 1.0 : 0.0;
-  __syncthreads();
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int r = blockIdx.x * kVecRows + w;
+  for (int x = lane; x < kMaxLp + 2; x += 64) rowv[w][x] = (x == r) ? 1.0 : 0.0;
+  double pre[kVecPer];
+  auto fetch = [&](int64_t t0) {
+    const int64_t nr = min((int64_t)kVecChunk, rounds - t0);
+    const int64_t cnt = nr * np * 2;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+      const int64_t idx = tid + (int64_t)u * kVecRows * 64;
+      pre[u] = idx < cnt ? rot[t0 * np * 2 + idx] : 0.0;
+    }
+  };
+  if (rounds > 0) fetch(0);
   for (int64_t t0 = 0; t0 < rounds; t0 += kVecChunk) {
     const int nr = (int)min((int64_t)kVecChunk, rounds - t0);
-    for (int e = threadIdx.x; e < nr * np * 2; e += blockDim.x) {
-      const int tt = e / (np * 2), rem = e % (np * 2);
-      cs[tt][rem / 2][rem % 2] = rot[(t0 + tt) * np * 2 + rem];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+      const int idx = tid + u * kVecRows * 64;
+      if (idx < nr * np * 2) cs[idx] = pre[u];
     }
     __syncthreads();
+    if (t0 + kVecChunk < rounds) fetch(t0 + kVecChunk);
     for (int tt = 0; tt < nr; ++tt) {
       const int tr = (int)((t0 + tt) % R);
       for (int i = lane; i < np; i += 64) {
-        const double c = cs[tt][i][0], s = cs[tt][i][1];
+        const double c = cs[(tt * np + i) * 2], s = cs[(tt * np + i) * 2 + 1];
         if (s != 0.0) {
           const int a = rr_pos(i, tr, le), b = rr_pos(le - 1 - i, tr, le);
           const int p = min(a, b), q = max(a, b);
-          const double vp = rowv[rsub][p], vq = rowv[rsub][q];
-          rowv[rsub][p] = c * vp - s * vq;
-          rowv[rsub][q] = s * vp + c * vq;
+          const double vp = rowv[w][p], vq = rowv[w][q];
+          rowv[w][p] = c * vp - s * vq;
+          rowv[w][q] = s * vp + c * vq;
         }
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (r < lp)
-    for (int x = lane; x < lp; x += 64) Ev[(int64_t)r * lp + x] = (r < l && x < l) ? rowv[rsub][x] : 0.0;
+    for (int x = lane; x < lp; x += 64) Ev[(int64_t)r * lp + x] = (r < l && x < l) ? rowv[w][x] : 0.0;
 }
 
 // Sort eigenvalues descending (ties by index), S = sqrt(lambda) for the first
@@ -542,16 +575,10 @@ hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int
   return hipGetLastError();
 }
 
-hipError_t launch_chol(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
-                       double tau, hipStream_t s) {
+hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
+                           double tau, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, s, G, lp, (int)l, L, status, tau);
-  return hipGetLastError();
-}
-
-hipError_t launch_trtri(const double* L, int64_t lp, int64_t l, float* W, hipStream_t s) {
-  if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trtri, dim3((unsigned)lp), dim3(64), 0, s, L, lp, (int)l, W);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W, status, tau);
   return hipGetLastError();
 }
 
@@ -585,16 +612,16 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
 hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
                          double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, G, lp, (int)l, rot, rot_rounds, lam,
-                     status, tol, max_sweeps);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), 0, s, G, lp, (int)l, rot, rot_rounds,
+                     lam, status, tol, max_sweeps);
   return hipGetLastError();
 }
 
 hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
                               double* Ev, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi_vecs, dim3((unsigned)ceil_div_dev(lp, 4)), dim3(256), 0, s, rot,
-                     status, lp, (int)l, Ev);
+  hipLaunchKernelGGL(k_jacobi_vecs, dim3((unsigned)ceil_div_dev(lp, kVecRows)),
+                     dim3(kVecRows * 64), 0, s, rot, status, lp, (int)l, Ev);
   return hipGetLastError();
 }
 

@@ -34,12 +34,23 @@ hipError_t launch_panel_copy(const float* src, int64_t lds, int64_t rows, int64_
 hipError_t launch_cast_f64_f32(const double* A, int64_t lda, int64_t m, int64_t n, float* out,
                                int64_t ldo, hipStream_t s);
 
+// --- BF16 products (k_gemm_bf16.hip) ---
+hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
+                          int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
+                          int64_t ldy, int64_t part_stride, hipStream_t s);
+hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
+                          int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
+                          int64_t ldz, int64_t part_stride, hipStream_t s);
+hipError_t launch_cast_to_bf16(const void* A, bool f64, int64_t lda, int64_t m, int64_t n,
+                               uint16_t* out, int64_t ldo, hipStream_t s);
+hipError_t launch_panel_to_bf16(const float* P, uint16_t* P16, int64_t count, hipStream_t s);
+
 // --- small dense FP64 steps (k_small.hip) ---
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
                        int64_t chunks, double* gpart, double* G, hipStream_t s);
-hipError_t launch_chol(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
-                       double tau, hipStream_t s);
-hipError_t launch_trtri(const double* L, int64_t lp, int64_t l, float* W, hipStream_t s);
+// W = L^-T (FP32, upper triangular) with G = L L^T; dropped directions zero.
+hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
+                           double tau, hipStream_t s);
 // out(:, 0:ncols) = P(:, 0:kdim) * W(0:kdim, 0:ncols); W row-major with ldw;
 // `tri`: W upper triangular (skip zero blocks).  Rows [rows, ld) written as 0.
 hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,

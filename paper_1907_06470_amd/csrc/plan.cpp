@@ -55,8 +55,8 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     if (prob.format == RSVD_CSR) return fail(p, RSVD_E_UNSUPPORTED, "CSR input is not implemented");
     return fail(p, RSVD_E_INVALID_ARG, "unknown format %lld", prob.format);
   }
-  if (prob.dtype != RSVD_F32 && prob.dtype != RSVD_F64) {
-    if (prob.dtype == RSVD_BF16 || prob.dtype == RSVD_FP8E4M3)
+  if (prob.dtype != RSVD_F32 && prob.dtype != RSVD_F64 && prob.dtype != RSVD_BF16) {
+    if (prob.dtype == RSVD_FP8E4M3)
       return fail(p, RSVD_E_UNSUPPORTED, "A stored as dtype %lld is not implemented", prob.dtype);
     return fail(p, RSVD_E_INVALID_ARG, "unknown dtype %lld", prob.dtype);
   }
@@ -68,9 +68,15 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   for (int32_t pr : {o.prec_sketch, o.prec_power, o.prec_project}) {
     if (pr != RSVD_F32 && pr != RSVD_BF16 && pr != RSVD_FP8E4M3)
       return fail(p, RSVD_E_INVALID_ARG, "unknown product precision %lld", pr);
-    if (pr != RSVD_F32)
+    if (pr == RSVD_FP8E4M3)
       return fail(p, RSVD_E_UNSUPPORTED, "product precision %lld is not implemented", pr);
   }
+  p.any_bf16 = o.prec_sketch == RSVD_BF16 || o.prec_project == RSVD_BF16 ||
+               (o.prec_power == RSVD_BF16 && prob.q > 0);
+  p.any_f32 = o.prec_sketch == RSVD_F32 || o.prec_project == RSVD_F32 ||
+              (o.prec_power == RSVD_F32 && prob.q > 0);
+  if (prob.dtype == RSVD_BF16 && p.any_f32)
+    return fail(p, RSVD_E_UNSUPPORTED, "A stored in BF16 needs BF16 products throughout");
   if (o.ortho != RSVD_ORTHO_EACH && o.ortho != RSVD_ORTHO_FINAL_ONLY)
     return fail(p, RSVD_E_INVALID_ARG, "unknown ortho schedule %lld", o.ortho);
   if (o.ortho == RSVD_ORTHO_FINAL_ONLY)
@@ -100,7 +106,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   // Gram chunking: enough chunks that the Gram kernels fill the device
   {
     const int64_t pairs = gram_pairs(p);
-    const int64_t want = 512;
+    const int64_t want = 256;
     const int64_t rows = std::max(m, n);
     int64_t chunks = std::max<int64_t>(1, ceil_div(want, pairs));
     p.gram_rows = std::max<int64_t>(256, round_up(ceil_div(rows, chunks), 64));
@@ -143,8 +149,12 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.rot = take((size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8);
   w.signs = take(lp * 4);
   w.status = take(kStatusWords * 4);
-  w.Acast = prob.dtype == RSVD_F64 ? take((size_t)m * round_up(n, 64) * 4) : off;
   p.ldac = round_up(n, 64);
+  p.lda16 = round_up(n, 64);
+  w.Acast = (prob.dtype == RSVD_F64 && p.any_f32) ? take((size_t)m * p.ldac * 4) : off;
+  w.A16 = (p.any_bf16 && prob.dtype != RSVD_BF16) ? take((size_t)m * p.lda16 * 2) : off;
+  w.Xop16 = p.any_bf16 ? take((size_t)p.ldn * lp * 2) : off;
+  w.Mop16 = p.any_bf16 ? take((size_t)p.ldm * lp * 2) : off;
   w.total = off;
 
   if (o.hbm_budget_bytes && w.total > o.hbm_budget_bytes)

@@ -48,6 +48,8 @@ struct Workspace {
   size_t signs;           // k int32 sign-fix argmax
   size_t status;          // kStatusWords int32
   size_t Acast;           // FP32 copy of an FP64 A
+  size_t A16;             // BF16 copy of A (when a product runs in BF16)
+  size_t Xop16, Mop16;    // BF16 copies of the operand panels
   size_t total;
 };
 
@@ -59,6 +61,9 @@ struct Plan {
   int64_t TI = 0, TJ = 0;       // tile counts (rows, cols)
   int64_t ldm = 0, ldn = 0;     // panel leading dimensions
   int64_t ldac = 0;             // leading dimension of the FP32 cast of A
+  int64_t lda16 = 0;            // leading dimension of the BF16 copy of A
+  bool any_bf16 = false;        // some product runs in BF16
+  bool any_f32 = false;         // some product runs in FP32
   int64_t gram_rows = 0;        // rows per Gram chunk
   int64_t gram_chunks = 0;      // max chunks over the m- and n-side panels
   int64_t rot_rounds = 0;       // capacity of the rotation log (rounds)

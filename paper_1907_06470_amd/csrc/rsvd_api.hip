@@ -90,6 +90,7 @@ rsvd_status hip_err(rsvd_plan_t h, hipError_t e, const char* what) {
 
 struct Buffers {
   float *Xop, *Mop, *M0, *M1, *N0, *N1, *part, *W, *W2, *Acast;
+  uint16_t *A16, *Xop16, *Mop16;
   double *gpart, *G, *L, *Ev, *lam, *rot;
   int32_t *order, *signs, *status;
 };
@@ -108,6 +109,9 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.W = (float*)(b + w.W);
   B.W2 = (float*)(b + w.W2);
   B.Acast = (float*)(b + w.Acast);
+  B.A16 = (uint16_t*)(b + w.A16);
+  B.Xop16 = (uint16_t*)(b + w.Xop16);
+  B.Mop16 = (uint16_t*)(b + w.Mop16);
   B.gpart = (double*)(b + w.gpart);
   B.G = (double*)(b + w.G);
   B.L = (double*)(b + w.L);
@@ -128,8 +132,9 @@ struct Runner {
   hipStream_t s;
   const float* A32 = nullptr;
   int64_t lda32 = 0;
+  const uint16_t* A16 = nullptr;
+  int64_t lda16 = 0;
   Events* ev = nullptr;        // non-null: time every product kernel
-  int nn_pairs = 0, tn_pairs = 0;
   std::vector<int> nn_idx, tn_idx;
   int next_pair = 0;
 
@@ -144,51 +149,74 @@ struct Runner {
 
   Runner(rsvd_plan_t hh, void* ws, hipStream_t ss) : h(hh), P(hh->p), B(carve(hh->p, ws)), s(ss) {}
 
-  // A (row-major FP32 or FP64) -> A32/lda32
+  // Operand copies of A the products need: FP32 (FP64 input is rounded once)
+  // and/or BF16 (rounded to nearest even once per call).
   rsvd_status bind_A(const void* A, int64_t lda) {
-    if (P.prob.dtype == RSVD_F64) {
-      RSVD_HIP(rsvd::launch_cast_f64_f32((const double*)A, lda, P.prob.m, P.prob.n, B.Acast,
-                                         P.ldac, s));
-      A32 = B.Acast;
-      lda32 = P.ldac;
-    } else {
-      A32 = (const float*)A;
-      lda32 = lda;
+    const int32_t dt = P.prob.dtype;
+    if (P.any_f32) {
+      if (dt == RSVD_F64) {
+        RSVD_HIP(rsvd::launch_cast_f64_f32((const double*)A, lda, P.prob.m, P.prob.n, B.Acast,
+                                           P.ldac, s));
+        A32 = B.Acast;
+        lda32 = P.ldac;
+      } else {
+        A32 = (const float*)A;
+        lda32 = lda;
+      }
+    }
+    if (P.any_bf16) {
+      if (dt == RSVD_BF16) {
+        A16 = (const uint16_t*)A;
+        lda16 = lda;
+      } else {
+        RSVD_HIP(rsvd::launch_cast_to_bf16(A, dt == RSVD_F64, lda, P.prob.m, P.prob.n, B.A16,
+                                           P.lda16, s));
+        A16 = B.A16;
+        lda16 = P.lda16;
+      }
     }
     return RSVD_OK;
   }
 
   // out (m-side panel, ld = ldm) = A X   (X: n-side panel, ld = ldn)
-  rsvd_status product_nn(const float* X, float* out) {
+  rsvd_status product_nn(const float* X, const uint16_t* X16, bool bf16, float* out) {
     const int64_t m = P.prob.m, n = P.prob.n;
+    const bool split = P.TJ > 1;
+    const int64_t stride = split ? P.ldm * P.lp : 0;
+    float* dst = split ? B.part : out;
     RSVD_HIP(tick(true, true));
-    if (P.TJ == 1) {
-      RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, 1, X, P.ldn, P.lp, out, P.ldm, 0, s));
-      RSVD_HIP(tick(true, false));
-    } else {
-      const int64_t stride = P.ldm * P.lp;
-      RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, P.TJ, X, P.ldn, P.lp, B.part, P.ldm,
+    if (bf16)
+      RSVD_HIP(rsvd::launch_nn_bf16(A16, lda16, m, n, P.tn, P.TJ, X16, P.ldn, P.lp, dst, P.ldm,
+                                    stride, s));
+    else
+      RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, P.TJ, X, P.ldn, P.lp, dst, P.ldm,
                                    stride, s));
-      RSVD_HIP(tick(true, false));
-      RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TJ, out, stride, s));
-    }
+    RSVD_HIP(tick(true, false));
+    if (split) RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TJ, out, stride, s));
     return RSVD_OK;
   }
 
   // out (n-side panel) = A^T Q   (Q: m-side panel)
-  rsvd_status product_tn(const float* Q, float* out) {
+  rsvd_status product_tn(const float* Q, const uint16_t* Q16, bool bf16, float* out) {
     const int64_t m = P.prob.m, n = P.prob.n;
+    const bool split = P.TI > 1;
+    const int64_t stride = split ? P.ldn * P.lp : 0;
+    float* dst = split ? B.part : out;
     RSVD_HIP(tick(false, true));
-    if (P.TI == 1) {
-      RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, 1, Q, P.ldm, P.lp, out, P.ldn, 0, s));
-      RSVD_HIP(tick(false, false));
-    } else {
-      const int64_t stride = P.ldn * P.lp;
-      RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, P.TI, Q, P.ldm, P.lp, B.part, P.ldn,
+    if (bf16)
+      RSVD_HIP(rsvd::launch_tn_bf16(A16, lda16, m, n, P.tm, P.TI, Q16, P.ldm, P.lp, dst, P.ldn,
+                                    stride, s));
+    else
+      RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, P.TI, Q, P.ldm, P.lp, dst, P.ldn,
                                    stride, s));
-      RSVD_HIP(tick(false, false));
-      RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TI, out, stride, s));
-    }
+    RSVD_HIP(tick(false, false));
+    if (split) RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, P.TI, out, stride, s));
+    return RSVD_OK;
+  }
+
+  // BF16 copy of a finished FP32 panel for the next BF16 product.
+  rsvd_status to_bf16(const float* src, uint16_t* dst, int64_t ld) {
+    RSVD_HIP(rsvd::launch_panel_to_bf16(src, dst, ld * P.lp, s));
     return RSVD_OK;
   }
 
@@ -202,8 +230,7 @@ struct Runner {
   rsvd_status cholqr_pass(const float* in, float* out, int64_t rows, int64_t ld) {
     rsvd_status st = gram(in, rows, ld);
     if (st != RSVD_OK) return st;
-    RSVD_HIP(rsvd::launch_chol(B.G, P.lp, P.l, B.L, B.status, kCholTau, s));
-    RSVD_HIP(rsvd::launch_trtri(B.L, P.lp, P.l, B.W, s));
+    RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
     RSVD_HIP(rsvd::launch_apply(in, ld, rows, P.l, B.W, P.lp, P.lp, P.lp, true, out, ld, ld, s));
     return RSVD_OK;
   }
@@ -243,6 +270,8 @@ rsvd_status check_A(rsvd_plan_t h, const void* A, int64_t lda) {
   if (lda < P.prob.n) return set_err(h, RSVD_E_INVALID_ARG, "lda < n");
   if (P.prob.dtype == RSVD_F32 && (((uintptr_t)A) & 3) != 0)
     return set_err(h, RSVD_E_INVALID_ARG, "FP32 A must be 4-byte aligned");
+  if (P.prob.dtype == RSVD_BF16 && ((lda % 8) != 0 || (((uintptr_t)A) & 15) != 0))
+    return set_err(h, RSVD_E_INVALID_ARG, "BF16 A needs lda % 8 == 0 and a 16-byte aligned base");
   if (P.prob.dtype == RSVD_F64 && (((uintptr_t)A) & 7) != 0)
     return set_err(h, RSVD_E_INVALID_ARG, "FP64 A must be 8-byte aligned");
   return RSVD_OK;
@@ -395,21 +424,27 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
   RSVD_HIP(mark(0));
   RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
   if ((st = R.bind_A(A, lda))) return st;
+  const bool bs = P.opt.prec_sketch == RSVD_BF16, bp = P.opt.prec_power == RSVD_BF16,
+             bj = P.opt.prec_project == RSVD_BF16;
   RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, R.B.Xop, P.ldn, s));   // step 1
+  if (bs && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
   RSVD_HIP(mark(1));
-  if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;                                // step 2
+  if ((st = R.product_nn(R.B.Xop, R.B.Xop16, bs, R.B.M0))) return st;                // step 2
   RSVD_HIP(mark(2));
   if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;  // 3-4
+  if ((P.prob.q > 0 ? bp : bj) && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
   RSVD_HIP(mark(3));
   for (int64_t t = 0; t < P.prob.q; ++t) {                                            // Eq. (2)
     const bool last = t + 1 == P.prob.q;
-    if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;
+    if ((st = R.product_tn(R.B.Mop, R.B.Mop16, bp, R.B.N0))) return st;
     if ((st = R.orth(R.B.N0, R.B.Xop, R.B.N1, n, P.ldn, !cq1))) return st;
-    if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;
+    if (bp && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
+    if ((st = R.product_nn(R.B.Xop, R.B.Xop16, bp, R.B.M0))) return st;
     if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || last))) return st;
+    if ((last ? bj : bp) && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
   }
   RSVD_HIP(mark(4));
-  if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;                                // step 5
+  if ((st = R.product_tn(R.B.Mop, R.B.Mop16, bj, R.B.N0))) return st;                 // step 5
   RSVD_HIP(mark(5));
   if ((st = R.small_svd_eig(R.B.N0))) return st;                                      // SVD0 prep
   RSVD_HIP(mark(6));
@@ -449,7 +484,13 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
   RSVD_HIP(hipMemcpy(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost));
   const double passes = 2.0 * (double)P.prob.q + 2.0;
   report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
-  report->bytes_alg = passes * ((double)m * (double)n * 4.0 + ((double)m + (double)n) * P.l * 4.0);
+  {
+    auto pass_bytes = [&](bool b16) {
+      const double e = b16 ? 2.0 : 4.0;
+      return (double)m * (double)n * e + ((double)m + (double)n) * P.l * e;
+    };
+    report->bytes_alg = pass_bytes(bs) + 2.0 * (double)P.prob.q * pass_bytes(bp) + pass_bytes(bj);
+  }
   report->ws_bytes = (int64_t)P.ws.total;
   report->dropped = stw[rsvd::kStDropped];
   report->jacobi_sweeps = stw[rsvd::kStSweeps];
@@ -475,12 +516,16 @@ rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t 
   rsvd_status st;
   if ((st = R.bind_A(A, lda))) return st;
   if (op == 0) {
+    const bool b16 = P.opt.prec_sketch == RSVD_BF16;
     RSVD_HIP(rsvd::launch_panel_copy(X, ldx, n, P.l, R.B.Xop, P.ldn, P.ldn, P.lp, s));
-    if ((st = R.product_nn(R.B.Xop, R.B.M0))) return st;
+    if (b16 && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
+    if ((st = R.product_nn(R.B.Xop, R.B.Xop16, b16, R.B.M0))) return st;
     RSVD_HIP(rsvd::launch_panel_copy(R.B.M0, P.ldm, m, P.l, out, ldo, m, P.l, s));
   } else {
+    const bool b16 = P.opt.prec_project == RSVD_BF16;
     RSVD_HIP(rsvd::launch_panel_copy(X, ldx, m, P.l, R.B.Mop, P.ldm, P.ldm, P.lp, s));
-    if ((st = R.product_tn(R.B.Mop, R.B.N0))) return st;
+    if (b16 && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
+    if ((st = R.product_tn(R.B.Mop, R.B.Mop16, b16, R.B.N0))) return st;
     RSVD_HIP(rsvd::launch_panel_copy(R.B.N0, P.ldn, n, P.l, out, ldo, n, P.l, s));
   }
   return RSVD_OK;

@@ -52,6 +52,7 @@ def make(m=100, n=80, k=5, p=5, q=1, **kw):
     (dict(k=50, p=40), L.E_INVALID_ARG),          # k + p > min(m, n)
     (dict(tile=(100, 64)), L.E_INVALID_ARG),      # not a multiple of 32
     (dict(precision="fp16"), L.E_INVALID_ARG),
+    (dict(precision="fp8"), L.E_UNSUPPORTED),
 ])
 def test_plan_rejects_bad_arguments(args, status):
     with pytest.raises(L.RsvdError) as e:
