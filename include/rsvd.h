@@ -58,7 +58,8 @@ enum { RSVD_LOC_DEVICE = 0, RSVD_LOC_HOST_PINNED = 1 };              /* location
 enum { RSVD_ORTHO_EACH = 0, RSVD_ORTHO_FINAL_ONLY = 2 };             /* schedules */
 enum {
   RSVD_FLAG_NO_SIGN_FIX = 1,   /* skip the sign convention                          */
-  RSVD_FLAG_CHOLQR1 = 2        /* one CholeskyQR pass for intermediate bases        */
+  RSVD_FLAG_CHOLQR1 = 2,       /* one CholeskyQR pass for intermediate bases        */
+  RSVD_FLAG_BACKWARD = 4       /* size the workspace for rsvd_backward too          */
 };
 
 /* The problem: A is m x n, rank k, oversampling p, q power steps
@@ -140,6 +141,35 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_pl
 rsvd_status rsvd_factor(rsvd_plan_t plan, const void* A, int64_t lda, void* ws,
                         float* U, int64_t ldu, double* S, float* V, int64_t ldv,
                         void* stream, rsvd_report* report);
+
+/* Reverse-mode derivative (adjoint) of rsvd_factor.  The paper has no
+ * derivative; this treats the l = k + p Ritz triplets (U_l, S_l, V_l) of the
+ * randomized SVD as exact singular triplets of A and applies the real-SVD
+ * adjoint: with cotangents gU (m x k), gS (k), gV (n x k) zero-padded to l
+ * columns, F_ij = 1 / (s_j^2 - s_i^2) (i != j, FP64) and skew(X) = X - X^T,
+ *   gA = U_l [(F o skew(U_l^T gU)) S_l + S_l (F o skew(V_l^T gV)) + diag(gS)] V_l^T
+ *        + (I - U_l U_l^T) gU S_k^-1 V_k^T + U_k S_k^-1 gV^T (I - V_l V_l^T).
+ * Ties |s_i^2 - s_j^2| <= 1e-12 s_1^2 set F_ij = 0 (status
+ * RSVD_W_DEGENERATE); 1/s_i = 0 for s_i <= 1e-12 s_1.
+ *   A       the same matrix passed to rsvd_factor (device, row-major, lda).
+ *   gU, gV  device, column-major (ldgu >= m, ldgv >= n), FP32; NULL = zero.
+ *   gS      device, k doubles; NULL = zero.
+ *   gA      device output, row-major m x n FP32, ldga >= n.
+ * The range basis is recomputed from the plan's seed (2q + 2 passes over A)
+ * instead of being stored by the forward call.  The plan must have been made
+ * with RSVD_FLAG_BACKWARD (else RSVD_E_INVALID_ARG).  `report` as in
+ * rsvd_factor. */
+rsvd_status rsvd_backward(rsvd_plan_t plan, const void* A, int64_t lda, const float* gU,
+                          int64_t ldgu, const double* gS, const float* gV, int64_t ldgv,
+                          float* gA, int64_t ldga, void* ws, void* stream, rsvd_report* report);
+
+/* Accuracy pass: *out (device, one double) = ||A - U diag(S) V^T||_F for the
+ * first k columns, computed directly tile by tile (U S V^T rebuilt on the
+ * matrix cores, differences squared and summed in FP64; no ||A||^2 - sum s^2
+ * cancellation).  One more pass over A.  Uses the plan's workspace. */
+rsvd_status rsvd_residual(rsvd_plan_t plan, const void* A, int64_t lda, const float* U, int64_t ldu,
+                          const double* S, const float* V, int64_t ldv, double* out, void* ws,
+                          void* stream);
 
 /* Free a plan (NULL is ignored). */
 void rsvd_plan_destroy(rsvd_plan_t plan);

@@ -25,7 +25,7 @@ DENSE, CSR = 0, 1
 F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
 LOC_DEVICE, LOC_HOST_PINNED = 0, 1
 ORTHO_EACH, ORTHO_FINAL_ONLY = 0, 2
-FLAG_NO_SIGN_FIX, FLAG_CHOLQR1 = 1, 2
+FLAG_NO_SIGN_FIX, FLAG_CHOLQR1, FLAG_BACKWARD = 1, 2, 4
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 c_vp, c_sz = ctypes.c_void_p, ctypes.c_size_t
@@ -58,6 +58,9 @@ _SIGS = {
     "rsvd_plan": (c_i32, [_P(Problem), _P(Options), _P(c_vp), _P(c_sz)]),
     "rsvd_factor": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
                             _P(Report)]),
+    "rsvd_backward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
+                              c_vp, c_vp, _P(Report)]),
+    "rsvd_residual": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "rsvd_plan_destroy": (None, [c_vp]),
     "rsvd_status_str": (ctypes.c_char_p, [c_i32]),
     "rsvd_last_error": (ctypes.c_char_p, [c_vp]),

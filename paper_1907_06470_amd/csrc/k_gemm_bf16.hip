@@ -214,10 +214,42 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
 }
 
 // A16 (m x ldo, BF16, round to nearest even) = A (m x n FP32 or FP64, lda);
-// columns [n, ldo) zero.  8 elements per thread.
-template <typename T>
+// columns [n, ldo) zero.  8 elements per thread; rows that are 16-byte aligned
+// take two 16-byte loads.
+__device__ inline uint32_t pack_bf16(float a, float b) {
+  const __bf16 x = (__bf16)a, y = (__bf16)b;
+  uint16_t u0, u1;
+  __builtin_memcpy(&u0, &x, 2);
+  __builtin_memcpy(&u1, &y, 2);
+  return (uint32_t)u0 | ((uint32_t)u1 << 16);
+}
+
+template <typename T, bool VEC>
 __global__ void k_cast_to_bf16(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                u16* __restrict__ out, int64_t ldo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_row = ldo / 8;
+  if (t >= m * per_row) return;
+  const int64_t i = t / per_row, j0 = (t % per_row) * 8;
+  float x[8];
+  if (VEC && j0 + 8 <= n) {
+    const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(A) + i * lda + j0);
+    const float4 b = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(A) + i * lda + j0 + 4);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = j0 + e < n ? (float)A[i * lda + j0 + e] : 0.f;
+  }
+  uint32_t w[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w[e] = pack_bf16(x[2 * e], x[2 * e + 1]);
+  *reinterpret_cast<uint4*>(out + i * ldo + j0) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// FP64 source: each value rounded once, FP64 -> BF16 (nearest even).
+__global__ void k_cast_f64_to_bf16(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                   u16* __restrict__ out, int64_t ldo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per_row = ldo / 8;
   if (t >= m * per_row) return;
@@ -225,9 +257,8 @@ __global__ void k_cast_to_bf16(const T* __restrict__ A, int64_t lda, int64_t m, 
   uint32_t w[4];
 #pragma unroll
   for (int e = 0; e < 8; e += 2) {
-    const T x0 = j0 + e < n ? A[i * lda + j0 + e] : T(0);
-    const T x1 = j0 + e + 1 < n ? A[i * lda + j0 + e + 1] : T(0);
-    const __bf16 b0 = (__bf16)x0, b1 = (__bf16)x1;
+    const __bf16 b0 = (__bf16)(j0 + e < n ? A[i * lda + j0 + e] : 0.0);
+    const __bf16 b1 = (__bf16)(j0 + e + 1 < n ? A[i * lda + j0 + e + 1] : 0.0);
     uint16_t u0, u1;
     __builtin_memcpy(&u0, &b0, 2);
     __builtin_memcpy(&u1, &b1, 2);
@@ -299,12 +330,16 @@ hipError_t launch_cast_to_bf16(const void* A, bool f64, int64_t lda, int64_t m, 
   if (ldo % 8) return hipErrorInvalidValue;
   const int64_t total = m * (ldo / 8);
   dim3 grid((unsigned)ceil_div_dev(total, 256));
-  if (f64)
-    hipLaunchKernelGGL(k_cast_to_bf16<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n,
-                       out, ldo);
-  else
-    hipLaunchKernelGGL(k_cast_to_bf16<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, n,
-                       out, ldo);
+  if (f64) {
+    hipLaunchKernelGGL(k_cast_f64_to_bf16, grid, dim3(256), 0, s, (const double*)A, lda, m, n, out,
+                       ldo);
+  } else if ((lda % 4) == 0 && (((uintptr_t)A) & 15) == 0) {
+    hipLaunchKernelGGL((k_cast_to_bf16<float, true>), grid, dim3(256), 0, s, (const float*)A, lda,
+                       m, n, out, ldo);
+  } else {
+    hipLaunchKernelGGL((k_cast_to_bf16<float, false>), grid, dim3(256), 0, s, (const float*)A, lda,
+                       m, n, out, ldo);
+  }
   return hipGetLastError();
 }
 

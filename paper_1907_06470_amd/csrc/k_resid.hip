@@ -15,6 +15,8 @@ __device__ inline f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+constexpr int kResidWGs = 2048;
+
 template <typename TA>
 __global__ __launch_bounds__(256) void k_residual(const TA* __restrict__ A, int64_t lda, int64_t m,
                                                   int64_t n, const float* __restrict__ U,
@@ -24,34 +26,37 @@ __global__ __launch_bounds__(256) void k_residual(const TA* __restrict__ A, int6
   __shared__ double red[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, half = lane >> 5;
-  const int64_t rb = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;   // rows of this wave
-  const int64_t cb = (int64_t)blockIdx.x * 128 + (wave & 1) * 64;   // columns of this wave
-  const int64_t i = rb + l32;
-  f32x16 acc[2] = {f32x16{}, f32x16{}};
-  for (int c0 = 0; c0 < k; c0 += 2) {
-    const int c = c0 + half;
-    const float a = (i < m && c < k) ? U[(int64_t)c * ldu + i] * (float)S[c] : 0.f;
+  const int64_t tiles_j = (n + 127) / 128, tiles = tiles_j * ((m + 63) / 64);
+  double sum = 0.0;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t rb = (tile / tiles_j) * 64 + (wave >> 1) * 32;   // rows of this wave
+    const int64_t cb = (tile % tiles_j) * 128 + (wave & 1) * 64;   // columns of this wave
+    const int64_t i = rb + l32;
+    f32x16 acc[2] = {f32x16{}, f32x16{}};
+    for (int c0 = 0; c0 < k; c0 += 2) {
+      const int c = c0 + half;
+      const float a = (i < m && c < k) ? U[(int64_t)c * ldu + i] * (float)S[c] : 0.f;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t j = cb + t * 32 + l32;
+        const float b = (j < n && c < k) ? V[(int64_t)c * ldv + j] : 0.f;
+        acc[t] = mfma32(a, b, acc[t]);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int64_t j = cb + t * 32 + l32;
-      const float b = (j < n && c < k) ? V[(int64_t)c * ldv + j] : 0.f;
-      acc[t] = mfma32(a, b, acc[t]);
-    }
-  }
-  double sum = 0.0;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int64_t j = cb + t * 32 + l32;
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t r = rb + 8 * g + 4 * half + e;
-        if (r < m && j < n) {
-          const double d = (double)A[r * lda + j] - (double)acc[t][4 * g + e];
-          sum += d * d;
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = rb + 8 * g + 4 * half + e;
+          if (r < m && j < n) {
+            const double d = (double)A[r * lda + j] - (double)acc[t][4 * g + e];
+            sum += d * d;
+          }
         }
-      }
+    }
   }
   red[tid] = sum;
   __syncthreads();
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(256) void k_residual(const TA* __restrict__ A, int6
     if (tid < off) red[tid] += red[tid + off];
     __syncthreads();
   }
-  if (tid == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  if (tid == 0) partial[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_sum_sqrt(const double* __restrict__ partial, int64_t count,
@@ -79,13 +84,12 @@ __global__ __launch_bounds__(256) void k_sum_sqrt(const double* __restrict__ par
 
 }  // namespace
 
-int64_t residual_partials(int64_t m, int64_t n) { return ceil_div_dev(n, 128) * ceil_div_dev(m, 64); }
+int64_t residual_partials(int64_t, int64_t) { return kResidWGs; }
 
 hipError_t launch_residual(const void* A, bool f64, int64_t lda, int64_t m, int64_t n,
                            const float* U, int64_t ldu, const double* S, const float* V,
                            int64_t ldv, int64_t k, double* partial, double* out, hipStream_t s) {
-  dim3 grid((unsigned)ceil_div_dev(n, 128), (unsigned)ceil_div_dev(m, 64));
-  if (grid.y > 65535u) return hipErrorInvalidValue;
+  dim3 grid(kResidWGs);
   if (f64)
     hipLaunchKernelGGL(k_residual<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n, U,
                        ldu, S, V, ldv, (int)k, partial);
@@ -94,8 +98,7 @@ hipError_t launch_residual(const void* A, bool f64, int64_t lda, int64_t m, int6
                        S, V, ldv, (int)k, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s, partial,
-                     (int64_t)grid.x * grid.y, out);
+  hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s, partial, (int64_t)kResidWGs, out);
   return hipGetLastError();
 }
 

@@ -146,7 +146,7 @@ __global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, 
 // direction: its column of L and its row and column of X are zero, so the
 // basis Q = Y W gets a zero column and the direction feeds no other column.
 constexpr int kCholThreads = 256;
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restrict__ G, int64_t lp,
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv_simple(const double* __restrict__ G, int64_t lp,
                                                            int l, float* __restrict__ W,
                                                            int32_t* status, double tau) {
   __shared__ double T[kTri];
@@ -227,6 +227,230 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv(const double* __restr
   }
 }
 
+// Blocked form of the same computation for sketch widths up to 160 (the
+// packed triangle plus a 32-row work panel fit in LDS).  Panels of 32
+// columns: one wave factors the diagonal block (no workgroup barriers inside),
+// all threads solve the rows below against it and update the trailing
+// triangle with register-blocked dot products.  The inverse proceeds by block
+// rows: one wave inverts the diagonal block while the others form
+// T_ij = sum_k L_ik X_kj, then X_ij = -X_ii T_ij.  Three barriers per block.
+constexpr int kCB = 32;                 // block edge
+constexpr int kBlkMaxLp = 160;
+constexpr int kBlkTri = kBlkMaxLp * (kBlkMaxLp + 1) / 2;
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double* __restrict__ G,
+                                                                   int64_t lp, int l,
+                                                                   float* __restrict__ W,
+                                                                   double* __restrict__ Lout,
+                                                                   int32_t* status, double tau) {
+  __shared__ double T[kBlkTri];
+  __shared__ double dinv[kBlkMaxLp];                 // 1 / L(j, j), 0 for dropped j
+  __shared__ double Trow[kCB * (kBlkMaxLp - kCB)];   // block-row work panel
+  __shared__ double Xd[kCB * kCB];                   // inverse of a diagonal block
+  __shared__ double d0[kBlkMaxLp];
+  __shared__ int ndrop, nbad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tot = l * (l + 1) / 2;
+  for (int e = tid; e < tot; e += kCholThreads) {
+    int i, c;
+    tri_decode(e, i, c);
+    T[e] = G[(int64_t)i * lp + c];
+  }
+  for (int i = tid; i < l; i += kCholThreads) d0[i] = G[(int64_t)i * lp + i];
+  if (tid == 0) {
+    ndrop = 0;
+    nbad = 0;
+  }
+  lds_barrier();
+  const int nb = (l + kCB - 1) / kCB;
+
+  // ---- Cholesky, right-looking by panels
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * kCB, k1 = min(l, k0 + kCB);
+    if (wave == 0) {   // diagonal block, one wave
+      for (int j = k0; j < k1; ++j) {
+        const double d = T[tidx(j, j)];
+        double piv = 0.0;
+        const bool bad = !is_finite_d(d);
+        if (!bad && d0[j] > 0.0 && d > tau * d0[j]) piv = sqrt(d);
+        const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+        const int i = j + 1 + lane;
+        if (i < k1) T[tidx(i, j)] *= inv;
+        if (lane == 0) {
+          T[tidx(j, j)] = piv;
+          dinv[j] = inv;
+          if (bad) ++nbad;
+          else if (piv == 0.0) ++ndrop;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        if (i < k1 && piv > 0.0) {
+          const double lij = T[tidx(i, j)];
+          for (int c = j + 1; c <= i; ++c) T[tidx(i, c)] -= lij * T[tidx(c, j)];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    lds_barrier();
+    // rows below: L_ij = (A_ij - sum_{k0<=p<j} L_ip L_jp) / L_jj, one row per thread
+    for (int i = k1 + tid; i < l; i += kCholThreads) {
+      double r[kCB];
+#pragma unroll
+      for (int q = 0; q < kCB; ++q) r[q] = (k0 + q < k1) ? T[tidx(i, k0 + q)] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kCB; ++q) {
+        const int j = k0 + q;
+        if (j < k1) {
+          double a0 = r[q], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          const int jb = tidx(j, k0);
+#pragma unroll
+          for (int pq = 0; pq + 3 < q; pq += 4) {
+            a0 -= r[pq] * T[jb + pq];
+            a1 -= r[pq + 1] * T[jb + pq + 1];
+            a2 -= r[pq + 2] * T[jb + pq + 2];
+            a3 -= r[pq + 3] * T[jb + pq + 3];
+          }
+#pragma unroll
+          for (int pq = q & ~3; pq < q; ++pq) a0 -= r[pq] * T[jb + pq];
+          r[q] = ((a0 + a1) + (a2 + a3)) * dinv[j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kCB; ++q)
+        if (k0 + q < k1) T[tidx(i, k0 + q)] = r[q];
+    }
+    lds_barrier();
+    // trailing update, 4 x 4 element blocks of the lower triangle
+    const int t0 = k1, nt = l - k1;
+    if (nt > 0) {
+      const int nbb = (nt + 3) / 4;
+      const int nblk = nbb * (nbb + 1) / 2;
+      for (int e = tid; e < nblk; e += kCholThreads) {
+        int bi, bc;
+        tri_decode(e, bi, bc);
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int q = k0; q < k1; ++q) {
+          double li[4], lc[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int i = t0 + 4 * bi + a, c = t0 + 4 * bc + a;
+            li[a] = i < l ? T[tidx(i, q)] : 0.0;
+            lc[a] = c < l ? T[tidx(c, q)] : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += li[a] * lc[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int i = t0 + 4 * bi + a, c = t0 + 4 * bc + b;
+            if (i < l && c <= i) T[tidx(i, c)] -= acc[a][b];
+          }
+      }
+    }
+    lds_barrier();
+  }
+
+  if (Lout) {   // factor only: L (FP64, lp x lp row-major, zero above the diagonal)
+    for (int e = tid; e < lp * lp; e += kCholThreads) {
+      const int i = e / (int)lp, c = e % (int)lp;
+      Lout[e] = (i < l && c <= i) ? T[tidx(i, c)] : 0.0;
+    }
+    if (tid == 0) {
+      status[kStDropped] += ndrop;
+      status[kStNonFinite] += nbad;
+    }
+    return;
+  }
+  // ---- X = L^-1 by block rows, in place
+  for (int ib = 0; ib < nb; ++ib) {
+    const int r0 = ib * kCB, r1 = min(l, r0 + kCB), rw = r1 - r0;
+    if (wave == 0) {
+      // X_ii = L_ii^-1: lane c < rw forward-substitutes column c
+      if (lane < rw) {
+        double x[kCB];
+#pragma unroll
+        for (int r = 0; r < kCB; ++r) {
+          double v = 0.0;
+          if (r < rw) {
+            const double ir = dinv[r0 + r];
+            if (ir > 0.0 && dinv[r0 + lane] > 0.0) {
+              double acc = (r == lane) ? 1.0 : 0.0;
+              const int rb = tidx(r0 + r, r0);
+#pragma unroll
+              for (int pq = 0; pq < r; ++pq) acc -= T[rb + pq] * x[pq];
+              v = acc * ir;
+            }
+          }
+          x[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < kCB; ++r) Xd[r * kCB + lane] = x[r];
+      }
+    } else if (r0 > 0) {
+      // T_ij = sum_{c <= p < r0} L(r, p) X(p, c) for rows r of the block, columns
+      // c < r0; four columns per thread share the L(r, p) reads
+      const int c4n = (r0 + 3) / 4;
+      const int cnt = rw * c4n;
+      for (int e = tid - 64; e < cnt; e += kCholThreads - 64) {
+        const int rr = e / c4n, c0 = (e % c4n) * 4;
+        const int r = r0 + rr;
+        const int rb = tidx(r, 0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int pq = c0; pq < r0; ++pq) {
+          const double lv = T[rb + pq];
+          const int pb = tidx(pq, 0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + u <= pq) acc[u] += lv * T[pb + c0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c0 + u < r0) Trow[rr * (kBlkMaxLp - kCB) + c0 + u] = acc[u];
+      }
+    }
+    lds_barrier();
+    // X_ij = -X_ii T_ij ; X_ii into place
+    {
+      const int c4n = (r0 + 3) / 4;
+      const int cnt = rw * c4n;
+      for (int e = tid; e < cnt; e += kCholThreads) {
+        const int rr = e / c4n, c0 = (e % c4n) * 4;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q <= rr; ++q) {
+          const double xv = Xd[rr * kCB + q];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] += xv * Trow[q * (kBlkMaxLp - kCB) + c0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c0 + u < r0) T[tidx(r0 + rr, c0 + u)] = -acc[u];
+      }
+      for (int e = tid; e < rw * kCB; e += kCholThreads) {
+        const int rr = e / kCB, c = e % kCB;
+        if (c <= rr) T[tidx(r0 + rr, r0 + c)] = Xd[rr * kCB + c];
+      }
+    }
+    lds_barrier();
+  }
+  for (int e = tid; e < lp * lp; e += kCholThreads) {
+    const int a = e / (int)lp, c = e % (int)lp;
+    W[e] = (c < l && a <= c) ? (float)T[tidx(c, a)] : 0.f;
+  }
+  if (tid == 0) {
+    status[kStDropped] += ndrop;
+    status[kStNonFinite] += nbad;
+  }
+}
+
 // ------------------------------------------------------ panel x matrix ----
 // out(i, c) = sum_a P(i, a) W(a, c) for c < ncols; rows [rows, out_rows)
 // receive zeros.  One wave per 32 rows, all lp output columns.
@@ -284,9 +508,16 @@ __global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int6
 }
 
 // --------------------------------------------------------------- Jacobi ----
-__device__ inline int rr_pos(int x, int t, int le) { return x == 0 ? 0 : 1 + (x - 1 + t) % (le - 1); }
+// Round-robin ("tournament") schedule: at round t, position x holds index
+// rr_pos(x, t); position 0 is fixed, the others rotate.  0 <= t < le - 1.
+__device__ inline int rr_pos(int x, int t, int le) {
+  if (x == 0) return 0;
+  int v = x - 1 + t;
+  if (v >= le - 1) v -= le - 1;
+  return 1 + v;
+}
 
-constexpr int kJacThreads = 512;
+constexpr int kJacThreads = 1024;
 constexpr int kJacMaxBlocks = (kMaxLp / 2 * (kMaxLp / 2 + 1) / 2 + kJacThreads - 1) / kJacThreads;
 
 __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int64_t lp,
@@ -297,7 +528,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   __shared__ double T[kTri];
   __shared__ double cc_s[kMaxLp / 2 + 1], ss_s[kMaxLp / 2 + 1];
   __shared__ int pp_s[kMaxLp / 2 + 1], qq_s[kMaxLp / 2 + 1];
-  __shared__ int any_s;
+  __shared__ int any_s, big_s;
   const int tid = threadIdx.x;
   const int le = l + (l & 1), np = le / 2, R = le - 1;
   const int tot = l * (l + 1) / 2;
@@ -322,7 +553,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   int sweeps = 0;
   int64_t ridx = 0;
   for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
-    if (tid == 0) any_s = 0;
+    if (tid == 0) {
+      any_s = 0;
+      big_s = 0;
+    }
     lds_barrier();
     for (int t = 0; t < R; ++t) {
       if (tid < np) {
@@ -331,12 +565,14 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         double c = 1.0, s = 0.0;
         if (q < l) {
           const double app = T[tidx(p, p)], aqq = T[tidx(q, q)], apq = T[tidx(q, p)];
-          if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const double scale = sqrt(fabs(app * aqq));
+          if (apq != 0.0 && fabs(apq) > tol * scale) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
             any_s = 1;
+            if (fabs(apq) > 1e-10 * scale) big_s = 1;
           }
         }
         pp_s[tid] = p;
@@ -349,50 +585,173 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         }
       }
       lds_barrier();
+      // gather every owned block first, then rotate, then write back
+      int ax[kJacMaxBlocks], ay[kJacMaxBlocks], az[kJacMaxBlocks], aw[kJacMaxBlocks];
+      double vx[kJacMaxBlocks], vy[kJacMaxBlocks], vz[kJacMaxBlocks], vw[kJacMaxBlocks];
 #pragma unroll
       for (int u = 0; u < kJacMaxBlocks; ++u) {
-        if (tid + u * kJacThreads >= nb) break;
-        const int b1 = P1[u], b2 = P2[u];
-        const int p1 = pp_s[b1], q1 = qq_s[b1], p2 = pp_s[b2], q2 = qq_s[b2];
-        const double c1 = cc_s[b1], s1 = ss_s[b1], c2 = cc_s[b2], s2 = ss_s[b2];
-        if (b1 == b2) {
-          if (q1 < l && s1 != 0.0) {
-            const double app = T[tidx(p1, p1)], aqq = T[tidx(q1, q1)], apq = T[tidx(q1, p1)];
-            const double tt = s1 / c1;
-            T[tidx(p1, p1)] = app - tt * apq;
-            T[tidx(q1, q1)] = aqq + tt * apq;
-            T[tidx(q1, p1)] = 0.0;
+        ax[u] = ay[u] = az[u] = aw[u] = -1;
+        if (tid + u * kJacThreads < nb) {
+          const int b1 = P1[u], b2 = P2[u];
+          const int p1 = pp_s[b1], q1 = qq_s[b1], p2 = pp_s[b2], q2 = qq_s[b2];
+          const double sa = ss_s[b1], sb = ss_s[b2];
+          const bool active = (b1 == b2) ? (q1 < l && sa != 0.0) : (sa != 0.0 || sb != 0.0);
+          if (active) {
+            auto idx = [&](int r, int cc) { return r >= cc ? tidx(r, cc) : tidx(cc, r); };
+            if (b1 == b2) {
+              ax[u] = tidx(p1, p1);
+              ay[u] = tidx(q1, p1);
+              aw[u] = tidx(q1, q1);
+            } else {
+              ax[u] = idx(p1, p2);
+              if (q2 < l) ay[u] = idx(p1, q2);
+              if (q1 < l) az[u] = idx(q1, p2);
+              if (q1 < l && q2 < l) aw[u] = idx(q1, q2);
+            }
           }
-          continue;
         }
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const bool hq1 = q1 < l, hq2 = q2 < l;
-        auto at = [&](int r, int cidx) -> double& {
-          return r >= cidx ? T[tidx(r, cidx)] : T[tidx(cidx, r)];
-        };
-        const double x = at(p1, p2);
-        const double y = hq2 ? at(p1, q2) : 0.0;
-        const double z = hq1 ? at(q1, p2) : 0.0;
-        const double w = (hq1 && hq2) ? at(q1, q2) : 0.0;
-        const double x1 = c1 * x - s1 * z, y1 = c1 * y - s1 * w;
-        const double z1 = s1 * x + c1 * z, w1 = s1 * y + c1 * w;
-        at(p1, p2) = c2 * x1 - s2 * y1;
-        if (hq2) at(p1, q2) = s2 * x1 + c2 * y1;
-        if (hq1) at(q1, p2) = c2 * z1 - s2 * w1;
-        if (hq1 && hq2) at(q1, q2) = s2 * z1 + c2 * w1;
+      }
+#pragma unroll
+      for (int u = 0; u < kJacMaxBlocks; ++u) {
+        vx[u] = ax[u] >= 0 ? T[ax[u]] : 0.0;
+        vy[u] = ay[u] >= 0 ? T[ay[u]] : 0.0;
+        vz[u] = az[u] >= 0 ? T[az[u]] : 0.0;
+        vw[u] = aw[u] >= 0 ? T[aw[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kJacMaxBlocks; ++u) {
+        if (ax[u] < 0) continue;
+        const double c1 = cc_s[P1[u]], s1 = ss_s[P1[u]];
+        if (P1[u] == P2[u]) {
+          // diagonal block: app, apq, aqq -> app - t apq, 0, aqq + t apq
+          const double tt = s1 / c1;
+          const double app = vx[u], apq = vy[u], aqq = vw[u];
+          T[ax[u]] = app - tt * apq;
+          T[ay[u]] = 0.0;
+          T[aw[u]] = aqq + tt * apq;
+        } else {
+          const double c2 = cc_s[P2[u]], s2 = ss_s[P2[u]];
+          const double x1 = c1 * vx[u] - s1 * vz[u], y1 = c1 * vy[u] - s1 * vw[u];
+          const double z1 = s1 * vx[u] + c1 * vz[u], w1 = s1 * vy[u] + c1 * vw[u];
+          T[ax[u]] = c2 * x1 - s2 * y1;
+          if (ay[u] >= 0) T[ay[u]] = s2 * x1 + c2 * y1;
+          if (az[u] >= 0) T[az[u]] = c2 * z1 - s2 * w1;
+          if (aw[u] >= 0) T[aw[u]] = s2 * z1 + c2 * w1;
+        }
       }
       lds_barrier();
       ++ridx;
     }
     ++sweeps;
-    const int any = any_s;
+    const int any = any_s, big = big_s;
     lds_barrier();
-    if (!any) break;
+    // every rotation of this sweep was below 1e-10 of its pair's scale: the
+    // quadratic convergence leaves nothing above tol for another sweep
+    if (!any || !big) break;
   }
   for (int i = tid; i < lp; i += kJacThreads) lam[i] = i < l ? T[tidx(i, i)] : 0.0;
   if (tid == 0) {
     status[kStSweeps] = sweeps;
     status[kStRounds] = (int32_t)min(ridx, rot_rounds);
+  }
+}
+
+// One-sided (Hestenes) Jacobi on the Cholesky factor L of C = B B^T
+// (C = L L^T), for sketch widths up to 128: the columns of M = L are rotated
+// in pairs until mutually orthogonal; then M = U_B diag(s), so s_c = |m_c|
+// and U_B(:, c) = m_c / s_c are the singular values of B and the
+// eigenvectors of C.  M lives in LDS column by column; a group of 16 threads
+// owns one column pair per round (round-robin schedule), so a round needs a
+// single barrier and no rotation has to be replayed afterwards.
+constexpr int kOjMaxLp = 128;
+constexpr int kOjLd = kOjMaxLp + 1;      // odd stride in doubles: no bank conflicts
+__global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, int64_t lp, int l,
+                                                  double* __restrict__ lam, double* __restrict__ Ev,
+                                                  int32_t* status, double tol, int max_sweeps) {
+  __shared__ double M[kOjMaxLp * kOjLd];   // column c at M[c * kOjLd + i]
+  __shared__ int any_s, big_s;
+  const int tid = threadIdx.x, grp = tid >> 4, sub = tid & 15;
+  const int le = l + (l & 1), np = le / 2, R = le - 1;
+  for (int e = tid; e < l * l; e += 1024) {
+    const int i = e / l, c = e % l;
+    M[c * kOjLd + i] = L[(int64_t)i * lp + c];
+  }
+  lds_barrier();
+  int sweeps = 0;
+  for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
+    if (tid == 0) {
+      any_s = 0;
+      big_s = 0;
+    }
+    lds_barrier();
+    for (int t = 0; t < R; ++t) {
+      if (grp < np) {
+        const int a = rr_pos(grp, t, le), b = rr_pos(le - 1 - grp, t, le);
+        const int p = min(a, b), q = max(a, b);
+        if (q < l) {
+          double* mp = &M[p * kOjLd];
+          double* mq = &M[q * kOjLd];
+          double xp[kOjMaxLp / 16], xq[kOjMaxLp / 16];
+          double aa = 0.0, bb = 0.0, gg = 0.0;
+#pragma unroll
+          for (int u = 0; u < kOjMaxLp / 16; ++u) {
+            const int i = sub + 16 * u;
+            xp[u] = i < l ? mp[i] : 0.0;
+            xq[u] = i < l ? mq[i] : 0.0;
+            aa += xp[u] * xp[u];
+            bb += xq[u] * xq[u];
+            gg += xp[u] * xq[u];
+          }
+#pragma unroll
+          for (int off = 8; off > 0; off >>= 1) {
+            aa += __shfl_xor(aa, off, 16);
+            bb += __shfl_xor(bb, off, 16);
+            gg += __shfl_xor(gg, off, 16);
+          }
+          const double scale = sqrt(aa * bb);
+          if (gg != 0.0 && fabs(gg) > tol * scale) {
+            const double zeta = (bb - aa) / (2.0 * gg);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt);
+            const double sn = cs * tt;
+#pragma unroll
+            for (int u = 0; u < kOjMaxLp / 16; ++u) {
+              const int i = sub + 16 * u;
+              if (i < l) {
+                mp[i] = cs * xp[u] - sn * xq[u];
+                mq[i] = sn * xp[u] + cs * xq[u];
+              }
+            }
+            if (sub == 0) {
+              any_s = 1;
+              if (fabs(gg) > 1e-10 * scale) big_s = 1;
+            }
+          }
+        }
+      }
+      lds_barrier();
+    }
+    ++sweeps;
+    const int any = any_s, big = big_s;
+    lds_barrier();
+    if (!any || !big) break;
+  }
+  // s_c = |m_c| (one group per column), U_B(:, c) = m_c / s_c
+  for (int c = grp; c < lp; c += 64) {
+    double ss = 0.0;
+    if (c < l)
+      for (int i = sub; i < l; i += 16) ss += M[c * kOjLd + i] * M[c * kOjLd + i];
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 16);
+    const double sv = sqrt(ss);
+    if (sub == 0) lam[c] = c < l ? ss : 0.0;
+    const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+    for (int i = sub; i < lp; i += 16)
+      Ev[(int64_t)i * lp + c] = (c < l && i < l) ? M[c * kOjLd + i] * inv : 0.0;
+  }
+  if (tid == 0) {
+    status[kStSweeps] = sweeps;
+    status[kStRounds] = 0;
   }
 }
 
@@ -435,8 +794,8 @@ __global__ __launch_bounds__(kVecRows * 64) void k_jacobi_vecs(const double* __r
     }
     __syncthreads();
     if (t0 + kVecChunk < rounds) fetch(t0 + kVecChunk);
-    for (int tt = 0; tt < nr; ++tt) {
-      const int tr = (int)((t0 + tt) % R);
+    int tr = (int)(t0 % R);
+    for (int tt = 0; tt < nr; ++tt, tr = (tr + 1 == R) ? 0 : tr + 1) {
       for (int i = lane; i < np; i += 64) {
         const double c = cs[(tt * np + i) * 2], s = cs[(tt * np + i) * 2 + 1];
         if (s != 0.0) {
@@ -518,12 +877,18 @@ __global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ U, int64_t
   const int c = blockIdx.x, tid = threadIdx.x;
   float best = -1.f;
   int64_t bidx = 0;
-  for (int64_t j = tid; j < n; j += blockDim.x) {
-    const float a = fabsf(V[(int64_t)c * ldv + j]);
-    if (a > best) {   // strided scan: earlier j of this thread wins ties
-      best = a;
-      bidx = j;
-    }
+  const float* col = V + (int64_t)c * ldv;
+  // four independent loads per iteration; each thread keeps its first maximum
+  for (int64_t j0 = (int64_t)tid * 4; j0 < n; j0 += 4 * (int64_t)blockDim.x) {
+    float a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = j0 + e < n ? fabsf(col[j0 + e]) : -1.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (a[e] > best) {
+        best = a[e];
+        bidx = j0 + e;
+      }
   }
   bv[tid] = best;
   bi[tid] = bidx;
@@ -578,7 +943,12 @@ hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int
 hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
                            double tau, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W, status, tau);
+  if (lp <= kBlkMaxLp)
+    hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
+                       (double*)nullptr, status, tau);
+  else
+    hipLaunchKernelGGL(k_chol_inv_simple, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
+                       status, tau);
   return hipGetLastError();
 }
 
@@ -606,6 +976,24 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
     default: return hipErrorInvalidValue;
   }
 #undef AP_CALL
+  return hipGetLastError();
+}
+
+bool small_svd_one_sided(int64_t lp) { return lp <= kOjMaxLp; }
+
+hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
+                              double tau, hipStream_t s) {
+  if (lp > kBlkMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l,
+                     (float*)nullptr, L, status, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
+                          int32_t* status, double tol, int max_sweeps, hipStream_t s) {
+  if (lp > kOjMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ojacobi, dim3(1), dim3(1024), 0, s, L, lp, (int)l, lam, Ev, status, tol,
+                     max_sweeps);
   return hipGetLastError();
 }
 

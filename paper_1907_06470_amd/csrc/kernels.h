@@ -56,6 +56,12 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
 hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
                         int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out,
                         int64_t ldo, int64_t out_rows_total, hipStream_t s);
+// Small SVD through the Cholesky factor of C and one-sided Jacobi (lp <= 128).
+bool small_svd_one_sided(int64_t lp);
+hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
+                              double tau, hipStream_t s);
+hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
+                          int32_t* status, double tol, int max_sweeps, hipStream_t s);
 hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
                          double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s);
 hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
@@ -69,5 +75,22 @@ hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, float* V, int64_t l
 hipError_t launch_gather_cols(const double* Ev, int64_t lp, int64_t l, const int32_t* order,
                               double* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+
+// --- adjoint (k_adjoint.hip) and accuracy pass (k_resid.hip) ---
+hipError_t launch_xgram(const float* P, int64_t ldp, int64_t cp, const float* R, int64_t ldr,
+                        int64_t cr, int64_t rows, int64_t chunk_rows, int64_t chunks,
+                        double* gpart, double* C, hipStream_t s);
+hipError_t launch_adj_core(const double* Sl, int64_t lp, int64_t l, int64_t k, int64_t kp,
+                           const double* Ju, const double* Jv, const double* gS, float* coreT,
+                           float* JuW, float* JvW, float* sinv, int32_t* status, hipStream_t s);
+hipError_t launch_colscale(const float* x, int64_t ldx, const float* y, int64_t ldy,
+                           const float* sc, int64_t rows, int64_t cols, float* out, int64_t ldo,
+                           int64_t out_rows, hipStream_t s);
+hipError_t launch_outer(const float* P, int64_t ldp, const float* R, int64_t ldr, int64_t K,
+                        int64_t m, int64_t n, float* gA, int64_t ldga, hipStream_t s);
+int64_t residual_partials(int64_t m, int64_t n);
+hipError_t launch_residual(const void* A, bool f64, int64_t lda, int64_t m, int64_t n,
+                           const float* U, int64_t ldu, const double* S, const float* V,
+                           int64_t ldv, int64_t k, double* partial, double* out, hipStream_t s);
 
 }  // namespace rsvd

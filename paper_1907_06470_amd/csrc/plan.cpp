@@ -86,7 +86,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (o.tile_m < 0 || o.tile_n < 0 || o.tile_m % 32 || o.tile_n % 32)
     return fail(p, RSVD_E_INVALID_ARG, "tile sizes %lld x %lld must be >= 0 and multiples of 32",
                 o.tile_m, o.tile_n);
-  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1))
+  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1 | RSVD_FLAG_BACKWARD))
     return fail(p, RSVD_E_INVALID_ARG, "unknown flags 0x%llx", o.flags);
 
   p.l = k + pp;
@@ -138,7 +138,17 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     size_t b = p.TI > 1 ? (size_t)p.TI * p.ldn * lp * 4 : 0;
     w.part = take(std::max<size_t>(std::max(a, b), 256));
   }
-  w.gpart = take((size_t)p.gram_chunks * gram_pairs(p) * kGramBlock * kGramBlock * 8);
+  p.backward = (o.flags & RSVD_FLAG_BACKWARD) != 0;
+  p.kp = round_up(k, kColAlign);
+  p.rcat = p.lp + 2 * p.kp;
+  {
+    // Gram partial blocks: lower pairs of lp x lp, or lp x kp cross blocks
+    const int64_t cross = ceil_div(p.lp, kGramBlock) * ceil_div(p.kp, kGramBlock);
+    const int64_t blocks = std::max<int64_t>(gram_pairs(p), p.backward ? cross : 0);
+    // also holds the 2048 partial sums of the accuracy pass
+    w.gpart = take(std::max<size_t>((size_t)p.gram_chunks * blocks * kGramBlock * kGramBlock * 8,
+                                    2048 * 8));
+  }
   w.G = take(lp * lp * 8);
   w.L = take(lp * lp * 8);
   w.W = take(lp * lp * 4);
@@ -155,6 +165,22 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.A16 = (p.any_bf16 && prob.dtype != RSVD_BF16) ? take((size_t)m * p.lda16 * 2) : off;
   w.Xop16 = p.any_bf16 ? take((size_t)p.ldn * lp * 2) : off;
   w.Mop16 = p.any_bf16 ? take((size_t)p.ldm * lp * 2) : off;
+  if (p.backward) {
+    const size_t kp = (size_t)p.kp, rc = (size_t)p.rcat;
+    w.Pcat = take((size_t)p.ldm * rc * 4);
+    w.Rcat = take((size_t)p.ldn * rc * 4);
+    w.gUp = take((size_t)p.ldm * kp * 4);
+    w.gVp = take((size_t)p.ldn * kp * 4);
+    w.Ju = take(lp * kp * 8);
+    w.Jv = take(lp * kp * 8);
+    w.Sl = take(lp * 8);
+    w.coreT = take(lp * lp * 4);
+    w.JuW = take(lp * kp * 4);
+    w.JvW = take(lp * kp * 4);
+    w.sinv = take(kp * 4);
+  } else {
+    w.Pcat = w.Rcat = w.gUp = w.gVp = w.Ju = w.Jv = w.Sl = w.coreT = w.JuW = w.JvW = w.sinv = off;
+  }
   w.total = off;
 
   if (o.hbm_budget_bytes && w.total > o.hbm_budget_bytes)

@@ -25,6 +25,7 @@ enum StatusWord {
   kStSweeps = 2,       // Jacobi sweeps of the small eigensolver
   kStRounds = 3,       // Jacobi rotation rounds logged
   kStRankSmall = 4,    // zero singular values in the small SVD
+  kStTies = 5,         // equal singular-value pairs met by the adjoint
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -50,6 +51,12 @@ struct Workspace {
   size_t Acast;           // FP32 copy of an FP64 A
   size_t A16;             // BF16 copy of A (when a product runs in BF16)
   size_t Xop16, Mop16;    // BF16 copies of the operand panels
+  // backward (RSVD_FLAG_BACKWARD)
+  size_t Pcat, Rcat;      // outer-product factors (ldm x R, ldn x R), R = lp + 2 kp
+  size_t gUp, gVp;        // imported cotangents (ldm x kp, ldn x kp)
+  size_t Ju, Jv;          // lp x kp FP64
+  size_t Sl;              // lp FP64 Ritz values
+  size_t coreT, JuW, JvW, sinv;
   size_t total;
 };
 
@@ -67,6 +74,9 @@ struct Plan {
   int64_t gram_rows = 0;        // rows per Gram chunk
   int64_t gram_chunks = 0;      // max chunks over the m- and n-side panels
   int64_t rot_rounds = 0;       // capacity of the rotation log (rounds)
+  int64_t kp = 0;               // k rounded up to 32 (backward)
+  int64_t rcat = 0;             // columns of the outer-product factors
+  bool backward = false;
   Workspace ws{};
   std::string last_error;
   void* hip_events = nullptr;   // created lazily by the driver

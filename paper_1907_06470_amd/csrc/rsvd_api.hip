@@ -91,6 +91,8 @@ rsvd_status hip_err(rsvd_plan_t h, hipError_t e, const char* what) {
 struct Buffers {
   float *Xop, *Mop, *M0, *M1, *N0, *N1, *part, *W, *W2, *Acast;
   uint16_t *A16, *Xop16, *Mop16;
+  float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
+  double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
   int32_t *order, *signs, *status;
 };
@@ -112,6 +114,17 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.A16 = (uint16_t*)(b + w.A16);
   B.Xop16 = (uint16_t*)(b + w.Xop16);
   B.Mop16 = (uint16_t*)(b + w.Mop16);
+  B.Pcat = (float*)(b + w.Pcat);
+  B.Rcat = (float*)(b + w.Rcat);
+  B.gUp = (float*)(b + w.gUp);
+  B.gVp = (float*)(b + w.gVp);
+  B.coreT = (float*)(b + w.coreT);
+  B.JuW = (float*)(b + w.JuW);
+  B.JvW = (float*)(b + w.JvW);
+  B.sinv = (float*)(b + w.sinv);
+  B.Ju = (double*)(b + w.Ju);
+  B.Jv = (double*)(b + w.Jv);
+  B.Sl = (double*)(b + w.Sl);
   B.gpart = (double*)(b + w.gpart);
   B.G = (double*)(b + w.G);
   B.L = (double*)(b + w.L);
@@ -243,6 +256,43 @@ struct Runner {
     return cholqr_pass(tmp, out, rows, ld);
   }
 
+  // Steps 1-6 of the randomized SVD on the power matrix (Section 2.1 on
+  // Section 2.2 Eq. (2)): leaves Q in Mop (FP32), B^T in N0, the first kout
+  // singular values in S and the small factors W (U_B) and W2 (U_B S^-1).
+  template <typename Mark>
+  rsvd_status forward(Mark& mark, double* S, int64_t kout) {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
+    const bool bs = P.opt.prec_sketch == RSVD_BF16, bp = P.opt.prec_power == RSVD_BF16,
+               bj = P.opt.prec_project == RSVD_BF16;
+    rsvd_status st;
+    RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, B.Xop, P.ldn, s));   // step 1
+    if (bs && (st = to_bf16(B.Xop, B.Xop16, P.ldn))) return st;
+    RSVD_HIP(mark(1));
+    if ((st = product_nn(B.Xop, B.Xop16, bs, B.M0))) return st;                       // step 2
+    RSVD_HIP(mark(2));
+    if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;   // 3-4
+    if ((P.prob.q > 0 ? bp : bj) && (st = to_bf16(B.Mop, B.Mop16, P.ldm))) return st;
+    RSVD_HIP(mark(3));
+    for (int64_t t = 0; t < P.prob.q; ++t) {                                          // Eq. (2)
+      const bool last = t + 1 == P.prob.q;
+      if ((st = product_tn(B.Mop, B.Mop16, bp, B.N0))) return st;
+      if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
+      if (bp && (st = to_bf16(B.Xop, B.Xop16, P.ldn))) return st;
+      if ((st = product_nn(B.Xop, B.Xop16, bp, B.M0))) return st;
+      if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last))) return st;
+      if ((last ? bj : bp) && (st = to_bf16(B.Mop, B.Mop16, P.ldm))) return st;
+    }
+    RSVD_HIP(mark(4));
+    if ((st = product_tn(B.Mop, B.Mop16, bj, B.N0))) return st;                        // step 5
+    RSVD_HIP(mark(5));
+    if ((st = small_svd_eig(B.N0))) return st;                                         // SVD0 prep
+    RSVD_HIP(mark(6));
+    if ((st = small_svd_solve(S, kout))) return st;                                    // step 6
+    RSVD_HIP(mark(7));
+    return RSVD_OK;
+  }
+
   // Small SVD of B from Bt (n-side panel): leaves sorted S (k), Wu, Wv.
   rsvd_status small_svd_eig(const float* Bt) {
     rsvd_status st = gram(Bt, P.prob.n, P.ldn);
@@ -250,9 +300,17 @@ struct Runner {
     return RSVD_OK;
   }
   rsvd_status small_svd_solve(double* S, int64_t kout) {
-    RSVD_HIP(rsvd::launch_jacobi(B.G, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status, kJacobiTol,
-                                 rsvd::kJacobiMaxSweeps, s));
-    RSVD_HIP(rsvd::launch_jacobi_vecs(B.rot, B.status, P.lp, P.l, B.Ev, s));
+    if (rsvd::small_svd_one_sided(P.lp)) {
+      // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
+      // positive pivot; exactly dependent directions give zero columns)
+      RSVD_HIP(rsvd::launch_chol_factor(B.G, P.lp, P.l, B.L, B.status, 0.0, s));
+      RSVD_HIP(rsvd::launch_ojacobi(B.L, P.lp, P.l, B.lam, B.Ev, B.status, kJacobiTol,
+                                    rsvd::kJacobiMaxSweeps, s));
+    } else {
+      RSVD_HIP(rsvd::launch_jacobi(B.G, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status,
+                                   kJacobiTol, rsvd::kJacobiMaxSweeps, s));
+      RSVD_HIP(rsvd::launch_jacobi_vecs(B.rot, B.status, P.lp, P.l, B.Ev, s));
+    }
     RSVD_HIP(rsvd::launch_finish_small(B.lam, B.Ev, P.lp, P.l, kout, S, B.W, B.W2, B.order,
                                        B.status, s));
     return RSVD_OK;
@@ -280,6 +338,71 @@ rsvd_status check_A(rsvd_plan_t h, const void* A, int64_t lda) {
 rsvd_status check_ws(rsvd_plan_t h, void* ws) {
   if (!ws) return set_err(h, RSVD_E_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255) return set_err(h, RSVD_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  return RSVD_OK;
+}
+
+
+Events* plan_events(rsvd_plan_t h, rsvd_status& st) {
+  st = RSVD_OK;
+  if (!h->p.hip_events) {
+    Events* e = new (std::nothrow) Events;
+    if (!e) {
+      st = set_err(h, RSVD_E_INVALID_ARG, "out of host memory");
+      return nullptr;
+    }
+    h->p.hip_events = e;
+  }
+  Events* ev = static_cast<Events*>(h->p.hip_events);
+  hipError_t err = make_events(*ev, (size_t)(2 * h->p.prob.q + 2));
+  if (err != hipSuccess) {
+    st = hip_err(h, err, "hipEventCreate");
+    return nullptr;
+  }
+  return ev;
+}
+
+// Wait for the stream, fill the report from the events and status words and
+// turn device-side outcomes into the status.
+rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_report* report) {
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n;
+  std::memset(report, 0, sizeof *report);
+  RSVD_HIP(hipStreamSynchronize(R.s));
+  float ms = 0.f;
+  for (int i = 0; i < 8; ++i) {
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[i], ev->ev[i + 1]));
+    report->stage_ms[i] = ms;
+  }
+  RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
+  report->total_ms = ms;
+  for (int i : R.nn_idx) {
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
+    report->gemm_nn_ms += ms;
+  }
+  for (int i : R.tn_idx) {
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
+    report->gemm_tn_ms += ms;
+  }
+  report->gemm_nn_launches = (int32_t)R.nn_idx.size();
+  report->gemm_tn_launches = (int32_t)R.tn_idx.size();
+  int32_t stw[rsvd::kStatusWords];
+  RSVD_HIP(hipMemcpy(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost));
+  const double passes = 2.0 * (double)P.prob.q + 2.0;
+  report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
+  auto pass_bytes = [&](int32_t prec) {
+    const double e = prec == RSVD_BF16 ? 2.0 : 4.0;
+    return (double)m * (double)n * e + ((double)m + (double)n) * P.l * e;
+  };
+  report->bytes_alg = pass_bytes(P.opt.prec_sketch) +
+                      2.0 * (double)P.prob.q * pass_bytes(P.opt.prec_power) +
+                      pass_bytes(P.opt.prec_project);
+  report->ws_bytes = (int64_t)P.ws.total;
+  report->dropped = stw[rsvd::kStDropped];
+  report->jacobi_sweeps = stw[rsvd::kStSweeps];
+  report->nonfinite = stw[rsvd::kStNonFinite];
+  if (stw[rsvd::kStNonFinite] > 0) return set_err(h, RSVD_E_NUMERIC, "NaN or Inf met on the device");
+  if (stw[rsvd::kStTies] > 0) return RSVD_W_DEGENERATE;
+  if (stw[rsvd::kStDropped] > 0 || stw[rsvd::kStRankSmall] > 0) return RSVD_W_RANK_DEFICIENT;
   return RSVD_OK;
 }
 
@@ -408,48 +531,17 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
   Runner R(h, ws, s);
   Events* ev = nullptr;
   if (report) {
-    if (!P.hip_events) {
-      Events* e = new (std::nothrow) Events;
-      if (!e) return set_err(h, RSVD_E_INVALID_ARG, "out of host memory");
-      h->p.hip_events = e;
-    }
-    ev = static_cast<Events*>(P.hip_events);
-    RSVD_HIP(make_events(*ev, (size_t)(2 * P.prob.q + 2)));
+    rsvd_status est;
+    if (!(ev = plan_events(h, est))) return est;
     R.ev = ev;
   }
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev->ev[i], s) : hipSuccess; };
-  const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
   rsvd_status st;
 
   RSVD_HIP(mark(0));
   RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
   if ((st = R.bind_A(A, lda))) return st;
-  const bool bs = P.opt.prec_sketch == RSVD_BF16, bp = P.opt.prec_power == RSVD_BF16,
-             bj = P.opt.prec_project == RSVD_BF16;
-  RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, R.B.Xop, P.ldn, s));   // step 1
-  if (bs && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
-  RSVD_HIP(mark(1));
-  if ((st = R.product_nn(R.B.Xop, R.B.Xop16, bs, R.B.M0))) return st;                // step 2
-  RSVD_HIP(mark(2));
-  if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;  // 3-4
-  if ((P.prob.q > 0 ? bp : bj) && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
-  RSVD_HIP(mark(3));
-  for (int64_t t = 0; t < P.prob.q; ++t) {                                            // Eq. (2)
-    const bool last = t + 1 == P.prob.q;
-    if ((st = R.product_tn(R.B.Mop, R.B.Mop16, bp, R.B.N0))) return st;
-    if ((st = R.orth(R.B.N0, R.B.Xop, R.B.N1, n, P.ldn, !cq1))) return st;
-    if (bp && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
-    if ((st = R.product_nn(R.B.Xop, R.B.Xop16, bp, R.B.M0))) return st;
-    if ((st = R.orth(R.B.M0, R.B.Mop, R.B.M1, m, P.ldm, !cq1 || last))) return st;
-    if ((last ? bj : bp) && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
-  }
-  RSVD_HIP(mark(4));
-  if ((st = R.product_tn(R.B.Mop, R.B.Mop16, bj, R.B.N0))) return st;                 // step 5
-  RSVD_HIP(mark(5));
-  if ((st = R.small_svd_eig(R.B.N0))) return st;                                      // SVD0 prep
-  RSVD_HIP(mark(6));
-  if ((st = R.small_svd_solve(S, k))) return st;                                      // step 6
-  RSVD_HIP(mark(7));
+  if ((st = R.forward(mark, S, k))) return st;
   // step 7: U = Q E_k (W), V = B^T E_k S^-1 (W2)
   RSVD_HIP(rsvd::launch_apply(R.B.Mop, P.ldm, m, P.l, R.B.W, P.lp, P.lp, k, false, U, ldu, m, s));
   RSVD_HIP(rsvd::launch_apply(R.B.N0, P.ldn, n, P.l, R.B.W2, P.lp, P.lp, k, false, V, ldv, n, s));
@@ -458,46 +550,7 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
   RSVD_HIP(mark(8));
 
   if (!report) return RSVD_OK;
-  std::memset(report, 0, sizeof *report);
-  RSVD_HIP(hipStreamSynchronize(s));
-  for (int i = 0; i < 8; ++i) {
-    float ms = 0.f;
-    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[i], ev->ev[i + 1]));
-    report->stage_ms[i] = ms;
-  }
-  {
-    float ms = 0.f;
-    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
-    report->total_ms = ms;
-    for (int i : R.nn_idx) {
-      RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
-      report->gemm_nn_ms += ms;
-    }
-    for (int i : R.tn_idx) {
-      RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
-      report->gemm_tn_ms += ms;
-    }
-    report->gemm_nn_launches = (int32_t)R.nn_idx.size();
-    report->gemm_tn_launches = (int32_t)R.tn_idx.size();
-  }
-  int32_t stw[rsvd::kStatusWords];
-  RSVD_HIP(hipMemcpy(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost));
-  const double passes = 2.0 * (double)P.prob.q + 2.0;
-  report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
-  {
-    auto pass_bytes = [&](bool b16) {
-      const double e = b16 ? 2.0 : 4.0;
-      return (double)m * (double)n * e + ((double)m + (double)n) * P.l * e;
-    };
-    report->bytes_alg = pass_bytes(bs) + 2.0 * (double)P.prob.q * pass_bytes(bp) + pass_bytes(bj);
-  }
-  report->ws_bytes = (int64_t)P.ws.total;
-  report->dropped = stw[rsvd::kStDropped];
-  report->jacobi_sweeps = stw[rsvd::kStSweeps];
-  report->nonfinite = stw[rsvd::kStNonFinite];
-  if (stw[rsvd::kStNonFinite] > 0) return set_err(h, RSVD_E_NUMERIC, "NaN or Inf met on the device");
-  if (stw[rsvd::kStDropped] > 0 || stw[rsvd::kStRankSmall] > 0) return RSVD_W_RANK_DEFICIENT;
-  return RSVD_OK;
+  return finish_report(h, R, ev, report);
 }
 
 rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t lda, const float* X,
@@ -588,6 +641,97 @@ rsvd_status rsvd_step_small_svd(rsvd_plan_t h, const float* Bt, int64_t ldb, dou
   if ((st = R.small_svd_solve(sig, P.l))) return st;
   // U_B(a, c) = Ev(a, order c) in FP64
   RSVD_HIP(rsvd::launch_gather_cols(R.B.Ev, P.lp, P.l, R.B.order, ub, s));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_backward(rsvd_plan_t h, const void* A, int64_t lda, const float* gU,
+                          int64_t ldgu, const double* gS, const float* gV, int64_t ldgv,
+                          float* gA, int64_t ldga, void* ws, void* stream, rsvd_report* report) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k, l = P.l, lp = P.lp, kp = P.kp;
+  if (!P.backward) return set_err(h, RSVD_E_INVALID_ARG, "plan was made without RSVD_FLAG_BACKWARD");
+  if (kp > 192) return set_err(h, RSVD_E_UNSUPPORTED, "backward needs k <= 192");
+  if (!gA || ldga < n) return set_err(h, RSVD_E_INVALID_ARG, "gA is NULL or ldga < n");
+  if ((gU && ldgu < m) || (gV && ldgv < n))
+    return set_err(h, RSVD_E_INVALID_ARG, "ldgu < m or ldgv < n");
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  Events* ev = nullptr;
+  if (report) {
+    rsvd_status est;
+    if (!(ev = plan_events(h, est))) return est;
+    R.ev = ev;
+  }
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev->ev[i], s) : hipSuccess; };
+  const Buffers& B = R.B;
+  rsvd_status st;
+  RSVD_HIP(mark(0));
+  RSVD_HIP(rsvd::launch_fill_i32(B.status, rsvd::kStatusWords, 0, s));
+  if ((st = R.bind_A(A, lda))) return st;
+  // the l Ritz triplets, recomputed from the seed (no stored sketch)
+  if ((st = R.forward(mark, B.Sl, l))) return st;
+  float* Ul = B.Pcat;                          // first lp columns of P
+  float* Vl = B.N1;
+  RSVD_HIP(rsvd::launch_apply(B.Mop, P.ldm, m, l, B.W, lp, lp, lp, false, Ul, P.ldm, P.ldm, s));
+  RSVD_HIP(rsvd::launch_apply(B.N0, P.ldn, n, l, B.W2, lp, lp, lp, false, Vl, P.ldn, P.ldn, s));
+  if (!(P.opt.flags & RSVD_FLAG_NO_SIGN_FIX))
+    RSVD_HIP(rsvd::launch_sign_fix(Ul, P.ldm, m, Vl, P.ldn, n, k, B.signs, s));
+  // cotangents, zero-padded to kp columns
+  if (gU)
+    RSVD_HIP(rsvd::launch_panel_copy(gU, ldgu, m, k, B.gUp, P.ldm, P.ldm, kp, s));
+  else
+    RSVD_HIP(rsvd::launch_colscale(nullptr, 0, nullptr, 0, nullptr, m, kp, B.gUp, P.ldm, P.ldm, s));
+  if (gV)
+    RSVD_HIP(rsvd::launch_panel_copy(gV, ldgv, n, k, B.gVp, P.ldn, P.ldn, kp, s));
+  else
+    RSVD_HIP(rsvd::launch_colscale(nullptr, 0, nullptr, 0, nullptr, n, kp, B.gVp, P.ldn, P.ldn, s));
+  // J_u = U_l^T gU, J_v = V_l^T gV (FP64)
+  RSVD_HIP(rsvd::launch_xgram(Ul, P.ldm, lp, B.gUp, P.ldm, kp, m, P.gram_rows,
+                              rsvd::gram_chunks_for(P, m), B.gpart, B.Ju, s));
+  RSVD_HIP(rsvd::launch_xgram(Vl, P.ldn, lp, B.gVp, P.ldn, kp, n, P.gram_rows,
+                              rsvd::gram_chunks_for(P, n), B.gpart, B.Jv, s));
+  RSVD_HIP(rsvd::launch_adj_core(B.Sl, lp, l, k, kp, B.Ju, B.Jv, gS, B.coreT, B.JuW, B.JvW,
+                                 B.sinv, B.status, s));
+  float* R1 = B.Rcat;
+  float* Vk = B.Rcat + lp * P.ldn;
+  float* R3 = B.Rcat + (lp + kp) * P.ldn;
+  float* P2 = B.Pcat + lp * P.ldm;
+  float* P3 = B.Pcat + (lp + kp) * P.ldm;
+  // R1 = V_l core^T
+  RSVD_HIP(rsvd::launch_apply(Vl, P.ldn, n, l, B.coreT, lp, lp, lp, false, R1, P.ldn, P.ldn, s));
+  // P2 = (gU - U_l J_u) S_k^-1, P3 = U_k S_k^-1
+  RSVD_HIP(rsvd::launch_apply(Ul, P.ldm, m, l, B.JuW, kp, kp, kp, false, B.M1, P.ldm, P.ldm, s));
+  RSVD_HIP(rsvd::launch_colscale(B.gUp, P.ldm, B.M1, P.ldm, B.sinv, m, kp, P2, P.ldm, P.ldm, s));
+  RSVD_HIP(rsvd::launch_colscale(Ul, P.ldm, nullptr, 0, B.sinv, m, kp, P3, P.ldm, P.ldm, s));
+  // R3 = gV - V_l J_v, V_k
+  RSVD_HIP(rsvd::launch_apply(Vl, P.ldn, n, l, B.JvW, kp, kp, kp, false, B.N0, P.ldn, P.ldn, s));
+  RSVD_HIP(rsvd::launch_colscale(B.gVp, P.ldn, B.N0, P.ldn, nullptr, n, kp, R3, P.ldn, P.ldn, s));
+  RSVD_HIP(rsvd::launch_colscale(Vl, P.ldn, nullptr, 0, nullptr, n, kp, Vk, P.ldn, P.ldn, s));
+  // gA = [U_l | P2 | P3] [R1 | V_k | R3]^T
+  RSVD_HIP(rsvd::launch_outer(B.Pcat, P.ldm, B.Rcat, P.ldn, P.rcat, m, n, gA, ldga, s));
+  RSVD_HIP(mark(8));
+  if (!report) return RSVD_OK;
+  return finish_report(h, R, ev, report);
+}
+
+rsvd_status rsvd_residual(rsvd_plan_t h, const void* A, int64_t lda, const float* U, int64_t ldu,
+                          const double* S, const float* V, int64_t ldv, double* out, void* ws,
+                          void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  if (!U || !S || !V || !out || ldu < P.prob.m || ldv < P.prob.n)
+    return set_err(h, RSVD_E_INVALID_ARG, "bad residual arguments");
+  if (P.prob.dtype == RSVD_BF16)
+    return set_err(h, RSVD_E_UNSUPPORTED, "residual of a BF16 A is not implemented");
+  hipStream_t s = (hipStream_t)stream;
+  Buffers B = carve(P, ws);
+  RSVD_HIP(rsvd::launch_residual(A, P.prob.dtype == RSVD_F64, lda, P.prob.m, P.prob.n, U, ldu, S, V,
+                                 ldv, P.prob.k, B.gpart, out, s));
   return RSVD_OK;
 }
 
