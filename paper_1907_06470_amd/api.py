@@ -47,7 +47,9 @@ class Plan:
     """A validated problem with its tile map and workspace size."""
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
-                 tile=None, grid=(1, 1), hbm_budget=0, flags=0):
+                 tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False):
+        if backward:
+            flags |= L.FLAG_BACKWARD
         prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE, dtype=_DT.get(dtype, -99),
                          loc=L.LOC_DEVICE, reserved=0, seed=seed, nnz=0)
         pr = _PREC.get(precision, -99) if isinstance(precision, str) else -99
@@ -124,6 +126,43 @@ class Plan:
                         jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite)
         return U, S, V, info
 
+    def backward(self, A, gU=None, gS=None, gV=None, ws=None, stream=None, report=True):
+        """gA (m x n, row-major FP32) of the truncated-SVD adjoint; the plan must
+        have been made with backward=True.  Cotangents may be None (zero)."""
+        lda = _ld_row_major(A)
+        ws = self.workspace(A.device) if ws is None else ws
+        gA = torch.empty(self.m, self.n, dtype=torch.float32, device=A.device)
+
+        def panel(g, rows):
+            if g is None:
+                return None, 0
+            g = g.to(torch.float32)
+            if g.dim() != 2 or g.shape != (rows, self.k):
+                raise ValueError("cotangent shape mismatch")
+            if g.stride(0) != 1:
+                g = g.T.contiguous().T            # column-major copy
+            return g, _ld_col_major(g)
+
+        gUc, ldgu = panel(gU, self.m)
+        gVc, ldgv = panel(gV, self.n)
+        gSc = None if gS is None else gS.to(torch.float64).contiguous()
+        rep = L.Report() if report else None
+        st = L.lib().rsvd_backward(self.handle, _ptr(A), lda, _ptr(gUc), ldgu, _ptr(gSc), _ptr(gVc),
+                                   ldgv, _ptr(gA), gA.stride(0), _ptr(ws), _stream_ptr(stream),
+                                   ctypes.byref(rep) if rep is not None else None)
+        L.check(st, self.handle)
+        return gA, {"status": st, "total_ms": rep.total_ms if rep is not None else None}
+
+    def residual(self, A, U, S, V, ws=None, stream=None):
+        """||A - U diag(S) V^T||_F computed on the device (FP64 sums)."""
+        ws = self.workspace(A.device) if ws is None else ws
+        out = torch.empty(1, dtype=torch.float64, device=A.device)
+        st = L.lib().rsvd_residual(self.handle, _ptr(A), _ld_row_major(A), _ptr(U), _ld_col_major(U),
+                                   _ptr(S), _ptr(V), _ld_col_major(V), _ptr(out), _ptr(ws),
+                                   _stream_ptr(stream))
+        L.check(st, self.handle)
+        return out
+
     def step_product(self, op, A, X, ws=None, stream=None):
         rows_out = self.m if op == 0 else self.n
         out = col_major(rows_out, self.l, device=A.device)
@@ -166,6 +205,29 @@ def factor(A, k, p, q, seed=0, precision="fp32", tile=None, flags=0, stream=None
     plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, dtype=A.dtype, precision=precision,
                 tile=tile, flags=flags)
     return plan.factor(A, stream=stream)
+
+
+class RSVD(torch.autograd.Function):
+    """Differentiable randomized SVD: forward rsvd_factor, backward
+    rsvd_backward (the range basis is recomputed from the seed).
+
+        U, S, V = RSVD.apply(A, k, p, q, seed, precision)
+    """
+
+    @staticmethod
+    def forward(ctx, A, k, p, q, seed=0, precision="fp32"):
+        plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, dtype=A.dtype,
+                    precision=precision, backward=True)
+        U, S, V, _ = plan.factor(A.detach())
+        ctx.plan = plan
+        ctx.save_for_backward(A.detach())
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, gU, gS, gV):
+        (A,) = ctx.saved_tensors
+        gA, _ = ctx.plan.backward(A, gU, gS, gV)
+        return gA.to(A.dtype), None, None, None, None, None
 
 
 def philox_raw(seed, stream_id, row0, rows, blocks, device="cuda"):

@@ -49,6 +49,57 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline int is_finite_d(double x) { return __builtin_isfinite(x); }
 
+// Lane exchange inside rows of 16 lanes through DPP (one VALU instruction per
+// 32-bit half; no LDS round trip).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  int lo, hi;
+  __builtin_memcpy(&lo, &v, 4);
+  __builtin_memcpy(&hi, reinterpret_cast<const char*>(&v) + 4, 4);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  double r;
+  __builtin_memcpy(&r, &lo, 4);
+  __builtin_memcpy(reinterpret_cast<char*>(&r) + 4, &hi, 4);
+  return r;
+}
+
+// Sum over each row of 16 lanes, the same bits in every lane of the row:
+// swap neighbours, swap pairs, mirror within 8, mirror within 16.
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  return v;
+}
+
+// Reciprocal and reciprocal square root from the hardware estimates plus two
+// Newton steps (relative error ~1e-16; enough for Jacobi rotations, whose
+// parameters need not be correctly rounded).
+__device__ inline double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+__device__ inline double fast_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  int lo, hi;
+  __builtin_memcpy(&lo, &v, 4);
+  __builtin_memcpy(&hi, reinterpret_cast<const char*>(&v) + 4, 4);
+  lo = __builtin_amdgcn_readlane(lo, lane);
+  hi = __builtin_amdgcn_readlane(hi, lane);
+  double r;
+  __builtin_memcpy(&r, &lo, 4);
+  __builtin_memcpy(reinterpret_cast<char*>(&r) + 4, &hi, 4);
+  return r;
+}
+
 // Workgroup barrier that orders LDS only: global stores issued before it stay
 // in flight (a plain __syncthreads() would wait for them to reach memory).
 __device__ inline void lds_barrier() {

@@ -267,30 +267,48 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
   // ---- Cholesky, right-looking by panels
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * kCB, k1 = min(l, k0 + kCB);
-    if (wave == 0) {   // diagonal block, one wave
-      for (int j = k0; j < k1; ++j) {
-        const double d = T[tidx(j, j)];
-        double piv = 0.0;
-        const bool bad = !is_finite_d(d);
-        if (!bad && d0[j] > 0.0 && d > tau * d0[j]) piv = sqrt(d);
-        const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-        const int i = j + 1 + lane;
-        if (i < k1) T[tidx(i, j)] *= inv;
-        if (lane == 0) {
-          T[tidx(j, j)] = piv;
-          dinv[j] = inv;
-          if (bad) ++nbad;
-          else if (piv == 0.0) ++ndrop;
+    if (wave == 0) {
+      // diagonal block, one wave: lane r holds row k0 + r in registers; the
+      // scaled pivot column goes through LDS once per step
+      const int kw = k1 - k0;
+      double d[kCB];
+#pragma unroll
+      for (int q = 0; q < kCB; ++q)
+        d[q] = (lane < kw && q <= lane) ? T[tidx(k0 + lane, k0 + q)] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kCB; ++j) {
+        if (j < kw) {
+          const double a = readlane_d(d[j], j);
+          const double o = d0[k0 + j];
+          const bool bad = !is_finite_d(a);
+          double piv = 0.0;
+          if (!bad && o > 0.0 && a > tau * o) piv = sqrt(a);
+          const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+          if (lane == j) d[j] = piv;
+          else if (lane > j) d[j] *= inv;
+          if (lane == 0) {
+            dinv[k0 + j] = inv;
+            if (bad) ++nbad;
+            else if (piv == 0.0) ++ndrop;
+          }
+          Xd[lane] = d[j];            // column j of L in this block (scratch)
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+          __builtin_amdgcn_wave_barrier();
+          if (piv > 0.0) {
+            double col[kCB];
+#pragma unroll
+            for (int c = j + 1; c < kCB; ++c) col[c] = Xd[c];
+#pragma unroll
+            for (int c = j + 1; c < kCB; ++c)
+              if (c <= lane) d[c] -= d[j] * col[c];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+          __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        if (i < k1 && piv > 0.0) {
-          const double lij = T[tidx(i, j)];
-          for (int c = j + 1; c <= i; ++c) T[tidx(i, c)] -= lij * T[tidx(c, j)];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
       }
+#pragma unroll
+      for (int q = 0; q < kCB; ++q)
+        if (lane < kw && q <= lane) T[tidx(k0 + lane, k0 + q)] = d[q];
     }
     lds_barrier();
     // rows below: L_ij = (A_ij - sum_{k0<=p<j} L_ip L_jp) / L_jj, one row per thread
@@ -405,12 +423,20 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
         const int r = r0 + rr;
         const int rb = tidx(r, 0);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int pq = c0; pq < r0; ++pq) {
-          const double lv = T[rb + pq];
-          const int pb = tidx(pq, 0);
+        for (int pq = c0; pq < r0; pq += 4) {
+          double lv[4], xv[4][4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (c0 + u <= pq) acc[u] += lv * T[pb + c0 + u];
+          for (int e = 0; e < 4; ++e) {
+            const int p = pq + e;
+            lv[e] = p < r0 ? T[rb + p] : 0.0;
+            const int pb = tidx(p, 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[e][u] = (p < r0 && c0 + u <= p) ? T[pb + c0 + u] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += lv[e] * xv[e][u];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -425,10 +451,19 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
       for (int e = tid; e < cnt; e += kCholThreads) {
         const int rr = e / c4n, c0 = (e % c4n) * 4;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int q = 0; q <= rr; ++q) {
-          const double xv = Xd[rr * kCB + q];
+        for (int q0 = 0; q0 <= rr; q0 += 4) {
+          double xv[4], tv[4][4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[u] += xv * Trow[q * (kBlkMaxLp - kCB) + c0 + u];
+          for (int e = 0; e < 4; ++e) {
+            const int q = q0 + e;
+            xv[e] = q <= rr ? Xd[rr * kCB + q] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) tv[e][u] = q <= rr ? Trow[q * (kBlkMaxLp - kCB) + c0 + u] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += xv[e] * tv[e][u];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -698,21 +733,26 @@ __global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, 
             const int i = sub + 16 * u;
             xp[u] = i < l ? mp[i] : 0.0;
             xq[u] = i < l ? mq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kOjMaxLp / 16; ++u) {
             aa += xp[u] * xp[u];
             bb += xq[u] * xq[u];
             gg += xp[u] * xq[u];
           }
-#pragma unroll
-          for (int off = 8; off > 0; off >>= 1) {
-            aa += __shfl_xor(aa, off, 16);
-            bb += __shfl_xor(bb, off, 16);
-            gg += __shfl_xor(gg, off, 16);
-          }
-          const double scale = sqrt(aa * bb);
+          aa = row16_sum(aa);
+          bb = row16_sum(bb);
+          gg = row16_sum(gg);
+          const double ab = aa * bb;
+          const double scale = ab > 0.0 ? ab * fast_rsq(ab) : 0.0;
           if (gg != 0.0 && fabs(gg) > tol * scale) {
-            const double zeta = (bb - aa) / (2.0 * gg);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt);
+            // Hestenes rotation zeroing the (p, q) entry of M^T M
+            const double zeta = (bb - aa) * fast_rcp(2.0 * gg);
+            const double az = fabs(zeta);
+            const double root = az < 1e150 ? az * az + 1.0 : 0.0;
+            const double den = az < 1e150 ? az + root * fast_rsq(root) : 2.0 * az;
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) * fast_rcp(den);
+            const double cs = fast_rsq(1.0 + tt * tt);
             const double sn = cs * tt;
 #pragma unroll
             for (int u = 0; u < kOjMaxLp / 16; ++u) {
@@ -741,8 +781,7 @@ __global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, 
     double ss = 0.0;
     if (c < l)
       for (int i = sub; i < l; i += 16) ss += M[c * kOjLd + i] * M[c * kOjLd + i];
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 16);
+    ss = row16_sum(ss);
     const double sv = sqrt(ss);
     if (sub == 0) lam[c] = c < l ? ss : 0.0;
     const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
