@@ -1,0 +1,244 @@
+// Cholesky factor and triangular inverse of the l x l FP64 Gram matrix of a
+// CholeskyQR pass (steps 1-3 of the orthonormalisation: G = Y^T Y = L L^T,
+// Q = Y L^-T), for sketch widths up to 128, in one workgroup.
+//
+// The whole matrix sits in LDS as a 128 x 128 square of doubles whose rows are
+// XOR-swizzled in groups of 16 (element (i, c) at i * 128 + (c ^ (i & 15))),
+// so that row-wise and column-wise reads of a 16 x 16 tile are both free of
+// bank conflicts.  The factorisation is right-looking over 16-column panels:
+//   * one wave factors the diagonal block in registers (lane = row; the
+//     pivot and the scaled column are broadcast with readlane) and forms its
+//     inverse X_kk by forward substitution;
+//   * the panel below is L_Ik = A_Ik X_kk^T and the trailing update
+//     A_IJ -= L_Ik L_Jk^T, both as 16 x 16 tiles on the FP64 matrix cores;
+//   * the wave that factors the next diagonal block first applies that
+//     block's own trailing update, so its factorisation overlaps the rest of
+//     the update (two workgroup barriers per panel).
+// The inverse X = L^-1 then proceeds by block rows, X_IJ = -X_II sum_K L_IK
+// X_KJ, with the partial sum kept in the accumulator registers and fed back as
+// the B operand of the product with X_II.  The off-diagonal blocks of X are
+// stored transposed in the upper triangle, which is exactly the layout of the
+// upper-triangular W = X^T the apply kernel consumes.
+//
+// A pivot a_jj <= tau * G_jj (or a non-positive original diagonal) drops the
+// direction: column j of L and row and column j of X become zero, so the
+// matching column of Q is zero; non-finite pivots are counted separately.
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int kB = 16;                  // panel / tile edge
+constexpr int kSq = 128;                // square held in LDS
+constexpr int kNbMax = kSq / kB;
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline int sq(int i, int c) { return i * kSq + (c ^ (i & 15)); }
+__device__ inline int xq(int i, int c) { return i * kB + (c ^ i); }   // inside one 16 x 16 block
+
+__device__ inline f64x4 mma(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Factor diagonal block kb in place and write its inverse to Xd[kb] (whole
+// wave; lanes 16..63 repeat the work of lanes 0..15 and store nothing).
+__device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0, int kb, int l,
+                           double tau, int& ndrop, int& nbad) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int g0 = kb * kB;
+  double d[kB];
+#pragma unroll
+  for (int p = 0; p < kB; ++p) d[p] = p <= r ? S[sq(g0 + r, g0 + p)] : 0.0;
+  const double od = d0[g0 + r];
+  double dv = 0.0;
+#pragma unroll
+  for (int j = 0; j < kB; ++j) {
+    const double a = readlane_d(d[j], j);
+    const double o = readlane_d(od, j);
+    const bool bad = !is_finite_d(a);
+    const bool ok = !bad && o > 0.0 && a > tau * o;
+    const double inv = ok ? fast_rsq(a) : 0.0;
+    d[j] = (r == j) ? a * inv : d[j] * inv;
+    dv = (r == j) ? inv : dv;
+    if (g0 + j < l) {
+      nbad += bad ? 1 : 0;
+      ndrop += (!bad && !ok) ? 1 : 0;
+    }
+    // rank-1 update of the columns to the right (rows above the diagonal
+    // collect values that are never read)
+#pragma unroll
+    for (int c = j + 1; c < kB; ++c) d[c] -= d[j] * readlane_d(d[j], c);
+  }
+  // lane r: column r of X_kk = L_kk^-1 by forward substitution
+  double x[kB];
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    double acc = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int p = 0; p < i; ++p) acc -= readlane_d(d[p], i) * x[p];
+    x[i] = acc * readlane_d(dv, i);
+  }
+  if (lane < kB) {
+#pragma unroll
+    for (int p = 0; p < kB; ++p)
+      if (p <= r) S[sq(g0 + r, g0 + p)] = d[p];
+    dinv[g0 + r] = dv;
+#pragma unroll
+    for (int i = 0; i < kB; ++i) Xd[kb * kB * kB + xq(i, r)] = x[i];
+  }
+}
+
+// L_Ik = A_Ik X_kk^T (one wave, one 16 x 16 tile).
+__device__ void panel_tile(double* S, const double* Xd, int kb, int I) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + q;
+    acc = mma(S[sq(I * kB + l16, kb * kB + k)], Xd[kb * kB * kB + xq(l16, k)], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[sq(I * kB + 4 * r + q, kb * kB + l16)] = acc[r];
+}
+
+// A_IJ -= L_Ik L_Jk^T (one wave, one 16 x 16 tile).
+__device__ void update_tile(double* S, int kb, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = S[sq(I * kB + 4 * r + q, J * kB + l16)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kb * kB + 4 * s + q;
+    acc = mma(-S[sq(I * kB + l16, k)], S[sq(J * kB + l16, k)], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[sq(I * kB + 4 * r + q, J * kB + l16)] = acc[r];
+}
+
+// X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ, stored transposed at block (J, I).
+__device__ void inverse_tile(double* S, const double* Xd, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 t = {0.0, 0.0, 0.0, 0.0};
+  for (int K = J; K < I; ++K) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const double b = (K == J) ? Xd[J * kB * kB + xq(k, l16)] : S[sq(J * kB + l16, K * kB + k)];
+      t = mma(S[sq(I * kB + l16, K * kB + k)], b, t);
+    }
+  }
+  // the accumulator register s holds row 4s + q, column l16 of T: exactly the
+  // B operand of k-step s
+  f64x4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) x = mma(-Xd[I * kB * kB + xq(l16, 4 * s + q)], t[s], x);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[sq(J * kB + l16, I * kB + 4 * r + q)] = x[r];
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ G, int64_t lp,
+                                                     int l, float* __restrict__ W,
+                                                     double* __restrict__ Lout,
+                                                     int32_t* __restrict__ status, double tau) {
+  __shared__ double S[kSq * kSq];
+  __shared__ double Xd[kNbMax * kB * kB];
+  __shared__ double dinv[kSq];
+  __shared__ double d0[kSq];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int n = (int)lp;
+  const int nb = (l + kB - 1) / kB;
+
+  // ---- load the leading l x l of G (zeros beyond), eight loads in flight
+  for (int e0 = tid; e0 < kSq * kSq; e0 += kThreads * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, i = e >> 7, c = e & (kSq - 1);
+      v[u] = (i < l && c < l) ? G[(int64_t)i * n + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kThreads, i = e >> 7, c = e & (kSq - 1);
+      S[sq(i, c)] = v[u];
+    }
+  }
+  for (int i = tid; i < kSq; i += kThreads) d0[i] = i < l ? G[(int64_t)i * n + i] : 0.0;
+  lds_barrier();
+
+  int ndrop = 0, nbad = 0;
+  if (wave == 0) diag_block(S, Xd, dinv, d0, 0, l, tau, ndrop, nbad);
+  lds_barrier();
+  for (int kb = 0; kb < nb; ++kb) {
+    for (int I = kb + 1 + wave; I < nb; I += kWaves) panel_tile(S, Xd, kb, I);
+    lds_barrier();
+    if (kb + 1 < nb) {
+      const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
+      if (wave == 0) {
+        update_tile(S, kb, kb + 1, kb + 1);
+        wave_lds_fence();
+        diag_block(S, Xd, dinv, d0, kb + 1, l, tau, ndrop, nbad);
+      } else {
+        for (int e = wave; e < ntile; e += kWaves - 1) {
+          // e -> (i, c), i >= c, in row-major order of the lower triangle
+          int i = 0;
+          while ((i + 1) * (i + 2) / 2 <= e) ++i;
+          const int c = e - i * (i + 1) / 2;
+          update_tile(S, kb, kb + 1 + i, kb + 1 + c);
+        }
+      }
+      lds_barrier();
+    }
+  }
+
+  if (Lout) {   // factor only: L (FP64, lp x lp row-major, zero above the diagonal)
+    for (int e = tid; e < kSq * kSq; e += kThreads) {
+      const int i = e >> 7, c = e & (kSq - 1);
+      if (i < n && c < n) Lout[(int64_t)i * n + c] = (i < l && c <= i) ? S[sq(i, c)] : 0.0;
+    }
+  } else {
+    for (int I = 1; I < nb; ++I) {
+      for (int J = wave; J < I; J += kWaves) inverse_tile(S, Xd, I, J);
+      lds_barrier();
+    }
+    // W(a, c) = X(c, a): the diagonal blocks come from Xd, the rest from the
+    // transposed copy in the upper triangle
+    for (int e = tid; e < kSq * kSq; e += kThreads) {
+      const int a = e >> 7, c = e & (kSq - 1);
+      if (a < n && c < n) {
+        float v = 0.f;
+        if (c < l && a <= c) {
+          const int ba = a >> 4, bc = c >> 4;
+          v = (float)(ba == bc ? Xd[bc * kB * kB + xq(c & 15, a & 15)] : S[sq(a, c)]);
+        }
+        W[(int64_t)a * n + c] = v;
+      }
+    }
+  }
+  if (tid == 0) {
+    status[kStDropped] += ndrop;
+    status[kStNonFinite] += nbad;
+  }
+}
+
+}  // namespace
+
+bool chol16_fits(int64_t lp) { return lp <= kSq; }
+
+hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, double* L,
+                         int32_t* status, double tau, hipStream_t s) {
+  if (lp > kSq || lp % kB != 0 || l > lp || l < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol16, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, L, status, tau);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -982,6 +982,7 @@ hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int
 hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
                            double tau, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
+  if (chol16_fits(lp)) return launch_chol16(G, lp, l, W, nullptr, status, tau, s);
   if (lp <= kBlkMaxLp)
     hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
                        (double*)nullptr, status, tau);
@@ -1023,6 +1024,7 @@ bool small_svd_one_sided(int64_t lp) { return lp <= kOjMaxLp; }
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
                               double tau, hipStream_t s) {
   if (lp > kBlkMaxLp) return hipErrorInvalidValue;
+  if (chol16_fits(lp)) return launch_chol16(G, lp, l, nullptr, L, status, tau, s);
   hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l,
                      (float*)nullptr, L, status, tau);
   return hipGetLastError();

@@ -56,6 +56,12 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
 hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
                         int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out,
                         int64_t ldo, int64_t out_rows_total, hipStream_t s);
+// Cholesky factor (L, FP64 row-major, when L != nullptr) or W = L^-T (when
+// W != nullptr) of G for lp <= 128 (k_chol.hip); the two launchers above
+// route there when the width fits.
+bool chol16_fits(int64_t lp);
+hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, double* L,
+                         int32_t* status, double tau, hipStream_t s);
 // Small SVD through the Cholesky factor of C and one-sided Jacobi (lp <= 128).
 bool small_svd_one_sided(int64_t lp);
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
