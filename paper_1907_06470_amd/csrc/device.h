@@ -100,6 +100,29 @@ __device__ inline double readlane_d(double v, int lane) {
   return r;
 }
 
+// Value of lane n of each row of 16 lanes, in every lane of that row (DPP
+// row_newbcast; n must fold to a constant).
+__device__ inline double row16_bcast(double v, int n) {
+  int lo, hi;
+  __builtin_memcpy(&lo, &v, 4);
+  __builtin_memcpy(&hi, reinterpret_cast<const char*>(&v) + 4, 4);
+  switch (n) {
+#define RSVD_BC(N)                                          \
+  case N:                                                   \
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x150 + N, 0xF, 0xF, false); \
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x150 + N, 0xF, 0xF, false); \
+    break;
+    RSVD_BC(0) RSVD_BC(1) RSVD_BC(2) RSVD_BC(3) RSVD_BC(4) RSVD_BC(5) RSVD_BC(6) RSVD_BC(7)
+    RSVD_BC(8) RSVD_BC(9) RSVD_BC(10) RSVD_BC(11) RSVD_BC(12) RSVD_BC(13) RSVD_BC(14) RSVD_BC(15)
+#undef RSVD_BC
+    default: break;
+  }
+  double r;
+  __builtin_memcpy(&r, &lo, 4);
+  __builtin_memcpy(reinterpret_cast<char*>(&r) + 4, &hi, 4);
+  return r;
+}
+
 // Workgroup barrier that orders LDS only: global stores issued before it stay
 // in flight (a plain __syncthreads() would wait for them to reach memory).
 __device__ inline void lds_barrier() {

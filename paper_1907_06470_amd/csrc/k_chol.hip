@@ -50,33 +50,40 @@ __device__ inline void wave_lds_fence() {
 }
 
 // Factor diagonal block kb in place and write its inverse to Xd[kb] (whole
-// wave; lanes 16..63 repeat the work of lanes 0..15 and store nothing).
+// wave; every row of 16 lanes holds the block, lane r of a row holding row r,
+// and only the first row stores).  Values of other rows of the block travel by
+// DPP broadcast inside the 16-lane row, so the wave needs no LDS round trip and
+// no scalar registers between steps.
 __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0, int kb, int l,
                            double tau, int& ndrop, int& nbad) {
   const int lane = threadIdx.x & 63, r = lane & 15;
   const int g0 = kb * kB;
   double d[kB];
 #pragma unroll
-  for (int p = 0; p < kB; ++p) d[p] = p <= r ? S[sq(g0 + r, g0 + p)] : 0.0;
+  for (int p = 0; p < kB; ++p) {
+    const double v = S[sq(g0 + r, g0 + p)];
+    d[p] = p <= r ? v : 0.0;
+  }
   const double od = d0[g0 + r];
   double dv = 0.0;
 #pragma unroll
   for (int j = 0; j < kB; ++j) {
-    const double a = readlane_d(d[j], j);
-    const double o = readlane_d(od, j);
+    const double a = row16_bcast(d[j], j);
+    const double o = row16_bcast(od, j);
     const bool bad = !is_finite_d(a);
     const bool ok = !bad && o > 0.0 && a > tau * o;
-    const double inv = ok ? fast_rsq(a) : 0.0;
+    const double rs = fast_rsq(ok ? a : 1.0);
+    const double inv = ok ? rs : 0.0;
     d[j] = (r == j) ? a * inv : d[j] * inv;
     dv = (r == j) ? inv : dv;
-    if (g0 + j < l) {
-      nbad += bad ? 1 : 0;
-      ndrop += (!bad && !ok) ? 1 : 0;
-    }
+    const int live = g0 + j < l ? 1 : 0;     // padding columns are not counted
+    nbad += bad ? live : 0;
+    ndrop += (!bad && !ok) ? live : 0;
     // rank-1 update of the columns to the right (rows above the diagonal
     // collect values that are never read)
 #pragma unroll
-    for (int c = j + 1; c < kB; ++c) d[c] -= d[j] * readlane_d(d[j], c);
+    for (int c = j + 1; c < kB; ++c) d[c] -= d[j] * row16_bcast(d[j], c);
+    __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of a step inside it
   }
   // lane r: column r of X_kk = L_kk^-1 by forward substitution
   double x[kB];
@@ -84,8 +91,9 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
   for (int i = 0; i < kB; ++i) {
     double acc = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-    for (int p = 0; p < i; ++p) acc -= readlane_d(d[p], i) * x[p];
-    x[i] = acc * readlane_d(dv, i);
+    for (int p = 0; p < i; ++p) acc -= row16_bcast(d[p], i) * x[p];
+    x[i] = acc * row16_bcast(dv, i);
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (lane < kB) {
 #pragma unroll
@@ -158,18 +166,25 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
   const int n = (int)lp;
   const int nb = (l + kB - 1) / kB;
 
-  // ---- load the leading l x l of G (zeros beyond), eight loads in flight
-  for (int e0 = tid; e0 < kSq * kSq; e0 += kThreads * 8) {
-    double v[8];
+  // ---- load the leading l x l of G (zeros beyond): pairs of doubles, 16 in
+  // flight per thread
+  constexpr int kPairs = kSq * kSq / 2, kBatch = 16;
+  for (int e0 = tid; e0 < kPairs; e0 += kThreads * kBatch) {
+    double2 v[kBatch];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * kThreads, i = e >> 7, c = e & (kSq - 1);
-      v[u] = (i < l && c < l) ? G[(int64_t)i * n + c] : 0.0;
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kThreads, i = e >> 6, c = (e & 63) * 2;
+      v[u] = make_double2(0.0, 0.0);
+      if (i < l && c < l) {
+        v[u] = *reinterpret_cast<const double2*>(G + (int64_t)i * n + c);
+        if (c + 1 >= l) v[u].y = 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * kThreads, i = e >> 7, c = e & (kSq - 1);
-      S[sq(i, c)] = v[u];
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kThreads, i = e >> 6, c = (e & 63) * 2;
+      S[sq(i, c)] = v[u].x;
+      S[sq(i, c + 1)] = v[u].y;
     }
   }
   for (int i = tid; i < kSq; i += kThreads) d0[i] = i < l ? G[(int64_t)i * n + i] : 0.0;
@@ -211,16 +226,21 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
       lds_barrier();
     }
     // W(a, c) = X(c, a): the diagonal blocks come from Xd, the rest from the
-    // transposed copy in the upper triangle
-    for (int e = tid; e < kSq * kSq; e += kThreads) {
-      const int a = e >> 7, c = e & (kSq - 1);
-      if (a < n && c < n) {
-        float v = 0.f;
-        if (c < l && a <= c) {
-          const int ba = a >> 4, bc = c >> 4;
-          v = (float)(ba == bc ? Xd[bc * kB * kB + xq(c & 15, a & 15)] : S[sq(a, c)]);
+    // transposed copy in the upper triangle; four columns per thread
+    constexpr int kQuads = kSq * kSq / 4;
+    for (int e = tid; e < kQuads; e += kThreads) {
+      const int a = e >> 5, c0 = (e & 31) * 4;
+      if (a < n && c0 < n) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u;
+          v[u] = 0.f;
+          if (c < l && a <= c)
+            v[u] = (float)((a >> 4) == (c >> 4) ? Xd[(c >> 4) * kB * kB + xq(c & 15, a & 15)]
+                                                : S[sq(a, c)]);
         }
-        W[(int64_t)a * n + c] = v;
+        st4(W + (int64_t)a * n + c0, make_float4(v[0], v[1], v[2], v[3]));
       }
     }
   }

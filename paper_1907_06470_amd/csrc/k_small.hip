@@ -695,19 +695,37 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
 // (C = L L^T), for sketch widths up to 128: the columns of M = L are rotated
 // in pairs until mutually orthogonal; then M = U_B diag(s), so s_c = |m_c|
 // and U_B(:, c) = m_c / s_c are the singular values of B and the
-// eigenvectors of C.  M lives in LDS column by column; a group of 16 threads
-// owns one column pair per round (round-robin schedule), so a round needs a
-// single barrier and no rotation has to be replayed afterwards.
+// eigenvectors of C.  M lives in LDS column by column; a group of 16 lanes
+// owns one column pair per round (round-robin schedule) and holds 8 rows of
+// each column in registers, so a round needs a single barrier and no rotation
+// has to be replayed afterwards.
+//
+// A round is a chain of dependent steps (load, three dot products, rotation,
+// update, barrier), so the rotation is kept short: its tangent comes from
+// FP32 arithmetic on the exponent-normalised pair (accurate to ~1e-7, which
+// only changes by how much the pair's cosine drops), while the cosine is
+// cs = (1 + t^2)^-1/2 in FP64 for that t, so every applied rotation is
+// orthogonal to FP64 rounding.  The rotate/skip test |g| > tol sqrt(a b)
+// runs beside it as g^2 > tol^2 a b.  The sweep loop ends after a sweep in
+// which no pair had |cos| above kOjStop: quadratic convergence leaves the
+// remaining off-diagonal mass near kOjStop^2.
 constexpr int kOjMaxLp = 128;
 constexpr int kOjLd = kOjMaxLp + 1;      // odd stride in doubles: no bank conflicts
-__global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, int64_t lp, int l,
-                                                  double* __restrict__ lam, double* __restrict__ Ev,
-                                                  int32_t* status, double tol, int max_sweeps) {
+constexpr int kOjG = 16;                 // lanes per column pair
+constexpr int kOjThreads = kOjG * (kOjMaxLp / 2);
+constexpr int kOjRows = kOjMaxLp / kOjG;
+constexpr double kOjStop = 1e-8;
+
+__global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict__ L, int64_t lp,
+                                                        int l, double* __restrict__ lam,
+                                                        double* __restrict__ Ev, int32_t* status,
+                                                        double tol, int max_sweeps) {
   __shared__ double M[kOjMaxLp * kOjLd];   // column c at M[c * kOjLd + i]
   __shared__ int any_s, big_s;
-  const int tid = threadIdx.x, grp = tid >> 4, sub = tid & 15;
+  const int tid = threadIdx.x, grp = tid / kOjG, sub = tid % kOjG;
   const int le = l + (l & 1), np = le / 2, R = le - 1;
-  for (int e = tid; e < l * l; e += 1024) {
+  const double tol2 = tol * tol, stop2 = kOjStop * kOjStop;
+  for (int e = tid; e < l * l; e += kOjThreads) {
     const int i = e / l, c = e % l;
     M[c * kOjLd + i] = L[(int64_t)i * lp + c];
   }
@@ -726,37 +744,43 @@ __global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, 
         if (q < l) {
           double* mp = &M[p * kOjLd];
           double* mq = &M[q * kOjLd];
-          double xp[kOjMaxLp / 16], xq[kOjMaxLp / 16];
-          double aa = 0.0, bb = 0.0, gg = 0.0;
+          double xp[kOjRows], xq[kOjRows];
 #pragma unroll
-          for (int u = 0; u < kOjMaxLp / 16; ++u) {
-            const int i = sub + 16 * u;
+          for (int u = 0; u < kOjRows; ++u) {
+            const int i = sub + kOjG * u;
             xp[u] = i < l ? mp[i] : 0.0;
             xq[u] = i < l ? mq[i] : 0.0;
           }
+          double aa0 = 0.0, bb0 = 0.0, gg0 = 0.0, aa1 = 0.0, bb1 = 0.0, gg1 = 0.0;
 #pragma unroll
-          for (int u = 0; u < kOjMaxLp / 16; ++u) {
-            aa += xp[u] * xp[u];
-            bb += xq[u] * xq[u];
-            gg += xp[u] * xq[u];
+          for (int u = 0; u < kOjRows; u += 2) {
+            aa0 += xp[u] * xp[u];
+            bb0 += xq[u] * xq[u];
+            gg0 += xp[u] * xq[u];
+            aa1 += xp[u + 1] * xp[u + 1];
+            bb1 += xq[u + 1] * xq[u + 1];
+            gg1 += xp[u + 1] * xq[u + 1];
           }
-          aa = row16_sum(aa);
-          bb = row16_sum(bb);
-          gg = row16_sum(gg);
-          const double ab = aa * bb;
-          const double scale = ab > 0.0 ? ab * fast_rsq(ab) : 0.0;
-          if (gg != 0.0 && fabs(gg) > tol * scale) {
-            // Hestenes rotation zeroing the (p, q) entry of M^T M
-            const double zeta = (bb - aa) * fast_rcp(2.0 * gg);
-            const double az = fabs(zeta);
-            const double root = az < 1e150 ? az * az + 1.0 : 0.0;
-            const double den = az < 1e150 ? az + root * fast_rsq(root) : 2.0 * az;
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) * fast_rcp(den);
-            const double cs = fast_rsq(1.0 + tt * tt);
-            const double sn = cs * tt;
+          const double aa = row16_sum(aa0 + aa1);
+          const double bb = row16_sum(bb0 + bb1);
+          const double gg = row16_sum(gg0 + gg1);
+          const double ab = aa * bb, g2 = gg * gg;
+          const bool rot = g2 > tol2 * ab;
+          // tangent of the Hestenes angle, t = sign(d) 2g / (|d| + sqrt(d^2 + 4g^2))
+          // with d = b - a, on the pair scaled by a power of two
+          const double dd = bb - aa, tg = 2.0 * gg;
+          const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(dd), fabs(tg)));
+          const float d32 = (float)__builtin_amdgcn_ldexp(dd, -ex);
+          const float g32 = (float)__builtin_amdgcn_ldexp(tg, -ex);
+          const float den = fabsf(d32) + __builtin_sqrtf(d32 * d32 + g32 * g32);
+          const float t32 = (d32 >= 0.f ? g32 : -g32) * __builtin_amdgcn_rcpf(den);
+          const double tt = rot ? (double)t32 : 0.0;
+          const double cs = fast_rsq(1.0 + tt * tt);
+          const double sn = cs * tt;
+          if (rot) {
 #pragma unroll
-            for (int u = 0; u < kOjMaxLp / 16; ++u) {
-              const int i = sub + 16 * u;
+            for (int u = 0; u < kOjRows; ++u) {
+              const int i = sub + kOjG * u;
               if (i < l) {
                 mp[i] = cs * xp[u] - sn * xq[u];
                 mq[i] = sn * xp[u] + cs * xq[u];
@@ -764,7 +788,7 @@ __global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, 
             }
             if (sub == 0) {
               any_s = 1;
-              if (fabs(gg) > 1e-10 * scale) big_s = 1;
+              if (g2 > stop2 * ab) big_s = 1;
             }
           }
         }
@@ -777,15 +801,15 @@ __global__ __launch_bounds__(1024) void k_ojacobi(const double* __restrict__ L, 
     if (!any || !big) break;
   }
   // s_c = |m_c| (one group per column), U_B(:, c) = m_c / s_c
-  for (int c = grp; c < lp; c += 64) {
+  for (int c = grp; c < lp; c += kOjThreads / kOjG) {
     double ss = 0.0;
     if (c < l)
-      for (int i = sub; i < l; i += 16) ss += M[c * kOjLd + i] * M[c * kOjLd + i];
+      for (int i = sub; i < l; i += kOjG) ss += M[c * kOjLd + i] * M[c * kOjLd + i];
     ss = row16_sum(ss);
     const double sv = sqrt(ss);
     if (sub == 0) lam[c] = c < l ? ss : 0.0;
     const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
-    for (int i = sub; i < lp; i += 16)
+    for (int i = sub; i < lp; i += kOjG)
       Ev[(int64_t)i * lp + c] = (c < l && i < l) ? M[c * kOjLd + i] * inv : 0.0;
   }
   if (tid == 0) {
@@ -1033,8 +1057,8 @@ hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L,
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
                           int32_t* status, double tol, int max_sweeps, hipStream_t s) {
   if (lp > kOjMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ojacobi, dim3(1), dim3(1024), 0, s, L, lp, (int)l, lam, Ev, status, tol,
-                     max_sweeps);
+  hipLaunchKernelGGL(k_ojacobi, dim3(1), dim3(kOjThreads), 0, s, L, lp, (int)l, lam, Ev, status,
+                     tol, max_sweeps);
   return hipGetLastError();
 }
 
