@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+PROFILES = os.path.join(ROOT, "profiles")
 PEAK = {"hbm_GBs": 8000.0, "fp32_TF": 157.3, "bf16_TF": 2500.0, "fp8_TF": 5000.0, "fp64_TF": 78.6}
 METRIC = "rank-k rSVD wall time & sketch TFLOP/s: BF16-MFMA vs FP32 at matched σ error"
 WORKLOAD = dict(name="plain_gpu", m=50000, n=20000, k=100, p=20, q=2, tile=(4096, 4096), seed=0)
@@ -33,6 +34,28 @@ WORKLOAD = dict(name="plain_gpu", m=50000, n=20000, k=100, p=20, q=2, tile=(4096
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel_file, summary):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, summary)
+    src = os.path.join(ROOT, "paper_1907_06470_amd", "csrc", kernel_file)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.lstrip().startswith("- "):
+            key, _, val = line.lstrip()[2:].partition(":")
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("source_sha256") != digest:
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def time_form(plan, A, steps, warmup):
@@ -60,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--forms", default="fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB elementwise copy kernel (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -77,6 +102,13 @@ def main():
     A, meta = workloads.make(W["name"], device=dev)
     torch.cuda.synchronize()
     log(f"generated A {m}x{n} on the GPU in {time.time() - t:.1f} s")
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
 
     flops_pass = 2.0 * m * n * l
     npass = 2 * q + 2
@@ -128,11 +160,14 @@ def main():
                 "kernel": "k_nn_f32 (sketch / power A*X product)",
                 "per_launch": f"2*m*n*l = {flops_pass:.4g} flop"}
     else:
-        bpl = m * n * 2 + (n + m) * l * 2
+        bpl = m * n * 2 + n * l * 2 + m * l * 4     # A and X in BF16 once, Y in FP32 once
         ach = bpl / (head["nn_kernel_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None,
-                "kernel": "bf16 A*X product", "per_launch": f"{bpl} bytes"}
+                "frac": round(ach / PEAK["hbm_GBs"], 4),
+                "traffic": measured_traffic("k_gemm_bf16.hip",
+                                            "counters_k_nn_bf16_dense_50000x20000.md"),
+                "kernel": "k_nn_bf16 (sketch / power A*X product, BF16 A)",
+                "per_launch": f"A {m}x{n} bf16 + X {n}x{l} bf16 + Y {m}x{l} fp32 = {bpl} bytes"}
     line = {
         "metric": METRIC, "value": round(head["tflops"], 3), "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
