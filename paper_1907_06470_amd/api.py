@@ -52,9 +52,13 @@ class Plan:
             flags |= L.FLAG_BACKWARD
         prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE, dtype=_DT.get(dtype, -99),
                          loc=L.LOC_DEVICE, reserved=0, seed=seed, nnz=0)
-        pr = _PREC.get(precision, -99) if isinstance(precision, str) else -99
+        # one precision for every pass, or (sketch, power, project)
+        names = (precision,) * 3 if isinstance(precision, str) else tuple(precision)
+        if len(names) != 3:
+            raise ValueError("precision: a name or a (sketch, power, project) triple")
+        ps, pw, pj = (_PREC.get(x, -99) for x in names)
         tm, tn = (tile if tile is not None else (0, 0))
-        opt = L.Options(prec_sketch=pr, prec_power=pr, prec_project=pr, ortho=L.ORTHO_EACH,
+        opt = L.Options(prec_sketch=ps, prec_power=pw, prec_project=pj, ortho=L.ORTHO_EACH,
                         tile_m=tm, tile_n=tn, grid_p=grid[0], grid_q=grid[1],
                         hbm_budget_bytes=int(hbm_budget), flags=flags, reserved=0)
         h = ctypes.c_void_p()

@@ -1,0 +1,335 @@
+// FP8 (OCP e4m3) form of the passes over A: A is stored once as FP8 with one
+// power-of-two scale per 64 x 64 block, in two layouts (A8 row-major for the
+// products A X, A8T = A^T row-major for A^T Q), and each panel operand is
+// stored as FP8 with one power-of-two scale per column.  The products run on
+// the gfx950 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4 with unit
+// hardware scales, FP32 accumulation); the block scale of A is applied per
+// 64-deep slab of the reduction (acc += s_block * slab product) and the column
+// scale of the panel in the epilogue.
+//
+// This extends the half-precision storage of Section 3.2 one step further:
+// A costs one byte per entry, a quarter of its FP32 size, and every pass over
+// A streams half the bytes of the BF16 form.  Quantisation (per value):
+//   s = 2^ceil(log2(amax / 448)) over the value's block (s = 1 for an all-zero
+//   block), q = round-to-nearest-even(x / s) in e4m3 (|x / s| <= 448, so the
+//   conversion never overflows).
+#include "device.h"
+#include "kernels.h"
+
+namespace rsvd {
+
+namespace {
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef uint8_t u8;
+
+constexpr int kQB = 64;          // quantisation block edge (rows and columns)
+constexpr float kFp8Max = 448.f;
+
+__device__ inline float pow2_scale(float amax) {
+  if (!(amax > 0.f)) return 1.f;                        // all-zero block
+  const float r = amax / kFp8Max;
+  int e;
+  const float f = __builtin_frexpf(r, &e);              // r = f 2^e, f in [0.5, 1)
+  return __builtin_ldexpf(1.f, f == 0.5f ? e - 1 : e);  // 2^ceil(log2 r)
+}
+
+// two FP32 values -> two e4m3 bytes (round to nearest even) in the low half
+__device__ inline uint32_t cvt2(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+}
+
+__device__ inline float wave_max(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One workgroup per 64 x 64 block: amax, scale, A8 rows, and the transposed
+// block through LDS for A8T.  Thread t covers rows t/16 + 16u (u < 4) and
+// columns 4 (t % 16) .. +3 of the block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_fp8(const T* __restrict__ A, int64_t lda, int64_t m,
+                                                  int64_t n, u8* __restrict__ A8, int64_t lda8,
+                                                  u8* __restrict__ A8T, int64_t ldat8,
+                                                  float* __restrict__ scale, int64_t nbk) {
+  __shared__ float red[8];
+  __shared__ __attribute__((aligned(16))) u8 Tt[kQB][kQB + 16];   // [column][row]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * kQB, j0 = (int64_t)blockIdx.x * kQB;
+  const int cr = tid >> 4, cc = (tid & 15) * 4;
+  float x[4][4];
+  float amax = 0.f, bad = 0.f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + cr + 16 * u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t j = j0 + cc + e;
+      x[u][e] = (i < m && j < n) ? (float)A[i * lda + j] : 0.f;
+      amax = fmaxf(amax, fabsf(x[u][e]));
+      bad = fmaxf(bad, __builtin_isfinite(x[u][e]) ? 0.f : 1.f);
+    }
+  }
+  amax = wave_max(amax);
+  bad = wave_max(bad);
+  if (lane == 0) {
+    red[wave] = amax;
+    red[4 + wave] = bad;
+  }
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  bad = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
+  // a non-finite value makes the whole block NaN, so the factorisation reports it
+  const float s = bad > 0.f ? __builtin_nanf("") : pow2_scale(amax);
+  const float inv = 1.f / s;   // exact: s is a power of two
+  if (tid == 0) scale[blockIdx.y * nbk + blockIdx.x] = s;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = cr + 16 * u;
+    const uint32_t w = cvt2(x[u][0] * inv, x[u][1] * inv) | (cvt2(x[u][2] * inv, x[u][3] * inv) << 16);
+    const int64_t i = i0 + r, j = j0 + cc;
+    if (i < m && j < n) {
+      if (j + 4 <= n && (lda8 & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(A8 + i * lda8 + j) = w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j + e < n) A8[i * lda8 + j + e] = (u8)(w >> (8 * e));
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Tt[cc + e][r] = (u8)(w >> (8 * e));
+  }
+  __syncthreads();
+  // A8T rows j0 + c, 16 bytes (rows i0 + 16 q ..) per thread
+  {
+    const int c = tid >> 2, q = (tid & 3) * 16;
+    const int64_t j = j0 + c, i = i0 + q;
+    if (j < n && i < m) {
+      if (i + 16 <= m && (ldat8 & 15) == 0) {
+        *reinterpret_cast<uint4*>(A8T + j * ldat8 + i) = *reinterpret_cast<const uint4*>(&Tt[c][q]);
+      } else {
+        for (int e = 0; e < 16 && i + e < m; ++e) A8T[j * ldat8 + i + e] = Tt[c][q + e];
+      }
+    }
+  }
+}
+
+// FP8 copy of an FP32 panel, one workgroup per column: amax over the column,
+// power-of-two scale, e4m3 values over the whole leading dimension.
+__global__ __launch_bounds__(256) void k_panel_to_fp8(const float* __restrict__ P, int64_t ld,
+                                                      int64_t rows, u8* __restrict__ P8,
+                                                      float* __restrict__ sc) {
+  __shared__ float red[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c = blockIdx.x;
+  const float* col = P + c * ld;
+  float amax = 0.f, bad = 0.f;
+  for (int64_t i = 4 * tid; i < rows; i += 1024) {
+    const float4 v = ld4_masked(col, i, rows);
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    const bool fin = __builtin_isfinite(v.x) && __builtin_isfinite(v.y) &&
+                     __builtin_isfinite(v.z) && __builtin_isfinite(v.w);
+    bad = fmaxf(bad, fin ? 0.f : 1.f);
+  }
+  amax = wave_max(amax);
+  bad = wave_max(bad);
+  if (lane == 0) {
+    red[wave] = amax;
+    red[4 + wave] = bad;
+  }
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  bad = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
+  const float s = bad > 0.f ? __builtin_nanf("") : pow2_scale(amax), inv = 1.f / s;
+  if (tid == 0) sc[c] = s;
+  for (int64_t i = 4 * tid; i < ld; i += 1024) {
+    const float4 v = i < rows ? ld4_masked(col, i, rows) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t w = cvt2(v.x * inv, v.y * inv) | (cvt2(v.z * inv, v.w * inv) << 16);
+    *reinterpret_cast<uint32_t*>(P8 + c * ld + i) = w;
+  }
+}
+
+__device__ inline f32x16 mfma_fp8(const v8i& a, const v8i& b, f32x16 c) {
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+
+// 16 consecutive bytes of a row from index k, zero past kend.
+__device__ inline uint4 ld16_masked(const u8* row, int64_t k, int64_t kend) {
+  if (k + 16 <= kend) return *reinterpret_cast<const uint4*>(row + k);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  for (int e = 0; e < 16; ++e)
+    if (k + e < kend) w[e >> 2] |= (uint32_t)row[k + e] << (8 * (e & 3));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Y (+ partial per reduction tile) = A8 X8 with the block scales of A and the
+// column scales of X.  A8: rows x kdim row-major FP8 (lda8 % 16 == 0); X8:
+// column-major FP8 (element (k, c) at X8[c * ldx8 + k]); the reduction tile of
+// blockIdx.y covers [y tk, (y + 1) tk) with tk % 64 == 0.  Block scale of rows
+// [64 r, 64 r + 64) and reduction slab [64 b, 64 b + 64): sA[r sc_r + b sc_k].
+// 4 waves; wave w owns rows [w WR, (w + 1) WR) of BM = 4 WR and all NT * 32
+// panel columns; a 128-deep stage holds two 64-deep slabs.
+constexpr int BKB = 128;
+constexpr int PADB = BKB + 16;
+template <int NT, int MT>
+__global__ __launch_bounds__(256) void k_nn_fp8(const u8* __restrict__ A, int64_t lda, int64_t rows,
+                                                int64_t kdim, int64_t tk,
+                                                const float* __restrict__ sA, int64_t sc_r,
+                                                int64_t sc_k, const u8* __restrict__ X, int64_t ldx,
+                                                const float* __restrict__ sx, float* __restrict__ Y,
+                                                int64_t ldy, int64_t part_stride) {
+  constexpr int LP = NT * 32, WR = MT * 32, BM = 4 * WR, AS = BM / 32;
+  __shared__ __attribute__((aligned(16))) u8 As[2][BM][PADB];
+  __shared__ __attribute__((aligned(16))) u8 Xs[2][LP][PADB];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tk;
+  const int64_t k1 = min(kdim, k0 + tk);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int lr = tid >> 3, lc = (tid & 7) * 16;
+
+  uint4 ra[AS];
+  uint4 rx[NT];
+  auto gload = [&](int64_t kt) {
+    const int64_t kk = kt + lc;
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+      const int64_t i = i0 + lr + 32 * s;
+      ra[s] = (i < rows && kk < k1) ? ld16_masked(A + i * lda, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const int c = lr + 32 * s;
+      rx[s] = kk < k1 ? ld16_masked(X + (int64_t)c * ldx, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < AS; ++s) *reinterpret_cast<uint4*>(&As[buf][lr + 32 * s][lc]) = ra[s];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) *reinterpret_cast<uint4*>(&Xs[buf][lr + 32 * s][lc]) = rx[s];
+  };
+
+  f32x16 acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[a][t] = f32x16{};
+  // row block (of the 64-row quantisation grid) of each M tile of this wave
+  int64_t rblk[MT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a) rblk[a] = min(i0 + wave * WR + a * 32, rows - 1) / kQB;
+
+  gload(k0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kt = k0; kt < k1; kt += BKB) {
+    const bool more = kt + BKB < k1;
+    if (more) gload(kt + BKB);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int64_t kb = kt / kQB + s2;
+      if (kb * kQB >= k1) break;
+      v8i av[MT], bv[NT];
+#pragma unroll
+      for (int a = 0; a < MT; ++a) {
+        const u8* p = &As[buf][wave * WR + a * 32 + l32][s2 * 64 + half * 32];
+        const uint4 lo = *reinterpret_cast<const uint4*>(p);
+        const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+        av[a] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const u8* p = &Xs[buf][t * 32 + l32][s2 * 64 + half * 32];
+        const uint4 lo = *reinterpret_cast<const uint4*>(p);
+        const uint4 hi = *reinterpret_cast<const uint4*>(p + 16);
+        bv[t] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+#pragma unroll
+      for (int a = 0; a < MT; ++a) {
+        const float sb = sA[rblk[a] * sc_r + kb * sc_k];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const f32x16 part = mfma_fp8(av[a], bv[t], f32x16{});
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[a][t][e] += sb * part[e];
+        }
+      }
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 32 + l32;
+    const float cs = sx[col];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const int64_t rb = i0 + wave * WR + a * 32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t r = rb + 8 * g + 4 * half;
+        st4(Yp + (int64_t)col * ldy + r,
+            make_float4(acc[a][t][4 * g + 0] * cs, acc[a][t][4 * g + 1] * cs,
+                        acc[a][t][4 * g + 2] * cs, acc[a][t][4 * g + 3] * cs));
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int64_t fp8_scale_blocks(int64_t rows, int64_t cols) {
+  return ceil_div_dev(rows, kQB) * ceil_div_dev(cols, kQB);
+}
+
+hipError_t launch_cast_fp8(const void* A, bool f64, int64_t lda, int64_t m, int64_t n, uint8_t* A8,
+                           int64_t lda8, uint8_t* A8T, int64_t ldat8, float* scale,
+                           hipStream_t s) {
+  if (lda8 < n || ldat8 < m) return hipErrorInvalidValue;
+  const int64_t nbk = ceil_div_dev(n, kQB);
+  dim3 grid((unsigned)nbk, (unsigned)ceil_div_dev(m, kQB));
+  if (f64)
+    hipLaunchKernelGGL(k_cast_fp8<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n, A8,
+                       lda8, A8T, ldat8, scale, nbk);
+  else
+    hipLaunchKernelGGL(k_cast_fp8<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, n, A8,
+                       lda8, A8T, ldat8, scale, nbk);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_to_fp8(const float* P, int64_t ld, int64_t rows, int64_t lp, uint8_t* P8,
+                               float* scale, hipStream_t s) {
+  if (ld % 4 != 0 || rows > ld) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_panel_to_fp8, dim3((unsigned)lp), dim3(256), 0, s, P, ld, rows, P8, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,
+                         int64_t TK, const float* sA, int64_t sc_r, int64_t sc_k,
+                         const uint8_t* X8, int64_t ldx8, const float* sx, int64_t lp, float* Y,
+                         int64_t ldy, int64_t part_stride, hipStream_t s) {
+  if (tk % kQB != 0 || lda8 % 16 != 0 || ldx8 % 16 != 0 || ldy % 4 != 0)
+    return hipErrorInvalidValue;
+  const int nt = (int)(lp / 32);
+  dim3 grid((unsigned)ceil_div_dev(rows, 128), (unsigned)TK);
+#define NN8(NT) hipLaunchKernelGGL((k_nn_fp8<NT, 1>), grid, dim3(256), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r, sc_k, X8, ldx8, sx, Y, ldy, part_stride)
+  switch (nt) {
+    case 1: NN8(1); break;
+    case 2: NN8(2); break;
+    case 3: NN8(3); break;
+    case 4: NN8(4); break;
+    case 5: NN8(5); break;
+    case 6: NN8(6); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NN8
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -45,6 +45,22 @@ hipError_t launch_cast_to_bf16(const void* A, bool f64, int64_t lda, int64_t m, 
                                uint16_t* out, int64_t ldo, hipStream_t s);
 hipError_t launch_panel_to_bf16(const float* P, uint16_t* P16, int64_t count, hipStream_t s);
 
+// --- FP8 (e4m3) form (k_gemm_fp8.hip) ---
+// A8 (m x lda8) and A8T (n x ldat8) FP8 copies of A with one power-of-two
+// scale per 64 x 64 block: scale[(i / 64) * ceil(n / 64) + j / 64].
+int64_t fp8_scale_blocks(int64_t rows, int64_t cols);
+hipError_t launch_cast_fp8(const void* A, bool f64, int64_t lda, int64_t m, int64_t n, uint8_t* A8,
+                           int64_t lda8, uint8_t* A8T, int64_t ldat8, float* scale, hipStream_t s);
+// P8 = FP8 copy of an FP32 column-major panel (same ld), scale[c] per column.
+hipError_t launch_panel_to_fp8(const float* P, int64_t ld, int64_t rows, int64_t lp, uint8_t* P8,
+                               float* scale, hipStream_t s);
+// Y (+ partial per reduction tile of tk) = A8 X8 with block scales sA and
+// column scales sx (see k_gemm_fp8.hip for the layouts).
+hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,
+                         int64_t TK, const float* sA, int64_t sc_r, int64_t sc_k,
+                         const uint8_t* X8, int64_t ldx8, const float* sx, int64_t lp, float* Y,
+                         int64_t ldy, int64_t part_stride, hipStream_t s);
+
 // --- small dense FP64 steps (k_small.hip) ---
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
                        int64_t chunks, double* gpart, double* G, hipStream_t s);

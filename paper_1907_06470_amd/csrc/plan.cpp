@@ -68,14 +68,14 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   for (int32_t pr : {o.prec_sketch, o.prec_power, o.prec_project}) {
     if (pr != RSVD_F32 && pr != RSVD_BF16 && pr != RSVD_FP8E4M3)
       return fail(p, RSVD_E_INVALID_ARG, "unknown product precision %lld", pr);
-    if (pr == RSVD_FP8E4M3)
-      return fail(p, RSVD_E_UNSUPPORTED, "product precision %lld is not implemented", pr);
   }
   p.any_bf16 = o.prec_sketch == RSVD_BF16 || o.prec_project == RSVD_BF16 ||
                (o.prec_power == RSVD_BF16 && prob.q > 0);
   p.any_f32 = o.prec_sketch == RSVD_F32 || o.prec_project == RSVD_F32 ||
               (o.prec_power == RSVD_F32 && prob.q > 0);
-  if (prob.dtype == RSVD_BF16 && p.any_f32)
+  p.any_fp8 = o.prec_sketch == RSVD_FP8E4M3 || o.prec_project == RSVD_FP8E4M3 ||
+              (o.prec_power == RSVD_FP8E4M3 && prob.q > 0);
+  if (prob.dtype == RSVD_BF16 && (p.any_f32 || p.any_fp8))
     return fail(p, RSVD_E_UNSUPPORTED, "A stored in BF16 needs BF16 products throughout");
   if (o.ortho != RSVD_ORTHO_EACH && o.ortho != RSVD_ORTHO_FINAL_ONLY)
     return fail(p, RSVD_E_INVALID_ARG, "unknown ortho schedule %lld", o.ortho);
@@ -100,6 +100,12 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   // block-cyclic tiles over A; one tile spans the whole dimension at most
   p.tm = o.tile_m ? std::min<int64_t>(o.tile_m, round_up(m, 32)) : auto_tile(m, ceil_div(n, 128));
   p.tn = o.tile_n ? std::min<int64_t>(o.tile_n, round_up(n, 32)) : auto_tile(n, ceil_div(m, 128));
+  if (p.any_fp8) {   // FP8 scale blocks are 64 x 64: tiles must not split one
+    if ((o.tile_m && o.tile_m % 64) || (o.tile_n && o.tile_n % 64))
+      return fail(p, RSVD_E_INVALID_ARG, "FP8 products need tile sizes that are multiples of 64");
+    p.tm = round_up(p.tm, 64);
+    p.tn = round_up(p.tn, 64);
+  }
   p.TI = ceil_div(m, p.tm);
   p.TJ = ceil_div(n, p.tn);
 
@@ -165,6 +171,15 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.A16 = (p.any_bf16 && prob.dtype != RSVD_BF16) ? take((size_t)m * p.lda16 * 2) : off;
   w.Xop16 = p.any_bf16 ? take((size_t)p.ldn * lp * 2) : off;
   w.Mop16 = p.any_bf16 ? take((size_t)p.ldm * lp * 2) : off;
+  p.lda8 = round_up(n, 64);
+  p.ldat8 = round_up(m, 64);
+  w.A8 = p.any_fp8 ? take((size_t)m * p.lda8) : off;
+  w.A8T = p.any_fp8 ? take((size_t)n * p.ldat8) : off;
+  w.sA8 = p.any_fp8 ? take((size_t)ceil_div(m, 64) * ceil_div(n, 64) * 4) : off;
+  w.Xop8 = p.any_fp8 ? take((size_t)p.ldn * lp) : off;
+  w.Mop8 = p.any_fp8 ? take((size_t)p.ldm * lp) : off;
+  w.sX8 = p.any_fp8 ? take(lp * 4) : off;
+  w.sM8 = p.any_fp8 ? take(lp * 4) : off;
   if (p.backward) {
     const size_t kp = (size_t)p.kp, rc = (size_t)p.rcat;
     w.Pcat = take((size_t)p.ldm * rc * 4);

@@ -51,6 +51,9 @@ struct Workspace {
   size_t Acast;           // FP32 copy of an FP64 A
   size_t A16;             // BF16 copy of A (when a product runs in BF16)
   size_t Xop16, Mop16;    // BF16 copies of the operand panels
+  size_t A8, A8T, sA8;    // FP8 copies of A and A^T, 64 x 64 block scales (FP32)
+  size_t Xop8, Mop8;      // FP8 copies of the operand panels
+  size_t sX8, sM8;        // their per-column scales
   // backward (RSVD_FLAG_BACKWARD)
   size_t Pcat, Rcat;      // outer-product factors (ldm x R, ldn x R), R = lp + 2 kp
   size_t gUp, gVp;        // imported cotangents (ldm x kp, ldn x kp)
@@ -70,6 +73,8 @@ struct Plan {
   int64_t ldac = 0;             // leading dimension of the FP32 cast of A
   int64_t lda16 = 0;            // leading dimension of the BF16 copy of A
   bool any_bf16 = false;        // some product runs in BF16
+  bool any_fp8 = false;         // some product runs in FP8 (e4m3)
+  int64_t lda8 = 0, ldat8 = 0;  // leading dimensions of the FP8 copies of A and A^T
   bool any_f32 = false;         // some product runs in FP32
   int64_t gram_rows = 0;        // rows per Gram chunk
   int64_t gram_chunks = 0;      // max chunks over the m- and n-side panels

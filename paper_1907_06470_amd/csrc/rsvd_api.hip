@@ -91,6 +91,8 @@ rsvd_status hip_err(rsvd_plan_t h, hipError_t e, const char* what) {
 struct Buffers {
   float *Xop, *Mop, *M0, *M1, *N0, *N1, *part, *W, *W2, *Acast;
   uint16_t *A16, *Xop16, *Mop16;
+  uint8_t *A8, *A8T, *Xop8, *Mop8;
+  float *sA8, *sX8, *sM8;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
@@ -114,6 +116,13 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.A16 = (uint16_t*)(b + w.A16);
   B.Xop16 = (uint16_t*)(b + w.Xop16);
   B.Mop16 = (uint16_t*)(b + w.Mop16);
+  B.A8 = (uint8_t*)(b + w.A8);
+  B.A8T = (uint8_t*)(b + w.A8T);
+  B.Xop8 = (uint8_t*)(b + w.Xop8);
+  B.Mop8 = (uint8_t*)(b + w.Mop8);
+  B.sA8 = (float*)(b + w.sA8);
+  B.sX8 = (float*)(b + w.sX8);
+  B.sM8 = (float*)(b + w.sM8);
   B.Pcat = (float*)(b + w.Pcat);
   B.Rcat = (float*)(b + w.Rcat);
   B.gUp = (float*)(b + w.gUp);
@@ -188,19 +197,38 @@ struct Runner {
         lda16 = P.lda16;
       }
     }
+    if (P.any_fp8)
+      RSVD_HIP(rsvd::launch_cast_fp8(A, dt == RSVD_F64, lda, P.prob.m, P.prob.n, B.A8, P.lda8,
+                                     B.A8T, P.ldat8, B.sA8, s));
     return RSVD_OK;
   }
 
-  // out (m-side panel, ld = ldm) = A X   (X: n-side panel, ld = ldn)
-  rsvd_status product_nn(const float* X, const uint16_t* X16, bool bf16, float* out) {
+  // Operand copies of an FP32 panel for a product in precision prec: n-side
+  // panels (ld = ldn) go to Xop16 / Xop8, m-side ones (ld = ldm) to Mop16 / Mop8.
+  rsvd_status prep(int32_t prec, const float* src, bool nside) {
+    const int64_t ld = nside ? P.ldn : P.ldm, rows = nside ? P.prob.n : P.prob.m;
+    if (prec == RSVD_BF16)
+      RSVD_HIP(rsvd::launch_panel_to_bf16(src, nside ? B.Xop16 : B.Mop16, ld * P.lp, s));
+    else if (prec == RSVD_FP8E4M3)
+      RSVD_HIP(rsvd::launch_panel_to_fp8(src, ld, rows, P.lp, nside ? B.Xop8 : B.Mop8,
+                                         nside ? B.sX8 : B.sM8, s));
+    return RSVD_OK;
+  }
+
+  // out (m-side panel, ld = ldm) = A X with X the n-side operand (Xop and its
+  // BF16 / FP8 copies), in precision prec
+  rsvd_status product_nn(int32_t prec, const float* X, float* out) {
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TJ > 1;
     const int64_t stride = split ? P.ldm * P.lp : 0;
     float* dst = split ? B.part : out;
     RSVD_HIP(tick(true, true));
-    if (bf16)
-      RSVD_HIP(rsvd::launch_nn_bf16(A16, lda16, m, n, P.tn, P.TJ, X16, P.ldn, P.lp, dst, P.ldm,
+    if (prec == RSVD_BF16)
+      RSVD_HIP(rsvd::launch_nn_bf16(A16, lda16, m, n, P.tn, P.TJ, B.Xop16, P.ldn, P.lp, dst, P.ldm,
                                     stride, s));
+    else if (prec == RSVD_FP8E4M3)
+      RSVD_HIP(rsvd::launch_nn_fp8(B.A8, P.lda8, m, n, P.tn, P.TJ, B.sA8, rsvd::ceil_div(n, 64), 1,
+                                   B.Xop8, P.ldn, B.sX8, P.lp, dst, P.ldm, stride, s));
     else
       RSVD_HIP(rsvd::launch_nn_f32(A32, lda32, m, n, P.tn, P.TJ, X, P.ldn, P.lp, dst, P.ldm,
                                    stride, s));
@@ -209,16 +237,19 @@ struct Runner {
     return RSVD_OK;
   }
 
-  // out (n-side panel) = A^T Q   (Q: m-side panel)
-  rsvd_status product_tn(const float* Q, const uint16_t* Q16, bool bf16, float* out) {
+  // out (n-side panel) = A^T Q with Q the m-side operand (Mop and its copies)
+  rsvd_status product_tn(int32_t prec, const float* Q, float* out) {
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TI > 1;
     const int64_t stride = split ? P.ldn * P.lp : 0;
     float* dst = split ? B.part : out;
     RSVD_HIP(tick(false, true));
-    if (bf16)
-      RSVD_HIP(rsvd::launch_tn_bf16(A16, lda16, m, n, P.tm, P.TI, Q16, P.ldm, P.lp, dst, P.ldn,
+    if (prec == RSVD_BF16)
+      RSVD_HIP(rsvd::launch_tn_bf16(A16, lda16, m, n, P.tm, P.TI, B.Mop16, P.ldm, P.lp, dst, P.ldn,
                                     stride, s));
+    else if (prec == RSVD_FP8E4M3)   // the same kernel on the transposed FP8 copy
+      RSVD_HIP(rsvd::launch_nn_fp8(B.A8T, P.ldat8, n, m, P.tm, P.TI, B.sA8, 1, rsvd::ceil_div(n, 64),
+                                   B.Mop8, P.ldm, B.sM8, P.lp, dst, P.ldn, stride, s));
     else
       RSVD_HIP(rsvd::launch_tn_f32(A32, lda32, m, n, P.tm, P.TI, Q, P.ldm, P.lp, dst, P.ldn,
                                    stride, s));
@@ -263,28 +294,27 @@ struct Runner {
   rsvd_status forward(Mark& mark, double* S, int64_t kout) {
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
-    const bool bs = P.opt.prec_sketch == RSVD_BF16, bp = P.opt.prec_power == RSVD_BF16,
-               bj = P.opt.prec_project == RSVD_BF16;
+    const int32_t ps = P.opt.prec_sketch, pw = P.opt.prec_power, pj = P.opt.prec_project;
     rsvd_status st;
     RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, B.Xop, P.ldn, s));   // step 1
-    if (bs && (st = to_bf16(B.Xop, B.Xop16, P.ldn))) return st;
+    if ((st = prep(ps, B.Xop, true))) return st;
     RSVD_HIP(mark(1));
-    if ((st = product_nn(B.Xop, B.Xop16, bs, B.M0))) return st;                       // step 2
+    if ((st = product_nn(ps, B.Xop, B.M0))) return st;                                 // step 2
     RSVD_HIP(mark(2));
     if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;   // 3-4
-    if ((P.prob.q > 0 ? bp : bj) && (st = to_bf16(B.Mop, B.Mop16, P.ldm))) return st;
+    if ((st = prep(P.prob.q > 0 ? pw : pj, B.Mop, false))) return st;
     RSVD_HIP(mark(3));
     for (int64_t t = 0; t < P.prob.q; ++t) {                                          // Eq. (2)
       const bool last = t + 1 == P.prob.q;
-      if ((st = product_tn(B.Mop, B.Mop16, bp, B.N0))) return st;
+      if ((st = product_tn(pw, B.Mop, B.N0))) return st;
       if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
-      if (bp && (st = to_bf16(B.Xop, B.Xop16, P.ldn))) return st;
-      if ((st = product_nn(B.Xop, B.Xop16, bp, B.M0))) return st;
+      if ((st = prep(pw, B.Xop, true))) return st;
+      if ((st = product_nn(pw, B.Xop, B.M0))) return st;
       if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last))) return st;
-      if ((last ? bj : bp) && (st = to_bf16(B.Mop, B.Mop16, P.ldm))) return st;
+      if ((st = prep(last ? pj : pw, B.Mop, false))) return st;
     }
     RSVD_HIP(mark(4));
-    if ((st = product_tn(B.Mop, B.Mop16, bj, B.N0))) return st;                        // step 5
+    if ((st = product_tn(pj, B.Mop, B.N0))) return st;                                 // step 5
     RSVD_HIP(mark(5));
     if ((st = small_svd_eig(B.N0))) return st;                                         // SVD0 prep
     RSVD_HIP(mark(6));
@@ -390,7 +420,7 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   const double passes = 2.0 * (double)P.prob.q + 2.0;
   report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
   auto pass_bytes = [&](int32_t prec) {
-    const double e = prec == RSVD_BF16 ? 2.0 : 4.0;
+    const double e = prec == RSVD_BF16 ? 2.0 : prec == RSVD_FP8E4M3 ? 1.0 : 4.0;
     return (double)m * (double)n * e + ((double)m + (double)n) * P.l * e;
   };
   report->bytes_alg = pass_bytes(P.opt.prec_sketch) +
@@ -569,16 +599,14 @@ rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t 
   rsvd_status st;
   if ((st = R.bind_A(A, lda))) return st;
   if (op == 0) {
-    const bool b16 = P.opt.prec_sketch == RSVD_BF16;
     RSVD_HIP(rsvd::launch_panel_copy(X, ldx, n, P.l, R.B.Xop, P.ldn, P.ldn, P.lp, s));
-    if (b16 && (st = R.to_bf16(R.B.Xop, R.B.Xop16, P.ldn))) return st;
-    if ((st = R.product_nn(R.B.Xop, R.B.Xop16, b16, R.B.M0))) return st;
+    if ((st = R.prep(P.opt.prec_sketch, R.B.Xop, true))) return st;
+    if ((st = R.product_nn(P.opt.prec_sketch, R.B.Xop, R.B.M0))) return st;
     RSVD_HIP(rsvd::launch_panel_copy(R.B.M0, P.ldm, m, P.l, out, ldo, m, P.l, s));
   } else {
-    const bool b16 = P.opt.prec_project == RSVD_BF16;
     RSVD_HIP(rsvd::launch_panel_copy(X, ldx, m, P.l, R.B.Mop, P.ldm, P.ldm, P.lp, s));
-    if (b16 && (st = R.to_bf16(R.B.Mop, R.B.Mop16, P.ldm))) return st;
-    if ((st = R.product_tn(R.B.Mop, R.B.Mop16, b16, R.B.N0))) return st;
+    if ((st = R.prep(P.opt.prec_project, R.B.Mop, false))) return st;
+    if ((st = R.product_tn(P.opt.prec_project, R.B.Mop, R.B.N0))) return st;
     RSVD_HIP(rsvd::launch_panel_copy(R.B.N0, P.ldn, n, P.l, out, ldo, n, P.l, s));
   }
   return RSVD_OK;

@@ -52,7 +52,8 @@ def make(m=100, n=80, k=5, p=5, q=1, **kw):
     (dict(k=50, p=40), L.E_INVALID_ARG),          # k + p > min(m, n)
     (dict(tile=(100, 64)), L.E_INVALID_ARG),      # not a multiple of 32
     (dict(precision="fp16"), L.E_INVALID_ARG),
-    (dict(precision="fp8"), L.E_UNSUPPORTED),
+    (dict(precision="fp8", tile=(96, 64)), L.E_INVALID_ARG),   # FP8 blocks are 64 x 64
+    (dict(precision=("fp8", "bf16", "fp4")), L.E_INVALID_ARG),
 ])
 def test_plan_rejects_bad_arguments(args, status):
     with pytest.raises(L.RsvdError) as e:
