@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--forms", default="fp32,bf16,fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB elementwise copy kernel (reference for HBM counters)")
@@ -119,8 +119,11 @@ def main():
         nn_ms = np.mean([i["gemm_nn_ms"] / max(1, i["gemm_nn_launches"]) for i in infos])
         tn_ms = np.mean([i["gemm_tn_ms"] / max(1, i["gemm_tn_launches"]) for i in infos])
         stage = np.mean([i["stage_ms"] for i in infos], axis=0)
+        ebytes = {"fp32": 4, "bf16": 2, "fp8": 1}[form]
+        nn_bytes = m * n * ebytes + n * l * ebytes + m * l * 4
         forms[form] = dict(ms_per_step=ms, tflops=npass * flops_pass / (ms * 1e-3) / 1e12,
                            sketch_tflops=flops_pass / (nn_ms * 1e-3) / 1e12,
+                           nn_alg_GBs=nn_bytes / (nn_ms * 1e-3) / 1e9,
                            nn_kernel_ms=nn_ms, tn_kernel_ms=tn_ms,
                            stage_ms=[round(float(x), 4) for x in stage],
                            status=infos[-1]["status"], dropped=infos[-1]["dropped"],

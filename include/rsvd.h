@@ -75,8 +75,12 @@ typedef struct {
 } rsvd_problem;
 
 /* Options.  prec_* choose the operand type of the products with A in the
- * sketch, the power steps and the projection (RSVD_F32 or RSVD_BF16); all
- * products accumulate in FP32, Gram/Cholesky/small SVD run in FP64.
+ * sketch, the power steps and the projection: RSVD_F32, RSVD_BF16 (A and the
+ * panel rounded to nearest even once; Section 3.2 stores half precision and
+ * computes in single) or RSVD_FP8E4M3 (OCP e4m3, A quantised once with one
+ * power-of-two scale per 64 x 64 block, panels with one per column; tiles must
+ * be multiples of 64).  All products accumulate in FP32; Gram, Cholesky and
+ * the small SVD run in FP64.
  * tile_m/tile_n: block-cyclic tile size (0 = chosen by the plan);
  * grid_p/grid_q: process grid of the block-cyclic map (1 x 1 on one GPU).
  * hbm_budget_bytes: cap on the device workspace (0 = none). */
