@@ -112,7 +112,9 @@ typedef struct {
   int32_t dropped;         /* sketch directions dropped as dependent        */
   int32_t jacobi_sweeps;   /* sweeps of the small eigensolver               */
   int32_t nonfinite;       /* NaN/Inf seen on the device                    */
-  int32_t reserved;
+  int32_t slots;           /* host-resident A: HBM tile slots               */
+  double h2d_bytes;        /* host-resident A: bytes copied host -> device  */
+  int64_t tile_loads;      /* host-resident A: tiles copied                 */
 } rsvd_report;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;

@@ -50,7 +50,7 @@ class Report(ctypes.Structure):
                 ("gemm_nn_ms", ctypes.c_double), ("gemm_tn_ms", ctypes.c_double),
                 ("ws_bytes", c_i64), ("gemm_nn_launches", c_i32), ("gemm_tn_launches", c_i32),
                 ("dropped", c_i32), ("jacobi_sweeps", c_i32), ("nonfinite", c_i32),
-                ("reserved", c_i32)]
+                ("slots", c_i32), ("h2d_bytes", ctypes.c_double), ("tile_loads", c_i64)]
 
 
 _P = ctypes.POINTER

@@ -47,11 +47,14 @@ class Plan:
     """A validated problem with its tile map and workspace size."""
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
-                 tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False):
+                 tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False):
+        """host=True: A stays in pinned host memory and is streamed to the
+        device tile by tile on every pass (hbm_budget bounds the slots)."""
         if backward:
             flags |= L.FLAG_BACKWARD
         prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE, dtype=_DT.get(dtype, -99),
-                         loc=L.LOC_DEVICE, reserved=0, seed=seed, nnz=0)
+                         loc=L.LOC_HOST_PINNED if host else L.LOC_DEVICE, reserved=0, seed=seed,
+                         nnz=0)
         # one precision for every pass, or (sketch, power, project)
         names = (precision,) * 3 if isinstance(precision, str) else tuple(precision)
         if len(names) != 3:
@@ -71,6 +74,7 @@ class Plan:
         self.m, self.n, self.k, self.p, self.q, self.seed = m, n, k, p, q, seed
         self.l = k + p
         self.dtype = dtype
+        self.host = host
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -105,13 +109,16 @@ class Plan:
         """Randomized SVD of A (cuda tensor, row-major).  Returns
         (U (m x k, column-major), S (k, FP64), V (n x k, column-major), info)."""
         lda = _ld_row_major(A)
-        if A.dtype != self.dtype or tuple(A.shape) != (self.m, self.n) or not A.is_cuda:
+        if A.dtype != self.dtype or tuple(A.shape) != (self.m, self.n):
             raise ValueError("A does not match the plan")
-        ws = self.workspace(A.device) if ws is None else ws
+        if self.host != (not A.is_cuda):
+            raise ValueError("A must be a pinned CPU tensor for a host plan, a cuda tensor otherwise")
+        dev = torch.device("cuda", torch.cuda.current_device()) if self.host else A.device
+        ws = self.workspace(dev) if ws is None else ws
         if out is None:
-            U = col_major(self.m, self.k, device=A.device)
-            S = torch.empty(self.k, dtype=torch.float64, device=A.device)
-            V = col_major(self.n, self.k, device=A.device)
+            U = col_major(self.m, self.k, device=dev)
+            S = torch.empty(self.k, dtype=torch.float64, device=dev)
+            V = col_major(self.n, self.k, device=dev)
         else:
             U, S, V = out
         rep = L.Report() if report else None
@@ -127,7 +134,8 @@ class Plan:
                         gemm_nn_launches=rep.gemm_nn_launches,
                         gemm_tn_launches=rep.gemm_tn_launches,
                         ws_bytes=rep.ws_bytes, dropped=rep.dropped,
-                        jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite)
+                        jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite,
+                        slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads)
         return U, S, V, info
 
     def backward(self, A, gU=None, gS=None, gV=None, ws=None, stream=None, report=True):
@@ -204,10 +212,12 @@ class Plan:
         return sig, ub
 
 
-def factor(A, k, p, q, seed=0, precision="fp32", tile=None, flags=0, stream=None):
-    """One-call randomized SVD: returns (U, S, V, info)."""
+def factor(A, k, p, q, seed=0, precision="fp32", tile=None, flags=0, stream=None,
+           hbm_budget=0):
+    """One-call randomized SVD: returns (U, S, V, info).  A pinned CPU tensor
+    is streamed from host memory (out of core); a cuda tensor is used in place."""
     plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, dtype=A.dtype, precision=precision,
-                tile=tile, flags=flags)
+                tile=tile, flags=flags, hbm_budget=hbm_budget, host=not A.is_cuda)
     return plan.factor(A, stream=stream)
 
 

@@ -60,11 +60,9 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
       return fail(p, RSVD_E_UNSUPPORTED, "A stored as dtype %lld is not implemented", prob.dtype);
     return fail(p, RSVD_E_INVALID_ARG, "unknown dtype %lld", prob.dtype);
   }
-  if (prob.loc != RSVD_LOC_DEVICE) {
-    if (prob.loc == RSVD_LOC_HOST_PINNED)
-      return fail(p, RSVD_E_UNSUPPORTED, "host-resident A is not implemented");
+  if (prob.loc != RSVD_LOC_DEVICE && prob.loc != RSVD_LOC_HOST_PINNED)
     return fail(p, RSVD_E_INVALID_ARG, "unknown location %lld", prob.loc);
-  }
+  p.host = prob.loc == RSVD_LOC_HOST_PINNED;
   for (int32_t pr : {o.prec_sketch, o.prec_power, o.prec_project}) {
     if (pr != RSVD_F32 && pr != RSVD_BF16 && pr != RSVD_FP8E4M3)
       return fail(p, RSVD_E_INVALID_ARG, "unknown product precision %lld", pr);
@@ -77,6 +75,20 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
               (o.prec_power == RSVD_FP8E4M3 && prob.q > 0);
   if (prob.dtype == RSVD_BF16 && (p.any_f32 || p.any_fp8))
     return fail(p, RSVD_E_UNSUPPORTED, "A stored in BF16 needs BF16 products throughout");
+  if (p.host) {
+    // streamed tiles are multiplied in their storage precision
+    const int32_t want = prob.dtype == RSVD_BF16 ? RSVD_BF16 : RSVD_F32;
+    if (prob.dtype == RSVD_F64)
+      return fail(p, RSVD_E_UNSUPPORTED, "host-resident A must be FP32 or BF16");
+    for (int32_t pr : {o.prec_sketch, o.prec_power, o.prec_project})
+      if (pr != want)
+        return fail(p, RSVD_E_UNSUPPORTED,
+                    want == RSVD_BF16
+                        ? "host-resident A is multiplied in its storage precision (BF16 products)"
+                        : "host-resident A is multiplied in its storage precision (FP32 products)");
+    if (o.flags & RSVD_FLAG_BACKWARD)
+      return fail(p, RSVD_E_UNSUPPORTED, "the adjoint needs A in device memory");
+  }
   if (o.ortho != RSVD_ORTHO_EACH && o.ortho != RSVD_ORTHO_FINAL_ONLY)
     return fail(p, RSVD_E_INVALID_ARG, "unknown ortho schedule %lld", o.ortho);
   if (o.ortho == RSVD_ORTHO_FINAL_ONLY)
@@ -100,6 +112,10 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   // block-cyclic tiles over A; one tile spans the whole dimension at most
   p.tm = o.tile_m ? std::min<int64_t>(o.tile_m, round_up(m, 32)) : auto_tile(m, ceil_div(n, 128));
   p.tn = o.tile_n ? std::min<int64_t>(o.tile_n, round_up(n, 32)) : auto_tile(n, ceil_div(m, 128));
+  if (p.host) {   // streamed tiles start on product-kernel row/column block boundaries
+    p.tm = round_up(p.tm, 256);
+    p.tn = round_up(p.tn, 256);
+  }
   if (p.any_fp8) {   // FP8 scale blocks are 64 x 64: tiles must not split one
     if ((o.tile_m && o.tile_m % 64) || (o.tile_n && o.tile_n % 64))
       return fail(p, RSVD_E_INVALID_ARG, "FP8 products need tile sizes that are multiples of 64");
@@ -195,6 +211,29 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.sinv = take(kp * 4);
   } else {
     w.Pcat = w.Rcat = w.gUp = w.gVp = w.Ju = w.Jv = w.Sl = w.coreT = w.JuW = w.JvW = w.sinv = off;
+  }
+  if (p.host) {
+    // tile slots: as many as the budget allows (at least two, so copies and
+    // products overlap), at most one per tile; four when there is no budget
+    p.elem = prob.dtype == RSVD_BF16 ? 2 : 4;
+    p.slot_ld = round_up(p.tn, 64);
+    p.slot_bytes = (size_t)round_up((int64_t)p.tm * p.slot_ld * p.elem, 256);
+    const int64_t tiles = p.TI * p.TJ;
+    int64_t S = std::min<int64_t>(tiles, 4);
+    if (o.hbm_budget_bytes) {
+      const size_t base = off;
+      if (o.hbm_budget_bytes < base + 2 * p.slot_bytes)
+        return fail(p, RSVD_E_BUDGET,
+                    "host-resident A needs %lld bytes (workspace plus two %lld-byte tile slots), "
+                    "budget is %lld",
+                    (long long)(base + 2 * p.slot_bytes), (long long)p.slot_bytes,
+                    (long long)o.hbm_budget_bytes);
+      S = std::min<int64_t>(tiles, (int64_t)((o.hbm_budget_bytes - base) / p.slot_bytes));
+    }
+    p.slots = std::max<int64_t>(S, std::min<int64_t>(tiles, 2));
+    w.slots = take((size_t)p.slots * p.slot_bytes);
+  } else {
+    w.slots = off;
   }
   w.total = off;
 

@@ -60,6 +60,7 @@ struct Workspace {
   size_t Ju, Jv;          // lp x kp FP64
   size_t Sl;              // lp FP64 Ritz values
   size_t coreT, JuW, JvW, sinv;
+  size_t slots;           // host-resident A: S tile slots of slot_bytes each
   size_t total;
 };
 
@@ -82,9 +83,15 @@ struct Plan {
   int64_t kp = 0;               // k rounded up to 32 (backward)
   int64_t rcat = 0;             // columns of the outer-product factors
   bool backward = false;
+  bool host = false;            // A in pinned host memory, streamed tile by tile
+  int64_t slots = 0;            // HBM tile slots (host-resident A)
+  int64_t slot_ld = 0;          // leading dimension (elements) of a slot
+  size_t slot_bytes = 0;
+  int64_t elem = 4;             // bytes per element of A
   Workspace ws{};
   std::string last_error;
   void* hip_events = nullptr;   // created lazily by the driver
+  void* streamer = nullptr;     // copy stream, slot events, slot contents (host A)
 };
 
 // Fill `plan` or return an error status with plan.last_error set.

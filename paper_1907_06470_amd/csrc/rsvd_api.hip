@@ -69,6 +69,56 @@ void destroy_events(Events* e) {
   delete e;
 }
 
+// Host-resident A (Section 3.5, out of core): a copy stream moves tiles from
+// pinned host memory into S HBM slots while the compute stream multiplies the
+// tiles already there.  Slot j is reused only after the product that read it
+// has finished (event free[j]); a product waits for its tile (event ready[j]).
+// Tiles stay in their slot across the passes of one call, so a pass that
+// starts where the previous one ended (serpentine order) finds them resident.
+struct Streamer {
+  hipStream_t copy = nullptr;
+  std::vector<hipEvent_t> ready, freed;
+  std::vector<int64_t> tile;       // tile held by each slot (-1: none)
+  std::vector<int64_t> last_use;
+  int64_t clock = 0;
+  double h2d_bytes = 0.0;
+  int64_t loads = 0;
+};
+
+void destroy_streamer(Streamer* st) {
+  if (!st) return;
+  for (hipEvent_t e : st->ready) (void)hipEventDestroy(e);
+  for (hipEvent_t e : st->freed) (void)hipEventDestroy(e);
+  if (st->copy) (void)hipStreamDestroy(st->copy);
+  delete st;
+}
+
+hipError_t make_streamer(rsvd::Plan& P, Streamer*& out) {
+  out = static_cast<Streamer*>(P.streamer);
+  if (out) return hipSuccess;
+  Streamer* st = new (std::nothrow) Streamer;
+  if (!st) return hipErrorOutOfMemory;
+  hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+  for (int64_t j = 0; e == hipSuccess && j < P.slots; ++j) {
+    hipEvent_t a, b;
+    e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    st->ready.push_back(a);
+    e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    st->freed.push_back(b);
+  }
+  if (e != hipSuccess) {
+    destroy_streamer(st);
+    return e;
+  }
+  st->tile.assign((size_t)P.slots, -1);
+  st->last_use.assign((size_t)P.slots, 0);
+  P.streamer = st;
+  out = st;
+  return hipSuccess;
+}
+
 rsvd_status set_err(rsvd_plan_t h, rsvd_status s, const std::string& msg) {
   if (h)
     h->p.last_error = msg;
@@ -93,6 +143,7 @@ struct Buffers {
   uint16_t *A16, *Xop16, *Mop16;
   uint8_t *A8, *A8T, *Xop8, *Mop8;
   float *sA8, *sX8, *sM8;
+  char* slots;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
@@ -123,6 +174,7 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.sA8 = (float*)(b + w.sA8);
   B.sX8 = (float*)(b + w.sX8);
   B.sM8 = (float*)(b + w.sM8);
+  B.slots = b + w.slots;
   B.Pcat = (float*)(b + w.Pcat);
   B.Rcat = (float*)(b + w.Rcat);
   B.gUp = (float*)(b + w.gUp);
@@ -159,6 +211,10 @@ struct Runner {
   Events* ev = nullptr;        // non-null: time every product kernel
   std::vector<int> nn_idx, tn_idx;
   int next_pair = 0;
+  const char* Ahost = nullptr; // host-resident A (pinned), streamed tile by tile
+  int64_t ldh = 0;
+  Streamer* st8 = nullptr;
+  int64_t pass_no = 0;         // passes over A so far in this call
 
   hipError_t tick(bool nn, bool start) {
     if (!ev) return hipSuccess;
@@ -175,6 +231,15 @@ struct Runner {
   // and/or BF16 (rounded to nearest even once per call).
   rsvd_status bind_A(const void* A, int64_t lda) {
     const int32_t dt = P.prob.dtype;
+    if (P.host) {
+      Ahost = static_cast<const char*>(A);
+      ldh = lda;
+      RSVD_HIP(make_streamer(h->p, st8));
+      std::fill(st8->tile.begin(), st8->tile.end(), -1);   // A may have changed since the last call
+      st8->h2d_bytes = 0.0;
+      st8->loads = 0;
+      return RSVD_OK;
+    }
     if (P.any_f32) {
       if (dt == RSVD_F64) {
         RSVD_HIP(rsvd::launch_cast_f64_f32((const double*)A, lda, P.prob.m, P.prob.n, B.Acast,
@@ -217,7 +282,79 @@ struct Runner {
 
   // out (m-side panel, ld = ldm) = A X with X the n-side operand (Xop and its
   // BF16 / FP8 copies), in precision prec
+  // One pass over host-resident A, tile by tile.  Even passes (A X) visit the
+  // tiles row-major, odd passes (A^T Q) column-major backwards, so every pass
+  // begins with the tiles the previous one ended on (the visit order of
+  // rsvd_visit_order).  Each tile writes its own rows of its partial panel,
+  // so the result does not depend on the order.
+  rsvd_status stream_pass(bool nn, int32_t prec, const float* op, float* out) {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    const bool split = nn ? P.TJ > 1 : P.TI > 1;
+    const int64_t stride = split ? (nn ? P.ldm : P.ldn) * P.lp : 0;
+    float* dst = split ? B.part : out;
+    const bool b16 = prec == RSVD_BF16;
+    std::vector<int64_t> order;
+    order.reserve((size_t)(P.TI * P.TJ));
+    if (pass_no % 2 == 0) {
+      for (int64_t I = 0; I < P.TI; ++I)
+        for (int64_t J = 0; J < P.TJ; ++J) order.push_back(I * P.TJ + J);
+    } else {
+      for (int64_t J = P.TJ - 1; J >= 0; --J)
+        for (int64_t I = P.TI - 1; I >= 0; --I) order.push_back(I * P.TJ + J);
+    }
+    ++pass_no;
+    Streamer& St = *st8;
+    RSVD_HIP(tick(nn, true));
+    for (int64_t t : order) {
+      const int64_t I = t / P.TJ, J = t % P.TJ;
+      const int64_t r0 = I * P.tm, rows = std::min(m, r0 + P.tm) - r0;
+      const int64_t c0 = J * P.tn, cols = std::min(n, c0 + P.tn) - c0;
+      int64_t j = -1;
+      for (int64_t x = 0; x < P.slots; ++x)
+        if (St.tile[x] == t) j = x;
+      if (j < 0) {   // least recently used slot
+        j = 0;
+        for (int64_t x = 1; x < P.slots; ++x)
+          if (St.last_use[x] < St.last_use[j]) j = x;
+        RSVD_HIP(hipStreamWaitEvent(St.copy, St.freed[j], 0));
+        RSVD_HIP(hipMemcpy2DAsync(B.slots + j * P.slot_bytes, P.slot_ld * P.elem,
+                                  Ahost + (r0 * ldh + c0) * P.elem, ldh * P.elem, cols * P.elem,
+                                  rows, hipMemcpyHostToDevice, St.copy));
+        RSVD_HIP(hipEventRecord(St.ready[j], St.copy));
+        St.tile[j] = t;
+        St.h2d_bytes += (double)rows * cols * P.elem;
+        ++St.loads;
+      }
+      St.last_use[j] = ++St.clock;
+      RSVD_HIP(hipStreamWaitEvent(s, St.ready[j], 0));
+      const char* slot = B.slots + j * P.slot_bytes;
+      if (nn) {
+        float* o = dst + J * stride + r0;
+        if (b16)
+          RSVD_HIP(rsvd::launch_nn_bf16((const uint16_t*)slot, P.slot_ld, rows, cols, P.tn, 1,
+                                        B.Xop16 + c0, P.ldn, P.lp, o, P.ldm, 0, s));
+        else
+          RSVD_HIP(rsvd::launch_nn_f32((const float*)slot, P.slot_ld, rows, cols, P.tn, 1, op + c0,
+                                       P.ldn, P.lp, o, P.ldm, 0, s));
+      } else {
+        float* o = dst + I * stride + c0;
+        if (b16)
+          RSVD_HIP(rsvd::launch_tn_bf16((const uint16_t*)slot, P.slot_ld, rows, cols, P.tm, 1,
+                                        B.Mop16 + r0, P.ldm, P.lp, o, P.ldn, 0, s));
+        else
+          RSVD_HIP(rsvd::launch_tn_f32((const float*)slot, P.slot_ld, rows, cols, P.tm, 1, op + r0,
+                                       P.ldm, P.lp, o, P.ldn, 0, s));
+      }
+      RSVD_HIP(hipEventRecord(St.freed[j], s));
+    }
+    RSVD_HIP(tick(nn, false));
+    if (split)
+      RSVD_HIP(rsvd::launch_reduce_parts(B.part, stride, nn ? P.TJ : P.TI, out, stride, s));
+    return RSVD_OK;
+  }
+
   rsvd_status product_nn(int32_t prec, const float* X, float* out) {
+    if (P.host) return stream_pass(true, prec, X, out);
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TJ > 1;
     const int64_t stride = split ? P.ldm * P.lp : 0;
@@ -239,6 +376,7 @@ struct Runner {
 
   // out (n-side panel) = A^T Q with Q the m-side operand (Mop and its copies)
   rsvd_status product_tn(int32_t prec, const float* Q, float* out) {
+    if (P.host) return stream_pass(false, prec, Q, out);
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TI > 1;
     const int64_t stride = split ? P.ldn * P.lp : 0;
@@ -356,6 +494,14 @@ rsvd_status check_A(rsvd_plan_t h, const void* A, int64_t lda) {
   const rsvd::Plan& P = h->p;
   if (!A) return set_err(h, RSVD_E_INVALID_ARG, "A is NULL");
   if (lda < P.prob.n) return set_err(h, RSVD_E_INVALID_ARG, "lda < n");
+  if (P.host) {
+    // the copies overlap the products only from page-locked memory
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, A);
+    (void)hipGetLastError();
+    if (e != hipSuccess || at.type != hipMemoryTypeHost)
+      return set_err(h, RSVD_E_INVALID_ARG, "host-resident A must be pinned (page-locked) memory");
+  }
   if (P.prob.dtype == RSVD_F32 && (((uintptr_t)A) & 3) != 0)
     return set_err(h, RSVD_E_INVALID_ARG, "FP32 A must be 4-byte aligned");
   if (P.prob.dtype == RSVD_BF16 && ((lda % 8) != 0 || (((uintptr_t)A) & 15) != 0))
@@ -430,6 +576,11 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   report->dropped = stw[rsvd::kStDropped];
   report->jacobi_sweeps = stw[rsvd::kStSweeps];
   report->nonfinite = stw[rsvd::kStNonFinite];
+  if (P.host && R.st8) {
+    report->slots = (int32_t)P.slots;
+    report->h2d_bytes = R.st8->h2d_bytes;
+    report->tile_loads = R.st8->loads;
+  }
   if (stw[rsvd::kStNonFinite] > 0) return set_err(h, RSVD_E_NUMERIC, "NaN or Inf met on the device");
   if (stw[rsvd::kStTies] > 0) return RSVD_W_DEGENERATE;
   if (stw[rsvd::kStDropped] > 0 || stw[rsvd::kStRankSmall] > 0) return RSVD_W_RANK_DEFICIENT;
@@ -482,6 +633,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_pl
 void rsvd_plan_destroy(rsvd_plan_t plan) {
   if (!plan) return;
   destroy_events(static_cast<Events*>(plan->p.hip_events));
+  destroy_streamer(static_cast<Streamer*>(plan->p.streamer));
   delete plan;
 }
 
@@ -586,6 +738,8 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
 rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t lda, const float* X,
                               int64_t ldx, float* out, int64_t ldo, void* ws, void* stream) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.host)
+    return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;
   if (rsvd_status st = check_ws(h, ws)) return st;
   const rsvd::Plan& P = h->p;
@@ -676,6 +830,8 @@ rsvd_status rsvd_backward(rsvd_plan_t h, const void* A, int64_t lda, const float
                           int64_t ldgu, const double* gS, const float* gV, int64_t ldgv,
                           float* gA, int64_t ldga, void* ws, void* stream, rsvd_report* report) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.host)
+    return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;
   if (rsvd_status st = check_ws(h, ws)) return st;
   const rsvd::Plan& P = h->p;
@@ -749,6 +905,8 @@ rsvd_status rsvd_residual(rsvd_plan_t h, const void* A, int64_t lda, const float
                           const double* S, const float* V, int64_t ldv, double* out, void* ws,
                           void* stream) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.host)
+    return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;
   if (rsvd_status st = check_ws(h, ws)) return st;
   const rsvd::Plan& P = h->p;

@@ -80,7 +80,9 @@ def test_plan_unsupported_combinations():
     assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
     prob.format = L.DENSE
     prob.loc = L.LOC_HOST_PINNED
+    prob.dtype = L.F64            # streamed tiles are FP32 or BF16
     assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
+    prob.dtype = L.F32
     prob.loc = 7
     assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
     assert L.lib().rsvd_plan(None, None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
@@ -134,3 +136,38 @@ def test_missing_library_fails_loudly():
             "L._lib = None\ntry:\n    L.lib()\nexcept RuntimeError as e:\n    print('LOUD', e)")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
     assert "LOUD" in out.stdout
+
+
+def _host_plan_ws(budget, flags=0, prec=None, m=4096, n=3072, tile=(1024, 1024)):
+    prob = L.Problem(m=m, n=n, k=20, p=12, q=1, format=L.DENSE, dtype=L.F32,
+                     loc=L.LOC_HOST_PINNED, seed=0)
+    pr = L.F32 if prec is None else prec
+    opt = L.Options(prec_sketch=pr, prec_power=pr, prec_project=pr, ortho=0, tile_m=tile[0],
+                    tile_n=tile[1], grid_p=1, grid_q=1, hbm_budget_bytes=budget, flags=flags)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    st = L.lib().rsvd_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h), ctypes.byref(ws))
+    if st == L.OK:
+        L.lib().rsvd_plan_destroy(h)
+    return st, ws.value
+
+
+def test_host_resident_plans_size_their_tile_slots_from_the_budget():
+    slot = 1024 * 1024 * 4
+    st, ws_free = _host_plan_ws(0)              # no budget: four slots
+    assert st == L.OK
+    st, ws2 = _host_plan_ws(ws_free)            # the same bytes as a budget: same plan
+    assert st == L.OK and ws2 == ws_free
+    base = ws_free - 4 * slot
+    st, ws_min = _host_plan_ws(base + 2 * slot)   # exactly two slots fit
+    assert st == L.OK and ws_min == base + 2 * slot
+    st, _ = _host_plan_ws(base + 2 * slot - 1)    # fewer than two: refused with the bytes
+    assert st == L.E_BUDGET
+    assert b"bytes" in L.lib().rsvd_last_error(None)
+    st, ws_all = _host_plan_ws(base + 100 * slot)  # never more slots than tiles (4 x 3)
+    assert st == L.OK and ws_all == base + 12 * slot
+
+
+def test_host_resident_plans_reject_other_precisions_and_the_adjoint():
+    assert _host_plan_ws(0, prec=L.BF16)[0] == L.E_UNSUPPORTED
+    assert _host_plan_ws(0, flags=L.FLAG_BACKWARD)[0] == L.E_UNSUPPORTED
