@@ -73,8 +73,13 @@ void destroy_events(Events* e) {
 // pinned host memory into S HBM slots while the compute stream multiplies the
 // tiles already there.  Slot j is reused only after the product that read it
 // has finished (event free[j]); a product waits for its tile (event ready[j]).
-// Tiles stay in their slot across the passes of one call, so a pass that
-// starts where the previous one ended (serpentine order) finds them resident.
+// Every pass visits every tile, so a least-recently-used cache smaller than A
+// would thrash; instead, with S slots and T > S tiles, tiles 0 .. S-3 own a
+// slot each and stay resident across the passes of a call (loaded once),
+// and the other tiles stream through the last two slots (double buffering;
+// a pass that starts where the previous one ended, serpentine order, still
+// finds that tile in its streaming slot).  Loads per call:
+// T + (passes - 1) (T - S + 2) - (passes - 1).
 struct Streamer {
   hipStream_t copy = nullptr;
   std::vector<hipEvent_t> ready, freed;
@@ -309,13 +314,21 @@ struct Runner {
       const int64_t I = t / P.TJ, J = t % P.TJ;
       const int64_t r0 = I * P.tm, rows = std::min(m, r0 + P.tm) - r0;
       const int64_t c0 = J * P.tn, cols = std::min(n, c0 + P.tn) - c0;
+      const int64_t tiles = P.TI * P.TJ;
+      const int64_t owned = P.slots >= tiles ? tiles : P.slots - 2;   // tiles with a slot of their own
       int64_t j = -1;
-      for (int64_t x = 0; x < P.slots; ++x)
-        if (St.tile[x] == t) j = x;
-      if (j < 0) {   // least recently used slot
-        j = 0;
-        for (int64_t x = 1; x < P.slots; ++x)
-          if (St.last_use[x] < St.last_use[j]) j = x;
+      if (t < owned) {
+        j = t;
+      } else {
+        for (int64_t x = owned; x < P.slots; ++x)
+          if (St.tile[x] == t) j = x;
+      }
+      if (j < 0 || St.tile[j] != t) {   // load: own slot, or the older streaming slot
+        if (j < 0) {
+          j = owned;
+          for (int64_t x = owned + 1; x < P.slots; ++x)
+            if (St.last_use[x] < St.last_use[j]) j = x;
+        }
         RSVD_HIP(hipStreamWaitEvent(St.copy, St.freed[j], 0));
         RSVD_HIP(hipMemcpy2DAsync(B.slots + j * P.slot_bytes, P.slot_ld * P.elem,
                                   Ahost + (r0 * ldh + c0) * P.elem, ldh * P.elem, cols * P.elem,

@@ -50,10 +50,16 @@ def test_slot_count_changes_traffic_not_results():
     slot = 1024 * 1024 * 4
     few = Plan(m, n, k, p, q, tile=tile, host=True, hbm_budget=base.ws_bytes - 2 * slot)
     many = Plan(m, n, k, p, q, tile=tile, host=True, hbm_budget=base.ws_bytes + 10 * slot)
+    mid = Plan(m, n, k, p, q, tile=tile, host=True, hbm_budget=base.ws_bytes)   # 4 slots
     r_few = few.factor(A)
     r_many = many.factor(A)
-    for x, y in zip(r_few[:3], r_many[:3]):
-        assert torch.equal(x, y)
+    r_mid = mid.factor(A)
+    for x, y, z in zip(r_few[:3], r_many[:3], r_mid[:3]):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    # 4 slots for 6 tiles: tiles 0 and 1 stay resident, the other four stream
+    # through two slots, and each later pass reuses the tile the last one ended on
+    assert r_mid[3]["slots"] == 4
+    assert r_mid[3]["tile_loads"] == 6 + (2 * q + 1) * (6 - 2 - 1)
     passes, tiles = 2 * q + 2, 6
     say("loads", r_few[3]["tile_loads"], r_many[3]["tile_loads"], r_few[3]["slots"], r_many[3]["slots"])
     assert r_few[3]["slots"] == 2 and r_many[3]["slots"] == tiles

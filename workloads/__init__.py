@@ -82,6 +82,9 @@ RECIPES = {
                       k=100, p=20, q=2, dtype="f32", tile=(4096, 4096)),
     "mixed": dict(m=65536, n=32768, spectrum=("pow", 32768, 0.5), noise=1e-4, seed=5,
                   k=128, p=32, q=3, dtype="f32", tile=(4096, 4096)),
+    # out-of-core: A lives in pinned host memory, HBM budget 16 GB
+    "ooc": dict(m=200000, n=100000, spectrum=("pow", 500, 0.8), noise=1e-5, seed=3,
+                k=200, p=30, q=2, dtype="f32", tile=(8192, 8192)),
 }
 
 
