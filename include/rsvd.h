@@ -66,9 +66,9 @@ enum {
  * (Section 2.1; Section 2.2, Eq. (1)), Gaussian test matrix from `seed`. */
 typedef struct {
   int64_t m, n, k, p, q;
-  int32_t format;   /* RSVD_DENSE (RSVD_CSR reserved)                   */
+  int32_t format;   /* RSVD_DENSE, or RSVD_CSR (see rsvd_factor_csr)      */
   int32_t dtype;    /* storage type of A: RSVD_F32 or RSVD_F64            */
-  int32_t loc;      /* RSVD_LOC_DEVICE                                    */
+  int32_t loc;      /* RSVD_LOC_DEVICE, or RSVD_LOC_HOST_PINNED (dense)   */
   int32_t reserved;
   uint64_t seed;
   int64_t nnz;      /* CSR only                                           */
@@ -224,10 +224,36 @@ rsvd_status rsvd_omega(uint64_t seed, int64_t n, int64_t l, int64_t row0, int64_
                        int32_t dtype, void* out, int64_t ldo, void* stream);
 
 
+/* Sparse A (Section 2.1 on a sparse matrix; the paper's library takes sparse
+ * input, Section 3.3): the plan's problem has format RSVD_CSR, dtype
+ * RSVD_F32, loc RSVD_LOC_DEVICE, nnz set, and all products in FP32.
+ *   rowptr  device int32[m + 1], rowptr[0] = 0, non-decreasing, rowptr[m] = nnz
+ *   colind  device int32[nnz], column of each nonzero in [0, n) (any order
+ *           within a row)
+ *   values  device float[nnz]
+ * A^T is applied through a CSC copy built in the workspace once per call by
+ * a stable sort of the nonzeros by column, so results are bitwise
+ * reproducible.  Malformed arrays are detected on the device: with a report
+ * the call returns RSVD_E_INVALID_ARG (without one the outputs are undefined
+ * but every kernel stays in bounds).  RSVD_E_BUDGET if the sort needs more
+ * scratch than the plan reserved (the message states the bytes).  Other
+ * arguments, outputs and the report are as for rsvd_factor. */
+rsvd_status rsvd_factor_csr(rsvd_plan_t plan, const int32_t* rowptr, const int32_t* colind,
+                            const float* values, void* ws, float* U, int64_t ldu, double* S,
+                            float* V, int64_t ldv, void* stream, rsvd_report* report);
+
 /* ---- single-step hooks: one step of rsvd_factor in isolation ------------- */
 /* They run the same kernels as rsvd_factor on caller panels, using the plan's
  * workspace `ws` for staging.  Panels are column-major FP32 (element (i, c) at
  * P[i + c * ld]) with l = k + p columns.  Asynchronous on `stream`. */
+
+/* Sparse product with the plan's CSR matrix (arrays as in rsvd_factor_csr):
+ * op 0: out (m x l) = A X with X n x l; op 1: out (n x l) = A^T X with X
+ * m x l.  Panels column-major FP32.  Synchronises `stream`; returns
+ * RSVD_E_INVALID_ARG for malformed CSR arrays. */
+rsvd_status rsvd_step_spmm(rsvd_plan_t plan, int32_t op, const int32_t* rowptr,
+                           const int32_t* colind, const float* values, const float* X,
+                           int64_t ldx, float* out, int64_t ldo, void* ws, void* stream);
 
 /* Block-wise product with A over the plan's tiles (Section 2.3, Eq. (3)):
  * op 0: out (m x l, ldo >= m) = A X with X n x l (ldx >= n);

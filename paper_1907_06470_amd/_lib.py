@@ -60,6 +60,9 @@ _SIGS = {
                             _P(Report)]),
     "rsvd_backward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
                               c_vp, c_vp, _P(Report)]),
+    "rsvd_factor_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
+                                _P(Report)]),
+    "rsvd_step_spmm": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "rsvd_residual": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "rsvd_plan_destroy": (None, [c_vp]),
     "rsvd_status_str": (ctypes.c_char_p, [c_i32]),

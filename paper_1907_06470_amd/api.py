@@ -43,18 +43,35 @@ def _ld_row_major(A):
     return A.stride(0) if A.shape[0] > 1 else A.shape[1]
 
 
+def _csr_arrays(rowptr, colind, values, plan):
+    if plan.nnz is None:
+        raise ValueError("the plan is for dense input")
+    rowptr = rowptr.to(torch.int32).contiguous()
+    colind = colind.to(torch.int32).contiguous()
+    values = values.to(torch.float32).contiguous()
+    if rowptr.numel() != plan.m + 1 or colind.numel() != plan.nnz or values.numel() != plan.nnz:
+        raise ValueError("CSR arrays do not match the plan")
+    if not (rowptr.is_cuda and colind.is_cuda and values.is_cuda):
+        raise ValueError("CSR arrays must be cuda tensors")
+    return rowptr, colind, values
+
+
 class Plan:
     """A validated problem with its tile map and workspace size."""
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
-                 tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False):
+                 tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False,
+                 nnz=None):
         """host=True: A stays in pinned host memory and is streamed to the
-        device tile by tile on every pass (hbm_budget bounds the slots)."""
+        device tile by tile on every pass (hbm_budget bounds the slots).
+        nnz: A is sparse (CSR with int32 indices, FP32 values) with nnz
+        nonzeros; use factor_csr / factor with a sparse CSR tensor."""
         if backward:
             flags |= L.FLAG_BACKWARD
-        prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE, dtype=_DT.get(dtype, -99),
+        prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE if nnz is None else L.CSR,
+                         dtype=_DT.get(dtype, -99),
                          loc=L.LOC_HOST_PINNED if host else L.LOC_DEVICE, reserved=0, seed=seed,
-                         nnz=0)
+                         nnz=0 if nnz is None else int(nnz))
         # one precision for every pass, or (sketch, power, project)
         names = (precision,) * 3 if isinstance(precision, str) else tuple(precision)
         if len(names) != 3:
@@ -75,6 +92,7 @@ class Plan:
         self.l = k + p
         self.dtype = dtype
         self.host = host
+        self.nnz = nnz
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -175,6 +193,45 @@ class Plan:
         L.check(st, self.handle)
         return out
 
+    def factor_csr(self, rowptr, colind, values, ws=None, out=None, stream=None, report=True):
+        """Randomized SVD of a sparse A given as CSR device arrays (int32
+        rowptr[m + 1], int32 colind[nnz], float32 values[nnz])."""
+        rowptr, colind, values = _csr_arrays(rowptr, colind, values, self)
+        dev = rowptr.device
+        ws = self.workspace(dev) if ws is None else ws
+        if out is None:
+            U = col_major(self.m, self.k, device=dev)
+            S = torch.empty(self.k, dtype=torch.float64, device=dev)
+            V = col_major(self.n, self.k, device=dev)
+        else:
+            U, S, V = out
+        rep = L.Report() if report else None
+        st = L.lib().rsvd_factor_csr(self.handle, _ptr(rowptr), _ptr(colind), _ptr(values), _ptr(ws),
+                                     _ptr(U), _ld_col_major(U), _ptr(S), _ptr(V), _ld_col_major(V),
+                                     _stream_ptr(stream),
+                                     ctypes.byref(rep) if rep is not None else None)
+        L.check(st, self.handle)
+        info = {"status": st}
+        if rep is not None:
+            info.update(stage_ms=list(rep.stage_ms), total_ms=rep.total_ms,
+                        flops_alg=rep.flops_alg, bytes_alg=rep.bytes_alg,
+                        gemm_nn_ms=rep.gemm_nn_ms, gemm_tn_ms=rep.gemm_tn_ms,
+                        gemm_nn_launches=rep.gemm_nn_launches,
+                        gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
+                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps)
+        return U, S, V, info
+
+    def step_spmm(self, op, rowptr, colind, values, X, ws=None, stream=None):
+        rowptr, colind, values = _csr_arrays(rowptr, colind, values, self)
+        rows_out = self.m if op == 0 else self.n
+        out = col_major(rows_out, self.l, device=X.device)
+        ws = self.workspace(X.device) if ws is None else ws
+        st = L.lib().rsvd_step_spmm(self.handle, op, _ptr(rowptr), _ptr(colind), _ptr(values),
+                                    _ptr(X), _ld_col_major(X), _ptr(out), _ld_col_major(out),
+                                    _ptr(ws), _stream_ptr(stream))
+        L.check(st, self.handle)
+        return out
+
     def step_product(self, op, A, X, ws=None, stream=None):
         rows_out = self.m if op == 0 else self.n
         out = col_major(rows_out, self.l, device=A.device)
@@ -215,7 +272,11 @@ class Plan:
 def factor(A, k, p, q, seed=0, precision="fp32", tile=None, flags=0, stream=None,
            hbm_budget=0):
     """One-call randomized SVD: returns (U, S, V, info).  A pinned CPU tensor
-    is streamed from host memory (out of core); a cuda tensor is used in place."""
+    is streamed from host memory (out of core); a cuda tensor is used in place;
+    a sparse CSR cuda tensor runs the sparse products."""
+    if A.layout == torch.sparse_csr:
+        plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, flags=flags, nnz=A._nnz())
+        return plan.factor_csr(A.crow_indices(), A.col_indices(), A.values(), stream=stream)
     plan = Plan(A.shape[0], A.shape[1], k, p, q, seed=seed, dtype=A.dtype, precision=precision,
                 tile=tile, flags=flags, hbm_budget=hbm_budget, host=not A.is_cuda)
     return plan.factor(A, stream=stream)

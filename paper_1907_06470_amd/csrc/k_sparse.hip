@@ -1,0 +1,355 @@
+// Sparse A (CSR, int32 indices, FP32 values): the products of Section 2.1
+// steps 2 and 5 and of the power steps (Section 2.2 Eq. (2)) as sparse x
+// tall-skinny products, with A^T applied through a CSC copy (the CSR of A^T)
+// built once per call by a stable sort of the nonzeros by column.
+//
+// Product Y = S X, S in compressed-row form (rows of A, or rows of A^T):
+//   * X is first copied row-major (n x lp), so the row of X a nonzero needs
+//     is one contiguous run of lp floats: a wave gathers it with lanes over
+//     the columns (coalesced) and accumulates a * X(col, :) in registers.
+//   * Work is split by nonzeros, not by rows: chunk c covers nonzeros
+//     [c C, (c + 1) C) (one wave each), so a column of A^T with millions of
+//     entries (a Zipf head column) is spread over many waves.  A row that
+//     starts inside a chunk is written by that chunk (complete, or its first
+//     part); every later chunk the row reaches writes its part to carry[c];
+//     a fix-up pass adds the carries to the row in chunk order.  The result
+//     does not depend on scheduling: runs are bitwise reproducible.
+//   * The result is written row-major and transposed into the column-major
+//     panel the orthonormalisation uses; empty rows become zero there.
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int kChunk = (int)kSpmmChunk;   // nonzeros per wave
+constexpr int kMaxCW = 3;        // columns per lane: lp <= 192 = 3 x 64
+
+// first row of each chunk: largest r with ptr[r] <= c C
+__global__ void k_chunk_rows(const int32_t* __restrict__ ptr, int64_t rows, int64_t nnz,
+                             int64_t chunks, int32_t* __restrict__ first) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= chunks) return;
+  const int64_t e = c * kChunk;
+  int64_t lo = 0, hi = rows - 1;   // ptr[lo] <= e always (ptr[0] = 0)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  // skip empty rows that also start at e (the row holding nonzero e is the
+  // last r with ptr[r] <= e, which is what the search returns)
+  first[c] = (int32_t)lo;
+  (void)nnz;
+}
+
+template <int CW>
+__device__ inline void flush_row(float* __restrict__ Yr, int64_t ldyr, float* __restrict__ carry,
+                                 int64_t c, int64_t r, bool continued, const float (&acc)[kMaxCW],
+                                 int lane, int lp) {
+  float* dst = continued ? carry + c * ldyr : Yr + r * ldyr;
+#pragma unroll
+  for (int u = 0; u < CW; ++u) {
+    const int col = lane + 64 * u;
+    if (col < lp) dst[col] = acc[u];
+  }
+}
+
+// One wave per chunk of nonzeros; 4 waves per workgroup.
+template <int CW>
+__global__ __launch_bounds__(256) void k_spmm_chunk(const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ idx,
+                                                    const float* __restrict__ val, int64_t rows,
+                                                    int64_t nnz, const int32_t* __restrict__ first,
+                                                    int64_t chunks, const float* __restrict__ Xr,
+                                                    int64_t ldxr, int64_t xrows, int lp,
+                                                    float* __restrict__ Yr, int64_t ldyr,
+                                                    float* __restrict__ carry) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= chunks) return;
+  const int64_t e0 = c * kChunk, e1 = min(nnz, e0 + kChunk);
+  int64_t r = first[c];
+  int64_t rend = ptr[r + 1];
+  while (rend <= e0 && r + 1 < rows) {   // empty rows at the chunk start
+    ++r;
+    rend = ptr[r + 1];
+  }
+  bool continued = ptr[r] < e0;
+  float acc[kMaxCW] = {0.f, 0.f, 0.f};
+  for (int64_t g = e0; g < e1; g += 64) {
+    const int cnt = (int)min<int64_t>(64, e1 - g);
+    // out-of-range indices (flagged by the input check) are clamped
+    const int32_t mycol = lane < cnt ? (int32_t)min<uint32_t>((uint32_t)idx[g + lane], (uint32_t)(xrows - 1)) : 0;
+    const float myval = lane < cnt ? val[g + lane] : 0.f;
+    int t = 0;
+    while (t < cnt) {
+      const int64_t e = g + t;
+      if (e >= rend) {   // row r is done
+        flush_row<CW>(Yr, ldyr, carry, c, r, continued, acc, lane, lp);
+#pragma unroll
+        for (int u = 0; u < kMaxCW; ++u) acc[u] = 0.f;
+        continued = false;
+        while (r + 1 < rows) {   // next row holding nonzero e
+          ++r;
+          rend = ptr[r + 1];
+          if (rend > e) break;
+        }
+      }
+      // nonzeros up to the row end (or this group's end), four at a time;
+      // malformed pointers (flagged by the input check) cannot stall the loop
+      const int run = (int)max<int64_t>(1, min<int64_t>(cnt - t, rend - e));
+      int s = 0;
+      for (; s + 4 <= run; s += 4) {
+        int32_t col[4];
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          col[q] = __builtin_amdgcn_readlane(mycol, t + s + q);
+          v[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myval), t + s + q));
+        }
+        float x[4][kMaxCW];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) {
+            const int cc = lane + 64 * u;
+            x[q][u] = cc < lp ? Xr[(int64_t)col[q] * ldxr + cc] : 0.f;
+          }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) acc[u] += v[q] * x[q][u];
+      }
+      for (; s < run; ++s) {
+        const int32_t col = __builtin_amdgcn_readlane(mycol, t + s);
+        const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myval), t + s));
+#pragma unroll
+        for (int u = 0; u < CW; ++u) {
+          const int cc = lane + 64 * u;
+          if (cc < lp) acc[u] += v * Xr[(int64_t)col * ldxr + cc];
+        }
+      }
+      t += run;
+    }
+  }
+  // the chunk's last row: complete, or the first part of a row that goes on
+  flush_row<CW>(Yr, ldyr, carry, c, r, continued, acc, lane, lp);
+}
+
+// For every row that continues into later chunks: add their carries in chunk
+// order.  Chunk c handles row first[c] when the row started inside chunk c-1.
+__global__ __launch_bounds__(256) void k_spmm_fixup(const int32_t* __restrict__ ptr,
+                                                    int64_t rows, const int32_t* __restrict__ first,
+                                                    int64_t chunks, const float* __restrict__ carry,
+                                                    int lp, float* __restrict__ Yr, int64_t ldyr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= chunks || c == 0) return;
+  // the row that owns chunk c's carry: the first non-empty row reaching past c C
+  int64_t r = first[c];
+  const int64_t e0 = c * kChunk;
+  while (ptr[r + 1] <= e0 && r + 1 < rows) ++r;
+  if (ptr[r] >= e0) return;                 // row starts in chunk c: no carry
+  if (ptr[r] < e0 - kChunk) return;         // row started before chunk c-1: handled earlier
+  for (int u = 0; u < kMaxCW; ++u) {
+    const int col = lane + 64 * u;
+    if (col >= lp) continue;
+    float s = Yr[r * ldyr + col];
+    for (int64_t c2 = c; c2 < chunks; ++c2) {
+      const int64_t f0 = c2 * kChunk;
+      if (c2 > c && f0 >= ptr[r + 1]) break;
+      s += carry[c2 * ldyr + col];
+    }
+    Yr[r * ldyr + col] = s;
+  }
+}
+
+// column-major panel (ld) -> row-major copy (rows x lp, ldr), 32 x 32 tiles
+__global__ __launch_bounds__(256) void k_to_rows(const float* __restrict__ P, int64_t ld,
+                                                 int64_t rows, int lp, float* __restrict__ R,
+                                                 int64_t ldr) {
+  __shared__ float t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of 32
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + tx;
+    const int c = c0 + k;
+    t[k][tx] = (r < rows && c < lp) ? P[(int64_t)c * ld + r] : 0.f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k;
+    const int c = c0 + tx;
+    if (r < rows && c < lp) R[r * ldr + c] = t[tx][k];
+  }
+}
+
+// row-major result (rows x lp) -> column-major panel (ld rows, padding rows
+// zero); rows without nonzeros are zero
+__global__ __launch_bounds__(256) void k_from_rows(const float* __restrict__ R, int64_t ldr,
+                                                   const int32_t* __restrict__ ptr, int64_t rows,
+                                                   int lp, float* __restrict__ P, int64_t ld) {
+  __shared__ float t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k;
+    const int c = c0 + tx;
+    float v = 0.f;
+    if (r < rows && c < lp && ptr[r + 1] > ptr[r]) v = R[r * ldr + c];
+    t[k][tx] = v;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + tx;
+    const int c = c0 + k;
+    if (r < ld && c < lp) P[(int64_t)c * ld + r] = t[tx][k];
+  }
+}
+
+// CSC build: keys = column, payload = (row << 32) | value bits
+__global__ void k_csc_keys(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                           const float* __restrict__ values, int64_t m, int64_t n, int64_t nnz,
+                           uint32_t* __restrict__ keys, uint64_t* __restrict__ payload) {
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (i >= m) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t lo = max<int64_t>(0, rowptr[i]), hi = min<int64_t>(nnz, rowptr[i + 1]);
+  for (int64_t e = lo + lane; e < hi; e += 64) {
+    keys[e] = min<uint32_t>((uint32_t)colind[e], (uint32_t)(n - 1));
+    payload[e] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)__builtin_bit_cast(uint32_t, values[e]);
+  }
+}
+
+__global__ void k_fill_keys(int64_t nnz, uint32_t key, uint32_t* __restrict__ keys,
+                            uint64_t* __restrict__ payload) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) {
+    keys[e] = key;
+    payload[e] = 0;
+  }
+}
+
+// Input check of a CSR matrix: pointers start at 0, end at nnz, never
+// decrease; column indices in [0, n).  Any violation sets the status word.
+__global__ void k_csr_check(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                            int64_t rows, int64_t cols, int64_t nnz, int32_t* __restrict__ status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (t <= rows) {
+    const int64_t p = ptr[t];
+    if (t == 0 && p != 0) bad = true;
+    if (t == rows && p != nnz) bad = true;
+    if (t < rows && ptr[t + 1] < p) bad = true;
+    if (p < 0 || p > nnz) bad = true;
+  }
+  for (int64_t e = t; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = idx[e];
+    if (j < 0 || j >= cols) bad = true;
+  }
+  if (bad) atomicOr(status + kStBadSparse, 1);
+}
+
+// column pointers from the sorted keys, then the row indices and values
+__global__ void k_csc_finish(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ payload,
+                             int64_t nnz, int64_t n, int32_t* __restrict__ colptr,
+                             int32_t* __restrict__ rowind, float* __restrict__ cval) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nnz) return;
+  if (e == nnz) {   // trailing empty columns (and n == 0 guard)
+    const int64_t last = nnz ? (int64_t)keys[nnz - 1] : -1;
+    for (int64_t j = last + 1; j <= n; ++j) colptr[j] = (int32_t)nnz;
+    return;
+  }
+  const int64_t k = keys[e];
+  const int64_t prev = e ? (int64_t)keys[e - 1] : -1;
+  for (int64_t j = prev + 1; j <= k; ++j) colptr[j] = (int32_t)e;
+  const uint64_t p = payload[e];
+  rowind[e] = (int32_t)(p >> 32);
+  cval[e] = __builtin_bit_cast(float, (uint32_t)(p & 0xffffffffu));
+}
+
+}  // namespace
+
+
+hipError_t launch_csr_check(const int32_t* ptr, const int32_t* idx, int64_t rows, int64_t cols,
+                            int64_t nnz, int32_t* status, hipStream_t s) {
+  const int64_t threads = std::max<int64_t>(rows + 1, 1);
+  hipLaunchKernelGGL(k_csr_check, dim3((unsigned)ceil_div_dev(threads, 256)), dim3(256), 0, s, ptr,
+                     idx, rows, cols, nnz, status);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const float* values,
+                            int64_t m, int64_t n, int64_t nnz, uint32_t* keys0, uint32_t* keys1,
+                            uint64_t* pay0, uint64_t* pay1, void* temp, size_t temp_bytes,
+                            int32_t* colptr, int32_t* rowind, float* cval, size_t* need,
+                            hipStream_t s) {
+  *need = 0;
+  if (nnz > 0) {
+    // entries no row covers (malformed pointers) keep defined keys
+    hipLaunchKernelGGL(k_fill_keys, dim3((unsigned)ceil_div_dev(nnz, 256)), dim3(256), 0, s, nnz,
+                       (uint32_t)(n - 1), keys0, pay0);
+    hipLaunchKernelGGL(k_csc_keys, dim3((unsigned)ceil_div_dev(m, 4)), dim3(256), 0, s, rowptr,
+                       colind, values, m, n, nnz, keys0, pay0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned bits = 1;
+    while (bits < 32 && (int64_t(1) << bits) < n) ++bits;
+    size_t want = 0;
+    e = rocprim::radix_sort_pairs(nullptr, want, keys0, keys1, pay0, pay1, (size_t)nnz, 0, bits, s);
+    if (e != hipSuccess) return e;
+    if (want > temp_bytes) {
+      *need = want;
+      return hipErrorOutOfMemory;
+    }
+    e = rocprim::radix_sort_pairs(temp, want, keys0, keys1, pay0, pay1, (size_t)nnz, 0, bits, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_csc_finish, dim3((unsigned)ceil_div_dev(nnz + 1, 256)), dim3(256), 0, s,
+                     keys1, pay1, nnz, n, colptr, rowind, cval);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val, int64_t rows,
+                       int64_t nnz, const float* X, int64_t ldx, int64_t xrows, int64_t lp,
+                       float* Xr, float* Yr, float* carry, int32_t* first, float* out,
+                       int64_t ldo, hipStream_t s) {
+  if (lp > 64 * kMaxCW) return hipErrorInvalidValue;
+  const int64_t chunks = spmm_chunk_count(nnz);
+  const int64_t ldr = lp;
+  dim3 gx((unsigned)ceil_div_dev(xrows, 32), (unsigned)ceil_div_dev(lp, 32));
+  hipLaunchKernelGGL(k_to_rows, gx, dim3(256), 0, s, X, ldx, xrows, (int)lp, Xr, ldr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)ceil_div_dev(chunks, 256)), dim3(256), 0, s,
+                       ptr, rows, nnz, chunks, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dim3 g((unsigned)ceil_div_dev(chunks, 4));
+    switch ((lp + 63) / 64) {
+      case 1: hipLaunchKernelGGL(k_spmm_chunk<1>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
+      case 2: hipLaunchKernelGGL(k_spmm_chunk<2>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
+      default: hipLaunchKernelGGL(k_spmm_chunk<3>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spmm_fixup, g, dim3(256), 0, s, ptr, rows, first, chunks, carry, (int)lp,
+                       Yr, ldr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  dim3 gy((unsigned)ceil_div_dev(ldo, 32), (unsigned)ceil_div_dev(lp, 32));
+  hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, rows, (int)lp, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

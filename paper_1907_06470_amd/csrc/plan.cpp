@@ -25,6 +25,10 @@ static rsvd_status fail(Plan& p, rsvd_status s, const char* fmt, long long a = 0
   return s;
 }
 
+int64_t spmm_chunk_count(int64_t nnz) { return std::max<int64_t>(1, ceil_div(nnz, kSpmmChunk)); }
+
+size_t csc_sort_scratch(int64_t nnz) { return (size_t)64 * 1024 * 1024 + (size_t)nnz * 4; }
+
 int64_t gram_chunks_for(const Plan& p, int64_t rows) {
   return std::max<int64_t>(1, ceil_div(rows, p.gram_rows));
 }
@@ -51,9 +55,20 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (k + pp > std::min(m, n))
     return fail(p, RSVD_E_INVALID_ARG, "k + p = %lld exceeds min(m, n) = %lld", k + pp,
                 std::min(m, n));
-  if (prob.format != RSVD_DENSE) {
-    if (prob.format == RSVD_CSR) return fail(p, RSVD_E_UNSUPPORTED, "CSR input is not implemented");
+  if (prob.format != RSVD_DENSE && prob.format != RSVD_CSR)
     return fail(p, RSVD_E_INVALID_ARG, "unknown format %lld", prob.format);
+  p.csr = prob.format == RSVD_CSR;
+  if (p.csr) {
+    if (prob.nnz < 0 || prob.nnz > 2147483647ll)
+      return fail(p, RSVD_E_INVALID_ARG, "nnz=%lld must be in [0, 2^31) (int32 indices)", prob.nnz);
+    if (prob.dtype != RSVD_F32)
+      return fail(p, RSVD_E_UNSUPPORTED, "CSR values must be FP32");
+    if (prob.loc != RSVD_LOC_DEVICE)
+      return fail(p, RSVD_E_UNSUPPORTED, "CSR input must be in device memory");
+    if (o.prec_sketch != RSVD_F32 || o.prec_power != RSVD_F32 || o.prec_project != RSVD_F32)
+      return fail(p, RSVD_E_UNSUPPORTED, "CSR products run in FP32");
+    if (o.flags & RSVD_FLAG_BACKWARD)
+      return fail(p, RSVD_E_UNSUPPORTED, "the adjoint needs dense A");
   }
   if (prob.dtype != RSVD_F32 && prob.dtype != RSVD_F64 && prob.dtype != RSVD_BF16) {
     if (prob.dtype == RSVD_FP8E4M3)
@@ -234,6 +249,26 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.slots = take((size_t)p.slots * p.slot_bytes);
   } else {
     w.slots = off;
+  }
+  if (p.csr) {
+    const size_t nnz = (size_t)prob.nnz, rows = (size_t)std::max(m, n);
+    p.chunks = spmm_chunk_count(prob.nnz);
+    w.colptr = take((size_t)(n + 1) * 4);
+    w.rowind = take(nnz * 4);
+    w.cval = take(nnz * 4);
+    w.keys0 = take(nnz * 4);
+    w.keys1 = take(nnz * 4);
+    w.pay0 = take(nnz * 8);
+    w.pay1 = take(nnz * 8);
+    p.sort_temp = csc_sort_scratch(prob.nnz);
+    w.sort_temp = take(p.sort_temp);
+    w.Xr = take(rows * lp * 4);
+    w.Yr = take(rows * lp * 4);
+    w.carry = take((size_t)p.chunks * lp * 4);
+    w.first = take((size_t)p.chunks * 4);
+  } else {
+    w.colptr = w.rowind = w.cval = w.keys0 = w.keys1 = w.pay0 = w.pay1 = w.sort_temp = off;
+    w.Xr = w.Yr = w.carry = w.first = off;
   }
   w.total = off;
 

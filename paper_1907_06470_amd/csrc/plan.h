@@ -17,6 +17,7 @@ constexpr int64_t kColAlign = 32;      // sketch width is padded to this
 constexpr int kGramBlock = 64;         // Gram output block edge
 constexpr int kJacobiMaxSweeps = 40;
 constexpr int kStatusWords = 64;
+constexpr int64_t kSpmmChunk = 2048;   // nonzeros per wave in the sparse products
 
 // Device status word indices (int32 array in the workspace).
 enum StatusWord {
@@ -26,6 +27,7 @@ enum StatusWord {
   kStRounds = 3,       // Jacobi rotation rounds logged
   kStRankSmall = 4,    // zero singular values in the small SVD
   kStTies = 5,         // equal singular-value pairs met by the adjoint
+  kStBadSparse = 6,    // malformed CSR input (pointers or column indices)
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -61,6 +63,9 @@ struct Workspace {
   size_t Sl;              // lp FP64 Ritz values
   size_t coreT, JuW, JvW, sinv;
   size_t slots;           // host-resident A: S tile slots of slot_bytes each
+  // CSR input: CSC copy, sort buffers, row-major operand/result, chunk carries
+  size_t colptr, rowind, cval, keys0, keys1, pay0, pay1, sort_temp;
+  size_t Xr, Yr, carry, first;
   size_t total;
 };
 
@@ -84,6 +89,9 @@ struct Plan {
   int64_t rcat = 0;             // columns of the outer-product factors
   bool backward = false;
   bool host = false;            // A in pinned host memory, streamed tile by tile
+  bool csr = false;             // A given as CSR (int32 indices, FP32 values)
+  int64_t chunks = 0;           // nonzero chunks of the sparse products
+  size_t sort_temp = 0;         // scratch reserved for the CSC sort
   int64_t slots = 0;            // HBM tile slots (host-resident A)
   int64_t slot_ld = 0;          // leading dimension (elements) of a slot
   size_t slot_bytes = 0;
@@ -103,5 +111,10 @@ inline int64_t gram_nb(const Plan& p) { return ceil_div(p.lp, kGramBlock); }
 inline int64_t gram_pairs(const Plan& p) { int64_t nb = gram_nb(p); return nb * (nb + 1) / 2; }
 
 rsvd_options default_options();
+
+// sparse products: nonzero chunks and the scratch reserved for the CSC sort
+// (host-side mirrors of the constants in k_sparse.hip)
+int64_t spmm_chunk_count(int64_t nnz);
+size_t csc_sort_scratch(int64_t nnz);
 
 }  // namespace rsvd

@@ -149,6 +149,11 @@ struct Buffers {
   uint8_t *A8, *A8T, *Xop8, *Mop8;
   float *sA8, *sX8, *sM8;
   char* slots;
+  int32_t *colptr, *rowind, *first;
+  float *cval, *Xr, *Yr, *carry;
+  uint32_t *keys0, *keys1;
+  uint64_t *pay0, *pay1;
+  void* sort_temp;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
@@ -180,6 +185,18 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.sX8 = (float*)(b + w.sX8);
   B.sM8 = (float*)(b + w.sM8);
   B.slots = b + w.slots;
+  B.colptr = (int32_t*)(b + w.colptr);
+  B.rowind = (int32_t*)(b + w.rowind);
+  B.first = (int32_t*)(b + w.first);
+  B.cval = (float*)(b + w.cval);
+  B.Xr = (float*)(b + w.Xr);
+  B.Yr = (float*)(b + w.Yr);
+  B.carry = (float*)(b + w.carry);
+  B.keys0 = (uint32_t*)(b + w.keys0);
+  B.keys1 = (uint32_t*)(b + w.keys1);
+  B.pay0 = (uint64_t*)(b + w.pay0);
+  B.pay1 = (uint64_t*)(b + w.pay1);
+  B.sort_temp = b + w.sort_temp;
   B.Pcat = (float*)(b + w.Pcat);
   B.Rcat = (float*)(b + w.Rcat);
   B.gUp = (float*)(b + w.gUp);
@@ -216,6 +233,9 @@ struct Runner {
   Events* ev = nullptr;        // non-null: time every product kernel
   std::vector<int> nn_idx, tn_idx;
   int next_pair = 0;
+  const int32_t* rowptr = nullptr;   // CSR input
+  const int32_t* colind = nullptr;
+  const float* values = nullptr;
   const char* Ahost = nullptr; // host-resident A (pinned), streamed tile by tile
   int64_t ldh = 0;
   Streamer* st8 = nullptr;
@@ -270,6 +290,26 @@ struct Runner {
     if (P.any_fp8)
       RSVD_HIP(rsvd::launch_cast_fp8(A, dt == RSVD_F64, lda, P.prob.m, P.prob.n, B.A8, P.lda8,
                                      B.A8T, P.ldat8, B.sA8, s));
+    return RSVD_OK;
+  }
+
+  // Sparse A: check the arrays (flag on the device) and build the CSC copy
+  // that applies A^T (stable sort of the nonzeros by column).
+  rsvd_status bind_csr(const int32_t* rp, const int32_t* ci, const float* v) {
+    rowptr = rp;
+    colind = ci;
+    values = v;
+    const int64_t m = P.prob.m, n = P.prob.n, nnz = P.prob.nnz;
+    RSVD_HIP(rsvd::launch_csr_check(rp, ci, m, n, nnz, B.status, s));
+    size_t need = 0;
+    const hipError_t e = rsvd::launch_build_csc(rp, ci, v, m, n, nnz, B.keys0, B.keys1, B.pay0,
+                                                B.pay1, B.sort_temp, P.sort_temp, B.colptr,
+                                                B.rowind, B.cval, &need, s);
+    if (e == hipErrorOutOfMemory && need > P.sort_temp)
+      return set_err(h, RSVD_E_BUDGET,
+                     "the CSC sort needs " + std::to_string(need) + " bytes of scratch, the plan "
+                     "reserved " + std::to_string(P.sort_temp));
+    RSVD_HIP(e);
     return RSVD_OK;
   }
 
@@ -368,6 +408,13 @@ struct Runner {
 
   rsvd_status product_nn(int32_t prec, const float* X, float* out) {
     if (P.host) return stream_pass(true, prec, X, out);
+    if (P.csr) {
+      RSVD_HIP(tick(true, true));
+      RSVD_HIP(rsvd::launch_spmm(rowptr, colind, values, P.prob.m, P.prob.nnz, X, P.ldn, P.prob.n,
+                                 P.lp, B.Xr, B.Yr, B.carry, B.first, out, P.ldm, s));
+      RSVD_HIP(tick(true, false));
+      return RSVD_OK;
+    }
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TJ > 1;
     const int64_t stride = split ? P.ldm * P.lp : 0;
@@ -390,6 +437,13 @@ struct Runner {
   // out (n-side panel) = A^T Q with Q the m-side operand (Mop and its copies)
   rsvd_status product_tn(int32_t prec, const float* Q, float* out) {
     if (P.host) return stream_pass(false, prec, Q, out);
+    if (P.csr) {
+      RSVD_HIP(tick(false, true));
+      RSVD_HIP(rsvd::launch_spmm(B.colptr, B.rowind, B.cval, P.prob.n, P.prob.nnz, Q, P.ldm,
+                                 P.prob.m, P.lp, B.Xr, B.Yr, B.carry, B.first, out, P.ldn, s));
+      RSVD_HIP(tick(false, false));
+      return RSVD_OK;
+    }
     const int64_t m = P.prob.m, n = P.prob.n;
     const bool split = P.TI > 1;
     const int64_t stride = split ? P.ldn * P.lp : 0;
@@ -594,10 +648,55 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
     report->h2d_bytes = R.st8->h2d_bytes;
     report->tile_loads = R.st8->loads;
   }
+  if (P.csr) {
+    report->flops_alg = passes * 2.0 * (double)P.prob.nnz * (double)P.l;
+    report->bytes_alg = passes * ((double)P.prob.nnz * 8.0 + ((double)m + (double)n) * P.l * 4.0);
+  }
+  if (stw[rsvd::kStBadSparse] > 0)
+    return set_err(h, RSVD_E_INVALID_ARG, "malformed CSR input (pointers or column indices)");
   if (stw[rsvd::kStNonFinite] > 0) return set_err(h, RSVD_E_NUMERIC, "NaN or Inf met on the device");
   if (stw[rsvd::kStTies] > 0) return RSVD_W_DEGENERATE;
   if (stw[rsvd::kStDropped] > 0 || stw[rsvd::kStRankSmall] > 0) return RSVD_W_RANK_DEFICIENT;
   return RSVD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The whole path after A has been bound (dense or sparse).
+template <typename Bind>
+rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t ldu, double* S,
+                          float* V, int64_t ldv, void* stream, rsvd_report* report) {
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k;
+  if (!U || !S || !V) return set_err(h, RSVD_E_INVALID_ARG, "U, S and V must be non-NULL");
+  if (ldu < m || ldv < n) return set_err(h, RSVD_E_INVALID_ARG, "ldu < m or ldv < n");
+
+  hipStream_t s = (hipStream_t)stream;
+  Runner R(h, ws, s);
+  Events* ev = nullptr;
+  if (report) {
+    rsvd_status est;
+    if (!(ev = plan_events(h, est))) return est;
+    R.ev = ev;
+  }
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev->ev[i], s) : hipSuccess; };
+  rsvd_status st;
+
+  RSVD_HIP(mark(0));
+  RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
+  if ((st = bind(R))) return st;
+  if ((st = R.forward(mark, S, k))) return st;
+  // step 7: U = Q E_k (W), V = B^T E_k S^-1 (W2)
+  RSVD_HIP(rsvd::launch_apply(R.B.Mop, P.ldm, m, P.l, R.B.W, P.lp, P.lp, k, false, U, ldu, m, s));
+  RSVD_HIP(rsvd::launch_apply(R.B.N0, P.ldn, n, P.l, R.B.W2, P.lp, P.lp, k, false, V, ldv, n, s));
+  if (!(P.opt.flags & RSVD_FLAG_NO_SIGN_FIX))
+    RSVD_HIP(rsvd::launch_sign_fix(U, ldu, m, V, ldv, n, k, R.B.signs, s));
+  RSVD_HIP(mark(8));
+
+  if (!report) return RSVD_OK;
+  return finish_report(h, R, ev, report);
 }
 
 }  // namespace
@@ -715,42 +814,63 @@ rsvd_status rsvd_omega(uint64_t seed, int64_t n, int64_t l, int64_t row0, int64_
 rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, float* U, int64_t ldu,
                         double* S, float* V, int64_t ldv, void* stream, rsvd_report* report) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "the plan is for CSR input: use rsvd_factor_csr");
   if (rsvd_status st = check_A(h, A, lda)) return st;
   if (rsvd_status st = check_ws(h, ws)) return st;
-  const rsvd::Plan& P = h->p;
-  const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k;
-  if (!U || !S || !V) return set_err(h, RSVD_E_INVALID_ARG, "U, S and V must be non-NULL");
-  if (ldu < m || ldv < n) return set_err(h, RSVD_E_INVALID_ARG, "ldu < m or ldv < n");
+  return factor_common(h, [&](Runner& R) { return R.bind_A(A, lda); }, ws, U, ldu, S, V, ldv,
+                       stream, report);
+}
 
+rsvd_status rsvd_factor_csr(rsvd_plan_t h, const int32_t* rowptr, const int32_t* colind,
+                            const float* values, void* ws, float* U, int64_t ldu, double* S,
+                            float* V, int64_t ldv, void* stream, rsvd_report* report) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "the plan is for dense input: use rsvd_factor");
+  if (!rowptr || (h->p.prob.nnz > 0 && (!colind || !values)))
+    return set_err(h, RSVD_E_INVALID_ARG, "CSR arrays must be non-NULL");
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  return factor_common(h, [&](Runner& R) { return R.bind_csr(rowptr, colind, values); }, ws, U, ldu,
+                       S, V, ldv, stream, report);
+}
+
+rsvd_status rsvd_step_spmm(rsvd_plan_t h, int32_t op, const int32_t* rowptr, const int32_t* colind,
+                           const float* values, const float* X, int64_t ldx, float* out,
+                           int64_t ldo, void* ws, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "the plan is for dense input");
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const rsvd::Plan& P = h->p;
+  const int64_t m = P.prob.m, n = P.prob.n;
+  if (op != 0 && op != 1) return set_err(h, RSVD_E_INVALID_ARG, "op must be 0 or 1");
+  const int64_t in_rows = op == 0 ? n : m, out_rows = op == 0 ? m : n;
+  if (!rowptr || !X || !out || ldx < in_rows || ldo < out_rows ||
+      (P.prob.nnz > 0 && (!colind || !values)))
+    return set_err(h, RSVD_E_INVALID_ARG, "bad arguments");
   hipStream_t s = (hipStream_t)stream;
   Runner R(h, ws, s);
-  Events* ev = nullptr;
-  if (report) {
-    rsvd_status est;
-    if (!(ev = plan_events(h, est))) return est;
-    R.ev = ev;
-  }
-  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev->ev[i], s) : hipSuccess; };
   rsvd_status st;
-
-  RSVD_HIP(mark(0));
   RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
-  if ((st = R.bind_A(A, lda))) return st;
-  if ((st = R.forward(mark, S, k))) return st;
-  // step 7: U = Q E_k (W), V = B^T E_k S^-1 (W2)
-  RSVD_HIP(rsvd::launch_apply(R.B.Mop, P.ldm, m, P.l, R.B.W, P.lp, P.lp, k, false, U, ldu, m, s));
-  RSVD_HIP(rsvd::launch_apply(R.B.N0, P.ldn, n, P.l, R.B.W2, P.lp, P.lp, k, false, V, ldv, n, s));
-  if (!(P.opt.flags & RSVD_FLAG_NO_SIGN_FIX))
-    RSVD_HIP(rsvd::launch_sign_fix(U, ldu, m, V, ldv, n, k, R.B.signs, s));
-  RSVD_HIP(mark(8));
-
-  if (!report) return RSVD_OK;
-  return finish_report(h, R, ev, report);
+  if ((st = R.bind_csr(rowptr, colind, values))) return st;
+  if (op == 0) {
+    RSVD_HIP(rsvd::launch_panel_copy(X, ldx, n, P.l, R.B.Xop, P.ldn, P.ldn, P.lp, s));
+    if ((st = R.product_nn(RSVD_F32, R.B.Xop, R.B.M0))) return st;
+    RSVD_HIP(rsvd::launch_panel_copy(R.B.M0, P.ldm, m, P.l, out, ldo, m, P.l, s));
+  } else {
+    RSVD_HIP(rsvd::launch_panel_copy(X, ldx, m, P.l, R.B.Mop, P.ldm, P.ldm, P.lp, s));
+    if ((st = R.product_tn(RSVD_F32, R.B.Mop, R.B.N0))) return st;
+    RSVD_HIP(rsvd::launch_panel_copy(R.B.N0, P.ldn, n, P.l, out, ldo, n, P.l, s));
+  }
+  int32_t bad = 0;
+  RSVD_HIP(hipMemcpyAsync(&bad, R.B.status + rsvd::kStBadSparse, 4, hipMemcpyDeviceToHost, s));
+  RSVD_HIP(hipStreamSynchronize(s));
+  if (bad) return set_err(h, RSVD_E_INVALID_ARG, "malformed CSR input (pointers or column indices)");
+  return RSVD_OK;
 }
 
 rsvd_status rsvd_step_product(rsvd_plan_t h, int32_t op, const void* A, int64_t lda, const float* X,
                               int64_t ldx, float* out, int64_t ldo, void* ws, void* stream) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "this call needs dense A (plan is for CSR)");
   if (h->p.host)
     return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;
@@ -843,6 +963,7 @@ rsvd_status rsvd_backward(rsvd_plan_t h, const void* A, int64_t lda, const float
                           int64_t ldgu, const double* gS, const float* gV, int64_t ldgv,
                           float* gA, int64_t ldga, void* ws, void* stream, rsvd_report* report) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "this call needs dense A (plan is for CSR)");
   if (h->p.host)
     return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;
@@ -918,6 +1039,7 @@ rsvd_status rsvd_residual(rsvd_plan_t h, const void* A, int64_t lda, const float
                           const double* S, const float* V, int64_t ldv, double* out, void* ws,
                           void* stream) {
   if (rsvd_status st = check_plan(h)) return st;
+  if (h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "this call needs dense A (plan is for CSR)");
   if (h->p.host)
     return set_err(h, RSVD_E_UNSUPPORTED, "this call needs A in device memory (plan is host-resident)");
   if (rsvd_status st = check_A(h, A, lda)) return st;

@@ -73,11 +73,22 @@ def test_plan_budget_error_names_the_bytes():
 
 
 def test_plan_unsupported_combinations():
-    prob = L.Problem(m=100, n=80, k=5, p=5, q=1, format=L.CSR, dtype=L.F32, loc=L.LOC_DEVICE,
-                     seed=0)
+    prob = L.Problem(m=100, n=80, k=5, p=5, q=1, format=L.CSR, dtype=L.F64, loc=L.LOC_DEVICE,
+                     seed=0, nnz=400)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
     assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
+    prob.dtype = L.F32
+    prob.loc = L.LOC_HOST_PINNED          # sparse input lives on the device
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_UNSUPPORTED
+    prob.loc = L.LOC_DEVICE
+    prob.nnz = -1
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
+    prob.nnz = 1 << 31                     # int32 indices
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.E_INVALID_ARG
+    prob.nnz = 400
+    assert L.lib().rsvd_plan(ctypes.byref(prob), None, ctypes.byref(h), ctypes.byref(ws)) == L.OK
+    L.lib().rsvd_plan_destroy(h)
     prob.format = L.DENSE
     prob.loc = L.LOC_HOST_PINNED
     prob.dtype = L.F64            # streamed tiles are FP32 or BF16

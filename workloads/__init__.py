@@ -23,6 +23,13 @@ Named recipes (sizes, spectra, seeds):
                  k = 128, p = 32, q = 3
   fd             256 x 128, sigma_i = i^-0.5 (i <= 128), noise 1e-4, seeds
                  100..104, k = 16, p = 112, q = 3
+  ooc            200000 x 100000 (run at half scale), sigma_i = i^-0.8 (i <= 500),
+                 noise 1e-5, FP32, seed 3, in pinned host memory, 16 GB HBM budget
+  sparse         zipf_csr: 2e6 x 5e5, exactly 50 distinct columns per row drawn
+                 Zipf(1.1) over ranks 1..n (duplicates redrawn), column =
+                 perm(rank - 1) with a seeded permutation, sorted within rows,
+                 values log(1 + c), c ~ Poisson(3) + 1; FP32 values, int32
+                 indices, seed 4 (the paper's SuiteSparse inputs are absent)
 Scaled-down variants keep the spectrum law and noise and shrink m, n.
 """
 
@@ -113,6 +120,40 @@ def make(name, device="cpu", scale=1.0, out_dtype=None):
     return A, meta
 
 
+def zipf_csr(m, n, per_row, s=1.1, seed=4, device="cpu", draws=None):
+    """CSR (rowptr int32 [m + 1], colind int32 [nnz], values float32 [nnz])
+    with exactly per_row distinct columns in every row; see the module
+    docstring for the distribution."""
+    g = _gen(seed, device)
+    draws = draws or max(2 * per_row, per_row + 64)
+    ranks = torch.arange(1, n + 1, device=device, dtype=torch.float64)
+    cdf = torch.cumsum(ranks ** (-float(s)), 0)
+    cdf /= cdf[-1].clone()
+    perm = torch.randperm(n, generator=g, device=device)
+    cols = torch.empty(m, per_row, dtype=torch.int64, device=device)
+    todo = torch.arange(m, device=device)
+    while todo.numel():
+        u = torch.rand(todo.numel(), draws, generator=g, device=device, dtype=torch.float64)
+        r = torch.searchsorted(cdf, u).clamp_(max=n - 1)          # rank - 1
+        srt, order = torch.sort(r, dim=1, stable=True)
+        first = torch.ones_like(srt, dtype=torch.bool)
+        first[:, 1:] = srt[:, 1:] != srt[:, :-1]
+        # keep the first occurrence of each rank, in draw order
+        pos = torch.where(first, order, torch.full_like(order, draws))
+        pos_sorted, _ = torch.sort(pos, dim=1)
+        ok = pos_sorted[:, per_row - 1] < draws
+        keep = pos_sorted[ok][:, :per_row]
+        picked = torch.gather(r[ok], 1, keep)
+        cols[todo[ok]] = perm[picked]
+        todo = todo[~ok]
+    cols, _ = torch.sort(cols, dim=1)
+    c = torch.poisson(torch.full((m, per_row), 3.0, device=device, dtype=torch.float64),
+                      generator=g) + 1.0
+    values = torch.log1p(c).to(torch.float32).reshape(-1)
+    rowptr = (torch.arange(m + 1, device=device, dtype=torch.int64) * per_row).to(torch.int32)
+    return rowptr, cols.reshape(-1).to(torch.int32), values
+
+
 def fd_instance(seed, m=256, n=128, noise=1e-4, device="cpu"):
     sigma = spectrum_pow(min(m, n), 0.5)
     return dense_lowrank(m, n, sigma, noise, seed, device=device, out_dtype=torch.float64)
@@ -126,5 +167,5 @@ def ceil_div(a, b):
     return -(-a // b)
 
 
-__all__ = ["dense_lowrank", "haar_columns", "make", "fd_instance",
+__all__ = ["dense_lowrank", "haar_columns", "make", "fd_instance", "zipf_csr",
            "RECIPES", "recipe_sigma", "spectrum_exp", "spectrum_pow", "math"]
