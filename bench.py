@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--forms", default="fp32,bf16,fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="dense", choices=["dense", "ooc"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "ooc", "sparse"],
                     help="dense: the headline GPU-resident workload; ooc: A in pinned host "
                          "memory streamed through a 16 GB HBM budget (a separate line)")
     ap.add_argument("--ooc-scale", type=float, default=0.5,
@@ -102,6 +102,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "ooc":
         return bench_ooc(args, dev)
+    if args.workload == "sparse":
+        return bench_sparse(args, dev)
     W = WORKLOAD
     m, n, k, p, q = W["m"], W["n"], W["k"], W["p"], W["q"]
     l = k + p
@@ -192,6 +194,56 @@ def main():
                        for kk, vv in f.items()} for kf, f in forms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sparse(args, dev):
+    """Sparse line: CSR 2e6 x 5e5 with 50 Zipf(1.1) columns per row (1e8
+    nonzeros), FP32 values; HBM-bound sparse products."""
+    import workloads
+    from paper_1907_06470_amd import Plan
+    m, n, per_row = 2_000_000, 500_000, 50
+    k, p, q = 160, 30, 3      # sketch widths above 192 are not implemented (the recipe has l = 330)
+    l = k + p
+    t = time.time()
+    rp, ci, v = workloads.zipf_csr(m, n, per_row, seed=4, device=dev)
+    torch.cuda.synchronize()
+    nnz = int(ci.numel())
+    log(f"generated CSR {m}x{n}, {nnz} nonzeros on the GPU in {time.time() - t:.1f} s")
+    plan = Plan(m, n, k, p, q, nnz=nnz)
+    ws = plan.workspace(dev)
+    for _ in range(args.warmup):
+        plan.factor_csr(rp, ci, v, ws=ws)
+    torch.cuda.synchronize()
+    infos, t0 = [], time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(plan.factor_csr(rp, ci, v, ws=ws)[3])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    nn_ms = float(np.mean([i["gemm_nn_ms"] / max(1, i["gemm_nn_launches"]) for i in infos]))
+    tn_ms = float(np.mean([i["gemm_tn_ms"] / max(1, i["gemm_tn_launches"]) for i in infos]))
+    # algorithmic bytes of one A X product: CSR arrays + X once + Y once (FP32)
+    alg = nnz * 8 + (m + 1) * 4 + n * l * 4 + m * l * 4
+    gbs = alg / (nn_ms * 1e-3) / 1e9
+    log(f"sparse: {ms:.2f} ms/rSVD, A X {nn_ms:.3f} ms ({gbs:.0f} GB/s algorithmic), "
+        f"A^T Q {tn_ms:.3f} ms, stages {[round(x, 3) for x in infos[-1]['stage_ms']]}")
+    line = {
+        "metric": "sparse rSVD wall time and A X product GB/s (algorithmic bytes)",
+        "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sparse CSR {m}x{n}, {nnz} nonzeros (50 distinct Zipf(1.1) "
+                               f"columns per row), k={k} p={p} q={q}",
+                   "m": m, "n": n, "nnz": nnz, "k": k, "p": p, "q": q,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"],
+                     "unit": "GB/s", "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": None,
+                     "kernel": "k_spmm_chunk (A X, CSR)",
+                     "per_launch": f"CSR {nnz * 8 + (m + 1) * 4} B + X {n}x{l} fp32 + Y {m}x{l} fp32 = {alg} bytes"},
+        "nn_ms": round(nn_ms, 4), "tn_ms": round(tn_ms, 4),
+        "stage_ms": [round(float(x), 3) for x in np.mean([i["stage_ms"] for i in infos], axis=0)],
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -306,18 +306,25 @@ hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const 
     if (e != hipSuccess) return e;
     unsigned bits = 1;
     while (bits < 32 && (int64_t(1) << bits) < n) ++bits;
+    // ping-pong buffers owned by the workspace: the sort's own scratch is
+    // only its histograms and look-back state
+    rocprim::double_buffer<uint32_t> kb(keys0, keys1);
+    rocprim::double_buffer<uint64_t> vb(pay0, pay1);
     size_t want = 0;
-    e = rocprim::radix_sort_pairs(nullptr, want, keys0, keys1, pay0, pay1, (size_t)nnz, 0, bits, s);
+    e = rocprim::radix_sort_pairs(nullptr, want, kb, vb, (size_t)nnz, 0, bits, s);
     if (e != hipSuccess) return e;
     if (want > temp_bytes) {
       *need = want;
       return hipErrorOutOfMemory;
     }
-    e = rocprim::radix_sort_pairs(temp, want, keys0, keys1, pay0, pay1, (size_t)nnz, 0, bits, s);
+    e = rocprim::radix_sort_pairs(temp, want, kb, vb, (size_t)nnz, 0, bits, s);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csc_finish, dim3((unsigned)ceil_div_dev(nnz + 1, 256)), dim3(256), 0, s,
+                       kb.current(), vb.current(), nnz, n, colptr, rowind, cval);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_csc_finish, dim3((unsigned)ceil_div_dev(nnz + 1, 256)), dim3(256), 0, s,
-                     keys1, pay1, nnz, n, colptr, rowind, cval);
+  hipLaunchKernelGGL(k_csc_finish, dim3(1), dim3(256), 0, s, keys1, pay1, nnz, n, colptr, rowind,
+                     cval);
   return hipGetLastError();
 }
 
