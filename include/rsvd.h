@@ -59,7 +59,8 @@ enum { RSVD_ORTHO_EACH = 0, RSVD_ORTHO_FINAL_ONLY = 2 };             /* schedule
 enum {
   RSVD_FLAG_NO_SIGN_FIX = 1,   /* skip the sign convention                          */
   RSVD_FLAG_CHOLQR1 = 2,       /* one CholeskyQR pass for intermediate bases        */
-  RSVD_FLAG_BACKWARD = 4       /* size the workspace for rsvd_backward too          */
+  RSVD_FLAG_BACKWARD = 4,      /* size the workspace for rsvd_backward too          */
+  RSVD_FLAG_AUTO_Q = 8         /* choose q <= prob.q automatically (q_tol)          */
 };
 
 /* The problem: A is m x n, rank k, oversampling p, q power steps
@@ -92,6 +93,13 @@ typedef struct {
   uint64_t hbm_budget_bytes;
   int32_t flags;
   int32_t reserved;
+  /* RSVD_FLAG_AUTO_Q (Section 2.2, automatic iteration parameter): after
+   * each product A^T Q the singular values the factorisation would return
+   * for the q reached so far are computed; the loop stops at the first q
+   * whose leading k values moved by at most q_tol (relative) from those of
+   * q - 1, or at prob.q.  0 means 1e-4.  Needs prec_power == prec_project;
+   * each step then waits for the device once. */
+  double q_tol;
 } rsvd_options;
 
 /* Stage timers follow the paper's stage list (Section 4.1): 0 Gaussian O,
@@ -115,6 +123,9 @@ typedef struct {
   int32_t slots;           /* host-resident A: HBM tile slots               */
   double h2d_bytes;        /* host-resident A: bytes copied host -> device  */
   int64_t tile_loads;      /* host-resident A: tiles copied                 */
+  int32_t q_used;          /* power steps run (RSVD_FLAG_AUTO_Q: chosen)    */
+  int32_t reserved2;
+  double q_delta;          /* last relative change of the leading k values  */
 } rsvd_report;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;

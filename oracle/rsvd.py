@@ -117,3 +117,40 @@ def rsvd(A, k, p, q, seed=0, ortho="each", signs=True, full=False):
     if full:
         out.update({"Q": Q, "Bt": Bt, "Ul": Ul, "Sl": s, "Vl": Vf})
     return out
+
+
+def rsvd_auto_q(A, k, p, q_max, tol=1e-4, seed=0):
+    """Randomized SVD with the iteration parameter chosen automatically
+    (Section 2.2: the decay of the singular values is measured for increasing
+    q and q stops growing once accuracy no longer improves).
+
+    Reading taken: after t power steps the projection B_t^T = A^T Q_t gives
+    the singular values s^(t) the factorisation returns with q = t; the first
+    t >= 1 with max_{i<k} |s_i^(t) - s_i^(t-1)| / s_i^(t) <= tol is chosen
+    (q_max if none).  Returns the rsvd() dict for that q plus "q_used" and
+    "deltas" (the relative changes, one per t >= 1).
+    """
+    m, n = A.shape
+    _check(m, n, k, p, q_max)
+    l = k + p
+    O = philox.omega(seed, n, l)
+    Q = _orth(np.asarray(A @ O, dtype=np.float64))
+    prev, deltas = None, []
+    t = 0
+    while True:
+        Bt = np.asarray(A.T @ Q, dtype=np.float64)
+        Ub, s, Vf = small_svd(Bt)
+        if prev is not None:
+            sk, pk = s[:k], prev[:k]
+            rel = np.where(sk > 0, np.abs(sk - pk) / np.where(sk > 0, sk, 1.0),
+                           np.where(pk != 0, 1.0, 0.0))
+            deltas.append(float(np.max(rel)))
+        if t == q_max or (deltas and deltas[-1] <= tol):
+            break
+        prev = s
+        Qw = _orth(Bt)
+        Q = _orth(np.asarray(A @ Qw, dtype=np.float64))
+        t += 1
+    Ul, Vf = sign_fix(Q @ Ub, Vf)
+    return {"U": Ul[:, :k].copy(), "S": s[:k].copy(), "V": Vf[:, :k].copy(), "q_used": t,
+            "deltas": deltas}

@@ -25,7 +25,7 @@ DENSE, CSR = 0, 1
 F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
 LOC_DEVICE, LOC_HOST_PINNED = 0, 1
 ORTHO_EACH, ORTHO_FINAL_ONLY = 0, 2
-FLAG_NO_SIGN_FIX, FLAG_CHOLQR1, FLAG_BACKWARD = 1, 2, 4
+FLAG_NO_SIGN_FIX, FLAG_CHOLQR1, FLAG_BACKWARD, FLAG_AUTO_Q = 1, 2, 4, 8
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 c_vp, c_sz = ctypes.c_void_p, ctypes.c_size_t
@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("prec_sketch", c_i32), ("prec_power", c_i32), ("prec_project", c_i32),
                 ("ortho", c_i32), ("tile_m", c_i64), ("tile_n", c_i64), ("grid_p", c_i64),
                 ("grid_q", c_i64), ("hbm_budget_bytes", c_u64), ("flags", c_i32),
-                ("reserved", c_i32)]
+                ("reserved", c_i32), ("q_tol", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -50,7 +50,8 @@ class Report(ctypes.Structure):
                 ("gemm_nn_ms", ctypes.c_double), ("gemm_tn_ms", ctypes.c_double),
                 ("ws_bytes", c_i64), ("gemm_nn_launches", c_i32), ("gemm_tn_launches", c_i32),
                 ("dropped", c_i32), ("jacobi_sweeps", c_i32), ("nonfinite", c_i32),
-                ("slots", c_i32), ("h2d_bytes", ctypes.c_double), ("tile_loads", c_i64)]
+                ("slots", c_i32), ("h2d_bytes", ctypes.c_double), ("tile_loads", c_i64),
+                ("q_used", c_i32), ("reserved2", c_i32), ("q_delta", ctypes.c_double)]
 
 
 _P = ctypes.POINTER

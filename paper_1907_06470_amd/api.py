@@ -61,13 +61,18 @@ class Plan:
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
                  tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False,
-                 nnz=None):
+                 nnz=None, auto_q=False, q_tol=0.0):
         """host=True: A stays in pinned host memory and is streamed to the
         device tile by tile on every pass (hbm_budget bounds the slots).
         nnz: A is sparse (CSR with int32 indices, FP32 values) with nnz
-        nonzeros; use factor_csr / factor with a sparse CSR tensor."""
+        nonzeros; use factor_csr / factor with a sparse CSR tensor.
+        auto_q: q is a maximum; the power iteration stops once the leading k
+        singular values change by at most q_tol (relative) from one q to the
+        next (Section 2.2); info["q_used"] reports the q chosen."""
         if backward:
             flags |= L.FLAG_BACKWARD
+        if auto_q:
+            flags |= L.FLAG_AUTO_Q
         prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE if nnz is None else L.CSR,
                          dtype=_DT.get(dtype, -99),
                          loc=L.LOC_HOST_PINNED if host else L.LOC_DEVICE, reserved=0, seed=seed,
@@ -80,7 +85,8 @@ class Plan:
         tm, tn = (tile if tile is not None else (0, 0))
         opt = L.Options(prec_sketch=ps, prec_power=pw, prec_project=pj, ortho=L.ORTHO_EACH,
                         tile_m=tm, tile_n=tn, grid_p=grid[0], grid_q=grid[1],
-                        hbm_budget_bytes=int(hbm_budget), flags=flags, reserved=0)
+                        hbm_budget_bytes=int(hbm_budget), flags=flags, reserved=0,
+                        q_tol=float(q_tol))
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         st = L.lib().rsvd_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h),
@@ -153,7 +159,8 @@ class Plan:
                         gemm_tn_launches=rep.gemm_tn_launches,
                         ws_bytes=rep.ws_bytes, dropped=rep.dropped,
                         jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite,
-                        slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads)
+                        slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads,
+                        q_used=rep.q_used, q_delta=rep.q_delta)
         return U, S, V, info
 
     def backward(self, A, gU=None, gS=None, gV=None, ws=None, stream=None, report=True):
@@ -218,7 +225,8 @@ class Plan:
                         gemm_nn_ms=rep.gemm_nn_ms, gemm_tn_ms=rep.gemm_tn_ms,
                         gemm_nn_launches=rep.gemm_nn_launches,
                         gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
-                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps)
+                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps,
+                        q_used=rep.q_used, q_delta=rep.q_delta)
         return U, S, V, info
 
     def step_spmm(self, op, rowptr, colind, values, X, ws=None, stream=None):

@@ -877,6 +877,30 @@ __global__ __launch_bounds__(kVecRows * 64) void k_jacobi_vecs(const double* __r
     for (int x = lane; x < lp; x += 64) Ev[(int64_t)r * lp + x] = (r < l && x < l) ? rowv[w][x] : 0.0;
 }
 
+// Automatic iteration parameter: largest relative change of the k leading
+// singular values from the previous power step (prev[k] receives it; +inf on
+// the first step), then prev = S.
+__global__ __launch_bounds__(256) void k_ritz_delta(const double* __restrict__ S, int k, int first,
+                                                    double* __restrict__ prev) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double d = 0.0;
+  for (int i = tid; i < k; i += 256) {
+    const double a = S[i], b = prev[i];
+    if (a > 0.0) d = fmax(d, fabs(a - b) / a);
+    else if (b != 0.0) d = fmax(d, 1.0);
+    if (!(a == a)) d = __builtin_inf();
+  }
+  red[tid] = d;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  for (int i = tid; i < k; i += 256) prev[i] = S[i];
+  if (tid == 0) prev[k] = first ? __builtin_inf() : red[0];
+}
+
 // Sort eigenvalues descending (ties by index), S = sqrt(lambda) for the first
 // k, Wu(a, c) = Ev(a, order c), Wv(a, c) = Wu(a, c) / sigma_c (0 if sigma_c is
 // negligible), both lp x lp row-major FP32 with zero columns from k on.
@@ -1084,6 +1108,12 @@ hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, 
   if (lp > kMaxLp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finish_small, dim3(1), dim3(256), 0, s, lam, Ev, lp, (int)l, (int)k, S, Wu,
                      Wv, order, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* prev,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_ritz_delta, dim3(1), dim3(256), 0, s, S, (int)k, first ? 1 : 0, prev);
   return hipGetLastError();
 }
 

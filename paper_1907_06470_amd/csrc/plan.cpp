@@ -113,8 +113,19 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (o.tile_m < 0 || o.tile_n < 0 || o.tile_m % 32 || o.tile_n % 32)
     return fail(p, RSVD_E_INVALID_ARG, "tile sizes %lld x %lld must be >= 0 and multiples of 32",
                 o.tile_m, o.tile_n);
-  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1 | RSVD_FLAG_BACKWARD))
+  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1 | RSVD_FLAG_BACKWARD | RSVD_FLAG_AUTO_Q))
     return fail(p, RSVD_E_INVALID_ARG, "unknown flags 0x%llx", o.flags);
+  p.auto_q = (o.flags & RSVD_FLAG_AUTO_Q) != 0;
+  if (p.auto_q) {
+    if (!(o.q_tol >= 0.0) || o.q_tol >= 1.0)
+      return fail(p, RSVD_E_INVALID_ARG, "q_tol must be in [0, 1)");
+    if (o.prec_power != o.prec_project)
+      return fail(p, RSVD_E_INVALID_ARG, "automatic q needs the same precision for the power steps "
+                                          "and the projection");
+    if (o.flags & RSVD_FLAG_BACKWARD)
+      return fail(p, RSVD_E_UNSUPPORTED, "automatic q with the adjoint is not implemented");
+    p.q_tol = o.q_tol > 0.0 ? o.q_tol : 1e-4;
+  }
 
   p.l = k + pp;
   p.lp = round_up(p.l, kColAlign);
@@ -196,6 +207,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.rot = take((size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8);
   w.signs = take(lp * 4);
   w.status = take(kStatusWords * 4);
+  w.prevS = take((size_t)k * 8 + 8);
   p.ldac = round_up(n, 64);
   p.lda16 = round_up(n, 64);
   w.Acast = (prob.dtype == RSVD_F64 && p.any_f32) ? take((size_t)m * p.ldac * 4) : off;

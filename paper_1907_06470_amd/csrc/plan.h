@@ -50,6 +50,7 @@ struct Workspace {
   size_t rot;             // Jacobi rotation log (FP64 pairs)
   size_t signs;           // k int32 sign-fix argmax
   size_t status;          // kStatusWords int32
+  size_t prevS;           // automatic q: previous k singular values + change
   size_t Acast;           // FP32 copy of an FP64 A
   size_t A16;             // BF16 copy of A (when a product runs in BF16)
   size_t Xop16, Mop16;    // BF16 copies of the operand panels
@@ -90,6 +91,8 @@ struct Plan {
   bool backward = false;
   bool host = false;            // A in pinned host memory, streamed tile by tile
   bool csr = false;             // A given as CSR (int32 indices, FP32 values)
+  bool auto_q = false;          // choose q <= prob.q (RSVD_FLAG_AUTO_Q)
+  double q_tol = 0.0;
   int64_t chunks = 0;           // nonzero chunks of the sparse products
   size_t sort_temp = 0;         // scratch reserved for the CSC sort
   int64_t slots = 0;            // HBM tile slots (host-resident A)

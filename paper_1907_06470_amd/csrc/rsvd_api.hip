@@ -158,6 +158,7 @@ struct Buffers {
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
   int32_t *order, *signs, *status;
+  double* prevS;
 };
 
 Buffers carve(const rsvd::Plan& P, void* ws) {
@@ -217,6 +218,7 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.order = (int32_t*)(b + w.order);
   B.signs = (int32_t*)(b + w.signs);
   B.status = (int32_t*)(b + w.status);
+  B.prevS = (double*)(b + w.prevS);
   return B;
 }
 
@@ -240,6 +242,8 @@ struct Runner {
   int64_t ldh = 0;
   Streamer* st8 = nullptr;
   int64_t pass_no = 0;         // passes over A so far in this call
+  int64_t q_used = 0;          // power steps run
+  double q_delta = 0.0;        // automatic q: last relative change
 
   hipError_t tick(bool nn, bool start) {
     if (!ev) return hipSuccess;
@@ -509,6 +513,33 @@ struct Runner {
     if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;   // 3-4
     if ((st = prep(P.prob.q > 0 ? pw : pj, B.Mop, false))) return st;
     RSVD_HIP(mark(3));
+    if (P.auto_q) {
+      // Section 2.2, automatic iteration parameter: each product A^T Q_t is
+      // the projection B^T the factorisation would use with q = t; its small
+      // SVD gives the singular values for that q.  Stop at the first q whose
+      // leading k values moved by at most q_tol from q - 1 (or at prob.q),
+      // keeping that B^T and its small SVD.
+      for (int64_t t = 0;; ++t) {
+        if ((st = product_tn(pw, B.Mop, B.N0))) return st;
+        if ((st = small_svd_eig(B.N0))) return st;
+        if ((st = small_svd_solve(S, kout))) return st;
+        RSVD_HIP(rsvd::launch_ritz_delta(S, kout, t == 0, B.prevS, s));
+        double delta = 0.0;
+        RSVD_HIP(hipMemcpyAsync(&delta, B.prevS + kout, sizeof delta, hipMemcpyDeviceToHost, s));
+        RSVD_HIP(hipStreamSynchronize(s));
+        q_used = t;
+        q_delta = delta;
+        if (t == P.prob.q || (t > 0 && delta <= P.q_tol)) break;
+        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
+        if ((st = prep(pw, B.Xop, true))) return st;
+        if ((st = product_nn(pw, B.Xop, B.M0))) return st;
+        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, true))) return st;
+        if ((st = prep(pw, B.Mop, false))) return st;
+      }
+      for (int i = 4; i <= 7; ++i) RSVD_HIP(mark(i));
+      return RSVD_OK;
+    }
+    q_used = P.prob.q;
     for (int64_t t = 0; t < P.prob.q; ++t) {                                          // Eq. (2)
       const bool last = t + 1 == P.prob.q;
       if ((st = product_tn(pw, B.Mop, B.N0))) return st;
@@ -643,6 +674,8 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   report->dropped = stw[rsvd::kStDropped];
   report->jacobi_sweeps = stw[rsvd::kStSweeps];
   report->nonfinite = stw[rsvd::kStNonFinite];
+  report->q_used = (int32_t)R.q_used;
+  report->q_delta = R.q_delta;
   if (P.host && R.st8) {
     report->slots = (int32_t)P.slots;
     report->h2d_bytes = R.st8->h2d_bytes;

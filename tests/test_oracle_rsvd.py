@@ -116,3 +116,44 @@ def test_sign_convention():
     for i in range(3):
         j = np.argmax(np.abs(out["V"][:, i]))
         assert out["V"][j, i] > 0
+
+
+# ---- automatic iteration parameter (Section 2.2) ------------------------------
+from oracle.rsvd import rsvd_auto_q  # noqa: E402
+
+
+def _graded(m, n, decay, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.arange(1, n + 1, dtype=np.float64) ** (-decay)
+    return (U * s) @ V.T
+
+
+def test_auto_q_equals_fixed_q_at_the_chosen_q():
+    A = _graded(300, 120, 0.7, 1)
+    auto = rsvd_auto_q(A, 10, 5, 6, tol=1e-6)
+    fixed = rsvd(A, 10, 5, auto["q_used"])
+    assert 1 <= auto["q_used"] <= 6
+    for key in ("U", "S", "V"):
+        assert np.array_equal(auto[key], fixed[key])
+
+
+def test_auto_q_zero_tolerance_runs_to_the_maximum():
+    A = _graded(200, 90, 0.5, 2)
+    auto = rsvd_auto_q(A, 8, 4, 3, tol=0.0)
+    assert auto["q_used"] == 3 and len(auto["deltas"]) == 3
+    assert np.array_equal(auto["S"], rsvd(A, 8, 4, 3)["S"])
+
+
+def test_auto_q_follows_the_decay_of_the_spectrum():
+    # fast decay: the sketch already captures the top k, q stops at 1;
+    # slow decay: more steps before the values settle
+    fast = rsvd_auto_q(_graded(300, 150, 3.0, 3), 10, 10, 8, tol=1e-8)
+    slow = rsvd_auto_q(_graded(300, 150, 0.3, 3), 10, 10, 8, tol=1e-8)
+    assert fast["q_used"] < slow["q_used"]
+    # the singular values grow toward the exact ones as q increases
+    exact = np.linalg.svd(_graded(300, 150, 0.3, 3), compute_uv=False)[:10]
+    assert np.all(slow["S"] <= exact * (1 + 1e-12))
+    assert np.max(np.abs(slow["S"] - exact) / exact) < np.max(
+        np.abs(rsvd(_graded(300, 150, 0.3, 3), 10, 10, 0)["S"] - exact) / exact)
