@@ -36,6 +36,17 @@ __device__ inline uint4 ld8_masked(const u16* row, int64_t k, int64_t kend) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// Same, with a non-temporal hint for the full 16-byte case (A is streamed
+// once per pass; keeping it out of the way leaves the caches to the panel).
+__device__ inline uint4 ld8_masked_nt(const u16* row, int64_t k, int64_t kend) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  if (k + 8 <= kend) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(row + k));
+    return make_uint4(v[0], v[1], v[2], v[3]);
+  }
+  return ld8_masked(row, k, kend);
+}
+
 __device__ inline void store_acc16(float* out, int64_t ld, int64_t row_base, int col,
                                    const f32x16& acc, int half) {
 #pragma unroll
@@ -127,13 +138,130 @@ __global__ __launch_bounds__(256) void k_nn_bf16(const u16* __restrict__ A, int6
       store_acc16(Yp, ldy, i0 + wave * WR + a * 32, t * 32 + l32, acc[a][t], half);
 }
 
+// Square wave tiles: the 128 x 128 output block of a workgroup is split 2 x 2
+// over the waves (64 rows x 64 panel columns each), so a wave reads 64 rows
+// of A and 64 columns of the panel from LDS per slab instead of 32 rows and
+// all 128 columns.  One LDS stage (37 KB, several workgroups per CU); the
+// next DEPTH slabs are in flight in registers while the current one is
+// multiplied, and A is loaded with a non-temporal hint (it is streamed once
+// per pass; the caches stay with the panel).  Panel width 128.
+//
+// CAST: A is the FP32 input (rows 16-byte aligned) instead of its BF16 copy;
+// each 8-value chunk is rounded to BF16 (nearest even) in registers, written
+// to A16 (the copy the later passes read) and multiplied, so the sketch pass
+// also produces the BF16 copy: one read of the FP32 matrix instead of two.
+// Every element of A belongs to exactly one workgroup, so A16 is written once.
+__device__ inline uint32_t pack_bf16(float a, float b);
+
+template <int DEPTH, int MR = 2, bool CAST = false>
+__global__ __launch_bounds__(256) void k_nn_bf16_sq(const u16* __restrict__ A, int64_t lda,
+                                                    int64_t m, int64_t n, int64_t tn,
+                                                    const u16* __restrict__ X, int64_t ldx,
+                                                    float* __restrict__ Y, int64_t ldy,
+                                                    int64_t part_stride,
+                                                    const float* __restrict__ A32 = nullptr,
+                                                    u16* __restrict__ A16 = nullptr,
+                                                    int64_t lda16 = 0) {
+  constexpr int BM = 64 * MR, LP = 128, CPR = BK / 8, RPI = 256 / CPR, AS = BM / RPI, XS = LP / RPI;
+  __shared__ __attribute__((aligned(16))) u16 As[BM][PADK];
+  __shared__ __attribute__((aligned(16))) u16 Xs[LP][PADK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tn;
+  const int64_t k1 = min(n, k0 + tn);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int lr = tid / CPR, lc = (tid % CPR) * 8;
+
+  uint4 ra[DEPTH][AS];
+  uint4 rx[DEPTH][XS];
+  auto gload = [&](int d, int64_t kt) {
+    const int64_t kk = kt + lc;
+#pragma unroll
+    for (int s = 0; s < AS; ++s) {
+      const int64_t i = i0 + lr + RPI * s;
+      if (CAST) {
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (i < m && kk < k1) {
+          const float* row = A32 + i * lda;
+          const float4 x0 = ld4_masked(row, kk, k1), x1 = ld4_masked(row, kk + 4, k1);
+          w = make_uint4(pack_bf16(x0.x, x0.y), pack_bf16(x0.z, x0.w), pack_bf16(x1.x, x1.y),
+                         pack_bf16(x1.z, x1.w));
+          u16* dst = A16 + i * lda16 + kk;
+          if (kk + 8 <= k1) {
+            *reinterpret_cast<uint4*>(dst) = w;
+          } else {
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+            for (int e = 0; kk + e < k1; ++e) dst[e] = (u16)(ww[e >> 1] >> (16 * (e & 1)));
+          }
+        }
+        ra[d][s] = w;
+      } else {
+        ra[d][s] = (i < m && kk < k1) ? ld8_masked_nt(A + i * lda, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < XS; ++s) {
+      const int c = lr + RPI * s;
+      rx[d][s] = kk < k1 ? ld8_masked(X + (int64_t)c * ldx, kk, k1) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+
+  f32x16 acc[MR][2];
+#pragma unroll
+  for (int a = 0; a < MR; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+
+  auto step = [&](int d, int64_t kt) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < AS; ++s) *reinterpret_cast<uint4*>(&As[lr + RPI * s][lc]) = ra[d][s];
+#pragma unroll
+    for (int s = 0; s < XS; ++s) *reinterpret_cast<uint4*>(&Xs[lr + RPI * s][lc]) = rx[d][s];
+    __syncthreads();
+    if (kt + DEPTH * BK < k1) gload(d, kt + DEPTH * BK);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kc = half * 32 + s * 8;
+      bf16x8 av[MR], bv[2];
+#pragma unroll
+      for (int a = 0; a < MR; ++a)
+        av[a] = *reinterpret_cast<const bf16x8*>(&As[wr * 32 * MR + a * 32 + l32][kc]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        bv[t] = *reinterpret_cast<const bf16x8*>(&Xs[wc * 64 + t * 32 + l32][kc]);
+#pragma unroll
+      for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+    }
+  };
+
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d)
+    if (k0 + d * BK < k1) gload(d, k0 + d * BK);
+  for (int64_t kt = k0; kt < k1; kt += DEPTH * BK) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+      if (kt + d * BK < k1) step(d, kt + d * BK);
+  }
+#pragma unroll
+  for (int a = 0; a < MR; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      store_acc16(Yp, ldy, i0 + wr * 32 * MR + a * 32, wc * 64 + t * 32 + l32, acc[a][t], half);
+}
+
 // Z (+ partial I) = A16(tile I, :)^T Q16(tile I, :).  The A tile is staged
 // row-major as loaded ([i][j], coalesced 16-byte loads); each lane gathers
 // its A^T fragment (8 consecutive i of one column j) with 16-bit LDS reads,
 // so no transposed copy of A is ever stored.
 constexpr int TBN = 128;
 constexpr int TPAD = TBN + 8;
-template <int NT>
+template <int NT, bool NTL = false>
 __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int64_t lda, int64_t m,
                                                  int64_t n, int64_t tm, const u16* __restrict__ Q,
                                                  int64_t ldq, float* __restrict__ Z, int64_t ldz,
@@ -158,7 +286,8 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t i = it + ar + 16 * s;
-      ra[s] = (i < ib1 && j < n) ? ld8_masked(A + i * lda, j, n) : make_uint4(0u, 0u, 0u, 0u);
+      ra[s] = (i < ib1 && j < n) ? (NTL ? ld8_masked_nt(A + i * lda, j, n) : ld8_masked(A + i * lda, j, n))
+                                 : make_uint4(0u, 0u, 0u, 0u);
     }
     const int64_t kk = it + qc;
 #pragma unroll
@@ -284,26 +413,35 @@ hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, 
                           int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
                           int64_t ldy, int64_t part_stride, hipStream_t s) {
   const int nt = (int)(lp / 32);
-  if (nt <= 4) {   // two M tiles per wave: 256 rows per workgroup
-    dim3 grid((unsigned)ceil_div_dev(m, 256), (unsigned)TJ);
-#define NN16(NT) hipLaunchKernelGGL((k_nn_bf16<NT, 2>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y, ldy, part_stride)
-    switch (nt) {
-      case 1: NN16(1); break;
-      case 2: NN16(2); break;
-      case 3: NN16(3); break;
-      case 4: NN16(4); break;
-    }
-#undef NN16
-  } else {
+  if (nt == 4) {   // square wave tiles, 128 rows per workgroup
     dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
-#define NN16(NT) hipLaunchKernelGGL((k_nn_bf16<NT, 1>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y, ldy, part_stride)
-    switch (nt) {
-      case 5: NN16(5); break;
-      case 6: NN16(6); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef NN16
+    hipLaunchKernelGGL((k_nn_bf16_sq<1, 2>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y,
+                       ldy, part_stride);
+    return hipGetLastError();
   }
+  dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
+#define NN16(NT) hipLaunchKernelGGL((k_nn_bf16<NT, 1>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y, ldy, part_stride)
+  switch (nt) {
+    case 1: NN16(1); break;
+    case 2: NN16(2); break;
+    case 3: NN16(3); break;
+    case 5: NN16(5); break;
+    case 6: NN16(6); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NN16
+  return hipGetLastError();
+}
+
+hipError_t launch_nn_bf16_cast(const float* A32, int64_t lda, int64_t m, int64_t n, int64_t tn,
+                               int64_t TJ, uint16_t* A16, int64_t lda16, const uint16_t* X,
+                               int64_t ldx, int64_t lp, float* Y, int64_t ldy,
+                               int64_t part_stride, hipStream_t s) {
+  if (lp != 128 || (lda % 4) != 0 || (((uintptr_t)A32) & 15) != 0 || (lda16 % 8) != 0)
+    return hipErrorInvalidValue;
+  dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
+  hipLaunchKernelGGL((k_nn_bf16_sq<1, 2, true>), grid, dim3(256), 0, s, (const u16*)nullptr, lda, m,
+                     n, tn, X, ldx, Y, ldy, part_stride, A32, A16, lda16);
   return hipGetLastError();
 }
 
@@ -311,7 +449,7 @@ hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, 
                           int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
                           int64_t ldz, int64_t part_stride, hipStream_t s) {
   dim3 grid((unsigned)ceil_div_dev(n, TBN), (unsigned)TI);
-#define TN16(NT) hipLaunchKernelGGL((k_tn_bf16<NT>), grid, dim3(256), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz, part_stride)
+#define TN16(NT) hipLaunchKernelGGL((k_tn_bf16<NT, true>), grid, dim3(256), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz, part_stride)
   switch (lp / 32) {
     case 1: TN16(1); break;
     case 2: TN16(2); break;

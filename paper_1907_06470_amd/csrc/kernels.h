@@ -38,6 +38,12 @@ hipError_t launch_cast_f64_f32(const double* A, int64_t lda, int64_t m, int64_t 
 hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
                           int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
                           int64_t ldy, int64_t part_stride, hipStream_t s);
+// The BF16 sketch product straight from the FP32 A (16-byte aligned rows,
+// panel width 128), writing the BF16 copy A16 on the way.
+hipError_t launch_nn_bf16_cast(const float* A32, int64_t lda, int64_t m, int64_t n, int64_t tn,
+                               int64_t TJ, uint16_t* A16, int64_t lda16, const uint16_t* X,
+                               int64_t ldx, int64_t lp, float* Y, int64_t ldy,
+                               int64_t part_stride, hipStream_t s);
 hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
                           int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
                           int64_t ldz, int64_t part_stride, hipStream_t s);

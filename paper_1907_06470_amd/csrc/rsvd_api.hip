@@ -238,6 +238,8 @@ struct Runner {
   const int32_t* rowptr = nullptr;   // CSR input
   const int32_t* colind = nullptr;
   const float* values = nullptr;
+  const float* cast_src = nullptr;   // FP32 A whose BF16 copy the sketch pass will write
+  int64_t cast_lda = 0;
   const char* Ahost = nullptr; // host-resident A (pinned), streamed tile by tile
   int64_t ldh = 0;
   Streamer* st8 = nullptr;
@@ -258,6 +260,18 @@ struct Runner {
 
   // Operand copies of A the products need: FP32 (FP64 input is rounded once)
   // and/or BF16 (rounded to nearest even once per call).
+  bool fuse_cast = true;       // allow the sketch pass to produce the BF16 copy
+
+  // The BF16 copy if it is still owed (a BF16 product other than the sketch
+  // comes first).
+  rsvd_status settle_cast() {
+    if (!cast_src) return RSVD_OK;
+    RSVD_HIP(rsvd::launch_cast_to_bf16(cast_src, false, cast_lda, P.prob.m, P.prob.n, B.A16,
+                                       P.lda16, s));
+    cast_src = nullptr;
+    return RSVD_OK;
+  }
+
   rsvd_status bind_A(const void* A, int64_t lda) {
     const int32_t dt = P.prob.dtype;
     if (P.host) {
@@ -284,6 +298,13 @@ struct Runner {
       if (dt == RSVD_BF16) {
         A16 = (const uint16_t*)A;
         lda16 = lda;
+      } else if (dt == RSVD_F32 && fuse_cast && P.opt.prec_sketch == RSVD_BF16 && P.lp == 128 &&
+                 lda % 4 == 0 && (((uintptr_t)A) & 15) == 0) {
+        // the BF16 sketch product writes the copy while it reads A (one read)
+        cast_src = (const float*)A;
+        cast_lda = lda;
+        A16 = B.A16;
+        lda16 = P.lda16;
       } else {
         RSVD_HIP(rsvd::launch_cast_to_bf16(A, dt == RSVD_F64, lda, P.prob.m, P.prob.n, B.A16,
                                            P.lda16, s));
@@ -424,7 +445,11 @@ struct Runner {
     const int64_t stride = split ? P.ldm * P.lp : 0;
     float* dst = split ? B.part : out;
     RSVD_HIP(tick(true, true));
-    if (prec == RSVD_BF16)
+    if (prec == RSVD_BF16 && cast_src) {
+      RSVD_HIP(rsvd::launch_nn_bf16_cast(cast_src, cast_lda, m, n, P.tn, P.TJ, B.A16, P.lda16,
+                                         B.Xop16, P.ldn, P.lp, dst, P.ldm, stride, s));
+      cast_src = nullptr;
+    } else if (prec == RSVD_BF16)
       RSVD_HIP(rsvd::launch_nn_bf16(A16, lda16, m, n, P.tn, P.TJ, B.Xop16, P.ldn, P.lp, dst, P.ldm,
                                     stride, s));
     else if (prec == RSVD_FP8E4M3)
@@ -452,6 +477,8 @@ struct Runner {
     const bool split = P.TI > 1;
     const int64_t stride = split ? P.ldn * P.lp : 0;
     float* dst = split ? B.part : out;
+    if (prec == RSVD_BF16)
+      if (rsvd_status st = settle_cast()) return st;
     RSVD_HIP(tick(false, true));
     if (prec == RSVD_BF16)
       RSVD_HIP(rsvd::launch_tn_bf16(A16, lda16, m, n, P.tm, P.TI, B.Mop16, P.ldm, P.lp, dst, P.ldn,
