@@ -126,6 +126,9 @@ typedef struct {
   int32_t q_used;          /* power steps run (RSVD_FLAG_AUTO_Q: chosen)    */
   int32_t reserved2;
   double q_delta;          /* last relative change of the leading k values  */
+  double sketch_ms;        /* device time of the first A X launch (the
+                              sketch pass; in the BF16 form it also writes
+                              the BF16 copy of an FP32 A)                  */
 } rsvd_report;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;

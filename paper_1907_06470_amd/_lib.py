@@ -51,7 +51,8 @@ class Report(ctypes.Structure):
                 ("ws_bytes", c_i64), ("gemm_nn_launches", c_i32), ("gemm_tn_launches", c_i32),
                 ("dropped", c_i32), ("jacobi_sweeps", c_i32), ("nonfinite", c_i32),
                 ("slots", c_i32), ("h2d_bytes", ctypes.c_double), ("tile_loads", c_i64),
-                ("q_used", c_i32), ("reserved2", c_i32), ("q_delta", ctypes.c_double)]
+                ("q_used", c_i32), ("reserved2", c_i32), ("q_delta", ctypes.c_double),
+                ("sketch_ms", ctypes.c_double)]
 
 
 _P = ctypes.POINTER

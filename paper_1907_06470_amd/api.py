@@ -160,7 +160,7 @@ class Plan:
                         ws_bytes=rep.ws_bytes, dropped=rep.dropped,
                         jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite,
                         slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads,
-                        q_used=rep.q_used, q_delta=rep.q_delta)
+                        q_used=rep.q_used, q_delta=rep.q_delta, sketch_ms=rep.sketch_ms)
         return U, S, V, info
 
     def backward(self, A, gU=None, gS=None, gV=None, ws=None, stream=None, report=True):

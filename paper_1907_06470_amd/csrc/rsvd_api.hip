@@ -676,9 +676,11 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   }
   RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
   report->total_ms = ms;
-  for (int i : R.nn_idx) {
+  for (size_t x = 0; x < R.nn_idx.size(); ++x) {
+    const int i = R.nn_idx[x];
     RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
     report->gemm_nn_ms += ms;
+    if (x == 0) report->sketch_ms = ms;
   }
   for (int i : R.tn_idx) {
     RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
