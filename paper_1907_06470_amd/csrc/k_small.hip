@@ -695,26 +695,71 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
 // (C = L L^T), for sketch widths up to 128: the columns of M = L are rotated
 // in pairs until mutually orthogonal; then M = U_B diag(s), so s_c = |m_c|
 // and U_B(:, c) = m_c / s_c are the singular values of B and the
-// eigenvectors of C.  M lives in LDS column by column; a group of 16 lanes
-// owns one column pair per round (round-robin schedule) and holds 8 rows of
-// each column in registers, so a round needs a single barrier and no rotation
-// has to be replayed afterwards.
+// eigenvectors of C.
 //
-// A round is a chain of dependent steps (load, three dot products, rotation,
-// update, barrier), so the rotation is kept short: its tangent comes from
-// FP32 arithmetic on the exponent-normalised pair (accurate to ~1e-7, which
-// only changes by how much the pair's cosine drops), while the cosine is
-// cs = (1 + t^2)^-1/2 in FP64 for that t, so every applied rotation is
-// orthogonal to FP64 rounding.  The rotate/skip test |g| > tol sqrt(a b)
-// runs beside it as g^2 > tol^2 a b.  The sweep loop ends after a sweep in
-// which no pair had |cos| above kOjStop: quadratic convergence leaves the
-// remaining off-diagonal mass near kOjStop^2.
+// Block form with two-column blocks: M lives in LDS column by column; each
+// round pairs the blocks by a round-robin schedule, and a group of 16 lanes
+// loads the four columns of its block pair into registers (8 rows each per
+// lane), rotates the four cross pairs (two steps of two independent
+// rotations; the two pairs inside the blocks in the first round of a sweep)
+// and writes them back.  A sweep (all block pairs)
+// takes half the rounds of the one-pair-per-group form, so M crosses LDS half
+// as often; LDS traffic, FP64 issue and the round barrier bound this kernel.
+//
+// A rotation is kept short: its tangent comes from FP32 arithmetic on the
+// exponent-normalised pair (accurate to ~1e-7, which only changes by how much
+// the pair's cosine drops), while the cosine is cs = (1 + t^2)^-1/2 in FP64
+// for that t, so every applied rotation is orthogonal to FP64 rounding.  The
+// rotate/skip test |g| > tol sqrt(a b) runs beside it as g^2 > tol^2 a b.  The
+// sweep loop ends after a sweep in which no column pair had the cosine of its
+// angle above kOjStop in magnitude:
+// quadratic convergence leaves the remaining off-diagonal mass near kOjStop^2,
+// far below what the FP64 rotations themselves leave on the singular values.
 constexpr int kOjMaxLp = 128;
 constexpr int kOjLd = kOjMaxLp + 1;      // odd stride in doubles: no bank conflicts
-constexpr int kOjG = 16;                 // lanes per column pair
-constexpr int kOjThreads = kOjG * (kOjMaxLp / 2);
+constexpr int kOjG = 16;                 // lanes per block pair
+constexpr int kOjThreads = kOjG * (kOjMaxLp / 4);
 constexpr int kOjRows = kOjMaxLp / kOjG;
-constexpr double kOjStop = 1e-8;
+constexpr double kOjStop = 1e-6;
+
+// Rotate columns x (p) and y (q) of one block pair; g2 > tol2 a b selects.
+__device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], double tol2,
+                                 double stop2, bool& any, bool& big) {
+  double aa0 = 0.0, bb0 = 0.0, gg0 = 0.0, aa1 = 0.0, bb1 = 0.0, gg1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kOjRows; u += 2) {
+    aa0 += x[u] * x[u];
+    bb0 += y[u] * y[u];
+    gg0 += x[u] * y[u];
+    aa1 += x[u + 1] * x[u + 1];
+    bb1 += y[u + 1] * y[u + 1];
+    gg1 += x[u + 1] * y[u + 1];
+  }
+  const double aa = row16_sum(aa0 + aa1);
+  const double bb = row16_sum(bb0 + bb1);
+  const double gg = row16_sum(gg0 + gg1);
+  const double ab = aa * bb, g2 = gg * gg;
+  const bool rot = g2 > tol2 * ab;
+  // tangent of the Hestenes angle, t = sign(d) 2g / (|d| + sqrt(d^2 + 4g^2))
+  // with d = b - a, on the pair scaled by a power of two
+  const double dd = bb - aa, tg = 2.0 * gg;
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(dd), fabs(tg)));
+  const float d32 = (float)__builtin_amdgcn_ldexp(dd, -ex);
+  const float g32 = (float)__builtin_amdgcn_ldexp(tg, -ex);
+  const float den = fabsf(d32) + __builtin_amdgcn_sqrtf(d32 * d32 + g32 * g32);
+  const float t32 = (d32 >= 0.f ? g32 : -g32) * __builtin_amdgcn_rcpf(den);
+  const double tt = rot ? (double)t32 : 0.0;
+  const double cs = fast_rsq(1.0 + tt * tt);
+  const double sn = cs * tt;
+#pragma unroll
+  for (int u = 0; u < kOjRows; ++u) {
+    const double xp = x[u], xq = y[u];
+    x[u] = cs * xp - sn * xq;
+    y[u] = sn * xp + cs * xq;
+  }
+  any = any || rot;
+  big = big || (rot && g2 > stop2 * ab);
+}
 
 __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict__ L, int64_t lp,
                                                         int l, double* __restrict__ lam,
@@ -723,74 +768,69 @@ __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict
   __shared__ double M[kOjMaxLp * kOjLd];   // column c at M[c * kOjLd + i]
   __shared__ int any_s, big_s;
   const int tid = threadIdx.x, grp = tid / kOjG, sub = tid % kOjG;
-  const int le = l + (l & 1), np = le / 2, R = le - 1;
+  const int nb = (l + 1) / 2;                      // two-column blocks
+  const int nbe = nb + (nb & 1), np = nbe / 2, R = nbe - 1;  // nbe >= 2
   const double tol2 = tol * tol, stop2 = kOjStop * kOjStop;
-  for (int e = tid; e < l * l; e += kOjThreads) {
-    const int i = e / l, c = e % l;
-    M[c * kOjLd + i] = L[(int64_t)i * lp + c];
+  // rows and columns at and beyond l are held at zero: a zero column never
+  // passes the rotate test and a zero row stays zero, so no load or store
+  // below needs a bound
+  for (int e = tid; e < kOjMaxLp * kOjMaxLp; e += kOjThreads) {
+    const int i = e / kOjMaxLp, c = e % kOjMaxLp;
+    M[c * kOjLd + i] = (i < l && c < l) ? L[(int64_t)i * lp + c] : 0.0;
   }
   lds_barrier();
   int sweeps = 0;
-  for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
+  for (int sw = 0; sw < max_sweeps && l > 1; ++sw) {
     if (tid == 0) {
       any_s = 0;
       big_s = 0;
     }
     lds_barrier();
     for (int t = 0; t < R; ++t) {
-      if (grp < np) {
-        const int a = rr_pos(grp, t, le), b = rr_pos(le - 1 - grp, t, le);
-        const int p = min(a, b), q = max(a, b);
-        if (q < l) {
-          double* mp = &M[p * kOjLd];
-          double* mq = &M[q * kOjLd];
-          double xp[kOjRows], xq[kOjRows];
+      // round t: block pair (a, b); a block paired with the padding block
+      // (odd nb) rotates only its own two columns
+      int a = rr_pos(grp, t, nbe), b = rr_pos(nbe - 1 - grp, t, nbe);
+      if (a >= nb) a = b;
+      if (b >= nb) b = a;
+      if (grp < np && a < nb) {
+        double* ma = M + 2 * a * kOjLd + sub;
+        double* mb = M + 2 * b * kOjLd + sub;
+        double x[4][kOjRows];
+#pragma unroll
+        for (int u = 0; u < kOjRows; ++u) {
+          x[0][u] = ma[kOjG * u];
+          x[1][u] = ma[kOjLd + kOjG * u];
+          x[2][u] = mb[kOjG * u];
+          x[3][u] = mb[kOjLd + kOjG * u];
+        }
+        bool any = false, big = false;
+        if (a == b) {
+          oj_rotate(x[0], x[1], tol2, stop2, any, big);
+        } else {
+          if (t == 0) {   // the pairs inside a block, once per sweep
+            oj_rotate(x[0], x[1], tol2, stop2, any, big);
+            oj_rotate(x[2], x[3], tol2, stop2, any, big);
+          }
+          oj_rotate(x[0], x[2], tol2, stop2, any, big);
+          oj_rotate(x[1], x[3], tol2, stop2, any, big);
+          oj_rotate(x[0], x[3], tol2, stop2, any, big);
+          oj_rotate(x[1], x[2], tol2, stop2, any, big);
+        }
+#pragma unroll
+        for (int u = 0; u < kOjRows; ++u) {
+          ma[kOjG * u] = x[0][u];
+          ma[kOjLd + kOjG * u] = x[1][u];
+        }
+        if (a != b) {
 #pragma unroll
           for (int u = 0; u < kOjRows; ++u) {
-            const int i = sub + kOjG * u;
-            xp[u] = i < l ? mp[i] : 0.0;
-            xq[u] = i < l ? mq[i] : 0.0;
+            mb[kOjG * u] = x[2][u];
+            mb[kOjLd + kOjG * u] = x[3][u];
           }
-          double aa0 = 0.0, bb0 = 0.0, gg0 = 0.0, aa1 = 0.0, bb1 = 0.0, gg1 = 0.0;
-#pragma unroll
-          for (int u = 0; u < kOjRows; u += 2) {
-            aa0 += xp[u] * xp[u];
-            bb0 += xq[u] * xq[u];
-            gg0 += xp[u] * xq[u];
-            aa1 += xp[u + 1] * xp[u + 1];
-            bb1 += xq[u + 1] * xq[u + 1];
-            gg1 += xp[u + 1] * xq[u + 1];
-          }
-          const double aa = row16_sum(aa0 + aa1);
-          const double bb = row16_sum(bb0 + bb1);
-          const double gg = row16_sum(gg0 + gg1);
-          const double ab = aa * bb, g2 = gg * gg;
-          const bool rot = g2 > tol2 * ab;
-          // tangent of the Hestenes angle, t = sign(d) 2g / (|d| + sqrt(d^2 + 4g^2))
-          // with d = b - a, on the pair scaled by a power of two
-          const double dd = bb - aa, tg = 2.0 * gg;
-          const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(dd), fabs(tg)));
-          const float d32 = (float)__builtin_amdgcn_ldexp(dd, -ex);
-          const float g32 = (float)__builtin_amdgcn_ldexp(tg, -ex);
-          const float den = fabsf(d32) + __builtin_sqrtf(d32 * d32 + g32 * g32);
-          const float t32 = (d32 >= 0.f ? g32 : -g32) * __builtin_amdgcn_rcpf(den);
-          const double tt = rot ? (double)t32 : 0.0;
-          const double cs = fast_rsq(1.0 + tt * tt);
-          const double sn = cs * tt;
-          if (rot) {
-#pragma unroll
-            for (int u = 0; u < kOjRows; ++u) {
-              const int i = sub + kOjG * u;
-              if (i < l) {
-                mp[i] = cs * xp[u] - sn * xq[u];
-                mq[i] = sn * xp[u] + cs * xq[u];
-              }
-            }
-            if (sub == 0) {
-              any_s = 1;
-              if (g2 > stop2 * ab) big_s = 1;
-            }
-          }
+        }
+        if (any && sub == 0) {
+          any_s = 1;
+          if (big) big_s = 1;
         }
       }
       lds_barrier();
