@@ -697,14 +697,18 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
 // and U_B(:, c) = m_c / s_c are the singular values of B and the
 // eigenvectors of C.
 //
-// Block form with two-column blocks: M lives in LDS column by column; each
-// round pairs the blocks by a round-robin schedule, and a group of 16 lanes
-// loads the four columns of its block pair into registers (8 rows each per
-// lane), rotates the four cross pairs (two steps of two independent
-// rotations; the two pairs inside the blocks in the first round of a sweep)
-// and writes them back.  A sweep (all block pairs)
-// takes half the rounds of the one-pair-per-group form, so M crosses LDS half
-// as often; LDS traffic, FP64 issue and the round barrier bound this kernel.
+// Block form with two-column blocks in the odd-even order: the nb blocks sit
+// at positions 0..nb-1; a round of parity par pairs positions (2i + par,
+// 2i + par + 1), rotates the four cross pairs of columns of each pair (two
+// steps of two independent rotations; the pairs inside the blocks once per
+// sweep), and the two blocks trade positions.  nb such rounds make a sweep in
+// which every two blocks meet exactly once (the exchanges of odd-even
+// transposition sort on a reversed sequence).  Group i of 16 lanes always
+// holds the block at position 2i + 1 in registers (8 rows each per lane),
+// so a round moves only one block per group through LDS (half the traffic of
+// an order in which both blocks move); LDS traffic, FP64 issue and the round
+// barrier bound this one-workgroup kernel.  Blocks end in permuted positions;
+// the output columns follow the original order.
 //
 // A rotation is kept short: its tangent comes from FP32 arithmetic on the
 // exponent-normalised pair (accurate to ~1e-7, which only changes by how much
@@ -722,22 +726,34 @@ constexpr int kOjThreads = kOjG * (kOjMaxLp / 4);
 constexpr int kOjRows = kOjMaxLp / kOjG;
 constexpr double kOjStop = 1e-6;
 
-// Rotate columns x (p) and y (q) of one block pair; g2 > tol2 a b selects.
-__device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], double tol2,
-                                 double stop2, bool& any, bool& big) {
-  double aa0 = 0.0, bb0 = 0.0, gg0 = 0.0, aa1 = 0.0, bb1 = 0.0, gg1 = 0.0;
+__device__ inline double oj_norm2(const double (&x)[kOjRows]) {
+  double s0 = 0.0, s1 = 0.0;
 #pragma unroll
   for (int u = 0; u < kOjRows; u += 2) {
-    aa0 += x[u] * x[u];
-    bb0 += y[u] * y[u];
-    gg0 += x[u] * y[u];
-    aa1 += x[u + 1] * x[u + 1];
-    bb1 += y[u + 1] * y[u + 1];
-    gg1 += x[u + 1] * y[u + 1];
+    s0 += x[u] * x[u];
+    s1 += x[u + 1] * x[u + 1];
   }
-  const double aa = row16_sum(aa0 + aa1);
-  const double bb = row16_sum(bb0 + bb1);
-  const double gg = row16_sum(gg0 + gg1);
+  return row16_sum(s0 + s1);
+}
+
+// Rotate columns x and y, whose squared norms na and nb are carried along:
+// only the inner product g is summed from the data, and the norms of the
+// rotated pair follow from the rotation actually applied,
+// a' = c^2 a - 2 c s g + s^2 b and b' = s^2 a + 2 c s g + c^2 b.  An updated
+// norm below 1/100 of the old one (nearly parallel columns: the update
+// cancels) sets `stale`, and the caller sums it afresh.  g2 > tol2 a b
+// selects the rotation.
+__device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], double& na,
+                                 double& nb, bool& stale, double tol2, double stop2, bool& any,
+                                 bool& big) {
+  double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kOjRows; u += 2) {
+    g0 += x[u] * y[u];
+    g1 += x[u + 1] * y[u + 1];
+  }
+  const double aa = na, bb = nb;
+  const double gg = row16_sum(g0 + g1);
   const double ab = aa * bb, g2 = gg * gg;
   const bool rot = g2 > tol2 * ab;
   // tangent of the Hestenes angle, t = sign(d) 2g / (|d| + sqrt(d^2 + 4g^2))
@@ -757,19 +773,35 @@ __device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], dou
     x[u] = cs * xp - sn * xq;
     y[u] = sn * xp + cs * xq;
   }
+  const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * gg;
+  const double a2 = c2 * aa - cg + s2 * bb;
+  const double b2 = s2 * aa + cg + c2 * bb;
+  stale = stale || a2 < 0.01 * aa || b2 < 0.01 * bb;
+  na = a2;
+  nb = b2;
   any = any || rot;
   big = big || (rot && g2 > stop2 * ab);
+}
+
+// Position p of the odd-even order is idle in a round of parity par when no
+// pair (2i + par, 2i + par + 1) of the nb positions covers it.
+__device__ inline bool oj_idle(int pos, int par, int nb) {
+  if (par == 0) return pos == nb - 1 && (nb & 1);
+  return pos == 0 || (pos == nb - 1 && !(nb & 1));
 }
 
 __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict__ L, int64_t lp,
                                                         int l, double* __restrict__ lam,
                                                         double* __restrict__ Ev, int32_t* status,
                                                         double tol, int max_sweeps) {
-  __shared__ double M[kOjMaxLp * kOjLd];   // column c at M[c * kOjLd + i]
+  __shared__ double M[kOjMaxLp * kOjLd];   // block at position p: columns 2p, 2p + 1
+  __shared__ int blk[kOjMaxLp / 2];        // block (pair of original columns) at position p
+  __shared__ double nrm[kOjMaxLp];         // squared column norms of the block at position p
+  __shared__ int pos_of[kOjMaxLp / 2];
   __shared__ int any_s, big_s;
   const int tid = threadIdx.x, grp = tid / kOjG, sub = tid % kOjG;
-  const int nb = (l + 1) / 2;                      // two-column blocks
-  const int nbe = nb + (nb & 1), np = nbe / 2, R = nbe - 1;  // nbe >= 2
+  const int nb = max((l + 1) / 2, 2);            // two-column blocks (a zero block pads l <= 2)
+  const int ng = nb / 2;                          // group i keeps the block at position 2i + 1
   const double tol2 = tol * tol, stop2 = kOjStop * kOjStop;
   // rows and columns at and beyond l are held at zero: a zero column never
   // passes the rotate test and a zero row stays zero, so no load or store
@@ -778,60 +810,95 @@ __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict
     const int i = e / kOjMaxLp, c = e % kOjMaxLp;
     M[c * kOjLd + i] = (i < l && c < l) ? L[(int64_t)i * lp + c] : 0.0;
   }
+  for (int p = tid; p < kOjMaxLp / 2; p += kOjThreads) blk[p] = p;
   lds_barrier();
-  int sweeps = 0;
+  const bool owner = grp < ng;
+  const int kpos = 2 * grp + 1;
+  double xk[2][kOjRows];                          // the kept block, in registers
+  int idk = kpos;
+  if (owner) {
+#pragma unroll
+    for (int u = 0; u < kOjRows; ++u) {
+      xk[0][u] = M[(2 * kpos) * kOjLd + sub + kOjG * u];
+      xk[1][u] = M[(2 * kpos + 1) * kOjLd + sub + kOjG * u];
+    }
+  }
+  int sweeps = 0, rnd = 0;
+  double nk[2];
   for (int sw = 0; sw < max_sweeps && l > 1; ++sw) {
+    // the norms carried through the rotations restart from the data each sweep
+    if (owner) {
+      nk[0] = oj_norm2(xk[0]);
+      nk[1] = oj_norm2(xk[1]);
+    }
+    for (int c = grp; c < kOjMaxLp; c += kOjThreads / kOjG) {
+      double v[kOjRows];
+#pragma unroll
+      for (int u = 0; u < kOjRows; ++u) v[u] = M[c * kOjLd + sub + kOjG * u];
+      const double ss = oj_norm2(v);
+      if (sub == 0) nrm[c] = ss;
+    }
     if (tid == 0) {
       any_s = 0;
       big_s = 0;
     }
     lds_barrier();
-    for (int t = 0; t < R; ++t) {
-      // round t: block pair (a, b); a block paired with the padding block
-      // (odd nb) rotates only its own two columns
-      int a = rr_pos(grp, t, nbe), b = rr_pos(nbe - 1 - grp, t, nbe);
-      if (a >= nb) a = b;
-      if (b >= nb) b = a;
-      if (grp < np && a < nb) {
-        double* ma = M + 2 * a * kOjLd + sub;
-        double* mb = M + 2 * b * kOjLd + sub;
-        double x[4][kOjRows];
+    const int par0 = rnd & 1;
+    for (int t = 0; t < nb; ++t, ++rnd) {
+      // round of parity par: positions (2i + par, 2i + par + 1) meet, then
+      // trade places.  Group i's kept block sits at 2i + 1 (the upper one of
+      // an even round, the lower one of an odd round); the other block, at
+      // slot position sp, comes from LDS, and after the exchange the kept
+      // block's data goes to sp while the slot block's data stays in
+      // registers as the new block at 2i + 1.
+      const int par = rnd & 1;
+      const int sp = par ? kpos + 1 : kpos - 1;
+      if (owner && sp < nb) {
+        double* ms = M + 2 * sp * kOjLd + sub;
+        double xs[2][kOjRows];
 #pragma unroll
         for (int u = 0; u < kOjRows; ++u) {
-          x[0][u] = ma[kOjG * u];
-          x[1][u] = ma[kOjLd + kOjG * u];
-          x[2][u] = mb[kOjG * u];
-          x[3][u] = mb[kOjLd + kOjG * u];
+          xs[0][u] = ms[kOjG * u];
+          xs[1][u] = ms[kOjLd + kOjG * u];
         }
-        bool any = false, big = false;
-        if (a == b) {
-          oj_rotate(x[0], x[1], tol2, stop2, any, big);
-        } else {
-          if (t == 0) {   // the pairs inside a block, once per sweep
-            oj_rotate(x[0], x[1], tol2, stop2, any, big);
-            oj_rotate(x[2], x[3], tol2, stop2, any, big);
-          }
-          oj_rotate(x[0], x[2], tol2, stop2, any, big);
-          oj_rotate(x[1], x[3], tol2, stop2, any, big);
-          oj_rotate(x[0], x[3], tol2, stop2, any, big);
-          oj_rotate(x[1], x[2], tol2, stop2, any, big);
+        const int ids = blk[sp];
+        double ns[2] = {nrm[2 * sp], nrm[2 * sp + 1]};
+        bool any = false, big = false, stale = false;
+        // the pairs inside a block, once per sweep: in the sweep's first
+        // round, or in its second for a block idle in the first
+        const bool ik = t == 0 || (t == 1 && oj_idle(kpos, par0, nb));
+        const bool is = t == 0 || (t == 1 && oj_idle(sp, par0, nb));
+        if (ik) oj_rotate(xk[0], xk[1], nk[0], nk[1], stale, tol2, stop2, any, big);
+        if (is) oj_rotate(xs[0], xs[1], ns[0], ns[1], stale, tol2, stop2, any, big);
+        oj_rotate(xk[0], xs[0], nk[0], ns[0], stale, tol2, stop2, any, big);
+        oj_rotate(xk[1], xs[1], nk[1], ns[1], stale, tol2, stop2, any, big);
+        oj_rotate(xk[0], xs[1], nk[0], ns[1], stale, tol2, stop2, any, big);
+        oj_rotate(xk[1], xs[0], nk[1], ns[0], stale, tol2, stop2, any, big);
+        if (stale) {   // rare: sum all four norms afresh
+          nk[0] = oj_norm2(xk[0]);
+          nk[1] = oj_norm2(xk[1]);
+          ns[0] = oj_norm2(xs[0]);
+          ns[1] = oj_norm2(xs[1]);
         }
 #pragma unroll
         for (int u = 0; u < kOjRows; ++u) {
-          ma[kOjG * u] = x[0][u];
-          ma[kOjLd + kOjG * u] = x[1][u];
+          ms[kOjG * u] = xk[0][u];
+          ms[kOjLd + kOjG * u] = xk[1][u];
+          xk[0][u] = xs[0][u];
+          xk[1][u] = xs[1][u];
         }
-        if (a != b) {
-#pragma unroll
-          for (int u = 0; u < kOjRows; ++u) {
-            mb[kOjG * u] = x[2][u];
-            mb[kOjLd + kOjG * u] = x[3][u];
+        if (sub == 0) {
+          nrm[2 * sp] = nk[0];
+          nrm[2 * sp + 1] = nk[1];
+          blk[sp] = idk;
+          if (any) {
+            any_s = 1;
+            if (big) big_s = 1;
           }
         }
-        if (any && sub == 0) {
-          any_s = 1;
-          if (big) big_s = 1;
-        }
+        idk = ids;
+        nk[0] = ns[0];
+        nk[1] = ns[1];
       }
       lds_barrier();
     }
@@ -840,17 +907,30 @@ __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict
     lds_barrier();
     if (!any || !big) break;
   }
-  // s_c = |m_c| (one group per column), U_B(:, c) = m_c / s_c
+  // kept blocks back to their positions, then the inverse of blk
+  if (owner) {
+#pragma unroll
+    for (int u = 0; u < kOjRows; ++u) {
+      M[(2 * kpos) * kOjLd + sub + kOjG * u] = xk[0][u];
+      M[(2 * kpos + 1) * kOjLd + sub + kOjG * u] = xk[1][u];
+    }
+    if (sub == 0) blk[kpos] = idk;
+  }
+  lds_barrier();
+  for (int p = tid; p < kOjMaxLp / 2; p += kOjThreads) pos_of[blk[p]] = p;
+  lds_barrier();
+  // s_c = |m_c| (one group per original column c), U_B(:, c) = m_c / s_c
   for (int c = grp; c < lp; c += kOjThreads / kOjG) {
+    const int mc = 2 * pos_of[c >> 1] + (c & 1);
     double ss = 0.0;
     if (c < l)
-      for (int i = sub; i < l; i += kOjG) ss += M[c * kOjLd + i] * M[c * kOjLd + i];
+      for (int i = sub; i < l; i += kOjG) ss += M[mc * kOjLd + i] * M[mc * kOjLd + i];
     ss = row16_sum(ss);
     const double sv = sqrt(ss);
     if (sub == 0) lam[c] = c < l ? ss : 0.0;
     const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
     for (int i = sub; i < lp; i += kOjG)
-      Ev[(int64_t)i * lp + c] = (c < l && i < l) ? M[c * kOjLd + i] * inv : 0.0;
+      Ev[(int64_t)i * lp + c] = (c < l && i < l) ? M[mc * kOjLd + i] * inv : 0.0;
   }
   if (tid == 0) {
     status[kStSweeps] = sweeps;
