@@ -121,6 +121,141 @@ __global__ __launch_bounds__(256) void k_gram_part(const float* __restrict__ P, 
       }
 }
 
+// Lower-triangle Gram for sketch widths up to 128 (lp = 16 NBK): the 16 x 16
+// tiles (I, J), I >= J, of P^T P, tile t = I (I + 1) / 2 + J handled by wave
+// t mod 4 in accumulator t / 4, over one row chunk per workgroup.  Each 64-row
+// slab of the chunk is staged in LDS column by column (the panel is
+// column-major) and the next slab is prefetched into registers meanwhile.
+// Lane (i, q) of a k-step takes rows 4 q + s of a 16-row group, so one
+// 16-byte LDS read gives a lane its values for four k-steps; both MFMA
+// operands of a tile come from the same read (A and B are both columns of
+// P).  gpart[(chunk * ntile + t) * 256 + r * 16 + c] = tile t's (r, c).
+constexpr int kGtSlab = 64;
+constexpr int kGtLd = kGtSlab + 4;          // floats per staged column
+
+// Wave W's share of k_gram_tri (tiles t = W mod 4, chosen at compile time so
+// that the MFMA sequence has no branches).  Every wave runs the same slab
+// loop, so the workgroup barriers match.
+template <int NBK, int W>
+__device__ inline void gram_tri_wave(const float* __restrict__ P, int64_t ld, int64_t r0,
+                                     int64_t r1, double* __restrict__ out, float* T) {
+  constexpr int NT = NBK * (NBK + 1) / 2, NA = (NT + 3 - W) / 4 > 0 ? (NT + 3 - W) / 4 : 1;
+  constexpr int LP = 16 * NBK;
+  constexpr int NQ = LP * (kGtSlab / 4) / 256;   // float4 loads per thread per slab
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i16 = lane & 15, kq = lane >> 4;
+  f64x4 acc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) acc[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+  float4 pre[NQ];
+  auto gload = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int idx = tid + 256 * u, c = idx / (kGtSlab / 4), q = idx % (kGtSlab / 4);
+      const int64_t i = rb + 4 * q;
+      pre[u] = i < r1 ? ld4_masked(P + (int64_t)c * ld, i, r1) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  if (r0 < r1) gload(r0);
+  for (int64_t rb = r0; rb < r1; rb += kGtSlab) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int idx = tid + 256 * u, c = idx / (kGtSlab / 4), q = idx % (kGtSlab / 4);
+      *reinterpret_cast<float4*>(&T[c * kGtLd + 4 * q]) = pre[u];
+    }
+    __syncthreads();
+    if (rb + kGtSlab < r1) gload(rb + kGtSlab);
+    // 16-row groups past the chunk's end hold zeros: skip them
+    const int ng = (int)min<int64_t>(kGtSlab / 16, (r1 - rb + 15) / 16);
+#pragma unroll
+    for (int g = 0; g < kGtSlab / 16; ++g) {
+      if (g < ng) {
+        float4 v[NBK];
+#pragma unroll
+        for (int b = 0; b < NBK; ++b)
+          v[b] = *reinterpret_cast<const float4*>(&T[(b * 16 + i16) * kGtLd + g * 16 + 4 * kq]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          double d[NBK];
+#pragma unroll
+          for (int b = 0; b < NBK; ++b) d[b] = (double)v[b][s];
+#pragma unroll
+          for (int I = 0, t = 0; I < NBK; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J, ++t)
+              if ((t & 3) == W) acc[t >> 2] = mfma64(d[I], d[J], acc[t >> 2]);
+        }
+      }
+    }
+  }
+  // accumulator register r of lane (c, q) holds row q + 4 r, column c
+#pragma unroll
+  for (int t = W; t < NT; t += 4)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[t * 256 + (kq + 4 * r) * 16 + i16] = acc[t >> 2][r];
+}
+
+template <int NBK>
+__global__ __launch_bounds__(256) void k_gram_tri(const float* __restrict__ P, int64_t ld,
+                                                  int64_t rows, int64_t chunk_rows,
+                                                  double* __restrict__ gpart) {
+  constexpr int NT = NBK * (NBK + 1) / 2;
+  __shared__ __attribute__((aligned(16))) float T[16 * NBK * kGtLd];
+  const int64_t r0 = (int64_t)blockIdx.x * chunk_rows;
+  const int64_t r1 = min(rows, r0 + chunk_rows);
+  double* out = gpart + (int64_t)blockIdx.x * NT * 256;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: gram_tri_wave<NBK, 0>(P, ld, r0, r1, out, T); break;
+    case 1: gram_tri_wave<NBK, 1>(P, ld, r0, r1, out, T); break;
+    case 2: gram_tri_wave<NBK, 2>(P, ld, r0, r1, out, T); break;
+    default: gram_tri_wave<NBK, 3>(P, ld, r0, r1, out, T); break;
+  }
+}
+
+// G (lp x lp, full symmetric) from the k_gram_tri partials: 16 threads per
+// element, thread j summing chunks j, j + 16, ... in order, then the 16
+// partial sums in a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void k_gram_tri_reduce(const double* __restrict__ gpart,
+                                                         int64_t chunks, int ntile, int64_t lp,
+                                                         double* __restrict__ G) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x, j = tid & 15;
+  const int64_t e = (int64_t)blockIdx.x * 16 + (tid >> 4);
+  const int64_t total = (int64_t)ntile * 256;
+  double v = 0.0;
+  if (e < total) {
+    int64_t c = j;
+    for (; c + 48 < chunks; c += 64) {
+      const double x0 = gpart[c * total + e], x1 = gpart[(c + 16) * total + e];
+      const double x2 = gpart[(c + 32) * total + e], x3 = gpart[(c + 48) * total + e];
+      v += x0;
+      v += x1;
+      v += x2;
+      v += x3;
+    }
+    for (; c < chunks; c += 16) v += gpart[c * total + e];
+  }
+  red[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    if (j < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (j == 0 && e < total) {
+    const int t = (int)(e / 256), w = (int)(e % 256);
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    const int64_t row = I * 16 + w / 16, col = J * 16 + w % 16;
+    if (row < lp && col < lp) {
+      G[row * lp + col] = red[tid];
+      G[col * lp + row] = red[tid];
+    }
+  }
+}
+
 // G (lp x lp, full symmetric) from the chunk partials, summed in chunk order.
 __global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, int npairs,
                               int64_t lp, double* __restrict__ G) {
@@ -1076,22 +1211,24 @@ __global__ __launch_bounds__(256) void k_finish_small(const double* __restrict__
 }
 
 // Sign convention: in every column c < k of V the entry of largest magnitude
-// (lowest row on ties) becomes positive; U's column flips with it.
-__global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ U, int64_t ldu, int64_t m,
-                                                  float* __restrict__ V, int64_t ldv, int64_t n) {
+// (lowest row on ties) becomes positive; U's column flips with it.  One
+// workgroup per column finds the entry and records the flip in flip[c]; a
+// second, wide kernel negates the flipped columns of U and V.
+__global__ __launch_bounds__(256) void k_sign_find(const float* __restrict__ V, int64_t ldv,
+                                                   int64_t n, int32_t* __restrict__ flip) {
   __shared__ float bv[256];
   __shared__ int64_t bi[256];
   const int c = blockIdx.x, tid = threadIdx.x;
   float best = -1.f;
   int64_t bidx = 0;
   const float* col = V + (int64_t)c * ldv;
-  // four independent loads per iteration; each thread keeps its first maximum
-  for (int64_t j0 = (int64_t)tid * 4; j0 < n; j0 += 4 * (int64_t)blockDim.x) {
-    float a[4];
+  // eight independent loads per iteration; each thread keeps its first maximum
+  for (int64_t j0 = (int64_t)tid * 8; j0 < n; j0 += 8 * (int64_t)blockDim.x) {
+    float a[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = j0 + e < n ? fabsf(col[j0 + e]) : -1.f;
+    for (int e = 0; e < 8; ++e) a[e] = j0 + e < n ? fabsf(col[j0 + e]) : -1.f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 8; ++e)
       if (a[e] > best) {
         best = a[e];
         bidx = j0 + e;
@@ -1111,10 +1248,25 @@ __global__ __launch_bounds__(256) void k_sign_fix(float* __restrict__ U, int64_t
     }
     __syncthreads();
   }
-  const bool flip = V[(int64_t)c * ldv + bi[0]] < 0.f;
-  if (!flip) return;
-  for (int64_t i = tid; i < m; i += blockDim.x) U[(int64_t)c * ldu + i] = -U[(int64_t)c * ldu + i];
-  for (int64_t j = tid; j < n; j += blockDim.x) V[(int64_t)c * ldv + j] = -V[(int64_t)c * ldv + j];
+  if (tid == 0) flip[c] = col[bi[0]] < 0.f ? 1 : 0;
+}
+
+// Negate column c of U (rows < m) and of V (rows < n) where flip[c]; block
+// (x, c) covers rows [1024 x, 1024 x + 1024) of both.
+__global__ __launch_bounds__(256) void k_sign_apply(float* __restrict__ U, int64_t ldu, int64_t m,
+                                                    float* __restrict__ V, int64_t ldv, int64_t n,
+                                                    const int32_t* __restrict__ flip) {
+  const int c = blockIdx.y;
+  if (!flip[c]) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  float* u = U + (int64_t)c * ldu;
+  float* v = V + (int64_t)c * ldv;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t r = r0 + 256 * e;
+    if (r < m) u[r] = -u[r];
+    if (r < n) v[r] = -v[r];
+  }
 }
 
 // out(a, c) = Ev(a, order c) for a, c < l (row-major l x l, FP64).
@@ -1136,6 +1288,27 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
 
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
                        int64_t chunks, double* gpart, double* G, hipStream_t s) {
+  if (gram_tri_fits(lp) && (ld % 4) == 0 && (((uintptr_t)P) & 15) == 0) {
+    const int64_t crow = gram_tri_chunk_rows(rows);
+    const int64_t nch = ceil_div_dev(rows, crow);
+    const int nbk = (int)(lp / 16), ntile = nbk * (nbk + 1) / 2;
+#define GT(NBK)                                                                              \
+  hipLaunchKernelGGL(k_gram_tri<NBK>, dim3((unsigned)nch), dim3(256), 0, s, P, ld, rows, crow, \
+                     gpart)
+    switch (nbk) {
+      case 2: GT(2); break;
+      case 4: GT(4); break;
+      case 6: GT(6); break;
+      case 8: GT(8); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef GT
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_tri_reduce, dim3((unsigned)ceil_div_dev((int64_t)ntile * 256, 16)),
+                       dim3(256), 0, s, gpart, nch, ntile, lp, G);
+    return hipGetLastError();
+  }
   const int nb = (int)ceil_div_dev(lp, 64);
   const int npairs = nb * (nb + 1) / 2;
   hipLaunchKernelGGL(k_gram_part, dim3((unsigned)npairs, (unsigned)chunks), dim3(256), 0, s, P, ld,
@@ -1239,8 +1412,13 @@ hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* pre
 
 hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, float* V, int64_t ldv, int64_t n,
                            int64_t k, int32_t* work, hipStream_t s) {
-  (void)work;
-  hipLaunchKernelGGL(k_sign_fix, dim3((unsigned)k), dim3(256), 0, s, U, ldu, m, V, ldv, n);
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sign_find, dim3((unsigned)k), dim3(256), 0, s, V, ldv, n, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t rows = m > n ? m : n;
+  hipLaunchKernelGGL(k_sign_apply, dim3((unsigned)ceil_div_dev(rows, 1024), (unsigned)k),
+                     dim3(256), 0, s, U, ldu, m, V, ldv, n, work);
   return hipGetLastError();
 }
 

@@ -194,8 +194,10 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     const int64_t cross = ceil_div(p.lp, kGramBlock) * ceil_div(p.kp, kGramBlock);
     const int64_t blocks = std::max<int64_t>(gram_pairs(p), p.backward ? cross : 0);
     // also holds the 2048 partial sums of the accuracy pass
-    w.gpart = take(std::max<size_t>((size_t)p.gram_chunks * blocks * kGramBlock * kGramBlock * 8,
-                                    2048 * 8));
+    size_t gbytes = std::max<size_t>((size_t)p.gram_chunks * blocks * kGramBlock * kGramBlock * 8,
+                                     2048 * 8);
+    if (gram_tri_fits(p.lp)) gbytes = std::max(gbytes, gram_tri_bytes(p.lp));
+    w.gpart = take(gbytes);
   }
   w.G = take(lp * lp * 8);
   w.L = take(lp * lp * 8);
