@@ -45,6 +45,7 @@ enum {
   RSVD_OK = 0,
   RSVD_W_RANK_DEFICIENT = 1, /* results valid; some sketch directions were dropped */
   RSVD_W_DEGENERATE = 2,     /* results valid; backward met equal singular values  */
+  RSVD_STOPPED = 3,          /* stopped after the requested pass; see checkpoints  */
   RSVD_E_INVALID_ARG = -1,
   RSVD_E_BUDGET = -2,        /* workspace does not fit the HBM budget              */
   RSVD_E_HIP = -3,           /* a HIP runtime call failed                          */
@@ -255,6 +256,66 @@ rsvd_status rsvd_omega(uint64_t seed, int64_t n, int64_t l, int64_t row0, int64_
 rsvd_status rsvd_factor_csr(rsvd_plan_t plan, const int32_t* rowptr, const int32_t* colind,
                             const float* values, void* ws, float* U, int64_t ldu, double* S,
                             float* V, int64_t ldv, void* stream, rsvd_report* report);
+
+/* ---- per-pass persistence and resume (Section 3.8) ----------------------- */
+/* The paper keeps every intermediate matrix with a header that places it in
+ * the execution plan, so that an interrupted run recomputes only what was not
+ * completed.  Here the state of a factorisation after each completed pass
+ * over A is one FP32 panel plus a header:
+ *   pass 1 (sketch A O, orthonormalised)           Q   m x lp   side 0
+ *   pass 2t   (t = 1..q, A^T Q, orthonormalised)   Z   n x lp   side 1
+ *   pass 2t+1 (t = 1..q, A Z, orthonormalised)     Q   m x lp   side 0
+ *   pass 2q+2 (the projection B^T = A^T Q)         B^T n x lp   side 1
+ * lp is the sketch width rounded up to 32 (columns l..lp-1 are zero).  The
+ * panel is column-major with leading dimension `rows` (host memory, owned by
+ * the caller).  All reductions of the library are deterministic, so a run
+ * resumed from the checkpoint of pass t returns the same U, S and V, bit for
+ * bit, as an uninterrupted run. */
+#define RSVD_CKPT_MAGIC 0x31504B4344565352ull   /* "RSVDCKP1" little-endian */
+typedef struct {
+  uint64_t magic;          /* RSVD_CKPT_MAGIC                                 */
+  int32_t version;         /* 1                                               */
+  int32_t passes;          /* passes over A completed, 1 .. 2q + 2            */
+  int64_t m, n, k, p, q;   /* the plan's problem                              */
+  uint64_t seed;
+  int32_t prec_sketch, prec_power, prec_project;
+  int32_t flags;           /* the plan's RSVD_FLAG_CHOLQR1 bit                */
+  int64_t rows, cols;      /* panel shape: rows x cols (cols = lp)            */
+  int32_t side;            /* 0: m-side basis, 1: n-side panel                */
+  int32_t dropped;         /* directions dropped so far                       */
+  int32_t nonfinite;       /* non-finite values met so far                    */
+  int32_t reserved;
+  uint64_t panel_hash;     /* 64-bit hash of the panel bytes (see below)      */
+} rsvd_checkpoint;
+
+/* Bytes of the largest checkpoint panel of the plan: max(m, n) * lp * 4. */
+rsvd_status rsvd_checkpoint_bytes(rsvd_plan_t plan, size_t* panel_bytes);
+
+/* rsvd_factor (dense A, device- or host-resident) with persistence:
+ *   resume, resume_panel  NULL: start from the beginning.  Otherwise a
+ *          checkpoint of this plan (problem, seed, precisions and CHOLQR1 bit
+ *          must match, the panel hash must match the bytes) and its panel
+ *          (host): the run continues after pass resume->passes.
+ *   ckpt, ckpt_panel      NULL: no saving.  Otherwise after every pass the
+ *          call waits for the stream and copies the state into *ckpt and
+ *          ckpt_panel (host, rsvd_checkpoint_bytes), so that they always hold
+ *          the last completed pass.
+ *   stop_after            0: run to the end.  1 .. 2q + 2: return
+ *          RSVD_STOPPED once that many passes are complete (U, S, V are then
+ *          not written); with ckpt the state of that pass is saved.
+ * The panel hash is 64-bit FNV-1a over the panel's 32-bit words taken as
+ * units (offset basis 0xcbf29ce484222325, prime 0x100000001b3).
+ * RSVD_E_INVALID_ARG for a checkpoint of another problem, a pass out of
+ * range, a shape that does not match its pass, or a hash mismatch (nothing
+ * runs).  RSVD_E_UNSUPPORTED for RSVD_FLAG_AUTO_Q plans and CSR plans.
+ * `report` as in rsvd_factor (not filled by a call that stops): stage times
+ * of a resumed call cover only the passes it ran.  A call that resumes after
+ * the projection runs no pass and leaves *ckpt untouched. */
+rsvd_status rsvd_factor_resumable(rsvd_plan_t plan, const void* A, int64_t lda, void* ws,
+                                  float* U, int64_t ldu, double* S, float* V, int64_t ldv,
+                                  void* stream, rsvd_report* report,
+                                  const rsvd_checkpoint* resume, const float* resume_panel,
+                                  int32_t stop_after, rsvd_checkpoint* ckpt, float* ckpt_panel);
 
 /* ---- single-step hooks: one step of rsvd_factor in isolation ------------- */
 /* They run the same kernels as rsvd_factor on caller panels, using the plan's

@@ -5,6 +5,6 @@ block-cyclic tiles with power iteration), behind the C ABI of librsvd.so.
     U, S, V, info = factor(A_cuda_fp32, k=100, p=20, q=2)
 """
 
-from .api import Plan, RSVD, factor, omega, philox_raw, col_major  # noqa: F401
+from .api import Checkpoint, Plan, RSVD, factor, omega, philox_raw, col_major  # noqa: F401
 
-__all__ = ["Plan", "RSVD", "factor", "omega", "philox_raw", "col_major"]
+__all__ = ["Checkpoint", "Plan", "RSVD", "factor", "omega", "philox_raw", "col_major"]

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsvd.so"
 OK = 0
 W_RANK_DEFICIENT = 1
 W_DEGENERATE = 2
+STOPPED = 3
 E_INVALID_ARG = -1
 E_BUDGET = -2
 E_HIP = -3
@@ -55,6 +56,18 @@ class Report(ctypes.Structure):
                 ("sketch_ms", ctypes.c_double)]
 
 
+CKPT_MAGIC = 0x31504B4344565352   # "RSVDCKP1" little-endian
+
+
+class Checkpoint(ctypes.Structure):
+    _fields_ = [("magic", c_u64), ("version", c_i32), ("passes", c_i32), ("m", c_i64),
+                ("n", c_i64), ("k", c_i64), ("p", c_i64), ("q", c_i64), ("seed", c_u64),
+                ("prec_sketch", c_i32), ("prec_power", c_i32), ("prec_project", c_i32),
+                ("flags", c_i32), ("rows", c_i64), ("cols", c_i64), ("side", c_i32),
+                ("dropped", c_i32), ("nonfinite", c_i32), ("reserved", c_i32),
+                ("panel_hash", c_u64)]
+
+
 _P = ctypes.POINTER
 _SIGS = {
     "rsvd_plan": (c_i32, [_P(Problem), _P(Options), _P(c_vp), _P(c_sz)]),
@@ -64,6 +77,10 @@ _SIGS = {
                               c_vp, c_vp, _P(Report)]),
     "rsvd_factor_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
                                 _P(Report)]),
+    "rsvd_checkpoint_bytes": (c_i32, [c_vp, _P(c_sz)]),
+    "rsvd_factor_resumable": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64,
+                                      c_vp, _P(Report), _P(Checkpoint), c_vp, c_i32,
+                                      _P(Checkpoint), c_vp]),
     "rsvd_step_spmm": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "rsvd_residual": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "rsvd_plan_destroy": (None, [c_vp]),

@@ -56,6 +56,42 @@ def _csr_arrays(rowptr, colind, values, plan):
     return rowptr, colind, values
 
 
+class Checkpoint:
+    """State of a factorisation after a completed pass over A (header fields
+    as in rsvd_checkpoint, plus the FP32 panel as a (rows, cols) column-major
+    numpy array).  Files hold the header's bytes followed by the panel's."""
+
+    def __init__(self, header, panel):
+        self.header = header          # L.Checkpoint
+        self.panel = panel            # numpy float32, shape (cols, rows) C-order = column-major
+
+    @property
+    def passes(self):
+        return self.header.passes
+
+    def save(self, path):
+        import numpy as np
+        with open(path, "wb") as f:
+            f.write(bytes(self.header))
+            f.write(np.ascontiguousarray(self.panel, dtype=np.float32).tobytes())
+
+    @classmethod
+    def load(cls, path):
+        import numpy as np
+        with open(path, "rb") as f:
+            raw = f.read(ctypes.sizeof(L.Checkpoint))
+            if len(raw) != ctypes.sizeof(L.Checkpoint):
+                raise ValueError("truncated checkpoint header")
+            hdr = L.Checkpoint.from_buffer_copy(raw)
+            if hdr.magic != L.CKPT_MAGIC:
+                raise ValueError("not a checkpoint file")
+            count = int(hdr.rows) * int(hdr.cols)
+            panel = np.fromfile(f, dtype=np.float32, count=count)
+        if panel.size != count:
+            raise ValueError("truncated checkpoint panel")
+        return cls(hdr, panel.reshape(int(hdr.cols), int(hdr.rows)))
+
+
 class Plan:
     """A validated problem with its tile map and workspace size."""
 
@@ -162,6 +198,54 @@ class Plan:
                         slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads,
                         q_used=rep.q_used, q_delta=rep.q_delta, sketch_ms=rep.sketch_ms)
         return U, S, V, info
+
+    def factor_resumable(self, A, stop_after=0, resume=None, save=True, ws=None, stream=None,
+                         report=True):
+        """rsvd_factor_resumable: returns (U, S, V, info, ckpt).  ``stop_after``
+        (1 .. 2q + 2) ends the call after that pass (U, S, V are then None);
+        ``resume`` is a Checkpoint to continue from; with ``save`` the returned
+        ckpt holds the state after the last completed pass."""
+        import numpy as np
+        lda = _ld_row_major(A)
+        if A.dtype != self.dtype or tuple(A.shape) != (self.m, self.n):
+            raise ValueError("A does not match the plan")
+        if self.host != (not A.is_cuda):
+            raise ValueError("A must be a pinned CPU tensor for a host plan, a cuda tensor otherwise")
+        dev = torch.device("cuda", torch.cuda.current_device()) if self.host else A.device
+        ws = self.workspace(dev) if ws is None else ws
+        U = col_major(self.m, self.k, device=dev)
+        S = torch.empty(self.k, dtype=torch.float64, device=dev)
+        V = col_major(self.n, self.k, device=dev)
+        nbytes = ctypes.c_size_t()
+        L.check(L.lib().rsvd_checkpoint_bytes(self.handle, ctypes.byref(nbytes)), self.handle)
+        out_hdr = L.Checkpoint() if save else None
+        out_panel = np.zeros(nbytes.value // 4, dtype=np.float32) if save else None
+        in_hdr, in_panel = None, None
+        if resume is not None:
+            in_hdr = resume.header
+            in_panel = np.ascontiguousarray(resume.panel, dtype=np.float32)
+        rep = L.Report() if report else None
+        st = L.lib().rsvd_factor_resumable(
+            self.handle, _ptr(A), lda, _ptr(ws), _ptr(U), _ld_col_major(U), _ptr(S), _ptr(V),
+            _ld_col_major(V), _stream_ptr(stream),
+            ctypes.byref(rep) if rep is not None else None,
+            ctypes.byref(in_hdr) if in_hdr is not None else None,
+            ctypes.c_void_p(in_panel.ctypes.data) if in_panel is not None else None,
+            int(stop_after),
+            ctypes.byref(out_hdr) if out_hdr is not None else None,
+            ctypes.c_void_p(out_panel.ctypes.data) if out_panel is not None else None)
+        L.check(st, self.handle)
+        ckpt = None
+        if save and out_hdr.magic == L.CKPT_MAGIC:
+            rows, cols = int(out_hdr.rows), int(out_hdr.cols)
+            ckpt = Checkpoint(out_hdr, out_panel[:rows * cols].reshape(cols, rows).copy())
+        info = {"status": st}
+        if st == L.STOPPED:
+            return None, None, None, info, ckpt
+        if rep is not None:
+            info.update(stage_ms=list(rep.stage_ms), total_ms=rep.total_ms,
+                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps)
+        return U, S, V, info, ckpt
 
     def backward(self, A, gU=None, gS=None, gV=None, ws=None, stream=None, report=True):
         """gA (m x n, row-major FP32) of the truncated-SVD adjoint; the plan must

@@ -85,15 +85,17 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
     for (int c = j + 1; c < kB; ++c) d[c] -= d[j] * row16_bcast(d[j], c);
     __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of a step inside it
   }
-  // lane r: column r of X_kk = L_kk^-1 by forward substitution
+  // lane r: column r of X_kk = L_kk^-1 by forward substitution, column
+  // oriented: once x_p is known it leaves every later row at once (the
+  // subtractions of each row keep the order p = 0, 1, ...)
   double x[kB];
 #pragma unroll
-  for (int i = 0; i < kB; ++i) {
-    double acc = (i == r) ? 1.0 : 0.0;
+  for (int i = 0; i < kB; ++i) x[i] = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-    for (int p = 0; p < i; ++p) acc -= row16_bcast(d[p], i) * x[p];
-    x[i] = acc * row16_bcast(dv, i);
-    __builtin_amdgcn_sched_barrier(0);
+  for (int p = 0; p < kB; ++p) {
+    x[p] *= row16_bcast(dv, p);
+#pragma unroll
+    for (int i = p + 1; i < kB; ++i) x[i] -= row16_bcast(d[p], i) * x[p];
   }
   if (lane < kB) {
 #pragma unroll
@@ -136,15 +138,23 @@ __device__ void update_tile(double* S, int kb, int I, int J) {
 // X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ, stored transposed at block (J, I).
 __device__ void inverse_tile(double* S, const double* Xd, int I, int J) {
   const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
-  f64x4 t = {0.0, 0.0, 0.0, 0.0};
+  // two accumulators (k-steps 0, 1 and 2, 3 of each block) halve the chain
+  // of dependent products
+  f64x4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
   for (int K = J; K < I; ++K) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 4 * s + q;
       const double b = (K == J) ? Xd[J * kB * kB + xq(k, l16)] : S[sq(J * kB + l16, K * kB + k)];
-      t = mma(S[sq(I * kB + l16, K * kB + k)], b, t);
+      if (s < 2)
+        t0 = mma(S[sq(I * kB + l16, K * kB + k)], b, t0);
+      else
+        t1 = mma(S[sq(I * kB + l16, K * kB + k)], b, t1);
     }
   }
+  f64x4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = t0[r] + t1[r];
   // the accumulator register s holds row 4s + q, column l16 of T: exactly the
   // B operand of k-step s
   f64x4 x = {0.0, 0.0, 0.0, 0.0};
@@ -173,12 +183,13 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
     double2 v[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
+      // every thread loads (from a clamped, in-range address) and then masks,
+      // so that the loads of a batch are all in flight together
       const int e = e0 + u * kThreads, i = e >> 6, c = (e & 63) * 2;
-      v[u] = make_double2(0.0, 0.0);
-      if (i < l && c < l) {
-        v[u] = *reinterpret_cast<const double2*>(G + (int64_t)i * n + c);
-        if (c + 1 >= l) v[u].y = 0.0;
-      }
+      const int ic = min(i, n - 1), cc = min(c, n - 2);
+      const double2 w = *reinterpret_cast<const double2*>(G + (int64_t)ic * n + cc);
+      v[u].x = (i < l && c < l) ? w.x : 0.0;
+      v[u].y = (i < l && c + 1 < l) ? w.y : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
@@ -230,18 +241,15 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
     constexpr int kQuads = kSq * kSq / 4;
     for (int e = tid; e < kQuads; e += kThreads) {
       const int a = e >> 5, c0 = (e & 31) * 4;
-      if (a < n && c0 < n) {
-        float v[4];
+      float v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = c0 + u;
-          v[u] = 0.f;
-          if (c < l && a <= c)
-            v[u] = (float)((a >> 4) == (c >> 4) ? Xd[(c >> 4) * kB * kB + xq(c & 15, a & 15)]
-                                                : S[sq(a, c)]);
-        }
-        st4(W + (int64_t)a * n + c0, make_float4(v[0], v[1], v[2], v[3]));
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u;
+        const double xd = Xd[(c >> 4) * kB * kB + xq(c & 15, a & 15)];
+        const double xs = S[sq(a, c)];
+        v[u] = (c < l && a <= c) ? (float)((a >> 4) == (c >> 4) ? xd : xs) : 0.f;
       }
+      if (a < n && c0 < n) st4(W + (int64_t)a * n + c0, make_float4(v[0], v[1], v[2], v[3]));
     }
   }
   if (tid == 0) {

@@ -222,6 +222,26 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   return B;
 }
 
+// ---- checkpoint layout (rsvd_factor_resumable) ---------------------------
+// side of the state after pass t of npass: 0 the m-side basis, 1 the n-side
+// panel, 2 (after the projection) the basis over B^T.
+int ckpt_side(int64_t t, int64_t npass) { return t == npass ? 2 : (t % 2 == 1 ? 0 : 1); }
+
+int64_t ckpt_rows(const rsvd::Plan& P, int side) {
+  return side == 0 ? P.prob.m : side == 1 ? P.prob.n : P.prob.m + P.prob.n;
+}
+
+// 64-bit FNV-1a over 32-bit words (each word is one unit of the hash).
+uint64_t ckpt_hash(const float* p, size_t words) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < words; ++i) {
+    h ^= w[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
 // The runner holds everything one call needs.
 struct Runner {
   rsvd_plan_t h;
@@ -246,6 +266,15 @@ struct Runner {
   int64_t pass_no = 0;         // passes over A so far in this call
   int64_t q_used = 0;          // power steps run
   double q_delta = 0.0;        // automatic q: last relative change
+  // per-pass persistence (rsvd_factor_resumable); null for the plain calls
+  struct Ckpt {
+    const rsvd_checkpoint* resume;
+    const float* resume_panel;
+    int32_t stop_after;
+    rsvd_checkpoint* out;
+    float* out_panel;
+  };
+  const Ckpt* ck = nullptr;
 
   hipError_t tick(bool nn, bool start) {
     if (!ev) return hipSuccess;
@@ -532,6 +561,7 @@ struct Runner {
     const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
     const int32_t ps = P.opt.prec_sketch, pw = P.opt.prec_power, pj = P.opt.prec_project;
     rsvd_status st;
+    if (ck && ck->resume) return forward_resumed(mark, S, kout);
     RSVD_HIP(rsvd::launch_omega_panel(P.prob.seed, n, P.l, P.lp, B.Xop, P.ldn, s));   // step 1
     if ((st = prep(ps, B.Xop, true))) return st;
     RSVD_HIP(mark(1));
@@ -540,6 +570,7 @@ struct Runner {
     if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;   // 3-4
     if ((st = prep(P.prob.q > 0 ? pw : pj, B.Mop, false))) return st;
     RSVD_HIP(mark(3));
+    if (ck && !P.auto_q && (st = ck_after(1))) return st;
     if (P.auto_q) {
       // Section 2.2, automatic iteration parameter: each product A^T Q_t is
       // the projection B^T the factorisation would use with q = t; its small
@@ -566,24 +597,137 @@ struct Runner {
       for (int i = 4; i <= 7; ++i) RSVD_HIP(mark(i));
       return RSVD_OK;
     }
+    return passes_from(mark, S, kout, 2);
+  }
+
+  // Passes t_from .. 2q + 2 over A, then the small SVD.  Pass 1 is the sketch;
+  // passes 2t and 2t + 1 are power step t = 1..q (Eq. (2), right to left),
+  // each product re-orthonormalised; pass 2q + 2 is the projection (step 5).
+  template <typename Mark>
+  rsvd_status passes_from(Mark& mark, double* S, int64_t kout, int64_t t_from) {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    const bool cq1 = (P.opt.flags & RSVD_FLAG_CHOLQR1) != 0;
+    const int32_t pw = P.opt.prec_power, pj = P.opt.prec_project;
+    const int64_t npass = 2 * P.prob.q + 2;
+    rsvd_status st;
     q_used = P.prob.q;
-    for (int64_t t = 0; t < P.prob.q; ++t) {                                          // Eq. (2)
-      const bool last = t + 1 == P.prob.q;
-      if ((st = product_tn(pw, B.Mop, B.N0))) return st;
-      if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
-      if ((st = prep(pw, B.Xop, true))) return st;
-      if ((st = product_nn(pw, B.Xop, B.M0))) return st;
-      if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last))) return st;
-      if ((st = prep(last ? pj : pw, B.Mop, false))) return st;
+    for (int64_t t = t_from; t <= npass; ++t) {
+      if (t == npass) {
+        RSVD_HIP(mark(4));
+        if ((st = product_tn(pj, B.Mop, B.N0))) return st;                             // step 5
+        RSVD_HIP(mark(5));
+      } else if (t % 2 == 0) {
+        if ((st = product_tn(pw, B.Mop, B.N0))) return st;
+        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
+        if ((st = prep(pw, B.Xop, true))) return st;
+      } else {
+        const bool last = t == npass - 1;
+        if ((st = product_nn(pw, B.Xop, B.M0))) return st;
+        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last))) return st;
+        if ((st = prep(last ? pj : pw, B.Mop, false))) return st;
+      }
+      if (ck && (st = ck_after(t))) return st;
     }
-    RSVD_HIP(mark(4));
-    if ((st = product_tn(pj, B.Mop, B.N0))) return st;                                 // step 5
-    RSVD_HIP(mark(5));
+    if (t_from > npass) {   // resumed after the projection
+      RSVD_HIP(mark(4));
+      RSVD_HIP(mark(5));
+    }
     if ((st = small_svd_eig(B.N0))) return st;                                         // SVD0 prep
     RSVD_HIP(mark(6));
     if ((st = small_svd_solve(S, kout))) return st;                                    // step 6
     RSVD_HIP(mark(7));
     return RSVD_OK;
+  }
+
+  // ---- per-pass persistence ------------------------------------------------
+  // The state after pass t: side 0 the m-side basis Q (Mop), side 1 the
+  // n-side panel (Xop), side 2 after the projection Q and B^T (Mop over N0).
+  struct PanelPart {
+    float* dev;
+    int64_t ld, rows, row0;
+  };
+  int parts_of(int side, PanelPart* pp) const {
+    const int64_t m = P.prob.m, n = P.prob.n;
+    if (side == 0) {
+      pp[0] = {B.Mop, P.ldm, m, 0};
+      return 1;
+    }
+    if (side == 1) {
+      pp[0] = {B.Xop, P.ldn, n, 0};
+      return 1;
+    }
+    pp[0] = {B.Mop, P.ldm, m, 0};
+    pp[1] = {B.N0, P.ldn, n, m};
+    return 2;
+  }
+
+  rsvd_status ck_after(int64_t t) {
+    if (ck->out) {
+      const int64_t npass = 2 * P.prob.q + 2;
+      const int side = ckpt_side(t, npass);
+      const int64_t rows = ckpt_rows(P, side);
+      PanelPart pp[2];
+      const int np = parts_of(side, pp);
+      RSVD_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < np; ++i)
+        RSVD_HIP(hipMemcpy2DAsync(ck->out_panel + pp[i].row0, (size_t)rows * 4, pp[i].dev,
+                                  (size_t)pp[i].ld * 4, (size_t)pp[i].rows * 4, (size_t)P.lp,
+                                  hipMemcpyDeviceToHost, s));
+      int32_t stw[rsvd::kStatusWords];
+      RSVD_HIP(hipMemcpyAsync(stw, B.status, sizeof stw, hipMemcpyDeviceToHost, s));
+      RSVD_HIP(hipStreamSynchronize(s));
+      rsvd_checkpoint c{};
+      c.magic = RSVD_CKPT_MAGIC;
+      c.version = 1;
+      c.passes = (int32_t)t;
+      c.m = P.prob.m;
+      c.n = P.prob.n;
+      c.k = P.prob.k;
+      c.p = P.prob.p;
+      c.q = P.prob.q;
+      c.seed = P.prob.seed;
+      c.prec_sketch = P.opt.prec_sketch;
+      c.prec_power = P.opt.prec_power;
+      c.prec_project = P.opt.prec_project;
+      c.flags = P.opt.flags & RSVD_FLAG_CHOLQR1;
+      c.rows = rows;
+      c.cols = P.lp;
+      c.side = side;
+      c.dropped = stw[rsvd::kStDropped];
+      c.nonfinite = stw[rsvd::kStNonFinite];
+      c.panel_hash = ckpt_hash(ck->out_panel, (size_t)rows * (size_t)P.lp);
+      *ck->out = c;
+    }
+    if (ck->stop_after == t) return RSVD_STOPPED;
+    return RSVD_OK;
+  }
+
+  // Continue after the checkpointed pass: load its panel(s) and counters,
+  // make the operand copy the next pass reads, then run the remaining passes.
+  template <typename Mark>
+  rsvd_status forward_resumed(Mark& mark, double* S, int64_t kout) {
+    const int32_t pw = P.opt.prec_power, pj = P.opt.prec_project;
+    const rsvd_checkpoint& c = *ck->resume;
+    const int64_t npass = 2 * P.prob.q + 2, t0 = c.passes;
+    PanelPart pp[2];
+    const int np = parts_of(c.side, pp);
+    for (int i = 0; i < np; ++i)
+      RSVD_HIP(hipMemcpy2DAsync(pp[i].dev, (size_t)pp[i].ld * 4, ck->resume_panel + pp[i].row0,
+                                (size_t)c.rows * 4, (size_t)pp[i].rows * 4, (size_t)P.lp,
+                                hipMemcpyHostToDevice, s));
+    const int32_t cnt[2] = {c.dropped, c.nonfinite};
+    RSVD_HIP(hipMemcpyAsync(B.status + rsvd::kStDropped, &cnt[0], 4, hipMemcpyHostToDevice, s));
+    RSVD_HIP(hipMemcpyAsync(B.status + rsvd::kStNonFinite, &cnt[1], 4, hipMemcpyHostToDevice, s));
+    RSVD_HIP(hipStreamSynchronize(s));   // the counters above live on this stack frame
+    pass_no = t0;
+    rsvd_status st;
+    if (c.side == 0) {
+      if ((st = prep(t0 == npass - 1 ? pj : pw, B.Mop, false))) return st;
+    } else if (c.side == 1) {
+      if ((st = prep(pw, B.Xop, true))) return st;
+    }
+    for (int i = 1; i <= 3; ++i) RSVD_HIP(mark(i));
+    return passes_from(mark, S, kout, t0 + 1);
   }
 
   // Small SVD of B from Bt (n-side panel): leaves sorted S (k), Wu, Wv.
@@ -729,7 +873,8 @@ namespace {
 // The whole path after A has been bound (dense or sparse).
 template <typename Bind>
 rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t ldu, double* S,
-                          float* V, int64_t ldv, void* stream, rsvd_report* report) {
+                          float* V, int64_t ldv, void* stream, rsvd_report* report,
+                          const Runner::Ckpt* ck = nullptr) {
   const rsvd::Plan& P = h->p;
   const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k;
   if (!U || !S || !V) return set_err(h, RSVD_E_INVALID_ARG, "U, S and V must be non-NULL");
@@ -737,6 +882,7 @@ rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t 
 
   hipStream_t s = (hipStream_t)stream;
   Runner R(h, ws, s);
+  R.ck = ck;
   Events* ev = nullptr;
   if (report) {
     rsvd_status est;
@@ -749,7 +895,7 @@ rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t 
   RSVD_HIP(mark(0));
   RSVD_HIP(rsvd::launch_fill_i32(R.B.status, rsvd::kStatusWords, 0, s));
   if ((st = bind(R))) return st;
-  if ((st = R.forward(mark, S, k))) return st;
+  if ((st = R.forward(mark, S, k))) return st;   // RSVD_STOPPED leaves U, S, V unwritten
   // step 7: U = Q E_k (W), V = B^T E_k S^-1 (W2)
   RSVD_HIP(rsvd::launch_apply(R.B.Mop, P.ldm, m, P.l, R.B.W, P.lp, P.lp, k, false, U, ldu, m, s));
   RSVD_HIP(rsvd::launch_apply(R.B.N0, P.ldn, n, P.l, R.B.W2, P.lp, P.lp, k, false, V, ldv, n, s));
@@ -772,6 +918,7 @@ const char* rsvd_status_str(rsvd_status s) {
     case RSVD_OK: return "ok";
     case RSVD_W_RANK_DEFICIENT: return "warning: rank deficient sketch (directions dropped)";
     case RSVD_W_DEGENERATE: return "warning: degenerate singular values";
+    case RSVD_STOPPED: return "stopped after the requested pass";
     case RSVD_E_INVALID_ARG: return "invalid argument";
     case RSVD_E_BUDGET: return "workspace exceeds the HBM budget";
     case RSVD_E_HIP: return "HIP runtime error";
@@ -893,6 +1040,55 @@ rsvd_status rsvd_factor_csr(rsvd_plan_t h, const int32_t* rowptr, const int32_t*
   if (rsvd_status st = check_ws(h, ws)) return st;
   return factor_common(h, [&](Runner& R) { return R.bind_csr(rowptr, colind, values); }, ws, U, ldu,
                        S, V, ldv, stream, report);
+}
+
+rsvd_status rsvd_checkpoint_bytes(rsvd_plan_t h, size_t* panel_bytes) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!panel_bytes) return set_err(h, RSVD_E_INVALID_ARG, "panel_bytes is NULL");
+  const rsvd::Plan& P = h->p;
+  *panel_bytes = (size_t)(P.prob.m + P.prob.n) * (size_t)P.lp * 4;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_factor_resumable(rsvd_plan_t h, const void* A, int64_t lda, void* ws, float* U,
+                                  int64_t ldu, double* S, float* V, int64_t ldv, void* stream,
+                                  rsvd_report* report, const rsvd_checkpoint* resume,
+                                  const float* resume_panel, int32_t stop_after,
+                                  rsvd_checkpoint* ckpt, float* ckpt_panel) {
+  if (rsvd_status st = check_plan(h)) return st;
+  const rsvd::Plan& P = h->p;
+  if (P.csr) return set_err(h, RSVD_E_UNSUPPORTED, "checkpoints are implemented for dense A");
+  if (P.auto_q)
+    return set_err(h, RSVD_E_UNSUPPORTED, "checkpoints are implemented for a fixed q (no AUTO_Q)");
+  const int64_t npass = 2 * P.prob.q + 2;
+  if (stop_after < 0 || stop_after > npass)
+    return set_err(h, RSVD_E_INVALID_ARG, "stop_after must lie in [0, 2q + 2]");
+  if (ckpt && !ckpt_panel) return set_err(h, RSVD_E_INVALID_ARG, "ckpt needs ckpt_panel");
+  if (resume) {
+    const rsvd_checkpoint& c = *resume;
+    if (!resume_panel) return set_err(h, RSVD_E_INVALID_ARG, "resume needs resume_panel");
+    if (c.magic != RSVD_CKPT_MAGIC || c.version != 1)
+      return set_err(h, RSVD_E_INVALID_ARG, "not a version-1 checkpoint");
+    if (c.m != P.prob.m || c.n != P.prob.n || c.k != P.prob.k || c.p != P.prob.p ||
+        c.q != P.prob.q || c.seed != P.prob.seed || c.prec_sketch != P.opt.prec_sketch ||
+        c.prec_power != P.opt.prec_power || c.prec_project != P.opt.prec_project ||
+        c.flags != (P.opt.flags & RSVD_FLAG_CHOLQR1))
+      return set_err(h, RSVD_E_INVALID_ARG, "the checkpoint belongs to another problem or plan");
+    if (c.passes < 1 || c.passes > npass)
+      return set_err(h, RSVD_E_INVALID_ARG, "checkpoint pass out of range");
+    const int side = ckpt_side(c.passes, npass);
+    if (c.side != side || c.rows != ckpt_rows(P, side) || c.cols != P.lp)
+      return set_err(h, RSVD_E_INVALID_ARG, "checkpoint shape does not match its pass");
+    if (ckpt_hash(resume_panel, (size_t)c.rows * (size_t)c.cols) != c.panel_hash)
+      return set_err(h, RSVD_E_INVALID_ARG, "checkpoint panel does not match its hash");
+    if (stop_after != 0 && stop_after <= c.passes)
+      return set_err(h, RSVD_E_INVALID_ARG, "stop_after must lie after the resumed pass");
+  }
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  const Runner::Ckpt ck{resume, resume_panel, stop_after, ckpt, ckpt_panel};
+  return factor_common(h, [&](Runner& R) { return R.bind_A(A, lda); }, ws, U, ldu, S, V, ldv,
+                       stream, report, &ck);
 }
 
 rsvd_status rsvd_step_spmm(rsvd_plan_t h, int32_t op, const int32_t* rowptr, const int32_t* colind,

@@ -1,0 +1,70 @@
+"""Per-pass persistence and resume (Section 3.8): a run stopped after any
+pass and resumed from its checkpoint file returns U, S and V bitwise equal to
+an uninterrupted run (every reduction of the library is deterministic), for
+FP32 and BF16 operands, device- and host-resident A, and a chain of stops."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from paper_1907_06470_amd import Checkpoint, Plan
+from paper_1907_06470_amd import _lib as L
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _A(m, n, seed):
+    return workloads.dense_lowrank(m, n, workloads.spectrum_pow(min(m, n), 0.8), 1e-5, seed=seed,
+                                   out_dtype=torch.float32)
+
+
+@pytest.mark.parametrize("precision,q,host", [("fp32", 2, False), ("bf16", 1, False),
+                                               ("fp32", 1, True)])
+def test_stop_and_resume_every_pass_bitwise(tmp_path, precision, q, host):
+    dev = need_gpu()
+    m, n, k, p = 2100, 1300, 16, 16       # lp = 32; several 512-tiles with ragged edges
+    say("checkpoint", precision, q, host)
+    A = _A(m, n, 21)
+    A = A.pin_memory() if host else A.to(dev)
+    plan = Plan(m, n, k, p, q, seed=5, precision=precision, tile=(512, 512), host=host)
+    U0, S0, V0, info0 = plan.factor(A)
+    npass = 2 * q + 2
+    for t in range(1, npass + 1):
+        Us, Ss, Vs, info, ck = plan.factor_resumable(A, stop_after=t)
+        assert info["status"] == L.STOPPED and Us is None
+        assert ck.passes == t and ck.header.side == (2 if t == npass else (0 if t % 2 else 1))
+        path = tmp_path / f"pass{t}.ckpt"
+        ck.save(path)
+        back = Checkpoint.load(path)
+        U1, S1, V1, info1, last = plan.factor_resumable(A, resume=back)
+        assert torch.equal(S0, S1) and torch.equal(U0, U1) and torch.equal(V0, V1), t
+        assert info1["dropped"] == info0["dropped"]
+        # the state saved is the last pass this call completed (none if it
+        # resumed after the projection)
+        assert last is None if t == npass else last.passes == npass
+
+
+def test_chain_of_stops_and_a_tampered_panel(tmp_path):
+    dev = need_gpu()
+    m, n, k, p, q = 1800, 2200, 20, 12, 2
+    A = _A(m, n, 22).to(dev)
+    plan = Plan(m, n, k, p, q, seed=9, tile=(1024, 768))
+    U0, S0, V0, _ = plan.factor(A)
+    _, _, _, info, c2 = plan.factor_resumable(A, stop_after=2)
+    assert info["status"] == L.STOPPED
+    _, _, _, info, c4 = plan.factor_resumable(A, resume=c2, stop_after=4)
+    assert info["status"] == L.STOPPED and c4.passes == 4
+    U1, S1, V1, _, _ = plan.factor_resumable(A, resume=c4)
+    assert torch.equal(S0, S1) and torch.equal(U0, U1) and torch.equal(V0, V1)
+    # the same state from a single stop at 4
+    _, _, _, _, d4 = plan.factor_resumable(A, stop_after=4)
+    assert np.array_equal(c4.panel, d4.panel) and c4.header.panel_hash == d4.header.panel_hash
+    bad = Checkpoint(c4.header, c4.panel.copy())
+    bad.panel[0, 0] = np.nextafter(bad.panel[0, 0], np.float32(np.inf))
+    with pytest.raises(L.RsvdError) as e:
+        plan.factor_resumable(A, resume=bad)
+    assert e.value.status == L.E_INVALID_ARG
+    other = Plan(m, n, k, p, q, seed=10, tile=(1024, 768))
+    with pytest.raises(L.RsvdError):
+        other.factor_resumable(A, resume=c4)
