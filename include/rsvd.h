@@ -53,7 +53,7 @@ enum {
   RSVD_E_NUMERIC = -5        /* NaN/Inf met on the device                          */
 };
 
-enum { RSVD_DENSE = 0, RSVD_CSR = 1 };                               /* formats   */
+enum { RSVD_DENSE = 0, RSVD_CSR = 1, RSVD_COO = 2 };                /* formats   */
 enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2, RSVD_FP8E4M3 = 3 }; /* dtypes    */
 enum { RSVD_LOC_DEVICE = 0, RSVD_LOC_HOST_PINNED = 1 };              /* locations */
 enum { RSVD_ORTHO_EACH = 0, RSVD_ORTHO_FINAL_ONLY = 2 };             /* schedules */
@@ -68,12 +68,12 @@ enum {
  * (Section 2.1; Section 2.2, Eq. (1)), Gaussian test matrix from `seed`. */
 typedef struct {
   int64_t m, n, k, p, q;
-  int32_t format;   /* RSVD_DENSE, or RSVD_CSR (see rsvd_factor_csr)      */
+  int32_t format;   /* RSVD_DENSE, RSVD_CSR or RSVD_COO (rsvd_factor_coo) */
   int32_t dtype;    /* storage type of A: RSVD_F32 or RSVD_F64            */
   int32_t loc;      /* RSVD_LOC_DEVICE, or RSVD_LOC_HOST_PINNED (dense)   */
   int32_t reserved;
   uint64_t seed;
-  int64_t nnz;      /* CSR only                                           */
+  int64_t nnz;      /* CSR and COO only                                   */
 } rsvd_problem;
 
 /* Options.  prec_* choose the operand type of the products with A in the
@@ -321,6 +321,25 @@ rsvd_status rsvd_factor_resumable(rsvd_plan_t plan, const void* A, int64_t lda, 
 /* They run the same kernels as rsvd_factor on caller panels, using the plan's
  * workspace `ws` for staging.  Panels are column-major FP32 (element (i, c) at
  * P[i + c * ld]) with l = k + p columns.  Asynchronous on `stream`. */
+
+/* Randomized SVD of a sparse A in coordinate (COO) form (Section 3.3: the
+ * paper's sparse format, with 32- or 64-bit indices).  The plan's problem has
+ * format RSVD_COO, dtype RSVD_F32, nnz entries, device location, FP32
+ * products (as for CSR).
+ *   rowind, colind  device arrays of nnz indices, int32 (index_bits 32) or
+ *                   int64 (index_bits 64); any order; repeated (row, col)
+ *                   pairs add up.
+ *   values          device, nnz FP32.
+ * The entries are ordered by row with a stable radix sort into CSR arrays in
+ * the workspace (within a row they keep their input order, so a row-sorted
+ * input gives exactly the CSR path's result), and the call continues as
+ * rsvd_factor_csr.  An index outside [0, m) x [0, n) returns
+ * RSVD_E_INVALID_ARG once `report` is given (every kernel stays in bounds).
+ * Other arguments and statuses as rsvd_factor_csr. */
+rsvd_status rsvd_factor_coo(rsvd_plan_t plan, const void* rowind, const void* colind,
+                            int32_t index_bits, const float* values, void* ws, float* U,
+                            int64_t ldu, double* S, float* V, int64_t ldv, void* stream,
+                            rsvd_report* report);
 
 /* Sparse product with the plan's CSR matrix (arrays as in rsvd_factor_csr):
  * op 0: out (m x l) = A X with X n x l; op 1: out (n x l) = A^T X with X

@@ -22,7 +22,7 @@ E_HIP = -3
 E_UNSUPPORTED = -4
 E_NUMERIC = -5
 
-DENSE, CSR = 0, 1
+DENSE, CSR, COO = 0, 1, 2
 F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
 LOC_DEVICE, LOC_HOST_PINNED = 0, 1
 ORTHO_EACH, ORTHO_FINAL_ONLY = 0, 2
@@ -77,6 +77,8 @@ _SIGS = {
                               c_vp, c_vp, _P(Report)]),
     "rsvd_factor_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
                                 _P(Report)]),
+    "rsvd_factor_coo": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp,
+                                c_i64, c_vp, _P(Report)]),
     "rsvd_checkpoint_bytes": (c_i32, [c_vp, _P(c_sz)]),
     "rsvd_factor_resumable": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64,
                                       c_vp, _P(Report), _P(Checkpoint), c_vp, c_i32,

@@ -97,11 +97,12 @@ class Plan:
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
                  tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False,
-                 nnz=None, auto_q=False, q_tol=0.0):
+                 nnz=None, auto_q=False, q_tol=0.0, coo=False):
         """host=True: A stays in pinned host memory and is streamed to the
         device tile by tile on every pass (hbm_budget bounds the slots).
         nnz: A is sparse (CSR with int32 indices, FP32 values) with nnz
-        nonzeros; use factor_csr / factor with a sparse CSR tensor.
+        nonzeros; use factor_csr / factor with a sparse CSR tensor.  With
+        coo=True the nnz entries come as COO arrays (factor_coo).
         auto_q: q is a maximum; the power iteration stops once the leading k
         singular values change by at most q_tol (relative) from one q to the
         next (Section 2.2); info["q_used"] reports the q chosen."""
@@ -109,7 +110,7 @@ class Plan:
             flags |= L.FLAG_BACKWARD
         if auto_q:
             flags |= L.FLAG_AUTO_Q
-        prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE if nnz is None else L.CSR,
+        prob = L.Problem(m=m, n=n, k=k, p=p, q=q, format=L.DENSE if nnz is None else (L.COO if coo else L.CSR),
                          dtype=_DT.get(dtype, -99),
                          loc=L.LOC_HOST_PINNED if host else L.LOC_DEVICE, reserved=0, seed=seed,
                          nnz=0 if nnz is None else int(nnz))
@@ -135,6 +136,7 @@ class Plan:
         self.dtype = dtype
         self.host = host
         self.nnz = nnz
+        self.coo = coo
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -311,6 +313,45 @@ class Plan:
                         gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
                         dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps,
                         q_used=rep.q_used, q_delta=rep.q_delta)
+        return U, S, V, info
+
+    def factor_coo(self, rowind, colind, values, ws=None, out=None, stream=None, report=True):
+        """Randomized SVD of a sparse A given as COO device arrays (rowind and
+        colind both int32 or both int64, nnz entries in any order; float32
+        values).  Returns (U, S, V, info) as factor_csr."""
+        if not self.coo:
+            raise ValueError("the plan is not for COO input (Plan(..., nnz=, coo=True))")
+        if rowind.dtype != colind.dtype or rowind.dtype not in (torch.int32, torch.int64):
+            raise ValueError("COO indices must both be int32 or both int64")
+        rowind, colind = rowind.contiguous(), colind.contiguous()
+        values = values.to(torch.float32).contiguous()
+        if rowind.numel() != self.nnz or colind.numel() != self.nnz or values.numel() != self.nnz:
+            raise ValueError("COO arrays do not match the plan")
+        if not (rowind.is_cuda and colind.is_cuda and values.is_cuda):
+            raise ValueError("COO arrays must be cuda tensors")
+        bits = 64 if rowind.dtype == torch.int64 else 32
+        dev = rowind.device
+        ws = self.workspace(dev) if ws is None else ws
+        if out is None:
+            U = col_major(self.m, self.k, device=dev)
+            S = torch.empty(self.k, dtype=torch.float64, device=dev)
+            V = col_major(self.n, self.k, device=dev)
+        else:
+            U, S, V = out
+        rep = L.Report() if report else None
+        st = L.lib().rsvd_factor_coo(self.handle, _ptr(rowind), _ptr(colind), bits, _ptr(values),
+                                     _ptr(ws), _ptr(U), _ld_col_major(U), _ptr(S), _ptr(V),
+                                     _ld_col_major(V), _stream_ptr(stream),
+                                     ctypes.byref(rep) if rep is not None else None)
+        L.check(st, self.handle)
+        info = {"status": st}
+        if rep is not None:
+            info.update(stage_ms=list(rep.stage_ms), total_ms=rep.total_ms,
+                        flops_alg=rep.flops_alg, bytes_alg=rep.bytes_alg,
+                        gemm_nn_ms=rep.gemm_nn_ms, gemm_tn_ms=rep.gemm_tn_ms,
+                        gemm_nn_launches=rep.gemm_nn_launches,
+                        gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
+                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps)
         return U, S, V, info
 
     def step_spmm(self, op, rowptr, colind, values, X, ws=None, stream=None):

@@ -278,6 +278,43 @@ __global__ void k_csc_finish(const uint32_t* __restrict__ keys, const uint64_t* 
   cval[e] = __builtin_bit_cast(float, (uint32_t)(p & 0xffffffffu));
 }
 
+// COO to CSR: keys = row, payload = (column << 32) | value bits.  Indices
+// outside [0, m) x [0, n) are clamped (every later access stays in bounds)
+// and flagged in the status word.
+template <typename IT>
+__global__ void k_coo_keys(const IT* __restrict__ ri, const IT* __restrict__ ci,
+                           const float* __restrict__ values, int64_t m, int64_t n, int64_t nnz,
+                           uint32_t* __restrict__ keys, uint64_t* __restrict__ payload,
+                           int32_t* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int64_t r = (int64_t)ri[e], c = (int64_t)ci[e];
+  if (r < 0 || r >= m || c < 0 || c >= n) atomicOr(status + kStBadSparse, 1);
+  const int64_t rc = min<int64_t>(max<int64_t>(r, 0), m - 1);
+  const int64_t cc = min<int64_t>(max<int64_t>(c, 0), n - 1);
+  keys[e] = (uint32_t)rc;
+  payload[e] = ((uint64_t)(uint32_t)cc << 32) | (uint64_t)__builtin_bit_cast(uint32_t, values[e]);
+}
+
+// row pointers from the sorted keys, then the column indices and values
+__global__ void k_coo_finish(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ payload,
+                             int64_t nnz, int64_t m, int32_t* __restrict__ rowptr,
+                             int32_t* __restrict__ colind, float* __restrict__ val) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nnz) return;
+  if (e == nnz) {   // trailing empty rows
+    const int64_t last = nnz ? (int64_t)keys[nnz - 1] : -1;
+    for (int64_t r = last + 1; r <= m; ++r) rowptr[r] = (int32_t)nnz;
+    return;
+  }
+  const int64_t k = keys[e];
+  const int64_t prev = e ? (int64_t)keys[e - 1] : -1;
+  for (int64_t r = prev + 1; r <= k; ++r) rowptr[r] = (int32_t)e;
+  const uint64_t p = payload[e];
+  colind[e] = (int32_t)(p >> 32);
+  val[e] = __builtin_bit_cast(float, (uint32_t)(p & 0xffffffffu));
+}
+
 }  // namespace
 
 
@@ -325,6 +362,44 @@ hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const 
   }
   hipLaunchKernelGGL(k_csc_finish, dim3(1), dim3(256), 0, s, keys1, pay1, nnz, n, colptr, rowind,
                      cval);
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_bits,
+                             const float* values, int64_t m, int64_t n, int64_t nnz,
+                             uint32_t* keys0, uint32_t* keys1, uint64_t* pay0, uint64_t* pay1,
+                             void* temp, size_t temp_bytes, int32_t* rowptr, int32_t* col,
+                             float* val, int32_t* status, size_t* need, hipStream_t s) {
+  *need = 0;
+  if (nnz == 0) {
+    hipLaunchKernelGGL(k_coo_finish, dim3(1), dim3(256), 0, s, keys1, pay1, nnz, m, rowptr, col,
+                       val);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)ceil_div_dev(nnz, 256));
+  if (index_bits == 64)
+    hipLaunchKernelGGL(k_coo_keys<int64_t>, grid, dim3(256), 0, s, (const int64_t*)rowind,
+                       (const int64_t*)colind, values, m, n, nnz, keys0, pay0, status);
+  else
+    hipLaunchKernelGGL(k_coo_keys<int32_t>, grid, dim3(256), 0, s, (const int32_t*)rowind,
+                       (const int32_t*)colind, values, m, n, nnz, keys0, pay0, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  unsigned bits = 1;
+  while (bits < 32 && (int64_t(1) << bits) < m) ++bits;
+  rocprim::double_buffer<uint32_t> kb(keys0, keys1);
+  rocprim::double_buffer<uint64_t> vb(pay0, pay1);
+  size_t want = 0;
+  e = rocprim::radix_sort_pairs(nullptr, want, kb, vb, (size_t)nnz, 0, bits, s);
+  if (e != hipSuccess) return e;
+  if (want > temp_bytes) {
+    *need = want;
+    return hipErrorOutOfMemory;
+  }
+  e = rocprim::radix_sort_pairs(temp, want, kb, vb, (size_t)nnz, 0, bits, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_coo_finish, dim3((unsigned)ceil_div_dev(nnz + 1, 256)), dim3(256), 0, s,
+                     kb.current(), vb.current(), nnz, m, rowptr, col, val);
   return hipGetLastError();
 }
 

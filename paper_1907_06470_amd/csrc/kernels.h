@@ -80,6 +80,11 @@ hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const 
                             hipStream_t s);
 // out (column-major, ldo rows) = S X for S (rows x xrows) in compressed-row
 // form and X column-major (ldx); Xr, Yr, carry, first are scratch
+hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_bits,
+                             const float* values, int64_t m, int64_t n, int64_t nnz,
+                             uint32_t* keys0, uint32_t* keys1, uint64_t* pay0, uint64_t* pay1,
+                             void* temp, size_t temp_bytes, int32_t* rowptr, int32_t* col,
+                             float* val, int32_t* status, size_t* need, hipStream_t s);
 hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val, int64_t rows,
                        int64_t nnz, const float* X, int64_t ldx, int64_t xrows, int64_t lp,
                        float* Xr, float* Yr, float* carry, int32_t* first, float* out,

@@ -55,9 +55,12 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (k + pp > std::min(m, n))
     return fail(p, RSVD_E_INVALID_ARG, "k + p = %lld exceeds min(m, n) = %lld", k + pp,
                 std::min(m, n));
-  if (prob.format != RSVD_DENSE && prob.format != RSVD_CSR)
+  if (prob.format != RSVD_DENSE && prob.format != RSVD_CSR && prob.format != RSVD_COO)
     return fail(p, RSVD_E_INVALID_ARG, "unknown format %lld", prob.format);
-  p.csr = prob.format == RSVD_CSR;
+  p.coo = prob.format == RSVD_COO;
+  p.csr = prob.format == RSVD_CSR || p.coo;
+  if (p.coo && (m > 2147483647ll || n > 2147483647ll))
+    return fail(p, RSVD_E_UNSUPPORTED, "COO input needs m, n < 2^31 (internal int32 CSR)");
   if (p.csr) {
     if (prob.nnz < 0 || prob.nnz > 2147483647ll)
       return fail(p, RSVD_E_INVALID_ARG, "nnz=%lld must be in [0, 2^31) (int32 indices)", prob.nnz);
@@ -283,6 +286,13 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   } else {
     w.colptr = w.rowind = w.cval = w.keys0 = w.keys1 = w.pay0 = w.pay1 = w.sort_temp = off;
     w.Xr = w.Yr = w.carry = w.first = off;
+  }
+  if (p.coo) {
+    w.coo_ptr = take((size_t)(m + 1) * 4);
+    w.coo_col = take((size_t)prob.nnz * 4);
+    w.coo_val = take((size_t)prob.nnz * 4);
+  } else {
+    w.coo_ptr = w.coo_col = w.coo_val = off;
   }
   w.total = off;
 

@@ -66,6 +66,7 @@ struct Workspace {
   size_t slots;           // host-resident A: S tile slots of slot_bytes each
   // CSR input: CSC copy, sort buffers, row-major operand/result, chunk carries
   size_t colptr, rowind, cval, keys0, keys1, pay0, pay1, sort_temp;
+  size_t coo_ptr, coo_col, coo_val;   // CSR arrays built from COO input
   size_t Xr, Yr, carry, first;
   size_t total;
 };
@@ -90,7 +91,8 @@ struct Plan {
   int64_t rcat = 0;             // columns of the outer-product factors
   bool backward = false;
   bool host = false;            // A in pinned host memory, streamed tile by tile
-  bool csr = false;             // A given as CSR (int32 indices, FP32 values)
+  bool csr = false;             // A given as CSR (int32 indices, FP32 values), or as COO
+  bool coo = false;             // A given as COO (converted to CSR in the workspace)
   bool auto_q = false;          // choose q <= prob.q (RSVD_FLAG_AUTO_Q)
   double q_tol = 0.0;
   int64_t chunks = 0;           // nonzero chunks of the sparse products

@@ -154,6 +154,8 @@ struct Buffers {
   uint32_t *keys0, *keys1;
   uint64_t *pay0, *pay1;
   void* sort_temp;
+  int32_t *coo_ptr, *coo_col;
+  float* coo_val;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
@@ -198,6 +200,9 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.pay0 = (uint64_t*)(b + w.pay0);
   B.pay1 = (uint64_t*)(b + w.pay1);
   B.sort_temp = b + w.sort_temp;
+  B.coo_ptr = (int32_t*)(b + w.coo_ptr);
+  B.coo_col = (int32_t*)(b + w.coo_col);
+  B.coo_val = (float*)(b + w.coo_val);
   B.Pcat = (float*)(b + w.Pcat);
   B.Rcat = (float*)(b + w.Rcat);
   B.gUp = (float*)(b + w.gUp);
@@ -365,6 +370,23 @@ struct Runner {
                      "reserved " + std::to_string(P.sort_temp));
     RSVD_HIP(e);
     return RSVD_OK;
+  }
+
+  // COO input: order the entries by row into CSR arrays in the workspace
+  // (stable: a row keeps its entries' input order), then continue as CSR.
+  rsvd_status bind_coo(const void* ri, const void* ci, int bits, const float* v) {
+    const int64_t m = P.prob.m, n = P.prob.n, nnz = P.prob.nnz;
+    size_t need = 0;
+    const hipError_t e = rsvd::launch_coo_to_csr(ri, ci, bits, v, m, n, nnz, B.keys0, B.keys1,
+                                                 B.pay0, B.pay1, B.sort_temp, P.sort_temp,
+                                                 B.coo_ptr, B.coo_col, B.coo_val, B.status, &need,
+                                                 s);
+    if (e == hipErrorOutOfMemory && need > P.sort_temp)
+      return set_err(h, RSVD_E_BUDGET,
+                     "the COO sort needs " + std::to_string(need) + " bytes of scratch, the plan "
+                     "reserved " + std::to_string(P.sort_temp));
+    RSVD_HIP(e);
+    return bind_csr(B.coo_ptr, B.coo_col, B.coo_val);
   }
 
   // Operand copies of an FP32 panel for a product in precision prec: n-side
@@ -1035,11 +1057,27 @@ rsvd_status rsvd_factor_csr(rsvd_plan_t h, const int32_t* rowptr, const int32_t*
                             float* V, int64_t ldv, void* stream, rsvd_report* report) {
   if (rsvd_status st = check_plan(h)) return st;
   if (!h->p.csr) return set_err(h, RSVD_E_INVALID_ARG, "the plan is for dense input: use rsvd_factor");
+  if (h->p.coo) return set_err(h, RSVD_E_INVALID_ARG, "the plan is for COO input: use rsvd_factor_coo");
   if (!rowptr || (h->p.prob.nnz > 0 && (!colind || !values)))
     return set_err(h, RSVD_E_INVALID_ARG, "CSR arrays must be non-NULL");
   if (rsvd_status st = check_ws(h, ws)) return st;
   return factor_common(h, [&](Runner& R) { return R.bind_csr(rowptr, colind, values); }, ws, U, ldu,
                        S, V, ldv, stream, report);
+}
+
+rsvd_status rsvd_factor_coo(rsvd_plan_t h, const void* rowind, const void* colind,
+                            int32_t index_bits, const float* values, void* ws, float* U,
+                            int64_t ldu, double* S, float* V, int64_t ldv, void* stream,
+                            rsvd_report* report) {
+  if (rsvd_status st = check_plan(h)) return st;
+  if (!h->p.coo) return set_err(h, RSVD_E_INVALID_ARG, "the plan is not for COO input");
+  if (index_bits != 32 && index_bits != 64)
+    return set_err(h, RSVD_E_INVALID_ARG, "index_bits must be 32 or 64");
+  if (h->p.prob.nnz > 0 && (!rowind || !colind || !values))
+    return set_err(h, RSVD_E_INVALID_ARG, "COO arrays must be non-NULL");
+  if (rsvd_status st = check_ws(h, ws)) return st;
+  return factor_common(h, [&](Runner& R) { return R.bind_coo(rowind, colind, index_bits, values); },
+                       ws, U, ldu, S, V, ldv, stream, report);
 }
 
 rsvd_status rsvd_checkpoint_bytes(rsvd_plan_t h, size_t* panel_bytes) {

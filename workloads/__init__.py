@@ -30,6 +30,14 @@ Named recipes (sizes, spectra, seeds):
                  perm(rank - 1) with a seeded permutation, sorted within rows,
                  values log(1 + c), c ~ Poisson(3) + 1; FP32 values, int32
                  indices, seed 4 (the paper's SuiteSparse inputs are absent)
+  hamrle3_like   banded_random_coo: 1,447,360 x 1,447,360 with 5,514,242 entries,
+                 the shape of the paper's first SuiteSparse test matrix (§4.1);
+                 tridiagonal band (values 4 + |N(0,1)| on the diagonal, N(0,1)
+                 off it) plus uniformly placed N(0,1) entries, seed 6
+  circuit5m_like banded_random_coo: 5,558,326 x 5,558,326 with 59,524,291
+                 entries (the second matrix's shape), band of half-width 2, seed 7
+  The structure of the real matrices is not known here: these stand-ins keep
+  only their order and entry counts.
 Scaled-down variants keep the spectrum law and noise and shrink m, n.
 """
 
@@ -154,6 +162,39 @@ def zipf_csr(m, n, per_row, s=1.1, seed=4, device="cpu", draws=None):
     return rowptr, cols.reshape(-1).to(torch.int32), values
 
 
+def banded_random_coo(n, nnz, half_width, seed, device="cpu", index_dtype=torch.int64):
+    """Square n x n COO (rowind, colind, values float32) with exactly nnz
+    entries: the band |i - j| <= half_width (clipped at the edges), then
+    uniformly placed entries up to nnz (a repeated (i, j) adds up).  Band
+    values: 4 + |N(0,1)| on the diagonal, N(0,1) off it; others N(0,1).
+    Entries come in band-then-random order (not sorted by row)."""
+    g = _gen(seed, device)
+    rows, cols = [], []
+    for d in range(-half_width, half_width + 1):
+        i = torch.arange(max(0, -d), min(n, n - d), device=device, dtype=torch.int64)
+        rows.append(i)
+        cols.append(i + d)
+    r = torch.cat(rows)
+    c = torch.cat(cols)
+    nb = int(r.numel())
+    if nb > nnz:
+        raise ValueError("nnz is smaller than the band")
+    extra = nnz - nb
+    r = torch.cat([r, torch.randint(0, n, (extra,), generator=g, device=device)])
+    c = torch.cat([c, torch.randint(0, n, (extra,), generator=g, device=device)])
+    v = torch.randn(nnz, generator=g, device=device, dtype=torch.float32)
+    diag = torch.zeros(nnz, dtype=torch.bool, device=device)
+    diag[:nb] = r[:nb] == c[:nb]
+    v = torch.where(diag, 4.0 + v.abs(), v)
+    return r.to(index_dtype), c.to(index_dtype), v
+
+
+SPARSE_STANDINS = {
+    "hamrle3_like": dict(n=1447360, nnz=5514242, half_width=1, seed=6),
+    "circuit5m_like": dict(n=5558326, nnz=59524291, half_width=2, seed=7),
+}
+
+
 def fd_instance(seed, m=256, n=128, noise=1e-4, device="cpu"):
     sigma = spectrum_pow(min(m, n), 0.5)
     return dense_lowrank(m, n, sigma, noise, seed, device=device, out_dtype=torch.float64)
@@ -168,4 +209,5 @@ def ceil_div(a, b):
 
 
 __all__ = ["dense_lowrank", "haar_columns", "make", "fd_instance", "zipf_csr",
+           "banded_random_coo", "SPARSE_STANDINS",
            "RECIPES", "recipe_sigma", "spectrum_exp", "spectrum_pow", "math"]
