@@ -14,9 +14,12 @@
 //   * the wave that factors the next diagonal block first applies that
 //     block's own trailing update, so its factorisation overlaps the rest of
 //     the update (two workgroup barriers per panel).
-// The inverse X = L^-1 then proceeds by block rows, X_IJ = -X_II sum_K L_IK
+// The inverse X = L^-1 proceeds by block rows, X_IJ = -X_II sum_K L_IK
 // X_KJ, with the partial sum kept in the accumulator registers and fed back as
-// the B operand of the product with X_II.  The off-diagonal blocks of X are
+// the B operand of the product with X_II.  Block row k needs only block
+// columns < k of L and block rows < k of X, so the waves that are not
+// factoring make it during panel step k; only the last row follows the
+// factorisation.  The off-diagonal blocks of X are
 // stored transposed in the upper triangle, which is exactly the layout of the
 // upper-triangular W = X^T the apply kernel consumes.
 //
@@ -98,9 +101,9 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
     for (int i = p + 1; i < kB; ++i) x[i] -= row16_bcast(d[p], i) * x[p];
   }
   if (lane < kB) {
+    // the whole row: entries above the diagonal are never read again
 #pragma unroll
-    for (int p = 0; p < kB; ++p)
-      if (p <= r) S[sq(g0 + r, g0 + p)] = d[p];
+    for (int p = 0; p < kB; ++p) S[sq(g0 + r, g0 + p)] = d[p];
     dinv[g0 + r] = dv;
 #pragma unroll
     for (int i = 0; i < kB; ++i) Xd[kb * kB * kB + xq(i, r)] = x[i];
@@ -214,6 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
         wave_lds_fence();
         diag_block(S, Xd, dinv, d0, kb + 1, l, tau, ndrop, nbad);
       } else {
+        // tile 0 (the next diagonal block) is wave 0's
         for (int e = wave; e < ntile; e += kWaves - 1) {
           // e -> (i, c), i >= c, in row-major order of the lower triangle
           int i = 0;
@@ -221,6 +225,10 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
           const int c = e - i * (i + 1) / 2;
           update_tile(S, kb, kb + 1 + i, kb + 1 + c);
         }
+        // block row kb of X = L^-1 while wave 0 factors the next diagonal
+        // block: it needs only L's block columns < kb and X's rows < kb
+        if (!Lout)
+          for (int J = wave - 1; J < kb; J += kWaves - 1) inverse_tile(S, Xd, kb, J);
       }
       lds_barrier();
     }
@@ -232,13 +240,13 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
       if (i < n && c < n) Lout[(int64_t)i * n + c] = (i < l && c <= i) ? S[sq(i, c)] : 0.0;
     }
   } else {
-    for (int I = 1; I < nb; ++I) {
-      for (int J = wave; J < I; J += kWaves) inverse_tile(S, Xd, I, J);
-      lds_barrier();
-    }
+    // the last block row of X (the others were made during the factorisation)
+    for (int J = wave; J < nb - 1; J += kWaves) inverse_tile(S, Xd, nb - 1, J);
+    lds_barrier();
     // W(a, c) = X(c, a): the diagonal blocks come from Xd, the rest from the
     // transposed copy in the upper triangle; four columns per thread
     constexpr int kQuads = kSq * kSq / 4;
+#pragma unroll 4
     for (int e = tid; e < kQuads; e += kThreads) {
       const int a = e >> 5, c0 = (e & 31) * 4;
       float v[4];
