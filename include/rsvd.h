@@ -265,10 +265,14 @@ rsvd_status rsvd_factor_csr(rsvd_plan_t plan, const int32_t* rowptr, const int32
  *   pass 1 (sketch A O, orthonormalised)           Q   m x lp   side 0
  *   pass 2t   (t = 1..q, A^T Q, orthonormalised)   Z   n x lp   side 1
  *   pass 2t+1 (t = 1..q, A Z, orthonormalised)     Q   m x lp   side 0
- *   pass 2q+2 (the projection B^T = A^T Q)         B^T n x lp   side 1
- * lp is the sketch width rounded up to 32 (columns l..lp-1 are zero).  The
- * panel is column-major with leading dimension `rows` (host memory, owned by
- * the caller).  All reductions of the library are deterministic, so a run
+ *   pass 2q+2 (the projection B^T = A^T Q)   Q over B^T  (m + n) x lp  side 2
+ * lp is the sketch width rounded up to 32 (columns l..lp-1 are zero).  Below
+ * the state come lp more rows: the basis is kept as Q1 W (the second
+ * CholeskyQR pass of a basis gives its right factor W while the next product
+ * already runs on Q1), and these rows hold that factor (column c of the
+ * lp x lp W under column c), zero unless `pending`.  The panel is
+ * column-major with leading dimension `rows` (host memory, owned by the
+ * caller).  All reductions of the library are deterministic, so a run
  * resumed from the checkpoint of pass t returns the same U, S and V, bit for
  * bit, as an uninterrupted run. */
 #define RSVD_CKPT_MAGIC 0x31504B4344565352ull   /* "RSVDCKP1" little-endian */
@@ -280,15 +284,16 @@ typedef struct {
   uint64_t seed;
   int32_t prec_sketch, prec_power, prec_project;
   int32_t flags;           /* the plan's RSVD_FLAG_CHOLQR1 bit                */
-  int64_t rows, cols;      /* panel shape: rows x cols (cols = lp)            */
+  int64_t rows, cols;      /* panel shape: rows x cols (cols = lp; rows
+                              include the lp rows of the pending factor)    */
   int32_t side;            /* 0: m-side basis, 1: n-side panel                */
   int32_t dropped;         /* directions dropped so far                       */
   int32_t nonfinite;       /* non-finite values met so far                    */
-  int32_t reserved;
+  int32_t pending;         /* 1: the last lp rows hold a pending right factor */
   uint64_t panel_hash;     /* 64-bit hash of the panel bytes (see below)      */
 } rsvd_checkpoint;
 
-/* Bytes of the largest checkpoint panel of the plan: max(m, n) * lp * 4. */
+/* Bytes of the largest checkpoint panel of the plan: (m + n + lp) * lp * 4. */
 rsvd_status rsvd_checkpoint_bytes(rsvd_plan_t plan, size_t* panel_bytes);
 
 /* rsvd_factor (dense A, device- or host-resident) with persistence:

@@ -64,7 +64,7 @@ class Checkpoint(ctypes.Structure):
                 ("n", c_i64), ("k", c_i64), ("p", c_i64), ("q", c_i64), ("seed", c_u64),
                 ("prec_sketch", c_i32), ("prec_power", c_i32), ("prec_project", c_i32),
                 ("flags", c_i32), ("rows", c_i64), ("cols", c_i64), ("side", c_i32),
-                ("dropped", c_i32), ("nonfinite", c_i32), ("reserved", c_i32),
+                ("dropped", c_i32), ("nonfinite", c_i32), ("pending", c_i32),
                 ("panel_hash", c_u64)]
 
 

@@ -175,6 +175,9 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
   __shared__ double Xd[kNbMax * kB * kB];
   __shared__ double dinv[kSq];
   __shared__ double d0[kSq];
+  // this latency-bound workgroup may share its CU with a bandwidth-bound
+  // product running on another stream: its waves take the issue slots first
+  __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x, wave = tid >> 6;
   const int n = (int)lp;
   const int nb = (l + kB - 1) / kB;

@@ -1279,6 +1279,32 @@ __global__ void k_gather_cols(const double* __restrict__ Ev, int64_t lp, int l,
   out[t] = Ev[(int64_t)a * lp + oc];
 }
 
+// C = op(A) B for lp x lp row-major matrices (lp a multiple of 16, at most
+// 192), FP64 accumulation in index order: one 16 x 16 tile of C per
+// workgroup; the tile's 16 rows of op(A) and 16 columns of B are loaded to
+// LDS in one batch (every load in flight at once), then each thread sums
+// its element.
+constexpr int kLpMax = 192;
+template <typename TA, typename TB, typename TC, bool TRANS_A>
+__global__ __launch_bounds__(256) void k_lp_gemm(const TA* __restrict__ A, const TB* __restrict__ B,
+                                                 TC* __restrict__ C, int lp) {
+  __shared__ double As[16][kLpMax + 1], Bs[kLpMax][17];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+#pragma unroll 12
+  for (int e = tid; e < 16 * lp; e += 256) {
+    // As[i][k] = op(A)(r0 + i, k); Bs[k][j] = B(k, c0 + j)
+    const int i = TRANS_A ? e % 16 : e / lp, k = TRANS_A ? e / 16 : e % lp;
+    As[i][k] = TRANS_A ? (double)A[(int64_t)k * lp + r0 + i] : (double)A[(int64_t)(r0 + i) * lp + k];
+    const int kb = e / 16, j = e % 16;
+    Bs[kb][j] = (double)B[(int64_t)kb * lp + c0 + j];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int k = 0; k < lp; ++k) acc += As[ty][k] * Bs[k][tx];
+  C[(int64_t)(r0 + ty) * lp + c0 + tx] = (TC)acc;
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) p[t] = v;
@@ -1392,6 +1418,27 @@ hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t 
   if (lp > kMaxLp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_jacobi_vecs, dim3((unsigned)ceil_div_dev(lp, kVecRows)),
                      dim3(kVecRows * 64), 0, s, rot, status, lp, (int)l, Ev);
+  return hipGetLastError();
+}
+
+hipError_t launch_congruence(const double* G, const float* W, double* T, double* out, int64_t lp,
+                             hipStream_t s) {
+  if (lp % 16 || lp > kLpMax) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(lp / 16), (unsigned)(lp / 16));
+  hipLaunchKernelGGL((k_lp_gemm<double, float, double, false>), grid, dim3(256), 0, s, G, W, T,
+                     (int)lp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_lp_gemm<float, double, double, true>), grid, dim3(256), 0, s, W, T, out,
+                     (int)lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_lp_product(const float* A, const float* B, float* C, int64_t lp, hipStream_t s) {
+  if (lp % 16 || lp > kLpMax) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(lp / 16), (unsigned)(lp / 16));
+  hipLaunchKernelGGL((k_lp_gemm<float, float, float, false>), grid, dim3(256), 0, s, A, B, C,
+                     (int)lp);
   return hipGetLastError();
 }
 

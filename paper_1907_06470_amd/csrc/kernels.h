@@ -98,6 +98,12 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
                            double tau, hipStream_t s);
 // out(:, 0:ncols) = P(:, 0:kdim) * W(0:kdim, 0:ncols); W row-major with ldw;
 // `tri`: W upper triangular (skip zero blocks).  Rows [rows, ld) written as 0.
+// out = W^T G W (G FP64 symmetric, W FP32, both lp x lp row-major; T is
+// lp x lp FP64 scratch), FP64 accumulation.
+hipError_t launch_congruence(const double* G, const float* W, double* T, double* out, int64_t lp,
+                             hipStream_t s);
+// C = A B (lp x lp row-major FP32), FP64 accumulation.
+hipError_t launch_lp_product(const float* A, const float* B, float* C, int64_t lp, hipStream_t s);
 hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
                         int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out,
                         int64_t ldo, int64_t out_rows_total, hipStream_t s);

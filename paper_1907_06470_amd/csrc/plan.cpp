@@ -201,7 +201,13 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
                                      2048 * 8);
     if (gram_tri_fits(p.lp)) gbytes = std::max(gbytes, gram_tri_bytes(p.lp));
     w.gpart = take(gbytes);
+    w.gpart2 = take(gbytes);
   }
+  w.G2 = take(lp * lp * 8);
+  w.Tc = take(lp * lp * 8);
+  w.Wpm = take(lp * lp * 4);
+  w.Wpn = take(lp * lp * 4);
+  w.Wc = take(lp * lp * 4);
   w.G = take(lp * lp * 8);
   w.L = take(lp * lp * 8);
   w.W = take(lp * lp * 4);

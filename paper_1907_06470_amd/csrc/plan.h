@@ -44,6 +44,10 @@ struct Workspace {
   size_t L;               // lp x lp FP64 Cholesky factor
   size_t W;               // lp x lp FP32 right factor applied to panels
   size_t W2;              // lp x lp FP32 second right factor
+  size_t gpart2, G2;      // Gram partials and Gram of the deferred second CholeskyQR pass
+  size_t Tc;              // lp x lp FP64 scratch of W^T G W
+  size_t Wpm, Wpn;        // lp x lp FP32 pending right factors of the m- and n-side bases
+  size_t Wc;              // lp x lp FP32 product of a pending factor and a first-pass factor
   size_t Ev;              // lp x lp FP64 eigenvectors
   size_t lam;             // lp FP64 eigenvalues / singular values
   size_t order;           // lp int32 sort order
@@ -105,6 +109,7 @@ struct Plan {
   std::string last_error;
   void* hip_events = nullptr;   // created lazily by the driver
   void* streamer = nullptr;     // copy stream, slot events, slot contents (host A)
+  void* side = nullptr;         // side stream + events of the deferred CholeskyQR passes
 };
 
 // Fill `plan` or return an error status with plan.last_error set.

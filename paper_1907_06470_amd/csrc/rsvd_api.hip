@@ -159,6 +159,8 @@ struct Buffers {
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *rot;
+  double *gpart2, *G2, *Tc;
+  float *Wpm, *Wpn, *Wc;
   int32_t *order, *signs, *status;
   double* prevS;
 };
@@ -216,6 +218,12 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.Sl = (double*)(b + w.Sl);
   B.gpart = (double*)(b + w.gpart);
   B.G = (double*)(b + w.G);
+  B.gpart2 = (double*)(b + w.gpart2);
+  B.G2 = (double*)(b + w.G2);
+  B.Tc = (double*)(b + w.Tc);
+  B.Wpm = (float*)(b + w.Wpm);
+  B.Wpn = (float*)(b + w.Wpn);
+  B.Wc = (float*)(b + w.Wc);
   B.L = (double*)(b + w.L);
   B.Ev = (double*)(b + w.Ev);
   B.lam = (double*)(b + w.lam);
@@ -227,13 +235,47 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   return B;
 }
 
+// Side stream of the deferred second CholeskyQR passes (default priority,
+// non-blocking), with the fork and join events; owned by the plan.
+struct Side {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+void destroy_side(Side* d) {
+  if (!d) return;
+  if (d->fork) (void)hipEventDestroy(d->fork);
+  if (d->join) (void)hipEventDestroy(d->join);
+  if (d->s) (void)hipStreamDestroy(d->s);
+  delete d;
+}
+
+hipError_t make_side(rsvd::Plan& P, Side*& out) {
+  out = static_cast<Side*>(P.side);
+  if (out) return hipSuccess;
+  Side* d = new (std::nothrow) Side;
+  if (!d) return hipErrorOutOfMemory;
+  hipError_t e = hipStreamCreateWithFlags(&d->s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&d->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&d->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_side(d);
+    return e;
+  }
+  P.side = d;
+  out = d;
+  return hipSuccess;
+}
+
 // ---- checkpoint layout (rsvd_factor_resumable) ---------------------------
 // side of the state after pass t of npass: 0 the m-side basis, 1 the n-side
 // panel, 2 (after the projection) the basis over B^T.
 int ckpt_side(int64_t t, int64_t npass) { return t == npass ? 2 : (t % 2 == 1 ? 0 : 1); }
 
+// Panel rows: the state panel(s), then lp rows holding the pending right
+// factor of the basis (row-major lp x lp factor, column c below column c).
 int64_t ckpt_rows(const rsvd::Plan& P, int side) {
-  return side == 0 ? P.prob.m : side == 1 ? P.prob.n : P.prob.m + P.prob.n;
+  return (side == 0 ? P.prob.m : side == 1 ? P.prob.n : P.prob.m + P.prob.n) + P.lp;
 }
 
 // 64-bit FNV-1a over 32-bit words (each word is one unit of the hash).
@@ -280,6 +322,16 @@ struct Runner {
     float* out_panel;
   };
   const Ckpt* ck = nullptr;
+  // Deferred second CholeskyQR pass: a basis Q1 = Y W1 is handed to the next
+  // product at once, while Q1's own Gram and Cholesky run on the side stream
+  // and give its pending right factor W2 (Q = Q1 W2).  Every consumer folds
+  // W2 in on its lp x lp side (the next Gram is W2^T G W2, the next right
+  // factor W2 W1, the final small factors W2 U_B), so W2 never touches a
+  // tall panel.  pend[0] / pend[1]: the m- / n-side basis has one.
+  Side* side = nullptr;
+  bool pend[2] = {false, false};
+  bool side_busy = false;
+  float* Wpend(int sd) const { return sd ? B.Wpn : B.Wpm; }
 
   hipError_t tick(bool nn, bool start) {
     if (!ev) return hipSuccess;
@@ -557,19 +609,67 @@ struct Runner {
     return RSVD_OK;
   }
 
-  // One CholeskyQR pass: out = in R^-1 with R^T R = in^T in.
-  rsvd_status cholqr_pass(const float* in, float* out, int64_t rows, int64_t ld) {
-    rsvd_status st = gram(in, rows, ld);
-    if (st != RSVD_OK) return st;
-    RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
-    RSVD_HIP(rsvd::launch_apply(in, ld, rows, P.l, B.W, P.lp, P.lp, P.lp, true, out, ld, ld, s));
+  // The main stream waits for the side stream's last deferred pass.
+  rsvd_status join_side() {
+    if (side_busy) {
+      RSVD_HIP(hipStreamWaitEvent(s, side->join, 0));
+      side_busy = false;
+    }
     return RSVD_OK;
   }
 
-  // Orthonormal basis of `in` written to `out` (CholeskyQR2, or one pass).
-  rsvd_status orth(const float* in, float* out, float* tmp, int64_t rows, int64_t ld, bool twice) {
-    if (!twice) return cholqr_pass(in, out, rows, ld);
-    rsvd_status st = cholqr_pass(in, tmp, rows, ld);
+  // One CholeskyQR pass: out = in R^-1 with R^T R = in^T in.  With pside >= 0
+  // and a pending factor Wp on that side (in = A X1 with X = X1 Wp), the pass
+  // is taken of in Wp: G = Wp^T (in^T in) Wp and out = in (Wp W1).
+  rsvd_status cholqr_pass(const float* in, float* out, int64_t rows, int64_t ld, int pside = -1) {
+    rsvd_status st = gram(in, rows, ld);
+    if (st != RSVD_OK) return st;
+    const float* Wuse = B.W;
+    if (pside >= 0 && pend[pside]) {
+      if ((st = join_side())) return st;
+      RSVD_HIP(rsvd::launch_congruence(B.G, Wpend(pside), B.Tc, B.G, P.lp, s));
+      RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
+      RSVD_HIP(rsvd::launch_lp_product(Wpend(pside), B.W, B.Wc, P.lp, s));
+      Wuse = B.Wc;
+      pend[pside] = false;
+    } else {
+      RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
+    }
+    RSVD_HIP(rsvd::launch_apply(in, ld, rows, P.l, Wuse, P.lp, P.lp, P.lp, true, out, ld, ld, s));
+    return RSVD_OK;
+  }
+
+  // Second pass of `q1` (side sd) on the side stream: its Gram and Cholesky
+  // give the pending factor; nothing else reads q1's buffer until a later
+  // pass of the same side, after the consumer has joined.
+  rsvd_status defer_second(const float* q1, int64_t rows, int64_t ld, int sd) {
+    RSVD_HIP(make_side(h->p, side));
+    RSVD_HIP(hipEventRecord(side->fork, s));
+    RSVD_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    const int64_t chunks = rsvd::gram_chunks_for(P, rows);
+    RSVD_HIP(rsvd::launch_gram(q1, ld, rows, P.lp, P.gram_rows, chunks, B.gpart2, B.G2, side->s));
+    RSVD_HIP(rsvd::launch_chol_inv(B.G2, P.lp, P.l, Wpend(sd), B.status, kCholTau, side->s));
+    RSVD_HIP(hipEventRecord(side->join, side->s));
+    side_busy = true;
+    pend[sd] = true;
+    return RSVD_OK;
+  }
+
+  // Orthonormal basis of `in` (side sd: 0 m-side, 1 n-side) written to
+  // `out`: CholeskyQR2, or one pass.  `in` is the product of A (or A^T) with
+  // the other side's basis, whose pending factor the first pass folds in.
+  // defer: the second pass runs on the side stream and leaves out = Q1 with
+  // a pending factor; otherwise it runs here through `tmp`.
+  rsvd_status orth(const float* in, float* out, float* tmp, int64_t rows, int64_t ld, bool twice,
+                   int sd = -1, bool defer = false) {
+    const int pside = sd < 0 ? -1 : 1 - sd;
+    if (!twice) return cholqr_pass(in, out, rows, ld, pside);
+    if (defer && sd >= 0) {
+      rsvd_status st = cholqr_pass(in, out, rows, ld, pside);
+      if (st != RSVD_OK) return st;
+      return defer_second(out, rows, ld, sd);
+    }
+    rsvd_status st = cholqr_pass(in, tmp, rows, ld, pside);
     if (st != RSVD_OK) return st;
     return cholqr_pass(tmp, out, rows, ld);
   }
@@ -589,7 +689,7 @@ struct Runner {
     RSVD_HIP(mark(1));
     if ((st = product_nn(ps, B.Xop, B.M0))) return st;                                 // step 2
     RSVD_HIP(mark(2));
-    if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0))) return st;   // 3-4
+    if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || P.prob.q == 0, 0, true))) return st;   // 3-4
     if ((st = prep(P.prob.q > 0 ? pw : pj, B.Mop, false))) return st;
     RSVD_HIP(mark(3));
     if (ck && !P.auto_q && (st = ck_after(1))) return st;
@@ -610,10 +710,10 @@ struct Runner {
         q_used = t;
         q_delta = delta;
         if (t == P.prob.q || (t > 0 && delta <= P.q_tol)) break;
-        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
+        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1, 1, true))) return st;
         if ((st = prep(pw, B.Xop, true))) return st;
         if ((st = product_nn(pw, B.Xop, B.M0))) return st;
-        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, true))) return st;
+        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, true, 0, true))) return st;
         if ((st = prep(pw, B.Mop, false))) return st;
       }
       for (int i = 4; i <= 7; ++i) RSVD_HIP(mark(i));
@@ -640,12 +740,12 @@ struct Runner {
         RSVD_HIP(mark(5));
       } else if (t % 2 == 0) {
         if ((st = product_tn(pw, B.Mop, B.N0))) return st;
-        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1))) return st;
+        if ((st = orth(B.N0, B.Xop, B.N1, n, P.ldn, !cq1, 1, true))) return st;
         if ((st = prep(pw, B.Xop, true))) return st;
       } else {
         const bool last = t == npass - 1;
         if ((st = product_nn(pw, B.Xop, B.M0))) return st;
-        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last))) return st;
+        if ((st = orth(B.M0, B.Mop, B.M1, m, P.ldm, !cq1 || last, 0, true))) return st;
         if ((st = prep(last ? pj : pw, B.Mop, false))) return st;
       }
       if (ck && (st = ck_after(t))) return st;
@@ -687,17 +787,25 @@ struct Runner {
     if (ck->out) {
       const int64_t npass = 2 * P.prob.q + 2;
       const int side = ckpt_side(t, npass);
-      const int64_t rows = ckpt_rows(P, side);
+      const int64_t rows = ckpt_rows(P, side), main_rows = rows - P.lp;
+      const int pside = side == 1 ? 1 : 0;
       PanelPart pp[2];
       const int np = parts_of(side, pp);
+      if (rsvd_status st = join_side()) return st;
       RSVD_HIP(hipStreamSynchronize(s));
       for (int i = 0; i < np; ++i)
         RSVD_HIP(hipMemcpy2DAsync(ck->out_panel + pp[i].row0, (size_t)rows * 4, pp[i].dev,
                                   (size_t)pp[i].ld * 4, (size_t)pp[i].rows * 4, (size_t)P.lp,
                                   hipMemcpyDeviceToHost, s));
+      std::vector<float> wp((size_t)P.lp * P.lp, 0.f);
+      if (pend[pside])
+        RSVD_HIP(hipMemcpyAsync(wp.data(), Wpend(pside), wp.size() * 4, hipMemcpyDeviceToHost, s));
       int32_t stw[rsvd::kStatusWords];
       RSVD_HIP(hipMemcpyAsync(stw, B.status, sizeof stw, hipMemcpyDeviceToHost, s));
       RSVD_HIP(hipStreamSynchronize(s));
+      for (int64_t c = 0; c < P.lp; ++c)
+        for (int64_t a = 0; a < P.lp; ++a)
+          ck->out_panel[c * rows + main_rows + a] = wp[(size_t)(a * P.lp + c)];
       rsvd_checkpoint c{};
       c.magic = RSVD_CKPT_MAGIC;
       c.version = 1;
@@ -717,6 +825,7 @@ struct Runner {
       c.side = side;
       c.dropped = stw[rsvd::kStDropped];
       c.nonfinite = stw[rsvd::kStNonFinite];
+      c.pending = pend[pside] ? 1 : 0;
       c.panel_hash = ckpt_hash(ck->out_panel, (size_t)rows * (size_t)P.lp);
       *ck->out = c;
     }
@@ -740,7 +849,17 @@ struct Runner {
     const int32_t cnt[2] = {c.dropped, c.nonfinite};
     RSVD_HIP(hipMemcpyAsync(B.status + rsvd::kStDropped, &cnt[0], 4, hipMemcpyHostToDevice, s));
     RSVD_HIP(hipMemcpyAsync(B.status + rsvd::kStNonFinite, &cnt[1], 4, hipMemcpyHostToDevice, s));
-    RSVD_HIP(hipStreamSynchronize(s));   // the counters above live on this stack frame
+    const int pside = c.side == 1 ? 1 : 0;
+    std::vector<float> wp((size_t)P.lp * P.lp);
+    if (c.pending) {
+      const int64_t main_rows = c.rows - P.lp;
+      for (int64_t cc = 0; cc < P.lp; ++cc)
+        for (int64_t a = 0; a < P.lp; ++a)
+          wp[(size_t)(a * P.lp + cc)] = ck->resume_panel[cc * c.rows + main_rows + a];
+      RSVD_HIP(hipMemcpyAsync(Wpend(pside), wp.data(), wp.size() * 4, hipMemcpyHostToDevice, s));
+      pend[pside] = true;
+    }
+    RSVD_HIP(hipStreamSynchronize(s));   // the host buffers above live on this stack frame
     pass_no = t0;
     rsvd_status st;
     if (c.side == 0) {
@@ -753,9 +872,15 @@ struct Runner {
   }
 
   // Small SVD of B from Bt (n-side panel): leaves sorted S (k), Wu, Wv.
+  // B^T = Bt Wp when the m-side basis has a pending factor Wp: C = Wp^T
+  // (Bt^T Bt) Wp here, and small_svd_solve folds Wp into the small factors.
   rsvd_status small_svd_eig(const float* Bt) {
     rsvd_status st = gram(Bt, P.prob.n, P.ldn);
     if (st != RSVD_OK) return st;
+    if (pend[0]) {
+      if ((st = join_side())) return st;
+      RSVD_HIP(rsvd::launch_congruence(B.G, B.Wpm, B.Tc, B.G, P.lp, s));
+    }
     return RSVD_OK;
   }
   rsvd_status small_svd_solve(double* S, int64_t kout) {
@@ -772,6 +897,12 @@ struct Runner {
     }
     RSVD_HIP(rsvd::launch_finish_small(B.lam, B.Ev, P.lp, P.l, kout, S, B.W, B.W2, B.order,
                                        B.status, s));
+    if (pend[0]) {   // U = Q1 (Wp U_B), V = Bt (Wp U_B S^-1)
+      RSVD_HIP(rsvd::launch_lp_product(B.Wpm, B.W, B.Wc, P.lp, s));
+      RSVD_HIP(hipMemcpyAsync(B.W, B.Wc, (size_t)P.lp * P.lp * 4, hipMemcpyDeviceToDevice, s));
+      RSVD_HIP(rsvd::launch_lp_product(B.Wpm, B.W2, B.Wc, P.lp, s));
+      RSVD_HIP(hipMemcpyAsync(B.W2, B.Wc, (size_t)P.lp * P.lp * 4, hipMemcpyDeviceToDevice, s));
+    }
     return RSVD_OK;
   }
 };
@@ -977,6 +1108,7 @@ void rsvd_plan_destroy(rsvd_plan_t plan) {
   if (!plan) return;
   destroy_events(static_cast<Events*>(plan->p.hip_events));
   destroy_streamer(static_cast<Streamer*>(plan->p.streamer));
+  destroy_side(static_cast<Side*>(plan->p.side));
   delete plan;
 }
 
@@ -1084,7 +1216,7 @@ rsvd_status rsvd_checkpoint_bytes(rsvd_plan_t h, size_t* panel_bytes) {
   if (rsvd_status st = check_plan(h)) return st;
   if (!panel_bytes) return set_err(h, RSVD_E_INVALID_ARG, "panel_bytes is NULL");
   const rsvd::Plan& P = h->p;
-  *panel_bytes = (size_t)(P.prob.m + P.prob.n) * (size_t)P.lp * 4;
+  *panel_bytes = (size_t)(P.prob.m + P.prob.n + P.lp) * (size_t)P.lp * 4;
   return RSVD_OK;
 }
 
@@ -1115,7 +1247,8 @@ rsvd_status rsvd_factor_resumable(rsvd_plan_t h, const void* A, int64_t lda, voi
     if (c.passes < 1 || c.passes > npass)
       return set_err(h, RSVD_E_INVALID_ARG, "checkpoint pass out of range");
     const int side = ckpt_side(c.passes, npass);
-    if (c.side != side || c.rows != ckpt_rows(P, side) || c.cols != P.lp)
+    if (c.side != side || c.rows != ckpt_rows(P, side) || c.cols != P.lp ||
+        (c.pending != 0 && c.pending != 1))
       return set_err(h, RSVD_E_INVALID_ARG, "checkpoint shape does not match its pass");
     if (ckpt_hash(resume_panel, (size_t)c.rows * (size_t)c.cols) != c.panel_hash)
       return set_err(h, RSVD_E_INVALID_ARG, "checkpoint panel does not match its hash");

@@ -26,17 +26,19 @@ def test_header_layout_matches_the_c_struct():
     assert L.Checkpoint.seed.offset == 56
     assert L.Checkpoint.rows.offset == 80
     assert L.Checkpoint.side.offset == 96
+    assert L.Checkpoint.pending.offset == 108
     assert L.Checkpoint.panel_hash.offset == 112
     assert bytes.fromhex("%016x" % L.CKPT_MAGIC)[::-1] == b"RSVDCKP1"
 
 
 def _header(plan, passes, side, rows, panel):
+    # rows: the state rows; the panel also carries lp rows of a pending factor
     h = L.Checkpoint()
     h.magic, h.version, h.passes = L.CKPT_MAGIC, 1, passes
     h.m, h.n, h.k, h.p, h.q, h.seed = plan.m, plan.n, plan.k, plan.p, plan.q, plan.seed
     h.prec_sketch = h.prec_power = h.prec_project = L.F32
     h.flags = 0
-    h.rows, h.cols, h.side = rows, panel.shape[0], side
+    h.rows, h.cols, h.side = rows + panel.shape[0], panel.shape[0], side
     h.panel_hash = _fnv1a_words(panel)
     return h
 
@@ -44,7 +46,7 @@ def _header(plan, passes, side, rows, panel):
 def test_file_round_trip(tmp_path):
     plan = Plan(60, 40, 5, 3, 1, seed=7)
     rng = np.random.default_rng(0)
-    panel = rng.standard_normal((32, 60)).astype(np.float32)
+    panel = rng.standard_normal((32, 60 + 32)).astype(np.float32)
     ck = Checkpoint(_header(plan, 1, 0, 60, panel), panel)
     path = tmp_path / "state.ckpt"
     ck.save(path)
@@ -70,7 +72,7 @@ def _call(plan, hdr, panel, stop_after=0):
 def test_resume_checks_reject_before_running():
     plan = Plan(60, 40, 5, 3, 1, seed=7)        # lp = 32, q = 1: passes 1..4
     rng = np.random.default_rng(1)
-    good = np.ascontiguousarray(rng.standard_normal((32, 40)).astype(np.float32))
+    good = np.ascontiguousarray(rng.standard_normal((32, 40 + 32)).astype(np.float32))
     hdr = _header(plan, 2, 1, 40, good)          # pass 2: the n-side panel
     bad = []
     h = _header(plan, 2, 1, 40, good); h.magic ^= 1; bad.append((h, good, "not a version-1"))
@@ -97,4 +99,4 @@ def test_resume_unsupported_combinations():
     n = ctypes.c_size_t()
     plan = Plan(60, 40, 5, 3, 1)
     assert L.lib().rsvd_checkpoint_bytes(plan.handle, ctypes.byref(n)) == L.OK
-    assert n.value == (60 + 40) * 32 * 4
+    assert n.value == (60 + 40 + 32) * 32 * 4
