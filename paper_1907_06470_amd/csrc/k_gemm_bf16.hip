@@ -261,7 +261,10 @@ __global__ __launch_bounds__(256) void k_nn_bf16_sq(const u16* __restrict__ A, i
 // so no transposed copy of A is ever stored.
 constexpr int TBN = 128;
 constexpr int TPAD = TBN + 8;
-template <int NT, bool NTL = false>
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+template <int NT, bool NTL = false, bool TR = false>
 __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int64_t lda, int64_t m,
                                                  int64_t n, int64_t tm, const u16* __restrict__ Q,
                                                  int64_t ldq, float* __restrict__ Z, int64_t ldz,
@@ -318,15 +321,29 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       // reduction indices of this step: 16 s + 8 half + v
-      uint32_t w[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t lo = As[buf][s * 16 + half * 8 + 2 * v][jl];
-        const uint32_t hi = As[buf][s * 16 + half * 8 + 2 * v + 1][jl];
-        w[v] = lo | (hi << 16);
-      }
       bf16x8 av;
-      __builtin_memcpy(&av, w, 16);
+      if (TR) {
+        // LDS transpose reads: in each 16-lane group, lane 4a + b names the
+        // 4 columns 4b.. of row a, and lane r receives column r of the 4 rows
+        // named, so lane (column jl, half) gets rows 16 s + 8 half + 0..3,
+        // then + 4..7, of its own column
+        const int g = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
+        const int col = wave * 32 + (g & 1) * 16 + 4 * b;
+        const int row = s * 16 + half * 8 + a;
+        const s16x4 lo4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)&As[buf][row][col]);
+        const s16x4 hi4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)&As[buf][row + 4][col]);
+        __builtin_memcpy(&av, &lo4, 8);
+        __builtin_memcpy(reinterpret_cast<char*>(&av) + 8, &hi4, 8);
+      } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t lo = As[buf][s * 16 + half * 8 + 2 * v][jl];
+          const uint32_t hi = As[buf][s * 16 + half * 8 + 2 * v + 1][jl];
+          w[v] = lo | (hi << 16);
+        }
+        __builtin_memcpy(&av, w, 16);
+      }
       bf16x8 bv[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t)

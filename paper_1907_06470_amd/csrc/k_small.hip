@@ -1157,38 +1157,45 @@ __global__ __launch_bounds__(256) void k_ritz_delta(const double* __restrict__ S
 }
 
 // Sort eigenvalues descending (ties by index), S = sqrt(lambda) for the first
-// k, Wu(a, c) = Ev(a, order c), Wv(a, c) = Wu(a, c) / sigma_c (0 if sigma_c is
+// k, Wu(a, c) = Ev(a, order c), Wv(a, c) = Wu(a, c) (1 / sigma_c) (0 if sigma_c is
 // negligible), both lp x lp row-major FP32 with zero columns from k on.
-__global__ __launch_bounds__(256) void k_finish_small(const double* __restrict__ lam,
-                                                      const double* __restrict__ Ev, int64_t lp,
-                                                      int l, int k, double* __restrict__ S,
-                                                      float* __restrict__ Wu,
-                                                      float* __restrict__ Wv,
-                                                      int32_t* __restrict__ order_out,
-                                                      int32_t* status) {
+__global__ __launch_bounds__(1024) void k_finish_small(const double* __restrict__ lam,
+                                                       const double* __restrict__ Ev, int64_t lp,
+                                                       int l, int k, double* __restrict__ S,
+                                                       float* __restrict__ Wu,
+                                                       float* __restrict__ Wv,
+                                                       int32_t* __restrict__ order_out,
+                                                       int32_t* status) {
   __shared__ int order[kMaxLp];
-  __shared__ double sig[kMaxLp];
+  __shared__ double lv[kMaxLp], sig[kMaxLp], inv[kMaxLp];
+  __shared__ double smax_s;
   __shared__ int nzero;
   const int tid = threadIdx.x;
   if (tid == 0) nzero = 0;
+  for (int i = tid; i < l; i += blockDim.x) lv[i] = nan_low(lam[i]);
+  __syncthreads();
   // Rank by a strict total order: NaN counts as -inf and ties go by index,
   // so the ranks are a permutation of [0, l) whatever the values are.
   for (int i = tid; i < l; i += blockDim.x) {
-    const double li = nan_low(lam[i]);
+    const double li = lv[i];
     int rank = 0;
     for (int j = 0; j < l; ++j) {
-      const double lj = nan_low(lam[j]);
+      const double lj = lv[j];
       rank += (lj > li) || (lj == li && j < i);
     }
     order[rank] = i;
   }
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < l; ++j) mx = fmax(mx, lv[j]);
+    smax_s = sqrt(fmax(mx, 0.0));
+  }
   __syncthreads();
-  double smax = 0.0;
-  for (int j = 0; j < l; ++j) smax = fmax(smax, nan_low(lam[j]));
-  smax = sqrt(fmax(smax, 0.0));
+  const double smax = smax_s;
   for (int c = tid; c < l; c += blockDim.x) {
     const double s = sqrt(fmax(lam[order[c]], 0.0));
     sig[c] = s;
+    inv[c] = s > 1e-12 * smax ? 1.0 / s : 0.0;
     if (c < k) {
       S[c] = s;
       if (!(s > 1e-12 * smax)) atomicAdd(&nzero, 1);
@@ -1196,13 +1203,14 @@ __global__ __launch_bounds__(256) void k_finish_small(const double* __restrict__
     order_out[c] = order[c];
   }
   __syncthreads();
+#pragma unroll 4
   for (int e = tid; e < lp * lp; e += blockDim.x) {
     const int a = e / (int)lp, c = e % (int)lp;
     float u = 0.f, v = 0.f;
     if (a < l && c < k) {
       const double ev = Ev[(int64_t)a * lp + order[c]];
       u = (float)ev;
-      v = sig[c] > 1e-12 * smax ? (float)(ev / sig[c]) : 0.f;
+      v = (float)(ev * inv[c]);
     }
     Wu[e] = u;
     Wv[e] = v;
@@ -1425,6 +1433,7 @@ hipError_t launch_congruence(const double* G, const float* W, double* T, double*
                              hipStream_t s) {
   if (lp % 16 || lp > kLpMax) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(lp / 16), (unsigned)(lp / 16));
+  if (T == G || T == out) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_lp_gemm<double, float, double, false>), grid, dim3(256), 0, s, G, W, T,
                      (int)lp);
   hipError_t e = hipGetLastError();
@@ -1446,7 +1455,7 @@ hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, 
                                int64_t k, double* S, float* Wu, float* Wv, int32_t* order,
                                int32_t* status, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finish_small, dim3(1), dim3(256), 0, s, lam, Ev, lp, (int)l, (int)k, S, Wu,
+  hipLaunchKernelGGL(k_finish_small, dim3(1), dim3(1024), 0, s, lam, Ev, lp, (int)l, (int)k, S, Wu,
                      Wv, order, status);
   return hipGetLastError();
 }

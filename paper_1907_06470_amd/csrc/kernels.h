@@ -99,7 +99,8 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
 // out(:, 0:ncols) = P(:, 0:kdim) * W(0:kdim, 0:ncols); W row-major with ldw;
 // `tri`: W upper triangular (skip zero blocks).  Rows [rows, ld) written as 0.
 // out = W^T G W (G FP64 symmetric, W FP32, both lp x lp row-major; T is
-// lp x lp FP64 scratch), FP64 accumulation.
+// lp x lp FP64 scratch distinct from G and out; out may alias G), FP64
+// accumulation.
 hipError_t launch_congruence(const double* G, const float* W, double* T, double* out, int64_t lp,
                              hipStream_t s);
 // C = A B (lp x lp row-major FP32), FP64 accumulation.

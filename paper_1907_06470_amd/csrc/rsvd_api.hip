@@ -331,6 +331,7 @@ struct Runner {
   Side* side = nullptr;
   bool pend[2] = {false, false};
   bool side_busy = false;
+  double* gsmall = nullptr;    // the l x l Gram the small SVD factors (B.G, or its congruence)
   float* Wpend(int sd) const { return sd ? B.Wpn : B.Wpm; }
 
   hipError_t tick(bool nn, bool start) {
@@ -627,8 +628,8 @@ struct Runner {
     const float* Wuse = B.W;
     if (pside >= 0 && pend[pside]) {
       if ((st = join_side())) return st;
-      RSVD_HIP(rsvd::launch_congruence(B.G, Wpend(pside), B.Tc, B.G, P.lp, s));
-      RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
+      RSVD_HIP(rsvd::launch_congruence(B.G, Wpend(pside), B.L, B.Tc, P.lp, s));
+      RSVD_HIP(rsvd::launch_chol_inv(B.Tc, P.lp, P.l, B.W, B.status, kCholTau, s));
       RSVD_HIP(rsvd::launch_lp_product(Wpend(pside), B.W, B.Wc, P.lp, s));
       Wuse = B.Wc;
       pend[pside] = false;
@@ -877,9 +878,11 @@ struct Runner {
   rsvd_status small_svd_eig(const float* Bt) {
     rsvd_status st = gram(Bt, P.prob.n, P.ldn);
     if (st != RSVD_OK) return st;
+    gsmall = B.G;
     if (pend[0]) {
       if ((st = join_side())) return st;
-      RSVD_HIP(rsvd::launch_congruence(B.G, B.Wpm, B.Tc, B.G, P.lp, s));
+      RSVD_HIP(rsvd::launch_congruence(B.G, B.Wpm, B.L, B.Tc, P.lp, s));
+      gsmall = B.Tc;
     }
     return RSVD_OK;
   }
@@ -887,11 +890,11 @@ struct Runner {
     if (rsvd::small_svd_one_sided(P.lp)) {
       // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
       // positive pivot; exactly dependent directions give zero columns)
-      RSVD_HIP(rsvd::launch_chol_factor(B.G, P.lp, P.l, B.L, B.status, 0.0, s));
+      RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
       RSVD_HIP(rsvd::launch_ojacobi(B.L, P.lp, P.l, B.lam, B.Ev, B.status, kJacobiTol,
                                     rsvd::kJacobiMaxSweeps, s));
     } else {
-      RSVD_HIP(rsvd::launch_jacobi(B.G, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status,
+      RSVD_HIP(rsvd::launch_jacobi(gsmall, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status,
                                    kJacobiTol, rsvd::kJacobiMaxSweeps, s));
       RSVD_HIP(rsvd::launch_jacobi_vecs(B.rot, B.status, P.lp, P.l, B.Ev, s));
     }
