@@ -57,6 +57,201 @@ __device__ inline void store_acc16(float* out, int64_t ld, int64_t row_base, int
   }
 }
 
+// Direct-to-LDS form of the A X product for panel width 128: 8 waves, a
+// 256 x 128 output block per workgroup (4 x 2 waves of 64 x 64).  The A slabs
+// (256 rows x 64 BF16) travel from HBM straight into a 4-deep LDS ring with
+// buffer_load ... lds (no registers in between), so three slabs (32 KB each)
+// are in flight per workgroup while one is multiplied.  Lane i of a 16-byte
+// load lands at LDS offset 16 i of its 1 KB run, so the XOR swizzle of
+// 16-byte chunks within a row (chunk c of row r at slot c ^ (r & 7);
+// conflict-free MFMA operand reads) is made by the choice of source
+// addresses.  The panel slabs (128 columns x 64, from the caches) are loaded
+// into registers two slabs ahead and written to a double buffer in LDS.
+// Loads complete in issue order, so waiting for a panel load also waits for
+// every A slab issued before it: the panel slab t + 1 is waited for at the
+// end of slab t, when A slab t + 1 (issued before it) is due anyway, and
+// three A slabs stay in flight.  Buffer (not global) loads: the compiler
+// counts them in order too, so its own waits stay at that depth.  One
+// workgroup barrier per slab.  A partial last slab (k1 not a multiple of 64)
+// goes through registers with masked loads, so padding beyond n is never
+// read.  Needs 256 * lda and 128 * ldx BF16 elements to fit a 31-bit byte
+// offset (the launcher checks).  CP: cache-policy bits of the A loads (2 =
+// non-temporal: A is streamed once per pass).
+constexpr int DL_BM = 256, DL_LP = 128, DL_ARUN = DL_BM / 8 / 8, DL_XRUN = DL_LP / 8 / 8;
+
+template <int SA, int CP = 0>
+__global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, int64_t lda,
+                                                    int64_t m, int64_t n, int64_t tn,
+                                                    const u16* __restrict__ X, int64_t ldx,
+                                                    float* __restrict__ Y, int64_t ldy,
+                                                    int64_t part_stride) {
+  static_assert(SA == 4, "the ring is unrolled for four stages");
+  static_assert(DL_XRUN == 2, "two panel loads per lane and slab");
+  // one LDS object per stage: the compiler then sees that reading one stage
+  // does not depend on the loads still landing in the others
+  __shared__ __attribute__((aligned(1024))) u16 As0[DL_BM * 64], As1[DL_BM * 64];
+  __shared__ __attribute__((aligned(1024))) u16 As2[DL_BM * 64], As3[DL_BM * 64];
+  __shared__ __attribute__((aligned(1024))) u16 Xs0[DL_LP * 64], Xs1[DL_LP * 64];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int64_t i0 = (int64_t)blockIdx.x * DL_BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tn;
+  const int64_t k1 = min(n, k0 + tn);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int64_t nfull = (k1 - k0) / 64;               // whole 64-deep slabs
+  const bool tail = k0 + nfull * 64 < k1;
+  // this lane's 16-byte source within a 1 KB run: row rr of the run, slot sl
+  const int rr = lane >> 3, sl = lane & 7;
+  const int rows = (int)min((int64_t)DL_BM, m - i0);  // valid rows of this block
+  // buffer descriptors (data format 32 in the fourth word); the byte extents
+  // end at the last element either matrix holds, so the hardware range check
+  // returns zeros rather than reading past it
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A + i0 * lda), (short)0, (int)(((int64_t)(rows - 1) * lda + n) * 2), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)X, (short)0, (int)(((int64_t)(DL_LP - 1) * ldx + n) * 2), 0x00020000);
+
+  // A slab t into LDS stage st, or past the last slab a re-read of panel
+  // slab 0 (from the caches) so that every slab issues the same loads.  One
+  // instruction sequence for both (descriptor and offsets are selected).
+  auto issue_a = [&](u16* st, int64_t t) {
+    const bool real = t < nfull;
+    const __amdgpu_buffer_rsrc_t rs = real ? ra : rx;
+    const int kk = (int)(k0 + t * 64);
+#pragma unroll
+    for (int j = 0; j < DL_ARUN; ++j) {
+      const int r = (wave * DL_ARUN + j) * 8 + rr;   // row within the block
+      const int rc = min(r, rows - 1);                // rows past m: any valid row
+      const int c = r & (DL_LP - 1);
+      const int off = real ? (rc * (int)lda + kk + 8 * (sl ^ (r & 7))) * 2
+                           : (c * (int)ldx + (int)k0 + 8 * sl) * 2;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + (wave * DL_ARUN + j) * 512, 16, off, 0, 0, CP);
+    }
+  };
+  // panel slab t (slab 0 past the last) into registers, and registers -> LDS
+  const int xc0 = (wave * DL_XRUN) * 8 + rr, xc1 = xc0 + 8;   // this lane's panel columns
+  auto load_x = [&](v4u& x0, v4u& x1, int64_t t) {
+    const int kk = (int)(k0 + (t < nfull ? t : 0) * 64);
+    x0 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc0 * (int)ldx + kk + 8 * (sl ^ (xc0 & 7))) * 2, 0, 0);
+    x1 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc1 * (int)ldx + kk + 8 * (sl ^ (xc1 & 7))) * 2, 0, 0);
+  };
+  auto store_x = [&](u16* st, const v4u& x0, const v4u& x1) {
+    *reinterpret_cast<v4u*>(st + (wave * DL_XRUN) * 512 + lane * 8) = x0;
+    *reinterpret_cast<v4u*>(st + (wave * DL_XRUN + 1) * 512 + lane * 8) = x1;
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+
+  auto compute = [&](const u16* as, const u16* xs) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = half * 4 + s;                    // 16-byte chunk of the 64-deep slab
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = wr * 64 + a * 32 + l32;
+        av[a] = *reinterpret_cast<const bf16x8*>(as + r * 64 + 8 * (q ^ (r & 7)));
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = wc * 64 + t * 32 + l32;
+        bv[t] = *reinterpret_cast<const bf16x8*>(xs + c * 64 + 8 * (q ^ (c & 7)));
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+    }
+  };
+
+  // Slab t: A stage t % 4, panel buffer t % 2.  Every slab issues the same
+  // loads (dummies past the end), so the wait counts are constants.  Issue
+  // order of slab t: panel registers of slab t + 2 (DL_XRUN loads), then A
+  // slab t + 3 (DL_ARUN loads).  One step, entered after a barrier that
+  // follows every wave's A slab t and panel slab t landing in LDS:
+  //   issue panel slab t + 2 -> registers xn, A slab t + 3 -> the stage slab
+  //   t - 1 used; compute slab t; wait for the panel registers xp of slab
+  //   t + 1 (issued before A slab t + 2 and t + 3: vmcnt(2 * DL_ARUN +
+  //   DL_XRUN)), which also means this wave's A slab t + 1 has landed; write
+  //   them to the panel buffer slab t - 1 used; barrier.
+  // s_waitcnt immediates: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and
+  // lgkmcnt 11:8 (0xc07f: lgkmcnt(0) only).
+  constexpr int kWaitStep = 0x0f70 | (2 * DL_ARUN + DL_XRUN);
+  auto step = [&](int64_t t, u16* as, u16* xs, u16* xs_next, u16* as_refill, v4u& xp0, v4u& xp1,
+                  v4u& xn0, v4u& xn1) {
+    load_x(xn0, xn1, t + 2);
+    issue_a(as_refill, t + 3);
+    __builtin_amdgcn_sched_barrier(0);          // loads go out before the compute
+    compute(as, xs);
+    __builtin_amdgcn_s_waitcnt(kWaitStep);
+    store_x(xs_next, xp0, xp1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  };
+
+  v4u xa0, xa1, xb0, xb1;                       // panel registers, two slabs
+  if (nfull > 0) {
+    load_x(xa0, xa1, 0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    store_x(Xs0, xa0, xa1);
+    load_x(xb0, xb1, 1);
+    issue_a(As0, 0);
+    issue_a(As1, 1);
+    issue_a(As2, 2);
+    // A slab 0 (and the panel registers of slab 1) are older than A slabs 1, 2
+    __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * DL_ARUN));
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  }
+  // slab t holds its panel registers: slab t + 1 in xb when t is even, else xa
+  int64_t tb = 0;
+  for (; tb + 3 < nfull; tb += 4) {     // four whole steps: no branch between them
+    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
+    step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
+    step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+    step(tb + 3, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1);
+  }
+  if (tb < nfull) {                     // up to three remaining slabs
+    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
+    if (tb + 1 < nfull) {
+      step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
+      if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0f70);   // the last (dummy) loads land before LDS is reused or freed
+  if (tail) {   // last, partial slab: masked loads through registers
+    __syncthreads();
+    const int64_t kk = k0 + nfull * 64;
+    for (int e = tid; e < DL_BM * 8; e += 512) {
+      const int r = e >> 3, c = e & 7;
+      const int64_t gi = min(i0 + r, m - 1);
+      *reinterpret_cast<uint4*>(As0 + r * 64 + 8 * (c ^ (r & 7))) =
+          ld8_masked(A + gi * lda, kk + 8 * c, k1);
+    }
+    for (int e = tid; e < DL_LP * 8; e += 512) {
+      const int r = e >> 3, c = e & 7;
+      *reinterpret_cast<uint4*>(Xs0 + r * 64 + 8 * (c ^ (r & 7))) =
+          ld8_masked(X + (int64_t)r * ldx, kk + 8 * c, k1);
+    }
+    __syncthreads();
+    compute(As0, Xs0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t rb = i0 + wr * 64 + a * 32;
+      if (rb < m) store_acc16(Yp, ldy, rb, wc * 64 + t * 32 + l32, acc[a][t], half);
+    }
+}
+
 // Y (+ partial J) = A16(:, tile J) X16(tile J, :).  4 waves; wave w owns rows
 // [w*WR, (w+1)*WR) of the BM = 4*WR rows and all NT*32 panel columns.
 // Within a 64-deep slab, lane half h takes reduction indices h*32 + 8s + v at
@@ -430,6 +625,17 @@ hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, 
                           int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
                           int64_t ldy, int64_t part_stride, hipStream_t s) {
   const int nt = (int)(lp / 32);
+  // direct-to-LDS form: 16-byte aligned rows and 31-bit buffer offsets over
+  // 256 rows of A and the 128 panel columns
+  const bool dl = nt == 4 && (lda % 8) == 0 && (ldx % 8) == 0 && (tn % 8) == 0 &&
+                  ((uintptr_t)A & 15) == 0 && ((uintptr_t)X & 15) == 0 &&
+                  (int64_t)DL_BM * lda * 2 <= INT32_MAX && (int64_t)DL_LP * ldx * 2 <= INT32_MAX;
+  if (dl) {
+    dim3 grid((unsigned)ceil_div_dev(m, DL_BM), (unsigned)TJ);
+    hipLaunchKernelGGL((k_nn_bf16_dl<4, 2>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
+                       ldy, part_stride);
+    return hipGetLastError();
+  }
   if (nt == 4) {   // square wave tiles, 128 rows per workgroup
     dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
     hipLaunchKernelGGL((k_nn_bf16_sq<1, 2>), grid, dim3(256), 0, s, A, lda, m, n, tn, X, ldx, Y,
