@@ -871,26 +871,20 @@ __device__ inline double oj_norm2(const double (&x)[kOjRows]) {
   return row16_sum(s0 + s1);
 }
 
-// Rotate columns x and y, whose squared norms na and nb are carried along:
-// only the inner product g is summed from the data, and the norms of the
-// rotated pair follow from the rotation actually applied,
-// a' = c^2 a - 2 c s g + s^2 b and b' = s^2 a + 2 c s g + c^2 b.  An updated
-// norm below 1/100 of the old one (nearly parallel columns: the update
-// cancels) sets `stale`, and the caller sums it afresh.  g2 > tol2 a b
-// selects the rotation.
-__device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], double& na,
-                                 double& nb, bool& stale, double tol2, double stop2, bool& any,
-                                 bool& big) {
-  double g0 = 0.0, g1 = 0.0;
-#pragma unroll
-  for (int u = 0; u < kOjRows; u += 2) {
-    g0 += x[u] * y[u];
-    g1 += x[u + 1] * y[u + 1];
-  }
-  const double aa = na, bb = nb;
-  const double gg = row16_sum(g0 + g1);
+// Rotate column pairs (x1, y1) and (x2, y2), four distinct columns, side by
+// side: the two inner products, angles and updates are independent, so their
+// dependent chains (16-lane sums, the angle, the updates) overlap.  The
+// squared norms are carried along: only the inner product g of each pair is
+// summed from the data, and the norms of a rotated pair follow from the
+// rotation actually applied, a' = c^2 a - 2 c s g + s^2 b and
+// b' = s^2 a + 2 c s g + c^2 b.  An updated norm below 1/100 of the old one
+// (nearly parallel columns: the update cancels) sets `stale`, and the caller
+// sums it afresh.  A pair rotates when g^2 > tol2 a b and its enable flag is
+// set.
+__device__ inline void oj_angle(double gg, double aa, double bb, bool en, double tol2,
+                                double stop2, double& cs, double& sn, bool& any, bool& big) {
   const double ab = aa * bb, g2 = gg * gg;
-  const bool rot = g2 > tol2 * ab;
+  const bool rot = en && g2 > tol2 * ab;
   // tangent of the Hestenes angle, t = sign(d) 2g / (|d| + sqrt(d^2 + 4g^2))
   // with d = b - a, on the pair scaled by a power of two
   const double dd = bb - aa, tg = 2.0 * gg;
@@ -900,22 +894,49 @@ __device__ inline void oj_rotate(double (&x)[kOjRows], double (&y)[kOjRows], dou
   const float den = fabsf(d32) + __builtin_amdgcn_sqrtf(d32 * d32 + g32 * g32);
   const float t32 = (d32 >= 0.f ? g32 : -g32) * __builtin_amdgcn_rcpf(den);
   const double tt = rot ? (double)t32 : 0.0;
-  const double cs = fast_rsq(1.0 + tt * tt);
-  const double sn = cs * tt;
-#pragma unroll
-  for (int u = 0; u < kOjRows; ++u) {
-    const double xp = x[u], xq = y[u];
-    x[u] = cs * xp - sn * xq;
-    y[u] = sn * xp + cs * xq;
-  }
+  cs = fast_rsq(1.0 + tt * tt);
+  sn = cs * tt;
+  any = any || rot;
+  big = big || (rot && g2 > stop2 * ab);
+}
+
+__device__ inline void oj_norms(double cs, double sn, double gg, double& na, double& nb,
+                                bool& stale) {
+  const double aa = na, bb = nb;
   const double c2 = cs * cs, s2 = sn * sn, cg = 2.0 * cs * sn * gg;
   const double a2 = c2 * aa - cg + s2 * bb;
   const double b2 = s2 * aa + cg + c2 * bb;
   stale = stale || a2 < 0.01 * aa || b2 < 0.01 * bb;
   na = a2;
   nb = b2;
-  any = any || rot;
-  big = big || (rot && g2 > stop2 * ab);
+}
+
+__device__ inline void oj_rotate2(double (&x1)[kOjRows], double (&y1)[kOjRows], double& na1,
+                                  double& nb1, bool en1, double (&x2)[kOjRows],
+                                  double (&y2)[kOjRows], double& na2, double& nb2, bool en2,
+                                  bool& stale, double tol2, double stop2, bool& any, bool& big) {
+  double g10 = 0.0, g11 = 0.0, g20 = 0.0, g21 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kOjRows; u += 2) {
+    g10 += x1[u] * y1[u];
+    g20 += x2[u] * y2[u];
+    g11 += x1[u + 1] * y1[u + 1];
+    g21 += x2[u + 1] * y2[u + 1];
+  }
+  const double gg1 = row16_sum(g10 + g11), gg2 = row16_sum(g20 + g21);
+  double c1, s1, c2, s2;
+  oj_angle(gg1, na1, nb1, en1, tol2, stop2, c1, s1, any, big);
+  oj_angle(gg2, na2, nb2, en2, tol2, stop2, c2, s2, any, big);
+#pragma unroll
+  for (int u = 0; u < kOjRows; ++u) {
+    const double p1 = x1[u], q1 = y1[u], p2 = x2[u], q2 = y2[u];
+    x1[u] = c1 * p1 - s1 * q1;
+    y1[u] = s1 * p1 + c1 * q1;
+    x2[u] = c2 * p2 - s2 * q2;
+    y2[u] = s2 * p2 + c2 * q2;
+  }
+  oj_norms(c1, s1, gg1, na1, nb1, stale);
+  oj_norms(c2, s2, gg2, na2, nb2, stale);
 }
 
 // Position p of the odd-even order is idle in a round of parity par when no
@@ -1003,12 +1024,15 @@ __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict
         // round, or in its second for a block idle in the first
         const bool ik = t == 0 || (t == 1 && oj_idle(kpos, par0, nb));
         const bool is = t == 0 || (t == 1 && oj_idle(sp, par0, nb));
-        if (ik) oj_rotate(xk[0], xk[1], nk[0], nk[1], stale, tol2, stop2, any, big);
-        if (is) oj_rotate(xs[0], xs[1], ns[0], ns[1], stale, tol2, stop2, any, big);
-        oj_rotate(xk[0], xs[0], nk[0], ns[0], stale, tol2, stop2, any, big);
-        oj_rotate(xk[1], xs[1], nk[1], ns[1], stale, tol2, stop2, any, big);
-        oj_rotate(xk[0], xs[1], nk[0], ns[1], stale, tol2, stop2, any, big);
-        oj_rotate(xk[1], xs[0], nk[1], ns[0], stale, tol2, stop2, any, big);
+        // the two inner pairs side by side, then the four cross pairs as two
+        // side-by-side steps of disjoint pairs
+        if (ik || is)
+          oj_rotate2(xk[0], xk[1], nk[0], nk[1], ik, xs[0], xs[1], ns[0], ns[1], is, stale, tol2,
+                     stop2, any, big);
+        oj_rotate2(xk[0], xs[0], nk[0], ns[0], true, xk[1], xs[1], nk[1], ns[1], true, stale, tol2,
+                   stop2, any, big);
+        oj_rotate2(xk[0], xs[1], nk[0], ns[1], true, xk[1], xs[0], nk[1], ns[0], true, stale, tol2,
+                   stop2, any, big);
         if (stale) {   // rare: sum all four norms afresh
           nk[0] = oj_norm2(xk[0]);
           nk[1] = oj_norm2(xk[1]);
