@@ -57,6 +57,18 @@ __device__ inline void store_acc16(float* out, int64_t ld, int64_t row_base, int
   }
 }
 
+// Same, with the rows at and past `valid` stored as zeros.
+__device__ inline void store_acc16_rows(float* out, int64_t ld, int64_t row_base, int col,
+                                        const f32x16& acc, int half, int64_t valid) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t r = row_base + 8 * g + 4 * half;
+    st4(out + (int64_t)col * ld + r,
+        make_float4(r + 0 < valid ? acc[4 * g + 0] : 0.f, r + 1 < valid ? acc[4 * g + 1] : 0.f,
+                    r + 2 < valid ? acc[4 * g + 2] : 0.f, r + 3 < valid ? acc[4 * g + 3] : 0.f));
+  }
+}
+
 // Direct-to-LDS form of the A X product for panel width 128: 8 waves, a
 // 256 x 128 output block per workgroup (4 x 2 waves of 64 x 64).  The A slabs
 // (256 rows x 64 BF16) travel from HBM straight into a 4-deep LDS ring with
@@ -243,12 +255,16 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
     __syncthreads();
     compute(As0, Xs0);
   }
+  // rows [m, m rounded up to 128) are written as zeros, as by the
+  // register-staged form (rows past m of the block hold sums of the clamped
+  // row m - 1)
+  const int64_t mz = (m + 127) / 128 * 128;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int64_t rb = i0 + wr * 64 + a * 32;
-      if (rb < m) store_acc16(Yp, ldy, rb, wc * 64 + t * 32 + l32, acc[a][t], half);
+      if (rb < mz) store_acc16_rows(Yp, ldy, rb, wc * 64 + t * 32 + l32, acc[a][t], half, m);
     }
 }
 
@@ -554,6 +570,181 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
   for (int t = 0; t < NT; ++t) store_acc16(Zp, ldz, j0 + wave * 32, t * 32 + l32, acc[t], half);
 }
 
+// Direct-to-LDS form of Z (+ partial I) = A16(tile I, :)^T Q16(tile I, :) for
+// panel width 128: 8 waves, a 256 x 128 output block per workgroup (4 x 2
+// waves of 64 x 64), the reduction running over the rows of the tile.  The A
+// slabs (64 rows x 256 BF16 columns = 32 KB) stream from HBM into a 4-deep LDS
+// ring with buffer_load ... lds and the panel slabs (128 columns x 64 rows)
+// go through registers two slabs ahead into a double buffer, as in the A X
+// form above.  The matrix-core A operand needs 8 consecutive rows of one
+// column per lane: ds_read_tr16_b64 transposes 4 rows x 16 columns across a
+// 16-lane group, so two such reads give each lane its 8 rows.  Layout of an A
+// slab in LDS: row r at 512 r bytes, its 16-byte chunk c at slot
+// c ^ 2 (r & 3), so the 4 rows of a transposed read fall on distinct banks
+// (the DMA writes lane i at offset 16 i, so the swizzle is in the source
+// addresses).  Rows past the tile read zeros through the buffer range check
+// (offsets past the descriptor's extent), so the reduction needs no tail
+// path; panel rows past the tile are zeroed the same way.  Columns past n
+// re-read the block's last chunk: with n a multiple of 32 their sums fill
+// only whole 32-row groups of the output past n, which are stored as zeros.
+// Needs n a multiple of 32, m a multiple of 8, tm * lda and 128 * ldq BF16
+// elements within a 31-bit byte offset (the launcher checks).
+constexpr int DT_BN = 256, DT_LP = 128, DT_ARUN = 64 * DT_BN / 512 / 8, DT_XRUN = 2;
+
+template <int CP>
+__global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, int64_t lda,
+                                                    int64_t m, int64_t n, int64_t tm,
+                                                    const u16* __restrict__ Q, int64_t ldq,
+                                                    float* __restrict__ Z, int64_t ldz,
+                                                    int64_t part_stride) {
+  static_assert(DT_ARUN == 4, "four 1 KB runs per wave and slab");
+  __shared__ __attribute__((aligned(1024))) u16 As0[64 * DT_BN], As1[64 * DT_BN];
+  __shared__ __attribute__((aligned(1024))) u16 As2[64 * DT_BN], As3[64 * DT_BN];
+  __shared__ __attribute__((aligned(1024))) u16 Qs0[DT_LP * 64], Qs1[DT_LP * 64];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wj = wave & 3, wc = wave >> 2;
+  const int64_t j0 = (int64_t)blockIdx.x * DT_BN;
+  const int64_t ib0 = (int64_t)blockIdx.y * tm;
+  const int64_t ib1 = min(m, ib0 + tm);
+  float* Zp = Z + (int64_t)blockIdx.y * part_stride;
+  const int64_t ns = (ib1 - ib0 + 63) / 64;            // slabs, the last one maybe partial
+  // columns of this block that exist; chunks past them re-read the last one
+  // (their sums land only in output rows past n, which are stored as zeros)
+  const int ncol = (int)min((int64_t)DT_BN, n - j0);
+  constexpr int kOob = 0x7ffffff0;                      // past every extent below: reads zero
+  // A rows [ib0, ib1) from column j0; the extent ends with row ib1 - 1
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A + ib0 * lda + j0), (short)0, (int)((ib1 - ib0) * lda * 2), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)Q, (short)0, (int)(((int64_t)(DT_LP - 1) * ldq + m) * 2), 0x00020000);
+
+  // A slab t: wave w fills the 1 KB runs 4 w .. 4 w + 3, run b = rows 2 b and
+  // 2 b + 1; lane i writes slot i & 31 of row 2 b + (i >> 5), which holds
+  // chunk (i & 31) ^ 2 (row & 3).  Past the last slab: a re-read of panel
+  // slab 0 (cached), so every slab issues the same loads.
+  auto issue_a = [&](u16* st, int64_t t) {
+    const bool real = t < ns;
+    const __amdgpu_buffer_rsrc_t rs = real ? ra : rq;
+#pragma unroll
+    for (int j = 0; j < DT_ARUN; ++j) {
+      const int b = wave * DT_ARUN + j;
+      const int r = 2 * b + (lane >> 5), slot = lane & 31;
+      const int ch = slot ^ (2 * (r & 3));
+      const int row = (int)(t * 64) + r;               // within the tile
+      const int off = (row * (int)lda + min(8 * ch, ncol - 8)) * 2;
+      const int c = (b * 2 + (lane >> 5)) & (DT_LP - 1);
+      const int doff = (c * (int)ldq + (int)ib0 + 8 * (slot & 7)) * 2;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + b * 512, 16, real ? off : doff, 0, 0, CP);
+    }
+  };
+  // panel slab t (slab 0 past the last) into registers; rows past the tile
+  // read zero
+  const int rr = lane >> 3, sl = lane & 7;
+  const int qc0 = (wave * DT_XRUN) * 8 + rr, qc1 = qc0 + 8;
+  auto load_q = [&](v4u& x0, v4u& x1, int64_t t) {
+    const int64_t i0 = ib0 + (t < ns ? t : 0) * 64;
+    const int64_t r0 = i0 + 8 * (sl ^ (qc0 & 7)), r1 = i0 + 8 * (sl ^ (qc1 & 7));
+    x0 = __builtin_amdgcn_raw_buffer_load_b128(rq, r0 < ib1 ? (int)((qc0 * ldq + r0) * 2) : kOob, 0, 0);
+    x1 = __builtin_amdgcn_raw_buffer_load_b128(rq, r1 < ib1 ? (int)((qc1 * ldq + r1) * 2) : kOob, 0, 0);
+  };
+  auto store_q = [&](u16* st, const v4u& x0, const v4u& x1) {
+    *reinterpret_cast<v4u*>(st + (wave * DT_XRUN) * 512 + lane * 8) = x0;
+    *reinterpret_cast<v4u*>(st + (wave * DT_XRUN + 1) * 512 + lane * 8) = x1;
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+
+  // transposed-read coordinates of this lane: 16-lane group g, row a4 of the
+  // four, columns 4 b4 .. 4 b4 + 3 of the group's sixteen
+  const int g = lane >> 4, a4 = (lane >> 2) & 3, b4 = lane & 3;
+  auto compute = [&](const u16* as, const u16* qs) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      bf16x8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int col = wj * 64 + a * 32 + (g & 1) * 16 + 4 * b4;
+        const int r0 = s * 16 + half * 8 + a4, r1 = r0 + 4;    // r0 & 3 == r1 & 3 == a4
+        const int cs = ((col >> 3) ^ (2 * a4)) * 8 + (col & 7);
+        const s16x4 lo4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(as + r0 * DT_BN + cs));
+        const s16x4 hi4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(as + r1 * DT_BN + cs));
+        __builtin_memcpy(&av[a], &lo4, 8);
+        __builtin_memcpy(reinterpret_cast<char*>(&av[a]) + 8, &hi4, 8);
+      }
+      const int q = s * 2 + half;                   // 16-byte chunk of the 64-row slab
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = wc * 64 + t * 32 + l32;
+        bv[t] = *reinterpret_cast<const bf16x8*>(qs + c * 64 + 8 * (q ^ (c & 7)));
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+    }
+  };
+
+  // the same slab schedule as the A X form: issue panel t + 2 and A t + 3,
+  // compute t, wait for the panel registers of t + 1 (and so A t + 1), write
+  // them to LDS, barrier
+  constexpr int kWaitStep = 0x0f70 | (2 * DT_ARUN + DT_XRUN);
+  auto step = [&](int64_t t, u16* as, u16* qs, u16* qs_next, u16* as_refill, v4u& xp0, v4u& xp1,
+                  v4u& xn0, v4u& xn1) {
+    load_q(xn0, xn1, t + 2);
+    issue_a(as_refill, t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(as, qs);
+    __builtin_amdgcn_s_waitcnt(kWaitStep);
+    store_q(qs_next, xp0, xp1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  };
+
+  v4u xa0, xa1, xb0, xb1;
+  load_q(xa0, xa1, 0);
+  __builtin_amdgcn_s_waitcnt(0x0f70);
+  store_q(Qs0, xa0, xa1);
+  load_q(xb0, xb1, 1);
+  issue_a(As0, 0);
+  issue_a(As1, 1);
+  issue_a(As2, 2);
+  __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * DT_ARUN));
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_s_barrier();
+  int64_t tb = 0;
+  for (; tb + 3 < ns; tb += 4) {
+    step(tb, As0, Qs0, Qs1, As3, xb0, xb1, xa0, xa1);
+    step(tb + 1, As1, Qs1, Qs0, As0, xa0, xa1, xb0, xb1);
+    step(tb + 2, As2, Qs0, Qs1, As1, xb0, xb1, xa0, xa1);
+    step(tb + 3, As3, Qs1, Qs0, As2, xa0, xa1, xb0, xb1);
+  }
+  if (tb < ns) {
+    step(tb, As0, Qs0, Qs1, As3, xb0, xb1, xa0, xa1);
+    if (tb + 1 < ns) {
+      step(tb + 1, As1, Qs1, Qs0, As0, xa0, xa1, xb0, xb1);
+      if (tb + 2 < ns) step(tb + 2, As2, Qs0, Qs1, As1, xb0, xb1, xa0, xa1);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0f70);   // the last (dummy) loads land before LDS is freed
+  // output rows [n, n rounded up to 128) are written as zeros, as by the
+  // register-staged form
+  const int64_t nz = (n + 127) / 128 * 128;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t jb = j0 + wj * 64 + a * 32;
+      if (jb < nz) store_acc16_rows(Zp, ldz, jb, wc * 64 + t * 32 + l32, acc[a][t], half, n);
+    }
+}
+
 // A16 (m x ldo, BF16, round to nearest even) = A (m x n FP32 or FP64, lda);
 // columns [n, ldo) zero.  8 elements per thread; rows that are 16-byte aligned
 // take two 16-byte loads.
@@ -671,6 +862,17 @@ hipError_t launch_nn_bf16_cast(const float* A32, int64_t lda, int64_t m, int64_t
 hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
                           int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
                           int64_t ldz, int64_t part_stride, hipStream_t s) {
+  // direct-to-LDS form: whole 16-byte chunks at both ends of every row and
+  // tile (n a multiple of 32, m of 8), 16-byte aligned rows, 31-bit offsets
+  const bool dl = lp == 128 && (n % 32) == 0 && (m % 8) == 0 && (tm % 8) == 0 && (lda % 8) == 0 &&
+                  (ldq % 8) == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)Q & 15) == 0 &&
+                  (tm + 64) * lda * 2 <= INT32_MAX && (int64_t)DT_LP * ldq * 2 <= INT32_MAX;
+  if (dl) {
+    dim3 grid((unsigned)ceil_div_dev(n, DT_BN), (unsigned)TI);
+    hipLaunchKernelGGL((k_tn_bf16_dl<2>), grid, dim3(512), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz,
+                       part_stride);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)ceil_div_dev(n, TBN), (unsigned)TI);
 #define TN16(NT) hipLaunchKernelGGL((k_tn_bf16<NT, true>), grid, dim3(256), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz, part_stride)
   switch (lp / 32) {

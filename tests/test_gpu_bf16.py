@@ -61,6 +61,34 @@ def test_bf16_product_from_bf16_storage():
     assert np.all(np.abs(Y - Ab @ Xb) <= gamma_bound(n, np.abs(Ab) @ np.abs(Xb)) + 1e-30)
 
 
+@pytest.mark.parametrize("m,n,l,tile", [
+    (1000, 1024, 120, (256, 320)),   # ragged row block of A X; partial last slab of each Aᵀ Q tile
+    (520, 2080, 128, (224, 416)),    # Aᵀ Q column block of 32; A X tiles end in a partial slab
+    (257, 4096, 100, (0, 0)),        # one row past a block; m not a multiple of 8 (Aᵀ Q other form)
+    (128, 160, 128, (32, 32)),       # tiles shallower than one slab
+])
+def test_bf16_products_from_bf16_storage_width_128(m, n, l, tile):
+    """Panel width 128 with BF16-stored A (the direct-to-LDS product kernels)
+    against the FP64 product of the same operands, within the FP32 summation
+    bound."""
+    dev = need_gpu()
+    say("bf16 width-128 products", m, n, l, tile)
+    k = max(1, l - 20)
+    rng = np.random.default_rng(m + 7 * n + l)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    A16 = torch.as_tensor(A).to(torch.bfloat16).to(dev)
+    plan = Plan(m, n, k, l - k, 1, dtype=torch.bfloat16, precision="bf16", tile=tile)
+    Ab = bf16_round(A)
+    X = rand_panel(n, l, 4)
+    Y = plan.step_product(0, A16, col_major_from_numpy(X, dev)).cpu().numpy()
+    Xb = bf16_round(X)
+    assert np.all(np.abs(Y - Ab @ Xb) <= gamma_bound(n, np.abs(Ab) @ np.abs(Xb)) + 1e-30)
+    Qp = rand_panel(m, l, 5)
+    Z = plan.step_product(1, A16, col_major_from_numpy(Qp, dev)).cpu().numpy()
+    Qb = bf16_round(Qp)
+    assert np.all(np.abs(Z - Ab.T @ Qb) <= gamma_bound(m, np.abs(Ab).T @ np.abs(Qb)) + 1e-30)
+
+
 def factor_vs_oracle(A_host, k, p, q, tile=None, dtype=torch.float32, precision="bf16"):
     dev = need_gpu()
     m, n = A_host.shape
