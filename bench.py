@@ -187,7 +187,7 @@ def main():
                 "traffic": measured_traffic("k_gemm_bf16.hip",
                                             "counters_k_nn_bf16_dense_50000x20000.md"),
                 "kernel": "k_nn_bf16_dl (A*X product of the power steps, BF16 A streamed "
-                          "straight into LDS; the sketch pass is k_nn_bf16_sq reading FP32 A "
+                          "straight into LDS; the sketch pass is k_nn_bf16_dl_cast reading FP32 A "
                           "and writing the BF16 copy)",
                 "per_launch": f"A {m}x{n} bf16 + X {n}x{l} bf16 + Y {m}x{l} fp32 = {bpl} bytes"}
     line = {

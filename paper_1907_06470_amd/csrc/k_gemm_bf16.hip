@@ -466,6 +466,212 @@ __global__ __launch_bounds__(256) void k_nn_bf16_sq(const u16* __restrict__ A, i
       store_acc16(Yp, ldy, i0 + wr * 32 * MR + a * 32, wc * 64 + t * 32 + l32, acc[a][t], half);
 }
 
+// Direct-to-LDS form of the sketch pass with the cast (panel width 128): A is
+// the FP32 input, and the pass both multiplies it and writes its BF16 copy.
+// 8 waves, a 128 x 128 output block per workgroup (4 x 2 waves of 32 x 64).
+// The FP32 slabs (128 rows x 64 values = 32 KB, 256-byte row pieces) stream
+// into a 4-deep LDS ring with buffer_load ... lds; each lane reads its 8
+// values per matrix-core step from LDS and rounds them to BF16 (nearest even,
+// as the register form) before multiplying, and the slab is also read once
+// more, row-contiguously, to write the copy (128 bytes per row and slab).
+// Layout of a slab in LDS: row r at 256 r bytes, its 16-byte chunk c (4
+// values) at slot c ^ (r & 7), which keeps the 8 rows read per LDS cycle on
+// distinct banks.  The panel slabs go through registers two slabs ahead, as
+// in the BF16 form, with the same slab schedule (the copy stores enter the
+// wait counts).  A partial last slab goes through registers with masked
+// loads and masked copy writes.  Needs 128 * lda FP32 values, 128 * ldx and
+// 128 * lda16 BF16 values within a 31-bit byte offset (the launcher checks).
+constexpr int DC_BM = 128, DC_LP = 128, DC_ARUN = 4, DC_XRUN = 2;
+
+__global__ __launch_bounds__(512) void k_nn_bf16_dl_cast(const float* __restrict__ A32, int64_t lda,
+                                                         int64_t m, int64_t n, int64_t tn,
+                                                         const u16* __restrict__ X, int64_t ldx,
+                                                         float* __restrict__ Y, int64_t ldy,
+                                                         int64_t part_stride,
+                                                         u16* __restrict__ A16, int64_t lda16) {
+  __shared__ __attribute__((aligned(1024))) float As0[DC_BM * 64], As1[DC_BM * 64];
+  __shared__ __attribute__((aligned(1024))) float As2[DC_BM * 64], As3[DC_BM * 64];
+  __shared__ __attribute__((aligned(1024))) u16 Xs0[DC_LP * 64], Xs1[DC_LP * 64];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int64_t i0 = (int64_t)blockIdx.x * DC_BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tn;
+  const int64_t k1 = min(n, k0 + tn);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int64_t nfull = (k1 - k0) / 64;
+  const bool tail = k0 + nfull * 64 < k1;
+  const int rows = (int)min((int64_t)DC_BM, m - i0);
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A32 + i0 * lda), (short)0, (int)(((int64_t)(rows - 1) * lda + n) * 4), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)X, (short)0, (int)(((int64_t)(DC_LP - 1) * ldx + n) * 2), 0x00020000);
+
+  // A slab t: wave w fills the 1 KB runs 4 w .. 4 w + 3, run b = rows 4 b ..
+  // 4 b + 3; lane i writes slot i & 15 of row 4 b + (i >> 4), which holds
+  // chunk (i & 15) ^ (row & 7).  Past the last slab: panel re-reads.
+  auto issue_a = [&](float* st, int64_t t) {
+    const bool real = t < nfull;
+    const __amdgpu_buffer_rsrc_t rs = real ? ra : rx;
+    const int kk = (int)(k0 + t * 64);
+#pragma unroll
+    for (int j = 0; j < DC_ARUN; ++j) {
+      const int b = wave * DC_ARUN + j;
+      const int r = 4 * b + (lane >> 4), slot = lane & 15;
+      const int rc = min(r, rows - 1);
+      const int off = (rc * (int)lda + kk + 4 * (slot ^ (r & 7))) * 4;
+      const int c = (4 * b + (lane >> 4)) & (DC_LP - 1);
+      const int doff = (c * (int)ldx + (int)k0 + 8 * (slot & 7)) * 2;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + b * 256, 16, real ? off : doff, 0, 0, 2);
+    }
+  };
+  const int rr = lane >> 3, sl = lane & 7;
+  const int xc0 = (wave * DC_XRUN) * 8 + rr, xc1 = xc0 + 8;
+  auto load_x = [&](v4u& x0, v4u& x1, int64_t t) {
+    const int kk = (int)(k0 + (t < nfull ? t : 0) * 64);
+    x0 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc0 * (int)ldx + kk + 8 * (sl ^ (xc0 & 7))) * 2, 0, 0);
+    x1 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc1 * (int)ldx + kk + 8 * (sl ^ (xc1 & 7))) * 2, 0, 0);
+  };
+  auto store_x = [&](u16* st, const v4u& x0, const v4u& x1) {
+    *reinterpret_cast<v4u*>(st + (wave * DC_XRUN) * 512 + lane * 8) = x0;
+    *reinterpret_cast<v4u*>(st + (wave * DC_XRUN + 1) * 512 + lane * 8) = x1;
+  };
+
+  f32x16 acc[2];
+  acc[0] = f32x16{};
+  acc[1] = f32x16{};
+  const int row = wr * 32 + l32;                   // this lane's A row in the block
+  // the copy's rows of this block; rows past m fall outside the extent, so
+  // their stores are dropped by the range check
+  const __amdgpu_buffer_rsrc_t rc16 = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A16 + i0 * lda16), (short)0, (int)((int64_t)rows * lda16 * 2), 0x00020000);
+  // slab in LDS -> BF16 copy: thread e / 8-value chunk: 8 threads per row,
+  // 128 contiguous bytes per row and slab, two 16-byte stores per thread
+  // (rows past m: offsets past the extent, dropped).  The partial slab stores
+  // element by element up to k1.
+  auto copy_out = [&](const float* as, int64_t kb, bool masked) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 512 * j, r = e >> 3, c8 = e & 7;
+      const float4 f0 = *reinterpret_cast<const float4*>(as + r * 64 + 4 * ((2 * c8) ^ (r & 7)));
+      const float4 f1 = *reinterpret_cast<const float4*>(as + r * 64 + 4 * ((2 * c8 + 1) ^ (r & 7)));
+      const v4u w = {pack_bf16(f0.x, f0.y), pack_bf16(f0.z, f0.w), pack_bf16(f1.x, f1.y),
+                     pack_bf16(f1.z, f1.w)};
+      const int64_t kk = kb + 8 * c8;
+      if (!masked) {
+        __builtin_amdgcn_raw_buffer_store_b128(w, rc16, (int)((r * lda16 + kk) * 2), 0, 2);
+      } else if (i0 + r < m) {
+        u16* dst = A16 + (i0 + r) * lda16 + kk;
+        for (int q = 0; q < 8 && kk + q < k1; ++q) dst[q] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+      }
+    }
+  };
+  // the matrix-core steps of a slab: lane half h takes the values 32 h + 8 s
+  // .. + 7 at step s (the order of the register form), rounded to BF16
+  auto compute = [&](const float* as, const u16* xs) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = 8 * half + 2 * s;              // first 16-byte chunk of this lane's 8 values
+      const float4 f0 = *reinterpret_cast<const float4*>(as + row * 64 + 4 * (q ^ (row & 7)));
+      const float4 f1 = *reinterpret_cast<const float4*>(as + row * 64 + 4 * ((q + 1) ^ (row & 7)));
+      const uint4 w = make_uint4(pack_bf16(f0.x, f0.y), pack_bf16(f0.z, f0.w),
+                                 pack_bf16(f1.x, f1.y), pack_bf16(f1.z, f1.w));
+      bf16x8 av;
+      __builtin_memcpy(&av, &w, 16);
+      const int qx = 4 * half + s;                 // panel chunk (8 values) of this step
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = wc * 64 + t * 32 + l32;
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(xs + c * 64 + 8 * (qx ^ (c & 7)));
+        acc[t] = mfma_bf16(av, bv, acc[t]);
+      }
+    }
+  };
+
+  // the slab schedule of the BF16 form, with this pass's copy stores in the
+  // count: issue order of slab t is panel t + 2 (DC_XRUN), A t + 3
+  // (DC_ARUN), the copy stores of slab t (4).  Waiting for the panel
+  // registers of t + 1 at the end of slab t allows the A slab t + 2, the
+  // stores of t - 1 and everything of t to stay in flight; at the end of slab
+  // 0 nothing of slab -1 exists, so the wait is shorter there (A slab 1 must
+  // have landed for slab 1).
+  auto vmwait = [](int cnt) { return 0x0f70 | (cnt & 15) | ((cnt >> 4) << 14); };
+  constexpr int kStores = 2;
+  auto step = [&](int64_t t, float* as, u16* xs, u16* xs_next, float* as_refill, v4u& xp0,
+                  v4u& xp1, v4u& xn0, v4u& xn1, bool first) {
+    load_x(xn0, xn1, t + 2);
+    issue_a(as_refill, t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    copy_out(as, k0 + t * 64, false);
+    compute(as, xs);
+    __builtin_amdgcn_sched_barrier(0);
+    if (first)
+      __builtin_amdgcn_s_waitcnt(vmwait(2 * DC_ARUN + DC_XRUN + kStores));
+    else
+      __builtin_amdgcn_s_waitcnt(vmwait(2 * DC_ARUN + DC_XRUN + 2 * kStores));
+    store_x(xs_next, xp0, xp1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  };
+
+  v4u xa0, xa1, xb0, xb1;
+  if (nfull > 0) {
+    load_x(xa0, xa1, 0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    store_x(Xs0, xa0, xa1);
+    load_x(xb0, xb1, 1);
+    issue_a(As0, 0);
+    issue_a(As1, 1);
+    issue_a(As2, 2);
+    __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * DC_ARUN));
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+    step(0, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1, true);
+  }
+  int64_t tb = 1;
+  for (; tb + 3 < nfull; tb += 4) {     // four whole steps: no branch between them
+    step(tb, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1, false);
+    step(tb + 1, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1, false);
+    step(tb + 2, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1, false);
+    step(tb + 3, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1, false);
+  }
+  if (tb < nfull) {                     // up to three remaining slabs
+    step(tb, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1, false);
+    if (tb + 1 < nfull) {
+      step(tb + 1, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1, false);
+      if (tb + 2 < nfull) step(tb + 2, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1, false);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0f70);
+  if (tail) {   // last, partial slab: masked loads through registers
+    __syncthreads();
+    const int64_t kk = k0 + nfull * 64;
+    for (int e = tid; e < DC_BM * 16; e += 512) {
+      const int r = e >> 4, c = e & 15;
+      const int64_t gi = min(i0 + r, m - 1);
+      *reinterpret_cast<float4*>(As0 + r * 64 + 4 * (c ^ (r & 7))) =
+          ld4_masked(A32 + gi * lda, kk + 4 * c, k1);
+    }
+    for (int e = tid; e < DC_LP * 8; e += 512) {
+      const int r = e >> 3, c = e & 7;
+      *reinterpret_cast<uint4*>(Xs0 + r * 64 + 8 * (c ^ (r & 7))) =
+          ld8_masked(X + (int64_t)r * ldx, kk + 8 * c, k1);
+    }
+    __syncthreads();
+    copy_out(As0, kk, true);
+    compute(As0, Xs0);
+  }
+  const int64_t mz = (m + 127) / 128 * 128;
+  const int64_t rb = i0 + wr * 32;
+  if (rb < mz) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      store_acc16_rows(Yp, ldy, rb, wc * 64 + t * 32 + l32, acc[t], half, m);
+  }
+}
+
 // Z (+ partial I) = A16(tile I, :)^T Q16(tile I, :).  The A tile is staged
 // row-major as loaded ([i][j], coalesced 16-byte loads); each lane gathers
 // its A^T fragment (8 consecutive i of one column j) with 16-bit LDS reads,
@@ -853,6 +1059,15 @@ hipError_t launch_nn_bf16_cast(const float* A32, int64_t lda, int64_t m, int64_t
                                int64_t part_stride, hipStream_t s) {
   if (lp != 128 || (lda % 4) != 0 || (((uintptr_t)A32) & 15) != 0 || (lda16 % 8) != 0)
     return hipErrorInvalidValue;
+  // direct-to-LDS form: 16-byte aligned copy rows and panel, 31-bit offsets
+  if ((tn % 8) == 0 && (ldx % 8) == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)A16 & 15) == 0 &&
+      (int64_t)DC_BM * lda * 4 <= INT32_MAX && (int64_t)DC_LP * ldx * 2 <= INT32_MAX &&
+      (int64_t)DC_BM * lda16 * 2 <= INT32_MAX) {
+    dim3 grid((unsigned)ceil_div_dev(m, DC_BM), (unsigned)TJ);
+    hipLaunchKernelGGL(k_nn_bf16_dl_cast, grid, dim3(512), 0, s, A32, lda, m, n, tn, X, ldx, Y, ldy,
+                       part_stride, A16, lda16);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)ceil_div_dev(m, 128), (unsigned)TJ);
   hipLaunchKernelGGL((k_nn_bf16_sq<1, 2, true>), grid, dim3(256), 0, s, (const u16*)nullptr, lda, m,
                      n, tn, X, ldx, Y, ldy, part_stride, A32, A16, lda16);

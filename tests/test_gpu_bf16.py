@@ -26,6 +26,8 @@ def bf16_round(x):
     (777, 1234, 70, (0, 0)),
     (300, 260, 190, (96, 64)),
     (513, 2049, 128, (512, 1024)),
+    (1000, 1024, 120, (256, 320)),
+    (520, 2080, 128, (224, 416)),
     (33, 5000, 3, (32, 4096)),
 ])
 def test_bf16_products_within_rounding_bound(m, n, l, tile):
