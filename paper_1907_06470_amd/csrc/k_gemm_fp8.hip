@@ -282,6 +282,195 @@ __global__ __launch_bounds__(256) void k_nn_fp8(const u8* __restrict__ A, int64_
   }
 }
 
+// Direct-to-LDS form for panel width 128 (the same byte geometry and slab
+// schedule as the BF16 direct-to-LDS A X kernel): 8 waves, a 256 x 128 output
+// block per workgroup (4 x 2 waves of 64 x 64); the A slabs (256 rows x 128
+// FP8 = 32 KB, two 64-deep quantisation slabs) stream from HBM into a 4-deep
+// LDS ring with buffer_load ... lds, three in flight; the panel slabs (128
+// columns x 128) go through registers two slabs ahead into a double buffer.
+// Row r of a slab stores its 16-byte chunk c at slot c ^ (r & 7) (the source
+// addresses make the swizzle).  Each wave's 64 rows are one quantisation row
+// block, so one block scale per wave and 64-deep slab; the per-slab products
+// and their scaling are those of the register-staged kernel, in the same
+// order.  A partial last slab goes through registers with masked loads.
+// Needs 256 * lda and 128 * ldx bytes within a 31-bit offset.
+constexpr int F8_BM = 256, F8_LP = 128, F8_ARUN = 4, F8_XRUN = 2;
+
+__global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int64_t lda,
+                                                   int64_t rows, int64_t kdim, int64_t tk,
+                                                   const float* __restrict__ sA, int64_t sc_r,
+                                                   int64_t sc_k, const u8* __restrict__ X,
+                                                   int64_t ldx, const float* __restrict__ sx,
+                                                   float* __restrict__ Y, int64_t ldy,
+                                                   int64_t part_stride) {
+  __shared__ __attribute__((aligned(1024))) u8 As0[F8_BM * 128], As1[F8_BM * 128];
+  __shared__ __attribute__((aligned(1024))) u8 As2[F8_BM * 128], As3[F8_BM * 128];
+  __shared__ __attribute__((aligned(1024))) u8 Xs0[F8_LP * 128], Xs1[F8_LP * 128];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, half = lane >> 5;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int64_t i0 = (int64_t)blockIdx.x * F8_BM;
+  const int64_t k0 = (int64_t)blockIdx.y * tk;
+  const int64_t k1 = min(kdim, k0 + tk);
+  float* Yp = Y + (int64_t)blockIdx.y * part_stride;
+  const int64_t nfull = (k1 - k0) / 128;
+  const bool tail = k0 + nfull * 128 < k1;
+  const int rr = lane >> 3, sl = lane & 7;
+  const int nrow = (int)min((int64_t)F8_BM, rows - i0);
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A + i0 * lda), (short)0, (int)((int64_t)(nrow - 1) * lda + kdim), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)X, (short)0, (int)((int64_t)(F8_LP - 1) * ldx + kdim), 0x00020000);
+  // quantisation row block of this wave's 64 rows (rows past the end: the last)
+  const int64_t rblk = min(i0 + wr * 64, rows - 1) / kQB;
+
+  auto issue_a = [&](u8* st, int64_t t) {   // past the last slab: panel re-reads
+    const bool real = t < nfull;
+    const __amdgpu_buffer_rsrc_t rs = real ? ra : rx;
+    const int kk = (int)(k0 + t * 128);
+#pragma unroll
+    for (int j = 0; j < F8_ARUN; ++j) {
+      const int r = (wave * F8_ARUN + j) * 8 + rr;
+      const int rc = min(r, nrow - 1);
+      const int c = r & (F8_LP - 1);
+      const int off = real ? rc * (int)lda + kk + 16 * (sl ^ (r & 7)) : c * (int)ldx + (int)k0 + 16 * sl;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + (wave * F8_ARUN + j) * 1024, 16, off, 0, 0, 2);
+    }
+  };
+  const int xc0 = (wave * F8_XRUN) * 8 + rr, xc1 = xc0 + 8;
+  auto load_x = [&](v4u& x0, v4u& x1, int64_t t) {
+    const int kk = (int)(k0 + (t < nfull ? t : 0) * 128);
+    x0 = __builtin_amdgcn_raw_buffer_load_b128(rx, xc0 * (int)ldx + kk + 16 * (sl ^ (xc0 & 7)), 0, 0);
+    x1 = __builtin_amdgcn_raw_buffer_load_b128(rx, xc1 * (int)ldx + kk + 16 * (sl ^ (xc1 & 7)), 0, 0);
+  };
+  auto store_x = [&](u8* st, const v4u& x0, const v4u& x1) {
+    *reinterpret_cast<v4u*>(st + (wave * F8_XRUN) * 1024 + lane * 16) = x0;
+    *reinterpret_cast<v4u*>(st + (wave * F8_XRUN + 1) * 1024 + lane * 16) = x1;
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+
+  // 64-deep quantisation slabs nq (1 or 2) of a 128-deep slab from column kb
+  auto compute = [&](const u8* as, const u8* xs, int64_t kb, int nq) {
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      if (s2 >= nq) break;
+      const int q = 4 * s2 + 2 * half;             // this lane's two 16-byte chunks
+      v8i av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = wr * 64 + a * 32 + l32;
+        const v4u lo = *reinterpret_cast<const v4u*>(as + r * 128 + 16 * (q ^ (r & 7)));
+        const v4u hi = *reinterpret_cast<const v4u*>(as + r * 128 + 16 * ((q + 1) ^ (r & 7)));
+        av[a] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = wc * 64 + t * 32 + l32;
+        const v4u lo = *reinterpret_cast<const v4u*>(xs + c * 128 + 16 * (q ^ (c & 7)));
+        const v4u hi = *reinterpret_cast<const v4u*>(xs + c * 128 + 16 * ((q + 1) ^ (c & 7)));
+        bv[t] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      }
+      const float sb = sA[rblk * sc_r + (kb / kQB + s2) * sc_k];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const f32x16 part = mfma_fp8(av[a], bv[t], f32x16{});
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[a][t][e] += sb * part[e];
+        }
+    }
+  };
+
+  constexpr int kWaitStep = 0x0f70 | (2 * F8_ARUN + F8_XRUN);
+  auto step = [&](int64_t t, u8* as, u8* xs, u8* xs_next, u8* as_refill, v4u& xp0, v4u& xp1,
+                  v4u& xn0, v4u& xn1) {
+    load_x(xn0, xn1, t + 2);
+    issue_a(as_refill, t + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(as, xs, k0 + t * 128, 2);
+    __builtin_amdgcn_s_waitcnt(kWaitStep);
+    store_x(xs_next, xp0, xp1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  };
+
+  v4u xa0, xa1, xb0, xb1;
+  if (nfull > 0) {
+    load_x(xa0, xa1, 0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    store_x(Xs0, xa0, xa1);
+    load_x(xb0, xb1, 1);
+    issue_a(As0, 0);
+    issue_a(As1, 1);
+    issue_a(As2, 2);
+    __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * F8_ARUN));
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+  }
+  int64_t tb = 0;
+  for (; tb + 3 < nfull; tb += 4) {
+    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
+    step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
+    step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+    step(tb + 3, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1);
+  }
+  if (tb < nfull) {
+    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
+    if (tb + 1 < nfull) {
+      step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
+      if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0f70);
+  if (tail) {   // last, partial slab: masked loads through registers
+    __syncthreads();
+    const int64_t kk = k0 + nfull * 128;
+    for (int e = tid; e < F8_BM * 8; e += 512) {
+      const int r = e >> 3, c = e & 7;
+      const int64_t gi = min(i0 + r, rows - 1);
+      *reinterpret_cast<uint4*>(As0 + r * 128 + 16 * (c ^ (r & 7))) =
+          ld16_masked(A + gi * lda, kk + 16 * c, k1);
+    }
+    for (int e = tid; e < F8_LP * 8; e += 512) {
+      const int r = e >> 3, c = e & 7;
+      *reinterpret_cast<uint4*>(Xs0 + r * 128 + 16 * (c ^ (r & 7))) =
+          ld16_masked(X + (int64_t)r * ldx, kk + 16 * c, k1);
+    }
+    __syncthreads();
+    compute(As0, Xs0, kk, (int)((k1 - kk + kQB - 1) / kQB));
+  }
+  // column scales; rows [rows, rows rounded up to 128) stored as zeros, as by
+  // the register-staged kernel
+  const int64_t rz = (rows + 127) / 128 * 128;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = wc * 64 + t * 32 + l32;
+    const float cs = sx[col];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int64_t rb = i0 + wr * 64 + a * 32;
+      if (rb >= rz) continue;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t r = rb + 8 * g + 4 * half;
+        st4(Yp + (int64_t)col * ldy + r,
+            make_float4(r + 0 < rows ? acc[a][t][4 * g + 0] * cs : 0.f,
+                        r + 1 < rows ? acc[a][t][4 * g + 1] * cs : 0.f,
+                        r + 2 < rows ? acc[a][t][4 * g + 2] * cs : 0.f,
+                        r + 3 < rows ? acc[a][t][4 * g + 3] * cs : 0.f));
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int64_t fp8_scale_blocks(int64_t rows, int64_t cols) {
@@ -317,6 +506,15 @@ hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t 
   if (tk % kQB != 0 || lda8 % 16 != 0 || ldx8 % 16 != 0 || ldy % 4 != 0)
     return hipErrorInvalidValue;
   const int nt = (int)(lp / 32);
+  // direct-to-LDS form: panel width 128, 16-byte aligned operands, 31-bit
+  // buffer offsets over 256 rows of A and the 128 panel columns
+  if (nt == 4 && ((uintptr_t)A8 & 15) == 0 && ((uintptr_t)X8 & 15) == 0 &&
+      (int64_t)F8_BM * lda8 <= INT32_MAX && (int64_t)F8_LP * ldx8 <= INT32_MAX) {
+    dim3 grid((unsigned)ceil_div_dev(rows, F8_BM), (unsigned)TK);
+    hipLaunchKernelGGL(k_nn_fp8_dl, grid, dim3(512), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r, sc_k,
+                       X8, ldx8, sx, Y, ldy, part_stride);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)ceil_div_dev(rows, 128), (unsigned)TK);
 #define NN8(NT) hipLaunchKernelGGL((k_nn_fp8<NT, 1>), grid, dim3(256), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r, sc_k, X8, ldx8, sx, Y, ldy, part_stride)
   switch (nt) {
