@@ -115,6 +115,110 @@ __global__ __launch_bounds__(256) void k_cast_fp8(const T* __restrict__ A, int64
   }
 }
 
+// Same cast for FP32 input, one workgroup per 128 x 256 strip (2 x 4 blocks):
+// wave w reads rows 16 w .. 16 w + 15 of the strip, lane L columns 4 L ..
+// 4 L + 3 (block L / 16) as 16-byte loads (1 KB per row and wave), so A8 rows
+// go out as 256 contiguous bytes and A8T rows (through LDS) as 128.  Each
+// thread packs the 16 bytes of one column over its 16 rows and writes them to
+// the transposed staging in one store; staging column p holds strip column
+// 4 (p % 64) + p / 64, which spreads a store's 64 lanes over all banks.
+// Same scales and values as the one-block kernel.
+__global__ __launch_bounds__(512) void k_cast_fp8_strip(const float* __restrict__ A, int64_t lda,
+                                                        int64_t m, int64_t n,
+                                                        u8* __restrict__ A8, int64_t lda8,
+                                                        u8* __restrict__ A8T, int64_t ldat8,
+                                                        float* __restrict__ scale, int64_t nbk) {
+  constexpr int SR = 128, SC = 256, TLD = SR + 16;
+  __shared__ float red[2][8][4];                                 // [amax / bad][wave][block column]
+  __shared__ __attribute__((aligned(16))) u8 Tt[SC * TLD];       // staging column p, row r
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * SR, j0 = (int64_t)blockIdx.x * SC;
+  const int bc = lane >> 4, br = wave >> 2;
+  const int64_t jc = j0 + 4 * lane;
+  const bool full = i0 + SR <= m && j0 + SC <= n;
+  float4 x[16];
+  float amax = 0.f, bad = 0.f;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int64_t i = i0 + 16 * wave + u;
+    if (full)
+      x[u] = ld4(A + i * lda + jc);
+    else
+      x[u] = (i < m && jc < n) ? ld4_masked(A + i * lda, jc, n) : make_float4(0.f, 0.f, 0.f, 0.f);
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(x[u].x), fabsf(x[u].y)), fmaxf(fabsf(x[u].z), fabsf(x[u].w))));
+    const bool fin = __builtin_isfinite(x[u].x) && __builtin_isfinite(x[u].y) &&
+                     __builtin_isfinite(x[u].z) && __builtin_isfinite(x[u].w);
+    bad = fmaxf(bad, fin ? 0.f : 1.f);
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {        // within the 16 lanes of a block column
+    amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    bad = fmaxf(bad, __shfl_xor(bad, off, 64));
+  }
+  if ((lane & 15) == 0) {
+    red[0][wave][bc] = amax;
+    red[1][wave][bc] = bad;
+  }
+  __syncthreads();
+  amax = fmaxf(fmaxf(red[0][4 * br][bc], red[0][4 * br + 1][bc]),
+               fmaxf(red[0][4 * br + 2][bc], red[0][4 * br + 3][bc]));
+  bad = fmaxf(fmaxf(red[1][4 * br][bc], red[1][4 * br + 1][bc]),
+              fmaxf(red[1][4 * br + 2][bc], red[1][4 * br + 3][bc]));
+  const float sc = bad > 0.f ? __builtin_nanf("") : pow2_scale(amax);
+  const float inv = 1.f / sc;   // exact: a power of two
+  if ((lane & 15) == 0 && (wave & 3) == 0) {
+    const int64_t gbr = blockIdx.y * 2 + br, gbc = blockIdx.x * 4 + bc;
+    if (gbr * kQB < m && gbc * kQB < n) scale[gbr * nbk + gbc] = sc;
+  }
+  uint32_t w[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    w[u] = cvt2(x[u].x * inv, x[u].y * inv) | (cvt2(x[u].z * inv, x[u].w * inv) << 16);
+    const int64_t i = i0 + 16 * wave + u;
+    if (full) {
+      *reinterpret_cast<uint32_t*>(A8 + i * lda8 + jc) = w[u];
+    } else if (i < m && jc < n) {
+      if (jc + 4 <= n && (lda8 & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(A8 + i * lda8 + jc) = w[u];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (jc + e < n) A8[i * lda8 + jc + e] = (u8)(w[u] >> (8 * e));
+      }
+    }
+  }
+  // column 4 lane + e of the strip, rows 16 wave .. + 15: 16 bytes
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t q[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      q[v] = ((w[4 * v + 0] >> (8 * e)) & 0xffu) | (((w[4 * v + 1] >> (8 * e)) & 0xffu) << 8) |
+             (((w[4 * v + 2] >> (8 * e)) & 0xffu) << 16) | (((w[4 * v + 3] >> (8 * e)) & 0xffu) << 24);
+    const int p = e * 64 + lane;
+    *reinterpret_cast<uint4*>(&Tt[p * TLD + 16 * wave]) = make_uint4(q[0], q[1], q[2], q[3]);
+  }
+  __syncthreads();
+  // A8T rows j0 + c: 8 threads per column, 16 bytes (rows i0 + 16 t8 ..) each
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int id = tid + 512 * k, c = id >> 3, t8 = id & 7;
+    const int p = (c & 3) * 64 + (c >> 2);
+    const int64_t j = j0 + c, i = i0 + 16 * t8;
+    const uint4 v = *reinterpret_cast<const uint4*>(&Tt[p * TLD + 16 * t8]);
+    if (full) {
+      *reinterpret_cast<uint4*>(A8T + j * ldat8 + i) = v;
+    } else if (j < n && i < m) {
+      if (i + 16 <= m && (ldat8 & 15) == 0) {
+        *reinterpret_cast<uint4*>(A8T + j * ldat8 + i) = v;
+      } else {
+        const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+        for (int e = 0; e < 16 && i + e < m; ++e) A8T[j * ldat8 + i + e] = (u8)(vv[e >> 2] >> (8 * (e & 3)));
+      }
+    }
+  }
+}
+
 // FP8 copy of an FP32 panel, one workgroup per column: amax over the column,
 // power-of-two scale, e4m3 values over the whole leading dimension.
 __global__ __launch_bounds__(256) void k_panel_to_fp8(const float* __restrict__ P, int64_t ld,
@@ -483,7 +587,12 @@ hipError_t launch_cast_fp8(const void* A, bool f64, int64_t lda, int64_t m, int6
   if (lda8 < n || ldat8 < m) return hipErrorInvalidValue;
   const int64_t nbk = ceil_div_dev(n, kQB);
   dim3 grid((unsigned)nbk, (unsigned)ceil_div_dev(m, kQB));
-  if (f64)
+  if (!f64 && (lda % 4) == 0 && ((uintptr_t)A & 15) == 0 && (lda8 % 4) == 0 &&
+      (ldat8 % 16) == 0 && ((uintptr_t)A8 & 3) == 0 && ((uintptr_t)A8T & 15) == 0) {
+    dim3 g2((unsigned)ceil_div_dev(n, 256), (unsigned)ceil_div_dev(m, 128));
+    hipLaunchKernelGGL(k_cast_fp8_strip, g2, dim3(512), 0, s, (const float*)A, lda, m, n, A8, lda8,
+                       A8T, ldat8, scale, nbk);
+  } else if (f64)
     hipLaunchKernelGGL(k_cast_fp8<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, n, A8,
                        lda8, A8T, ldat8, scale, nbk);
   else
