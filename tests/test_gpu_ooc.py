@@ -84,6 +84,20 @@ def test_host_resident_bf16_storage():
     assert info["h2d_bytes"] >= m * n * 2
 
 
+def test_host_resident_bf16_panel_width_128():
+    """Width-128 panels take the direct-to-LDS product kernels, launched per
+    tile slot here and over the whole matrix in HBM: bitwise the same."""
+    dev = need_gpu()
+    m, n, tile = 2048, 1536, (512, 512)
+    A = _workload(m, n, seed=15)
+    A16 = A.to(torch.bfloat16)
+    Ud, Sd, Vd, _ = Plan(m, n, 100, 20, 1, dtype=torch.bfloat16, precision="bf16",
+                         tile=tile).factor(A16.to(dev))
+    Uh, Sh, Vh, info = Plan(m, n, 100, 20, 1, dtype=torch.bfloat16, precision="bf16", tile=tile,
+                            host=True).factor(A16.pin_memory())
+    assert torch.equal(Sd, Sh) and torch.equal(Ud, Uh) and torch.equal(Vd, Vh)
+
+
 def test_pageable_host_memory_is_rejected():
     need_gpu()
     m, n = 1024, 768
