@@ -91,13 +91,12 @@ __device__ inline void store_acc16_rows(float* out, int64_t ld, int64_t row_base
 // non-temporal: A is streamed once per pass).
 constexpr int DL_BM = 256, DL_LP = 128, DL_ARUN = DL_BM / 8 / 8, DL_XRUN = DL_LP / 8 / 8;
 
-template <int SA, int CP = 0>
+template <int CP>
 __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, int64_t lda,
                                                     int64_t m, int64_t n, int64_t tn,
                                                     const u16* __restrict__ X, int64_t ldx,
                                                     float* __restrict__ Y, int64_t ldy,
                                                     int64_t part_stride) {
-  static_assert(SA == 4, "the ring is unrolled for four stages");
   static_assert(DL_XRUN == 2, "two panel loads per lane and slab");
   // one LDS object per stage: the compiler then sees that reading one stage
   // does not depend on the loads still landing in the others
@@ -681,7 +680,7 @@ constexpr int TPAD = TBN + 8;
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
 
-template <int NT, bool NTL = false, bool TR = false>
+template <int NT, bool NTL = false>
 __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int64_t lda, int64_t m,
                                                  int64_t n, int64_t tm, const u16* __restrict__ Q,
                                                  int64_t ldq, float* __restrict__ Z, int64_t ldz,
@@ -739,28 +738,14 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
     for (int s = 0; s < 4; ++s) {
       // reduction indices of this step: 16 s + 8 half + v
       bf16x8 av;
-      if (TR) {
-        // LDS transpose reads: in each 16-lane group, lane 4a + b names the
-        // 4 columns 4b.. of row a, and lane r receives column r of the 4 rows
-        // named, so lane (column jl, half) gets rows 16 s + 8 half + 0..3,
-        // then + 4..7, of its own column
-        const int g = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
-        const int col = wave * 32 + (g & 1) * 16 + 4 * b;
-        const int row = s * 16 + half * 8 + a;
-        const s16x4 lo4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)&As[buf][row][col]);
-        const s16x4 hi4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)&As[buf][row + 4][col]);
-        __builtin_memcpy(&av, &lo4, 8);
-        __builtin_memcpy(reinterpret_cast<char*>(&av) + 8, &hi4, 8);
-      } else {
-        uint32_t w[4];
+      uint32_t w[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const uint32_t lo = As[buf][s * 16 + half * 8 + 2 * v][jl];
-          const uint32_t hi = As[buf][s * 16 + half * 8 + 2 * v + 1][jl];
-          w[v] = lo | (hi << 16);
-        }
-        __builtin_memcpy(&av, w, 16);
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t lo = As[buf][s * 16 + half * 8 + 2 * v][jl];
+        const uint32_t hi = As[buf][s * 16 + half * 8 + 2 * v + 1][jl];
+        w[v] = lo | (hi << 16);
       }
+      __builtin_memcpy(&av, w, 16);
       bf16x8 bv[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t)
@@ -1029,7 +1014,7 @@ hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, 
                   (int64_t)DL_BM * lda * 2 <= INT32_MAX && (int64_t)DL_LP * ldx * 2 <= INT32_MAX;
   if (dl) {
     dim3 grid((unsigned)ceil_div_dev(m, DL_BM), (unsigned)TJ);
-    hipLaunchKernelGGL((k_nn_bf16_dl<4, 2>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
+    hipLaunchKernelGGL((k_nn_bf16_dl<2>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
                        ldy, part_stride);
     return hipGetLastError();
   }
