@@ -68,6 +68,7 @@ def test_bf16_product_from_bf16_storage():
     (520, 2080, 128, (224, 416)),    # Aᵀ Q column block of 32; A X tiles end in a partial slab
     (257, 4096, 100, (0, 0)),        # one row past a block; m not a multiple of 8 (Aᵀ Q other form)
     (128, 160, 128, (32, 32)),       # tiles shallower than one slab
+    (136, 224, 120, (64, 96)),       # one partial row block; a whole slab plus a tail per tile
 ])
 def test_bf16_products_from_bf16_storage_width_128(m, n, l, tile):
     """Panel width 128 with BF16-stored A (the direct-to-LDS product kernels)

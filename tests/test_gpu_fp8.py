@@ -28,6 +28,7 @@ SLAB_REL = 2.0 ** -8
     (300, 260, 128, (128, 64)),
     (513, 2049, 100, (512, 1024)),
     (65, 5000, 3, (64, 4096)),
+    (136, 224, 120, (64, 128)),
 ])
 def test_fp8_products_match_quantised_operands(m, n, l, tile):
     dev = need_gpu()
