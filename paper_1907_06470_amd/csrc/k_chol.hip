@@ -86,7 +86,6 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
     // collect values that are never read)
 #pragma unroll
     for (int c = j + 1; c < kB; ++c) d[c] -= d[j] * row16_bcast(d[j], c);
-    __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of a step inside it
   }
   // lane r: column r of X_kk = L_kk^-1 by forward substitution, column
   // oriented: once x_p is known it leaves every later row at once (the
