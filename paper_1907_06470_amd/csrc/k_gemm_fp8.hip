@@ -15,6 +15,7 @@
 //   conversion never overflows).
 #include "device.h"
 #include "kernels.h"
+#include "plan.h"
 
 namespace rsvd {
 
@@ -575,6 +576,62 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
   }
 }
 
+// The same conversion split over kPanelFp8Chunks row chunks per column (lp x
+// chunks workgroups instead of lp): the chunk maxima and non-finite flags go
+// to `part`, and every converting workgroup takes the maximum of its column's
+// chunks, so the scale is that of the one-pass kernel (a maximum does not
+// depend on its order) and so are the bytes.
+__global__ __launch_bounds__(256) void k_panel_amax(const float* __restrict__ P, int64_t ld,
+                                                    int64_t rows, int64_t crow,
+                                                    float* __restrict__ part) {
+  __shared__ float red[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c = blockIdx.x, q = blockIdx.y, nq = gridDim.y;
+  const float* col = P + c * ld;
+  const int64_t r0 = q * crow, r1 = min(rows, r0 + crow);
+  float amax = 0.f, bad = 0.f;
+  for (int64_t i = r0 + 4 * tid; i < r1; i += 1024) {
+    const float4 v = ld4_masked(col, i, r1);
+    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    const bool fin = __builtin_isfinite(v.x) && __builtin_isfinite(v.y) &&
+                     __builtin_isfinite(v.z) && __builtin_isfinite(v.w);
+    bad = fmaxf(bad, fin ? 0.f : 1.f);
+  }
+  amax = wave_max(amax);
+  bad = wave_max(bad);
+  if (lane == 0) {
+    red[wave] = amax;
+    red[4 + wave] = bad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[c * nq + q] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    part[(gridDim.x + c) * nq + q] = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_panel_conv_fp8(const float* __restrict__ P, int64_t ld,
+                                                        int64_t rows, int64_t cld,
+                                                        const float* __restrict__ part,
+                                                        u8* __restrict__ P8,
+                                                        float* __restrict__ sc) {
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x, q = blockIdx.y, nq = gridDim.y;
+  // every wave gathers the column's chunk maxima (lane j % nq) and reduces them
+  const int64_t j = (tid & 63) % nq;
+  const float amax = wave_max(part[c * nq + j]);
+  const float bad = wave_max(part[(gridDim.x + c) * nq + j]);
+  const float s = bad > 0.f ? __builtin_nanf("") : pow2_scale(amax), inv = 1.f / s;
+  if (q == 0 && tid == 0) sc[c] = s;
+  const float* col = P + c * ld;
+  const int64_t i0 = q * cld, i1 = min(ld, i0 + cld);
+  for (int64_t i = i0 + 4 * tid; i < i1; i += 1024) {
+    const float4 v = i < rows ? ld4_masked(col, i, rows) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t w = cvt2(v.x * inv, v.y * inv) | (cvt2(v.z * inv, v.w * inv) << 16);
+    *reinterpret_cast<uint32_t*>(P8 + c * ld + i) = w;
+  }
+}
+
 }  // namespace
 
 int64_t fp8_scale_blocks(int64_t rows, int64_t cols) {
@@ -602,9 +659,19 @@ hipError_t launch_cast_fp8(const void* A, bool f64, int64_t lda, int64_t m, int6
 }
 
 hipError_t launch_panel_to_fp8(const float* P, int64_t ld, int64_t rows, int64_t lp, uint8_t* P8,
-                               float* scale, hipStream_t s) {
+                               float* scale, float* part, hipStream_t s) {
   if (ld % 4 != 0 || rows > ld) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_panel_to_fp8, dim3((unsigned)lp), dim3(256), 0, s, P, ld, rows, P8, scale);
+  if (part == nullptr) {
+    hipLaunchKernelGGL(k_panel_to_fp8, dim3((unsigned)lp), dim3(256), 0, s, P, ld, rows, P8, scale);
+    return hipGetLastError();
+  }
+  const int64_t crow = ceil_div_dev(ceil_div_dev(rows, kPanelFp8Chunks), 4) * 4;
+  const int64_t cld = ceil_div_dev(ceil_div_dev(ld, kPanelFp8Chunks), 4) * 4;
+  const dim3 grid((unsigned)lp, (unsigned)kPanelFp8Chunks);
+  hipLaunchKernelGGL(k_panel_amax, grid, dim3(256), 0, s, P, ld, rows, crow, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_panel_conv_fp8, grid, dim3(256), 0, s, P, ld, rows, cld, part, P8, scale);
   return hipGetLastError();
 }
 

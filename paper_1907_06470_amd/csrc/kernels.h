@@ -58,8 +58,11 @@ int64_t fp8_scale_blocks(int64_t rows, int64_t cols);
 hipError_t launch_cast_fp8(const void* A, bool f64, int64_t lda, int64_t m, int64_t n, uint8_t* A8,
                            int64_t lda8, uint8_t* A8T, int64_t ldat8, float* scale, hipStream_t s);
 // P8 = FP8 copy of an FP32 column-major panel (same ld), scale[c] per column.
+// part (2 * lp * kPanelFp8Chunks floats, plan.h; or nullptr for the one-pass
+// kernel): chunk maxima, so the panel is read by lp x kPanelFp8Chunks
+// workgroups.
 hipError_t launch_panel_to_fp8(const float* P, int64_t ld, int64_t rows, int64_t lp, uint8_t* P8,
-                               float* scale, hipStream_t s);
+                               float* scale, float* part, hipStream_t s);
 // Y (+ partial per reduction tile of tk) = A8 X8 with block scales sA and
 // column scales sx (see k_gemm_fp8.hip for the layouts).
 hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,

@@ -234,6 +234,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.Mop8 = p.any_fp8 ? take((size_t)p.ldm * lp) : off;
   w.sX8 = p.any_fp8 ? take(lp * 4) : off;
   w.sM8 = p.any_fp8 ? take(lp * 4) : off;
+  w.f8part = p.any_fp8 ? take((size_t)2 * lp * kPanelFp8Chunks * 4) : off;
   if (p.backward) {
     const size_t kp = (size_t)p.kp, rc = (size_t)p.rcat;
     w.Pcat = take((size_t)p.ldm * rc * 4);

@@ -16,6 +16,7 @@ constexpr int64_t kPanelAlign = 256;   // panel leading dimensions (elements)
 constexpr int64_t kColAlign = 32;      // sketch width is padded to this
 constexpr int kGramBlock = 64;         // Gram output block edge
 constexpr int kJacobiMaxSweeps = 40;
+constexpr int64_t kPanelFp8Chunks = 32;   // row chunks per column of the panel FP8 conversion
 constexpr int kStatusWords = 64;
 constexpr int64_t kSpmmChunk = 2048;   // nonzeros per wave in the sparse products
 
@@ -61,6 +62,7 @@ struct Workspace {
   size_t A8, A8T, sA8;    // FP8 copies of A and A^T, 64 x 64 block scales (FP32)
   size_t Xop8, Mop8;      // FP8 copies of the operand panels
   size_t sX8, sM8;        // their per-column scales
+  size_t f8part;          // chunk maxima of the panel FP8 conversion
   // backward (RSVD_FLAG_BACKWARD)
   size_t Pcat, Rcat;      // outer-product factors (ldm x R, ldn x R), R = lp + 2 kp
   size_t gUp, gVp;        // imported cotangents (ldm x kp, ldn x kp)

@@ -147,7 +147,7 @@ struct Buffers {
   float *Xop, *Mop, *M0, *M1, *N0, *N1, *part, *W, *W2, *Acast;
   uint16_t *A16, *Xop16, *Mop16;
   uint8_t *A8, *A8T, *Xop8, *Mop8;
-  float *sA8, *sX8, *sM8;
+  float *sA8, *sX8, *sM8, *f8part;
   char* slots;
   int32_t *colptr, *rowind, *first;
   float *cval, *Xr, *Yr, *carry;
@@ -189,6 +189,7 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.sA8 = (float*)(b + w.sA8);
   B.sX8 = (float*)(b + w.sX8);
   B.sM8 = (float*)(b + w.sM8);
+  B.f8part = (float*)(b + w.f8part);
   B.slots = b + w.slots;
   B.colptr = (int32_t*)(b + w.colptr);
   B.rowind = (int32_t*)(b + w.rowind);
@@ -450,7 +451,7 @@ struct Runner {
       RSVD_HIP(rsvd::launch_panel_to_bf16(src, nside ? B.Xop16 : B.Mop16, ld * P.lp, s));
     else if (prec == RSVD_FP8E4M3)
       RSVD_HIP(rsvd::launch_panel_to_fp8(src, ld, rows, P.lp, nside ? B.Xop8 : B.Mop8,
-                                         nside ? B.sX8 : B.sM8, s));
+                                         nside ? B.sX8 : B.sM8, B.f8part, s));
     return RSVD_OK;
   }
 
