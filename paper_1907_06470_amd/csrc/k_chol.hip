@@ -52,23 +52,17 @@ __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Factor diagonal block kb in place and write its inverse to Xd[kb] (whole
-// wave; every row of 16 lanes holds the block, lane r of a row holding row r,
-// and only the first row stores).  Values of other rows of the block travel by
-// DPP broadcast inside the 16-lane row, so the wave needs no LDS round trip and
-// no scalar registers between steps.
-__device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0, int kb, int l,
-                           double tau, int& ndrop, int& nbad) {
-  const int lane = threadIdx.x & 63, r = lane & 15;
-  const int g0 = kb * kB;
-  double d[kB];
-#pragma unroll
-  for (int p = 0; p < kB; ++p) {
-    const double v = S[sq(g0 + r, g0 + p)];
-    d[p] = p <= r ? v : 0.0;
-  }
-  const double od = d0[g0 + r];
-  double dv = 0.0;
+// Register part of a diagonal block (whole wave; every row of 16 lanes holds
+// the block, lane r of a row holding row r in d, entries right of the
+// diagonal ignored, and od = the original diagonal entry of row r).  Values of
+// other rows of the block travel by DPP broadcast inside the 16-lane row, so
+// the wave needs no LDS round trip and no scalar registers between steps.  On
+// return d[p] (p <= r) is row r of L_kk, dv = 1 / L_kk(r, r) (0 for a dropped
+// direction) and x[i] = X_kk(i, r), column r of X_kk = L_kk^-1.
+__device__ inline void diag_factor(double (&d)[kB], double od, int g0, int l, double tau,
+                                   int& ndrop, int& nbad, double& dv, double (&x)[kB]) {
+  const int r = threadIdx.x & 15;
+  dv = 0.0;
 #pragma unroll
   for (int j = 0; j < kB; ++j) {
     const double a = row16_bcast(d[j], j);
@@ -90,7 +84,6 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
   // lane r: column r of X_kk = L_kk^-1 by forward substitution, column
   // oriented: once x_p is known it leaves every later row at once (the
   // subtractions of each row keep the order p = 0, 1, ...)
-  double x[kB];
 #pragma unroll
   for (int i = 0; i < kB; ++i) x[i] = (i == r) ? 1.0 : 0.0;
 #pragma unroll
@@ -99,6 +92,21 @@ __device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0
 #pragma unroll
     for (int i = p + 1; i < kB; ++i) x[i] -= row16_bcast(d[p], i) * x[p];
   }
+}
+
+// Factor diagonal block kb in place and write its inverse to Xd[kb] (only
+// the first row of 16 lanes stores).
+__device__ void diag_block(double* S, double* Xd, double* dinv, const double* d0, int kb, int l,
+                           double tau, int& ndrop, int& nbad) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int g0 = kb * kB;
+  double d[kB], x[kB], dv;
+#pragma unroll
+  for (int p = 0; p < kB; ++p) {
+    const double v = S[sq(g0 + r, g0 + p)];
+    d[p] = p <= r ? v : 0.0;
+  }
+  diag_factor(d, d0[g0 + r], g0, l, tau, ndrop, nbad, dv, x);
   if (lane < kB) {
     // the whole row: entries above the diagonal are never read again
 #pragma unroll
@@ -268,6 +276,224 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
   }
 }
 
+// ---- widths 129 .. 192: tile-packed lower triangle ------------------------
+// A 192 x 192 square of doubles does not fit in LDS, so only the 78 lower
+// 16 x 16 tiles are kept (tile (I, J), I >= J, at I (I + 1) / 2 + J; element
+// (r, c) of a tile at r * 16 + (c ^ r)).  The factorisation is the one above;
+// the inverse overwrites L in place.  X_kk of a diagonal block keeps its
+// diagonal in dinv and its strict lower part transposed in the strict upper
+// part of the diagonal tile.  Block row kb of X replaces row kb of L: its
+// tiles are formed in registers during panel step kb (they read L_kb,K for
+// K >= J, which the in-place stores would destroy) and stored at the start of
+// step kb + 1, before anything reads them.
+constexpr int kTpMax = 192;
+constexpr int kTpNb = kTpMax / kB;
+constexpr int kTpTiles = kTpNb * (kTpNb + 1) / 2;
+constexpr int kTpSlots = (kTpNb - 1 + kWaves - 2) / (kWaves - 1);   // X tiles per wave and row
+
+__device__ inline int tp(int I, int J, int r, int c) {   // I >= J
+  return ((I * (I + 1) / 2 + J) * kB + r) * kB + (c ^ r);
+}
+
+// X_kk(a, b) of diagonal block kb
+__device__ inline double tp_xkk(const double* S, const double* dinv, int kb, int a, int b) {
+  const double up = S[tp(kb, kb, min(a, b), max(a, b))];
+  return a == b ? dinv[kb * kB + a] : (a > b ? up : 0.0);
+}
+
+__device__ void tp_diag_block(double* S, double* dinv, const double* d0, int kb, int l,
+                              double tau, int& ndrop, int& nbad) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int g0 = kb * kB;
+  double d[kB], x[kB], dv;
+#pragma unroll
+  for (int p = 0; p < kB; ++p) {
+    const double v = S[tp(kb, kb, r, p)];
+    d[p] = p <= r ? v : 0.0;
+  }
+  diag_factor(d, d0[g0 + r], g0, l, tau, ndrop, nbad, dv, x);
+  if (lane < kB) {
+    // row r of the tile: L_kk(r, p) for p <= r, X_kk(p, r) for p > r
+#pragma unroll
+    for (int p = 0; p < kB; ++p) S[tp(kb, kb, r, p)] = p <= r ? d[p] : x[p];
+    dinv[g0 + r] = dv;
+  }
+}
+
+// L_Ik = A_Ik X_kk^T
+__device__ void tp_panel_tile(double* S, const double* dinv, int kb, int I) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + q;
+    acc = mma(S[tp(I, kb, l16, k)], tp_xkk(S, dinv, kb, l16, k), acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[tp(I, kb, 4 * r + q, l16)] = acc[r];
+}
+
+// A_IJ -= L_Ik L_Jk^T
+__device__ void tp_update_tile(double* S, int kb, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = S[tp(I, J, 4 * r + q, l16)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + q;
+    acc = mma(-S[tp(I, kb, l16, k)], S[tp(J, kb, l16, k)], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[tp(I, J, 4 * r + q, l16)] = acc[r];
+}
+
+// X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ, returned in accumulator layout
+// (register r of lane (c, q): row 4 r + q, column c); rows < I of X are in
+// place, row I still holds L.
+__device__ f64x4 tp_inverse_tile(const double* S, const double* dinv, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
+  for (int K = J; K < I; ++K) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const double b = (K == J) ? tp_xkk(S, dinv, J, k, l16) : S[tp(K, J, k, l16)];
+      if (s < 2)
+        t0 = mma(S[tp(I, K, l16, k)], b, t0);
+      else
+        t1 = mma(S[tp(I, K, l16, k)], b, t1);
+    }
+  }
+  f64x4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = t0[r] + t1[r];
+  f64x4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) x = mma(-tp_xkk(S, dinv, I, l16, 4 * s + q), t[s], x);
+  return x;
+}
+
+__device__ inline void tp_store_tile(double* S, int I, int J, const f64x4& x) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[tp(I, J, 4 * r + q, l16)] = x[r];
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_tp(const double* __restrict__ G, int64_t lp,
+                                                      int l, float* __restrict__ W,
+                                                      int32_t* __restrict__ status, double tau) {
+  __shared__ double S[kTpTiles * kB * kB];
+  __shared__ double dinv[kTpMax];
+  __shared__ double d0[kTpMax];
+  __builtin_amdgcn_s_setprio(3);
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int n = (int)lp;
+  const int nb = (l + kB - 1) / kB;
+
+  // ---- the lower tiles of the leading l x l of G (zeros beyond); the
+  // square is read in pairs of doubles, 16 in flight per thread
+  constexpr int kHalf = kTpMax / 2, kPairs = kTpMax * kHalf, kBatch = 16;
+  for (int e0 = tid; e0 < kPairs; e0 += kThreads * kBatch) {
+    double2 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kThreads, i = e / kHalf, c = (e % kHalf) * 2;
+      const int ic = min(min(i, n - 1), kTpMax - 1), cc = min(c, n - 2);
+      const double2 w = *reinterpret_cast<const double2*>(G + (int64_t)ic * n + cc);
+      v[u].x = (e < kPairs && i < l && c < l) ? w.x : 0.0;
+      v[u].y = (e < kPairs && i < l && c + 1 < l) ? w.y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kThreads, i = e / kHalf, c = (e % kHalf) * 2;
+      if (e < kPairs && (i >> 4) >= (c >> 4)) {
+        S[tp(i >> 4, c >> 4, i & 15, c & 15)] = v[u].x;
+        S[tp(i >> 4, c >> 4, i & 15, (c & 15) + 1)] = v[u].y;
+      }
+    }
+  }
+  for (int i = tid; i < kTpMax; i += kThreads) d0[i] = i < l ? G[(int64_t)i * n + i] : 0.0;
+  lds_barrier();
+
+  int ndrop = 0, nbad = 0;
+  f64x4 xr[kTpSlots];
+  if (wave == 0) tp_diag_block(S, dinv, d0, 0, l, tau, ndrop, nbad);
+  lds_barrier();
+  for (int kb = 0; kb < nb; ++kb) {
+    // block row kb - 1 of X, made during the previous step, replaces L
+    if (wave > 0 && kb >= 2) {
+#pragma unroll
+      for (int u = 0; u < kTpSlots; ++u) {
+        const int J = wave - 1 + u * (kWaves - 1);
+        if (J < kb - 1) tp_store_tile(S, kb - 1, J, xr[u]);
+      }
+    }
+    for (int I = kb + 1 + wave; I < nb; I += kWaves) tp_panel_tile(S, dinv, kb, I);
+    lds_barrier();
+    if (kb + 1 < nb) {
+      const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
+      if (wave == 0) {
+        tp_update_tile(S, kb, kb + 1, kb + 1);
+        wave_lds_fence();
+        tp_diag_block(S, dinv, d0, kb + 1, l, tau, ndrop, nbad);
+      } else {
+        for (int e = wave; e < ntile; e += kWaves - 1) {
+          int i = 0;
+          while ((i + 1) * (i + 2) / 2 <= e) ++i;
+          const int c = e - i * (i + 1) / 2;
+          tp_update_tile(S, kb, kb + 1 + i, kb + 1 + c);
+        }
+#pragma unroll
+        for (int u = 0; u < kTpSlots; ++u) {
+          const int J = wave - 1 + u * (kWaves - 1);
+          if (J < kb) xr[u] = tp_inverse_tile(S, dinv, kb, J);
+        }
+      }
+      lds_barrier();
+    }
+  }
+  // the last block row of X (row nb - 2 was stored at the start of the last
+  // step): every wave forms its tiles, then all store
+  {
+    constexpr int kLast = (kTpNb - 1 + kWaves - 1) / kWaves;
+    f64x4 xl[kLast];
+#pragma unroll
+    for (int u = 0; u < kLast; ++u) {
+      const int J = wave + u * kWaves;
+      if (J < nb - 1) xl[u] = tp_inverse_tile(S, dinv, nb - 1, J);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < kLast; ++u) {
+      const int J = wave + u * kWaves;
+      if (J < nb - 1) tp_store_tile(S, nb - 1, J, xl[u]);
+    }
+    lds_barrier();
+  }
+  // W(a, c) = X(c, a) (a <= c), FP32; four columns per thread
+  const int nq = n / 4;
+  for (int e = tid; e < n * nq; e += kThreads) {
+    const int a = e / nq, c0 = (e % nq) * 4;
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u;
+      double xv = 0.0;
+      if (c < l && a <= c) {
+        const int C = c >> 4, A = a >> 4;
+        xv = C == A ? tp_xkk(S, dinv, C, c & 15, a & 15) : S[tp(C, A, c & 15, a & 15)];
+      }
+      v[u] = (float)xv;
+    }
+    st4(W + (int64_t)a * n + c0, make_float4(v[0], v[1], v[2], v[3]));
+  }
+  if (tid == 0) {
+    status[kStDropped] += ndrop;
+    status[kStNonFinite] += nbad;
+  }
+}
+
 }  // namespace
 
 bool chol16_fits(int64_t lp) { return lp <= kSq; }
@@ -276,6 +502,15 @@ hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, doubl
                          int32_t* status, double tau, hipStream_t s) {
   if (lp > kSq || lp % kB != 0 || l > lp || l < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol16, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, L, status, tau);
+  return hipGetLastError();
+}
+
+bool chol_tp_fits(int64_t lp) { return lp > kSq && lp <= kTpMax && lp % kB == 0; }
+
+hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
+                          double tau, hipStream_t s) {
+  if (!chol_tp_fits(lp) || l > lp || l < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_tp, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, status, tau);
   return hipGetLastError();
 }
 

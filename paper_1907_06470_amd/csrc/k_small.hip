@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_gram_part(const float* __restrict__ P, 
       }
 }
 
-// Lower-triangle Gram for sketch widths up to 128 (lp = 16 NBK): the 16 x 16
+// Lower-triangle Gram for sketch widths up to 192 (lp = 16 NBK): the 16 x 16
 // tiles (I, J), I >= J, of P^T P, tile t = I (I + 1) / 2 + J handled by wave
 // t mod 4 in accumulator t / 4, over one row chunk per workgroup.  Each 64-row
 // slab of the chunk is staged in LDS column by column (the panel is
@@ -275,95 +275,16 @@ __global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, 
 }
 
 // ------------------------------------------------------------ Cholesky ----
-// One workgroup: G = L L^T (right-looking, packed lower triangle in LDS),
-// then X = L^-1 in place, row by row, and W = X^T written as FP32.  A pivot
-// at or below tau times its original diagonal (or not finite) drops the
-// direction: its column of L and its row and column of X are zero, so the
-// basis Q = Y W gets a zero column and the direction feeds no other column.
+// One workgroup: G = L L^T (right-looking, in LDS), X = L^-1 and W = X^T
+// written as FP32 (or L itself as FP64).  A pivot at or below tau times its
+// original diagonal (or not finite) drops the direction: its column of L and
+// its row and column of X are zero, so the basis Q = Y W gets a zero column
+// and the direction feeds no other column.  Widths up to 192 go to the
+// kernels of k_chol.hip; this one factors widths 129 .. 160 for the small SVD.
 constexpr int kCholThreads = 256;
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv_simple(const double* __restrict__ G, int64_t lp,
-                                                           int l, float* __restrict__ W,
-                                                           int32_t* status, double tau) {
-  __shared__ double T[kTri];
-  __shared__ double d0[kMaxLp];
-  __shared__ double rowtmp[kMaxLp];
-  __shared__ double piv_s;
-  __shared__ int ndrop, nbad;
-  const int tid = threadIdx.x;
-  const int tot = l * (l + 1) / 2;
-  for (int e = tid; e < tot; e += kCholThreads) {
-    int i, c;
-    tri_decode(e, i, c);
-    T[e] = G[(int64_t)i * lp + c];
-  }
-  for (int i = tid; i < l; i += kCholThreads) d0[i] = G[(int64_t)i * lp + i];
-  if (tid == 0) {
-    ndrop = 0;
-    nbad = 0;
-  }
-  lds_barrier();
-  const int ty = tid >> 4, tx = tid & 15;
-  for (int j = 0; j < l; ++j) {
-    if (tid == 0) {
-      const double d = T[tidx(j, j)];
-      double piv = 0.0;
-      if (!is_finite_d(d)) {
-        ++nbad;
-      } else if (!(d0[j] > 0.0) || !(d > tau * d0[j])) {
-        ++ndrop;
-      } else {
-        piv = sqrt(d);
-      }
-      T[tidx(j, j)] = piv;
-      piv_s = piv;
-    }
-    lds_barrier();
-    const double piv = piv_s;
-    const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-    for (int i = j + 1 + tid; i < l; i += kCholThreads) T[tidx(i, j)] *= inv;
-    lds_barrier();
-    if (piv > 0.0) {
-      for (int i = j + 1 + ty; i < l; i += 16) {
-        const double lij = T[tidx(i, j)];
-        const int base = tidx(i, 0);
-        for (int c = j + 1 + tx; c <= i; c += 16) T[base + c] -= lij * T[tidx(c, j)];
-      }
-    }
-    lds_barrier();
-  }
-  // X = L^-1 in place: row i of X needs row i of L and rows < i of X.
-  for (int i = 0; i < l; ++i) {
-    const double lii = T[tidx(i, i)];
-    for (int c = tid; c <= i; c += kCholThreads) {
-      double v = 0.0;
-      if (lii > 0.0) {
-        if (c == i) {
-          v = 1.0 / lii;
-        } else if (T[tidx(c, c)] != 0.0) {
-          double acc = 0.0;
-          for (int p = c; p < i; ++p) acc += T[tidx(i, p)] * T[tidx(p, c)];
-          v = -acc / lii;
-        }
-      }
-      rowtmp[c] = v;
-    }
-    lds_barrier();
-    for (int c = tid; c <= i; c += kCholThreads) T[tidx(i, c)] = rowtmp[c];
-    lds_barrier();
-  }
-  // W(a, c) = X(c, a), upper triangular, FP32
-  for (int e = tid; e < lp * lp; e += kCholThreads) {
-    const int a = e / (int)lp, c = e % (int)lp;
-    W[e] = (c < l && a <= c) ? (float)T[tidx(c, a)] : 0.f;
-  }
-  if (tid == 0) {
-    status[kStDropped] += ndrop;
-    status[kStNonFinite] += nbad;
-  }
-}
 
-// Blocked form of the same computation for sketch widths up to 160 (the
-// packed triangle plus a 32-row work panel fit in LDS).  Panels of 32
+// Packed-triangle form for widths up to 160 (the packed triangle plus a
+// 32-row work panel fit in LDS).  Panels of 32
 // columns: one wave factors the diagonal block (no workgroup barriers inside),
 // all threads solve the rows below against it and update the trailing
 // triangle with register-blocked dot products.  The inverse proceeds by block
@@ -1358,6 +1279,8 @@ hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int
       case 4: GT(4); break;
       case 6: GT(6); break;
       case 8: GT(8); break;
+      case 10: GT(10); break;
+      case 12: GT(12); break;
       default: return hipErrorInvalidValue;
     }
 #undef GT
@@ -1382,12 +1305,9 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
                            double tau, hipStream_t s) {
   if (lp > kMaxLp) return hipErrorInvalidValue;
   if (chol16_fits(lp)) return launch_chol16(G, lp, l, W, nullptr, status, tau, s);
-  if (lp <= kBlkMaxLp)
-    hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
-                       (double*)nullptr, status, tau);
-  else
-    hipLaunchKernelGGL(k_chol_inv_simple, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
-                       status, tau);
+  if (chol_tp_fits(lp)) return launch_chol_tp(G, lp, l, W, status, tau, s);
+  hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
+                     (double*)nullptr, status, tau);
   return hipGetLastError();
 }
 

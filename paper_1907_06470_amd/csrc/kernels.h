@@ -117,6 +117,10 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
 bool chol16_fits(int64_t lp);
 hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, double* L,
                          int32_t* status, double tau, hipStream_t s);
+// W = L^-T for 128 < lp <= 192 (k_chol.hip, lower tiles packed in LDS).
+bool chol_tp_fits(int64_t lp);
+hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
+                          double tau, hipStream_t s);
 // Automatic q: prev[k] = max_i<k |S_i - prev_i| / S_i (+inf if first), prev = S.
 hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* prev, hipStream_t s);
 // Small SVD through the Cholesky factor of C and one-sided Jacobi (lp <= 128).

@@ -121,10 +121,10 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* opt, Plan& p
 int64_t gram_chunks_for(const Plan& p, int64_t rows);
 inline int64_t gram_nb(const Plan& p) { return ceil_div(p.lp, kGramBlock); }
 inline int64_t gram_pairs(const Plan& p) { int64_t nb = gram_nb(p); return nb * (nb + 1) / 2; }
-// Lower-triangle Gram (widths up to 128): at most kGramTriChunks row chunks
+// Lower-triangle Gram (widths up to 192): at most kGramTriChunks row chunks
 // of a multiple of 4 rows, one 16 x 16 FP64 partial tile per chunk and tile.
 constexpr int64_t kGramTriChunks = 256;
-inline bool gram_tri_fits(int64_t lp) { return lp <= 128 && lp % 32 == 0; }
+inline bool gram_tri_fits(int64_t lp) { return lp <= 192 && lp % 32 == 0; }
 inline int64_t gram_tri_chunk_rows(int64_t rows) {
   return round_up(ceil_div(rows < 1 ? 1 : rows, kGramTriChunks), 4);
 }

@@ -94,7 +94,7 @@ def test_products_with_fp64_input_use_the_fp32_rounding():
 
 
 @pytest.mark.parametrize("rows,l,side", [(3000, 40, 0), (2500, 120, 1), (777, 190, 0), (100, 1, 0),
-                                         (70000, 64, 0)])
+                                         (70000, 64, 0), (20000, 150, 1), (70001, 190, 0)])
 def test_gram_is_the_fp64_product(rows, l, side):
     dev = need_gpu()
     say("gram", rows, l)
@@ -112,7 +112,7 @@ def test_gram_is_the_fp64_product(rows, l, side):
 
 
 @pytest.mark.parametrize("rows,l,cond,side", [(3000, 40, 10.0, 0), (2500, 120, 1e4, 1), (777, 190, 1e3, 0),
-                                              (64, 64, 1.0, 0)])
+                                              (64, 64, 1.0, 0), (3000, 150, 1e3, 1), (5000, 176, 1e5, 0)])
 def test_cholqr2_orthonormal_basis_of_the_span(rows, l, cond, side):
     dev = need_gpu()
     say("orth", rows, l, cond)
@@ -127,10 +127,11 @@ def test_cholqr2_orthonormal_basis_of_the_span(rows, l, cond, side):
     assert metrics.sin_theta(Qref, Q) < 1e-6 * cond * 10
 
 
-def test_cholqr2_drops_dependent_directions():
+@pytest.mark.parametrize("rows,l,r", [(2000, 24, 9), (3000, 170, 40)])
+def test_cholqr2_drops_dependent_directions(rows, l, r):
     dev = need_gpu()
-    rows, l, r = 2000, 24, 9
-    plan = Plan(rows, 100, 12, 12, 1)
+    say("orth drop", rows, l, r)
+    plan = Plan(rows, max(100, l), l // 2, l - l // 2, 1)
     rng = np.random.default_rng(1)
     Y = (rng.standard_normal((rows, r)) @ rng.standard_normal((r, l))).astype(np.float32)
     Q = plan.step_orth(0, col_major_from_numpy(Y, dev)).cpu().numpy().astype(np.float64)
