@@ -171,24 +171,44 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(const int32_t* __restrict__ 
   }
 }
 
-// column-major panel (ld) -> row-major copy (rows x lp, ldr), 32 x 32 tiles
+// Panel layout changes around the products, 64 x 64 tiles through LDS with
+// 16-byte accesses on both sides (ld, ldr multiples of 4, lp a multiple of 4,
+// 16-byte aligned pointers; a row index r < ld that is a multiple of 4 keeps
+// r + 3 < ld).  t[c][r] holds column c, row r of the tile; its odd stride
+// keeps the column-wise and the row-wise element accesses free of bank
+// conflicts.
+constexpr int kTT = 64;
+
+// column-major panel (ld) -> row-major copy (rows x lp, ldr)
 __global__ __launch_bounds__(256) void k_to_rows(const float* __restrict__ P, int64_t ld,
                                                  int64_t rows, int lp, float* __restrict__ R,
                                                  int64_t ldr) {
-  __shared__ float t[32][33];
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int c0 = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of 32
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t r = r0 + tx;
-    const int c = c0 + k;
-    t[k][tx] = (r < rows && c < lp) ? P[(int64_t)c * ld + r] : 0.f;
+  __shared__ float t[kTT][kTT + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kTT;
+  const int c0 = blockIdx.y * kTT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, c = e >> 4, q = e & 15;
+    const int64_t r = r0 + 4 * q;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c0 + c < lp && r < rows) {
+      v = *reinterpret_cast<const float4*>(P + (int64_t)(c0 + c) * ld + r);
+      if (r + 1 >= rows) v.y = 0.f;
+      if (r + 2 >= rows) v.z = 0.f;
+      if (r + 3 >= rows) v.w = 0.f;
+    }
+    t[c][4 * q] = v.x;
+    t[c][4 * q + 1] = v.y;
+    t[c][4 * q + 2] = v.z;
+    t[c][4 * q + 3] = v.w;
   }
   __syncthreads();
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t r = r0 + k;
-    const int c = c0 + tx;
-    if (r < rows && c < lp) R[r * ldr + c] = t[tx][k];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e >> 4, c = (e & 15) * 4;
+    if (r0 + r < rows && c0 + c < lp)
+      st4(R + (r0 + r) * ldr + c0 + c, make_float4(t[c][r], t[c + 1][r], t[c + 2][r], t[c + 3][r]));
   }
 }
 
@@ -197,22 +217,29 @@ __global__ __launch_bounds__(256) void k_to_rows(const float* __restrict__ P, in
 __global__ __launch_bounds__(256) void k_from_rows(const float* __restrict__ R, int64_t ldr,
                                                    const int32_t* __restrict__ ptr, int64_t rows,
                                                    int lp, float* __restrict__ P, int64_t ld) {
-  __shared__ float t[32][33];
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int c0 = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t r = r0 + k;
-    const int c = c0 + tx;
-    float v = 0.f;
-    if (r < rows && c < lp && ptr[r + 1] > ptr[r]) v = R[r * ldr + c];
-    t[k][tx] = v;
+  __shared__ float t[kTT][kTT + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kTT;
+  const int c0 = blockIdx.y * kTT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, r = e >> 4, c = (e & 15) * 4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + r < rows && c0 + c < lp && ptr[r0 + r + 1] > ptr[r0 + r])
+      v = *reinterpret_cast<const float4*>(R + (r0 + r) * ldr + c0 + c);
+    t[c][r] = v.x;
+    t[c + 1][r] = v.y;
+    t[c + 2][r] = v.z;
+    t[c + 3][r] = v.w;
   }
   __syncthreads();
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t r = r0 + tx;
-    const int c = c0 + k;
-    if (r < ld && c < lp) P[(int64_t)c * ld + r] = t[tx][k];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, c = e >> 4, q = e & 15;
+    const int64_t r = r0 + 4 * q;
+    if (r < ld && c0 + c < lp)
+      st4(P + (int64_t)(c0 + c) * ld + r,
+          make_float4(t[c][4 * q], t[c][4 * q + 1], t[c][4 * q + 2], t[c][4 * q + 3]));
   }
 }
 
@@ -410,7 +437,11 @@ hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val,
   if (lp > 64 * kMaxCW) return hipErrorInvalidValue;
   const int64_t chunks = spmm_chunk_count(nnz);
   const int64_t ldr = lp;
-  dim3 gx((unsigned)ceil_div_dev(xrows, 32), (unsigned)ceil_div_dev(lp, 32));
+  // the layout kernels move 16-byte pieces
+  if (lp % 4 || ldx % 4 || ldo % 4 || (((uintptr_t)X | (uintptr_t)Xr | (uintptr_t)Yr |
+                                         (uintptr_t)out) & 15))
+    return hipErrorInvalidValue;
+  dim3 gx((unsigned)ceil_div_dev(xrows, kTT), (unsigned)ceil_div_dev(lp, kTT));
   hipLaunchKernelGGL(k_to_rows, gx, dim3(256), 0, s, X, ldx, xrows, (int)lp, Xr, ldr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -429,7 +460,7 @@ hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val,
                        Yr, ldr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  dim3 gy((unsigned)ceil_div_dev(ldo, 32), (unsigned)ceil_div_dev(lp, 32));
+  dim3 gy((unsigned)ceil_div_dev(ldo, kTT), (unsigned)ceil_div_dev(lp, kTT));
   hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, rows, (int)lp, out, ldo);
   return hipGetLastError();
 }
