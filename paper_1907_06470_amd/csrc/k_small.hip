@@ -598,6 +598,100 @@ __global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int6
   }
 }
 
+// The same product for tall panels: W (kdim x 32 NT, kdim <= KR) is staged in
+// LDS once per workgroup, and each wave then takes 32-row blocks in turn
+// (grid stride), with the next 16 rows of P's k-range loaded while the
+// current ones go through the matrix cores.  Reading W through the caches
+// for every 32-row block costs more than the product at width 192 and
+// millions of rows; on short panels the staging is not repaid.
+constexpr int kApThreads = 512;
+
+template <int NT, bool TRI, int KR>
+__global__ __launch_bounds__(kApThreads) void k_apply_staged(const float* __restrict__ P,
+                                                             int64_t ldp, int64_t rows, int kdim,
+                                                             const float* __restrict__ W,
+                                                             int64_t ldw, int ncols,
+                                                             float* __restrict__ out, int64_t ldo,
+                                                             int64_t out_rows, int vec_ok) {
+  constexpr int WC = NT * 32;
+  __shared__ __attribute__((aligned(16))) float Ws[KR * WC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int kd2 = (kdim + 1) & ~1;
+  if ((ldw & 3) == 0 && (((uintptr_t)W) & 15) == 0) {
+    // 16-byte pieces, eight in flight per thread
+    constexpr int WQ = WC / 4;
+#pragma unroll 8
+    for (int e = tid; e < kd2 * WQ; e += blockDim.x) {
+      const int a = e / WQ, c = (e % WQ) * 4;
+      const float4 v = a < kdim ? *reinterpret_cast<const float4*>(W + (int64_t)a * ldw + c)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(&Ws[a * WC + c]) = v;
+    }
+  } else {
+    for (int e = tid; e < kd2 * WC; e += blockDim.x) {
+      const int a = e / WC, c = e % WC;
+      Ws[e] = a < kdim ? W[(int64_t)a * ldw + c] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int kWaves = blockDim.x / 64;
+  const int64_t nblk = (out_rows + 31) / 32;
+  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblk;
+       blk += (int64_t)gridDim.x * kWaves) {
+    const int64_t rbase = blk * 32;
+    const int64_t i = rbase + l32;
+    const bool iok = i < rows;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+    float av[8], an[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int a = 2 * s + half;
+      av[s] = (iok && a < kdim) ? P[(int64_t)a * ldp + i] : 0.f;
+    }
+    for (int a0 = 0; a0 < kd2; a0 += 16) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int a = a0 + 16 + 2 * s + half;
+        an[s] = (iok && a < kdim) ? P[(int64_t)a * ldp + i] : 0.f;
+      }
+      // triangular W: output block t takes k < 32 (t + 1) only
+      const int tlo = TRI ? a0 >> 5 : 0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t < tlo) continue;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int a = a0 + 2 * s;
+          if (a < kd2) acc[t] = mfma32(av[s], Ws[(a + half) * WC + t * 32 + l32], acc[t]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) av[s] = an[s];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int c = t * 32 + l32;
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int64_t r = rbase + 8 * g + 4 * half;
+        float* dst = out + (int64_t)c * ldo + r;
+        if (vec_ok && r + 3 < out_rows) {
+          st4(dst, make_float4(acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2],
+                               acc[t][4 * g + 3]));
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r + e < out_rows) dst[e] = acc[t][4 * g + e];
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- Jacobi ----
 // Round-robin ("tournament") schedule: at round t, position x holds index
 // rr_pos(x, t); position 0 is fixed, the others rotate.  0 <= t < le - 1.
@@ -1314,16 +1408,32 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
 hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
                         int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out, int64_t ldo,
                         int64_t out_rows_total, hipStream_t s) {
+  if (kdim < 0 || kdim > kMaxLp) return hipErrorInvalidValue;
   const int vec_ok = ((ldo % 4) == 0 && (((uintptr_t)out) & 15) == 0) ? 1 : 0;
-  dim3 grid((unsigned)ceil_div_dev(out_rows_total, 128));
-#define AP_CALL(NT)                                                                           \
-  do {                                                                                        \
-    if (tri)                                                                                  \
+  const int64_t nblk = ceil_div_dev(out_rows_total, 32);
+  // tall panels (4096 or more 32-row blocks): W staged in LDS, 8 waves per
+  // workgroup, at most 1024 workgroups; otherwise one wave per 32-row block
+  const bool tall = nblk >= 4096;
+  const bool wide = kdim > lp;   // W has more rows than columns (the adjoint's factors)
+  const dim3 grid_s((unsigned)std::min<int64_t>(1024, ceil_div_dev(nblk, kApThreads / 64)));
+  const dim3 grid((unsigned)ceil_div_dev(out_rows_total, 128));
+#define AP_ST(NT, TRI, KR)                                                                  \
+  hipLaunchKernelGGL((k_apply_staged<NT, TRI, KR>), grid_s, dim3(kApThreads), 0, s, P, ldp, \
+                     rows, (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok)
+#define AP_CALL(NT)                                                                         \
+  do {                                                                                      \
+    if (tall && tri && !wide)                                                               \
+      AP_ST(NT, true, NT * 32);                                                             \
+    else if (tall && !wide)                                                                 \
+      AP_ST(NT, false, NT * 32);                                                            \
+    else if (tall)                                                                          \
+      AP_ST(NT, false, kMaxLp);                                                             \
+    else if (tri)                                                                           \
       hipLaunchKernelGGL((k_apply<NT, true>), grid, dim3(256), 0, s, P, ldp, rows, (int)kdim, \
-                         W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);               \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_apply<NT, false>), grid, dim3(256), 0, s, P, ldp, rows,           \
-                         (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);    \
+                         W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);             \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_apply<NT, false>), grid, dim3(256), 0, s, P, ldp, rows,         \
+                         (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);  \
   } while (0)
   switch (lp / 32) {
     case 1: AP_CALL(1); break;
@@ -1335,6 +1445,7 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
     default: return hipErrorInvalidValue;
   }
 #undef AP_CALL
+#undef AP_ST
   return hipGetLastError();
 }
 

@@ -212,11 +212,14 @@ __global__ __launch_bounds__(256) void k_to_rows(const float* __restrict__ P, in
   }
 }
 
-// row-major result (rows x lp) -> column-major panel (ld rows, padding rows
-// zero); rows without nonzeros are zero
+// row-major result -> column-major panel (ld rows, padding rows zero).  The
+// result holds `parts` row sets of `rows` rows each (the products of the row
+// blocks of A); row r of the panel is their sum, taken in part order.  Rows
+// without nonzeros are zero.
 __global__ __launch_bounds__(256) void k_from_rows(const float* __restrict__ R, int64_t ldr,
                                                    const int32_t* __restrict__ ptr, int64_t rows,
-                                                   int lp, float* __restrict__ P, int64_t ld) {
+                                                   int64_t parts, int lp, float* __restrict__ P,
+                                                   int64_t ld) {
   __shared__ float t[kTT][kTT + 1];
   const int64_t r0 = (int64_t)blockIdx.x * kTT;
   const int c0 = blockIdx.y * kTT;
@@ -225,8 +228,17 @@ __global__ __launch_bounds__(256) void k_from_rows(const float* __restrict__ R, 
   for (int u = 0; u < 4; ++u) {
     const int e = tid + 256 * u, r = e >> 4, c = (e & 15) * 4;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r0 + r < rows && c0 + c < lp && ptr[r0 + r + 1] > ptr[r0 + r])
-      v = *reinterpret_cast<const float4*>(R + (r0 + r) * ldr + c0 + c);
+    if (r0 + r < rows && c0 + c < lp)
+      for (int64_t b = 0; b < parts; ++b) {
+        const int64_t rv = b * rows + r0 + r;
+        if (ptr[rv + 1] > ptr[rv]) {
+          const float4 w = *reinterpret_cast<const float4*>(R + rv * ldr + c0 + c);
+          v.x += w.x;
+          v.y += w.y;
+          v.z += w.z;
+          v.w += w.w;
+        }
+      }
     t[c][r] = v.x;
     t[c + 1][r] = v.y;
     t[c + 2][r] = v.z;
@@ -246,13 +258,15 @@ __global__ __launch_bounds__(256) void k_from_rows(const float* __restrict__ R, 
 // CSC build: keys = column, payload = (row << 32) | value bits
 __global__ void k_csc_keys(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                            const float* __restrict__ values, int64_t m, int64_t n, int64_t nnz,
-                           uint32_t* __restrict__ keys, uint64_t* __restrict__ payload) {
+                           int64_t block_rows, uint32_t* __restrict__ keys,
+                           uint64_t* __restrict__ payload) {
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (i >= m) return;
   const int lane = threadIdx.x & 63;
   const int64_t lo = max<int64_t>(0, rowptr[i]), hi = min<int64_t>(nnz, rowptr[i + 1]);
+  const uint32_t base = (uint32_t)((i / block_rows) * n);
   for (int64_t e = lo + lane; e < hi; e += 64) {
-    keys[e] = min<uint32_t>((uint32_t)colind[e], (uint32_t)(n - 1));
+    keys[e] = base + min<uint32_t>((uint32_t)colind[e], (uint32_t)(n - 1));
     payload[e] = ((uint64_t)(uint32_t)i << 32) | (uint64_t)__builtin_bit_cast(uint32_t, values[e]);
   }
 }
@@ -355,21 +369,24 @@ hipError_t launch_csr_check(const int32_t* ptr, const int32_t* idx, int64_t rows
 
 
 hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const float* values,
-                            int64_t m, int64_t n, int64_t nnz, uint32_t* keys0, uint32_t* keys1,
-                            uint64_t* pay0, uint64_t* pay1, void* temp, size_t temp_bytes,
-                            int32_t* colptr, int32_t* rowind, float* cval, size_t* need,
-                            hipStream_t s) {
+                            int64_t m, int64_t n, int64_t nnz, int64_t parts, uint32_t* keys0,
+                            uint32_t* keys1, uint64_t* pay0, uint64_t* pay1, void* temp,
+                            size_t temp_bytes, int32_t* colptr, int32_t* rowind, float* cval,
+                            size_t* need, hipStream_t s) {
   *need = 0;
+  const int64_t nv = parts * n;   // columns of the row blocks, block-major
+  if (parts < 1 || nv > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+  const int64_t block_rows = ceil_div_dev(m > 0 ? m : 1, parts);
   if (nnz > 0) {
     // entries no row covers (malformed pointers) keep defined keys
     hipLaunchKernelGGL(k_fill_keys, dim3((unsigned)ceil_div_dev(nnz, 256)), dim3(256), 0, s, nnz,
-                       (uint32_t)(n - 1), keys0, pay0);
+                       (uint32_t)(nv - 1), keys0, pay0);
     hipLaunchKernelGGL(k_csc_keys, dim3((unsigned)ceil_div_dev(m, 4)), dim3(256), 0, s, rowptr,
-                       colind, values, m, n, nnz, keys0, pay0);
+                       colind, values, m, n, nnz, block_rows, keys0, pay0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned bits = 1;
-    while (bits < 32 && (int64_t(1) << bits) < n) ++bits;
+    while (bits < 32 && (int64_t(1) << bits) < nv) ++bits;
     // ping-pong buffers owned by the workspace: the sort's own scratch is
     // only its histograms and look-back state
     rocprim::double_buffer<uint32_t> kb(keys0, keys1);
@@ -384,10 +401,10 @@ hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const 
     e = rocprim::radix_sort_pairs(temp, want, kb, vb, (size_t)nnz, 0, bits, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_csc_finish, dim3((unsigned)ceil_div_dev(nnz + 1, 256)), dim3(256), 0, s,
-                       kb.current(), vb.current(), nnz, n, colptr, rowind, cval);
+                       kb.current(), vb.current(), nnz, nv, colptr, rowind, cval);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_csc_finish, dim3(1), dim3(256), 0, s, keys1, pay1, nnz, n, colptr, rowind,
+  hipLaunchKernelGGL(k_csc_finish, dim3(1), dim3(256), 0, s, keys1, pay1, nnz, nv, colptr, rowind,
                      cval);
   return hipGetLastError();
 }
@@ -431,10 +448,12 @@ hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_b
 }
 
 hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val, int64_t rows,
-                       int64_t nnz, const float* X, int64_t ldx, int64_t xrows, int64_t lp,
-                       float* Xr, float* Yr, float* carry, int32_t* first, float* out,
-                       int64_t ldo, hipStream_t s) {
-  if (lp > 64 * kMaxCW) return hipErrorInvalidValue;
+                       int64_t parts, int64_t nnz, const float* X, int64_t ldx, int64_t xrows,
+                       int64_t lp, float* Xr, float* Yr, float* carry, int32_t* first,
+                       float* out, int64_t ldo, hipStream_t s) {
+  if (lp > 64 * kMaxCW || parts < 1) return hipErrorInvalidValue;
+  const int64_t out_rows = rows;
+  rows *= parts;   // the compressed rows the product walks
   const int64_t chunks = spmm_chunk_count(nnz);
   const int64_t ldr = lp;
   // the layout kernels move 16-byte pieces
@@ -461,7 +480,8 @@ hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val,
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   dim3 gy((unsigned)ceil_div_dev(ldo, kTT), (unsigned)ceil_div_dev(lp, kTT));
-  hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, rows, (int)lp, out, ldo);
+  hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, out_rows, parts, (int)lp,
+                     out, ldo);
   return hipGetLastError();
 }
 

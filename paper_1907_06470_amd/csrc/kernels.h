@@ -74,24 +74,29 @@ hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t 
 // status[kStBadSparse] = 1 when the CSR arrays are malformed
 hipError_t launch_csr_check(const int32_t* ptr, const int32_t* idx, int64_t rows, int64_t cols,
                             int64_t nnz, int32_t* status, hipStream_t s);
-// CSC (= CSR of A^T) by a stable radix sort of the nonzeros by column; on a
-// scratch shortfall returns hipErrorOutOfMemory with the bytes needed in *need
+// CSC (= CSR of A^T) of each of `parts` row blocks of A (ceil(m / parts) rows
+// each), stored one after the other: compressed row b n + j is column j of
+// block b.  A stable radix sort of the nonzeros by (block, column) keeps each
+// column's row order.  On a scratch shortfall returns hipErrorOutOfMemory with
+// the bytes needed in *need.
 hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const float* values,
-                            int64_t m, int64_t n, int64_t nnz, uint32_t* keys0, uint32_t* keys1,
-                            uint64_t* pay0, uint64_t* pay1, void* temp, size_t temp_bytes,
-                            int32_t* colptr, int32_t* rowind, float* cval, size_t* need,
-                            hipStream_t s);
-// out (column-major, ldo rows) = S X for S (rows x xrows) in compressed-row
-// form and X column-major (ldx); Xr, Yr, carry, first are scratch
+                            int64_t m, int64_t n, int64_t nnz, int64_t parts, uint32_t* keys0,
+                            uint32_t* keys1, uint64_t* pay0, uint64_t* pay1, void* temp,
+                            size_t temp_bytes, int32_t* colptr, int32_t* rowind, float* cval,
+                            size_t* need, hipStream_t s);
 hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_bits,
                              const float* values, int64_t m, int64_t n, int64_t nnz,
                              uint32_t* keys0, uint32_t* keys1, uint64_t* pay0, uint64_t* pay1,
                              void* temp, size_t temp_bytes, int32_t* rowptr, int32_t* col,
                              float* val, int32_t* status, size_t* need, hipStream_t s);
+// out (column-major, ldo rows) = S X for S (rows x xrows) in compressed-row
+// form and X column-major (ldx); with parts > 1 the compressed rows are parts
+// blocks of `rows` rows, and row r of out sums row r of every block in block
+// order.  Xr, Yr, carry, first are scratch.
 hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val, int64_t rows,
-                       int64_t nnz, const float* X, int64_t ldx, int64_t xrows, int64_t lp,
-                       float* Xr, float* Yr, float* carry, int32_t* first, float* out,
-                       int64_t ldo, hipStream_t s);
+                       int64_t parts, int64_t nnz, const float* X, int64_t ldx, int64_t xrows,
+                       int64_t lp, float* Xr, float* Yr, float* carry, int32_t* first,
+                       float* out, int64_t ldo, hipStream_t s);
 
 // --- small dense FP64 steps (k_small.hip) ---
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,

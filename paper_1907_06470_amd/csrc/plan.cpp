@@ -27,6 +27,15 @@ static rsvd_status fail(Plan& p, rsvd_status s, const char* fmt, long long a = 0
 
 int64_t spmm_chunk_count(int64_t nnz) { return std::max<int64_t>(1, ceil_div(nnz, kSpmmChunk)); }
 
+int64_t csc_part_count(int64_t m, int64_t n, int64_t lp) {
+  constexpr int64_t kCscSliceBytes = int64_t(128) << 20;
+  constexpr int64_t kMaxParts = 16;
+  int64_t parts = std::max<int64_t>(1, ceil_div(m * lp * 4, kCscSliceBytes));
+  parts = std::min(parts, kMaxParts);
+  while (parts > 1 && parts * n > (int64_t)UINT32_MAX - 1) --parts;   // 32-bit sort keys
+  return parts;
+}
+
 size_t csc_sort_scratch(int64_t nnz) { return (size_t)64 * 1024 * 1024 + (size_t)nnz * 4; }
 
 int64_t gram_chunks_for(const Plan& p, int64_t rows) {
@@ -275,9 +284,11 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.slots = off;
   }
   if (p.csr) {
-    const size_t nnz = (size_t)prob.nnz, rows = (size_t)std::max(m, n);
     p.chunks = spmm_chunk_count(prob.nnz);
-    w.colptr = take((size_t)(n + 1) * 4);
+    p.csc_parts = csc_part_count(m, n, p.lp);
+    const size_t nnz = (size_t)prob.nnz;
+    const size_t rows = (size_t)std::max<int64_t>(m, std::max<int64_t>(n, p.csc_parts * n));
+    w.colptr = take((size_t)(p.csc_parts * n + 1) * 4);
     w.rowind = take(nnz * 4);
     w.cval = take(nnz * 4);
     w.keys0 = take(nnz * 4);

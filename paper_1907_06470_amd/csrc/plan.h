@@ -102,6 +102,7 @@ struct Plan {
   bool auto_q = false;          // choose q <= prob.q (RSVD_FLAG_AUTO_Q)
   double q_tol = 0.0;
   int64_t chunks = 0;           // nonzero chunks of the sparse products
+  int64_t csc_parts = 1;        // row blocks of the CSC copy (A^T Q gathers within one)
   size_t sort_temp = 0;         // scratch reserved for the CSC sort
   int64_t slots = 0;            // HBM tile slots (host-resident A)
   int64_t slot_ld = 0;          // leading dimension (elements) of a slot
@@ -138,6 +139,9 @@ rsvd_options default_options();
 // sparse products: nonzero chunks and the scratch reserved for the CSC sort
 // (host-side mirrors of the constants in k_sparse.hip)
 int64_t spmm_chunk_count(int64_t nnz);
+// row blocks of the CSC copy: the rows of Q one block's columns gather from
+// stay within kCscSliceBytes, so that they are served from the caches
+int64_t csc_part_count(int64_t m, int64_t n, int64_t lp);
 size_t csc_sort_scratch(int64_t nnz);
 
 }  // namespace rsvd

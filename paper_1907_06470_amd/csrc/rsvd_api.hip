@@ -415,9 +415,10 @@ struct Runner {
     const int64_t m = P.prob.m, n = P.prob.n, nnz = P.prob.nnz;
     RSVD_HIP(rsvd::launch_csr_check(rp, ci, m, n, nnz, B.status, s));
     size_t need = 0;
-    const hipError_t e = rsvd::launch_build_csc(rp, ci, v, m, n, nnz, B.keys0, B.keys1, B.pay0,
-                                                B.pay1, B.sort_temp, P.sort_temp, B.colptr,
-                                                B.rowind, B.cval, &need, s);
+    const hipError_t e = rsvd::launch_build_csc(rp, ci, v, m, n, nnz, P.csc_parts, B.keys0,
+                                                B.keys1, B.pay0, B.pay1, B.sort_temp,
+                                                P.sort_temp, B.colptr, B.rowind, B.cval, &need,
+                                                s);
     if (e == hipErrorOutOfMemory && need > P.sort_temp)
       return set_err(h, RSVD_E_BUDGET,
                      "the CSC sort needs " + std::to_string(need) + " bytes of scratch, the plan "
@@ -540,8 +541,8 @@ struct Runner {
     if (P.host) return stream_pass(true, prec, X, out);
     if (P.csr) {
       RSVD_HIP(tick(true, true));
-      RSVD_HIP(rsvd::launch_spmm(rowptr, colind, values, P.prob.m, P.prob.nnz, X, P.ldn, P.prob.n,
-                                 P.lp, B.Xr, B.Yr, B.carry, B.first, out, P.ldm, s));
+      RSVD_HIP(rsvd::launch_spmm(rowptr, colind, values, P.prob.m, 1, P.prob.nnz, X, P.ldn,
+                                 P.prob.n, P.lp, B.Xr, B.Yr, B.carry, B.first, out, P.ldm, s));
       RSVD_HIP(tick(true, false));
       return RSVD_OK;
     }
@@ -573,8 +574,9 @@ struct Runner {
     if (P.host) return stream_pass(false, prec, Q, out);
     if (P.csr) {
       RSVD_HIP(tick(false, true));
-      RSVD_HIP(rsvd::launch_spmm(B.colptr, B.rowind, B.cval, P.prob.n, P.prob.nnz, Q, P.ldm,
-                                 P.prob.m, P.lp, B.Xr, B.Yr, B.carry, B.first, out, P.ldn, s));
+      RSVD_HIP(rsvd::launch_spmm(B.colptr, B.rowind, B.cval, P.prob.n, P.csc_parts, P.prob.nnz,
+                                 Q, P.ldm, P.prob.m, P.lp, B.Xr, B.Yr, B.carry, B.first, out,
+                                 P.ldn, s));
       RSVD_HIP(tick(false, false));
       return RSVD_OK;
     }

@@ -112,7 +112,8 @@ def test_gram_is_the_fp64_product(rows, l, side):
 
 
 @pytest.mark.parametrize("rows,l,cond,side", [(3000, 40, 10.0, 0), (2500, 120, 1e4, 1), (777, 190, 1e3, 0),
-                                              (64, 64, 1.0, 0), (3000, 150, 1e3, 1), (5000, 176, 1e5, 0)])
+                                              (64, 64, 1.0, 0), (3000, 150, 1e3, 1), (5000, 176, 1e5, 0),
+                                              (140001, 190, 1e3, 0), (133000, 96, 10.0, 1)])
 def test_cholqr2_orthonormal_basis_of_the_span(rows, l, cond, side):
     dev = need_gpu()
     say("orth", rows, l, cond)

@@ -63,6 +63,7 @@ def test_plain_small_workload_fp32_storage():
     (900, 1500, 15, 10, 2, (192, 256)),
     (1000, 1000, 40, 24, 0, (0, 0)),
     (3000, 400, 100, 90, 1, (1024, 128)),
+    (140000, 300, 40, 24, 1, (0, 0)),    # tall: the m-side panel products stage W in LDS
 ])
 def test_ragged_tiles_and_shapes(m, n, k, p, q, tile):
     sigma = workloads.spectrum_pow(min(m, n), 1.0)

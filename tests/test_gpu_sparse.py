@@ -40,6 +40,7 @@ def _csr(m, n, per_row, seed, drop_rows=0):
     (7000, 9000, 13, 100, 3),      # empty rows, unused columns, wide panel
     (300, 200, 1, 20, 0),          # fewer nonzeros than one chunk
     (5000, 3000, 37, 190, 7),      # widest panel (three columns per lane)
+    (200000, 3000, 3, 190, 5),     # tall: the CSC copy is split into two row blocks
 ])
 def test_sparse_products_match_scipy(m, n, per_row, l, drop):
     dev = need_gpu()
@@ -56,7 +57,8 @@ def test_sparse_products_match_scipy(m, n, per_row, l, drop):
     Q = rand_panel(m, l, 2)
     Z = plan.step_spmm(1, *args, col_major_from_numpy(Q, dev)).cpu().numpy().astype(np.float64)
     ref = M.T @ Q.astype(np.float64)
-    K = int(np.max(np.diff(M.tocsc().indptr))) + 2
+    # a column sums per row block of A (at most 16), then the blocks in order
+    K = int(np.max(np.diff(M.tocsc().indptr))) + 2 + 16
     assert np.all(np.abs(Z - ref) <= gamma_bound(K, absM.T @ np.abs(Q)) + 1e-30)
     Z2 = plan.step_spmm(1, *args, col_major_from_numpy(Q, dev)).cpu().numpy().astype(np.float64)
     assert np.array_equal(Z, Z2)
