@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kChunk = (int)kSpmmChunk;   // nonzeros per wave
 constexpr int kMaxCW = 3;        // columns per lane: lp <= 192 = 3 x 64
+constexpr int kGather = 8;       // nonzeros whose rows of X are loaded together
 
 // first row of each chunk: largest r with ptr[r] <= c C
 __global__ void k_chunk_rows(const int32_t* __restrict__ ptr, int64_t rows, int64_t nnz,
@@ -88,55 +89,49 @@ __global__ __launch_bounds__(256) void k_spmm_chunk(const int32_t* __restrict__ 
     // out-of-range indices (flagged by the input check) are clamped
     const int32_t mycol = lane < cnt ? (int32_t)min<uint32_t>((uint32_t)idx[g + lane], (uint32_t)(xrows - 1)) : 0;
     const float myval = lane < cnt ? val[g + lane] : 0.f;
-    int t = 0;
-    while (t < cnt) {
-      const int64_t e = g + t;
-      if (e >= rend) {   // row r is done
-        flush_row<CW>(Yr, ldyr, carry, c, r, continued, acc, lane, lp);
+    // kGather nonzeros at a time: their rows of X are loaded together, then
+    // added in nonzero order, closing a row of the result wherever one ends
+    // (so short rows keep as many loads in flight as long ones)
+    for (int t = 0; t < cnt; t += kGather) {
+      float v[kGather], x[kGather][kMaxCW];
 #pragma unroll
-        for (int u = 0; u < kMaxCW; ++u) acc[u] = 0.f;
-        continued = false;
-        while (r + 1 < rows) {   // next row holding nonzero e
-          ++r;
-          rend = ptr[r + 1];
-          if (rend > e) break;
-        }
-      }
-      // nonzeros up to the row end (or this group's end), four at a time;
-      // malformed pointers (flagged by the input check) cannot stall the loop
-      const int run = (int)max<int64_t>(1, min<int64_t>(cnt - t, rend - e));
-      int s = 0;
-      for (; s + 4 <= run; s += 4) {
-        int32_t col[4];
-        float v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          col[q] = __builtin_amdgcn_readlane(mycol, t + s + q);
-          v[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myval), t + s + q));
-        }
-        float x[4][kMaxCW];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int u = 0; u < CW; ++u) {
-            const int cc = lane + 64 * u;
-            x[q][u] = cc < lp ? Xr[(int64_t)col[q] * ldxr + cc] : 0.f;
-          }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int u = 0; u < CW; ++u) acc[u] += v[q] * x[q][u];
-      }
-      for (; s < run; ++s) {
-        const int32_t col = __builtin_amdgcn_readlane(mycol, t + s);
-        const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myval), t + s));
+      for (int q = 0; q < kGather; ++q) {
+        const int tq = min(t + q, cnt - 1);
+        const int32_t col = __builtin_amdgcn_readlane(mycol, tq);
+        v[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myval), tq));
 #pragma unroll
         for (int u = 0; u < CW; ++u) {
           const int cc = lane + 64 * u;
-          if (cc < lp) acc[u] += v * Xr[(int64_t)col * ldxr + cc];
+          x[q][u] = cc < lp ? Xr[(int64_t)col * ldxr + cc] : 0.f;
         }
       }
-      t += run;
+      if (t + kGather <= cnt && g + t + kGather <= rend) {   // all in row r
+#pragma unroll
+        for (int q = 0; q < kGather; ++q)
+#pragma unroll
+          for (int u = 0; u < CW; ++u) acc[u] += v[q] * x[q][u];
+        continue;
+      }
+#pragma unroll
+      for (int q = 0; q < kGather; ++q) {
+        if (t + q >= cnt) break;
+        const int64_t e = g + t + q;
+        if (e >= rend) {   // row r is done
+          flush_row<CW>(Yr, ldyr, carry, c, r, continued, acc, lane, lp);
+#pragma unroll
+          for (int u = 0; u < kMaxCW; ++u) acc[u] = 0.f;
+          continued = false;
+          // next row holding nonzero e (malformed pointers, flagged by the
+          // input check, end at the last row)
+          while (r + 1 < rows) {
+            ++r;
+            rend = ptr[r + 1];
+            if (rend > e) break;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CW; ++u) acc[u] += v[q] * x[q][u];
+      }
     }
   }
   // the chunk's last row: complete, or the first part of a row that goes on
