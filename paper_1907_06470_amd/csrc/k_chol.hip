@@ -1,6 +1,8 @@
 // Cholesky factor and triangular inverse of the l x l FP64 Gram matrix of a
 // CholeskyQR pass (steps 1-3 of the orthonormalisation: G = Y^T Y = L L^T,
-// Q = Y L^-T), for sketch widths up to 128, in one workgroup.
+// Q = Y L^-T), in one workgroup: k_chol16 for sketch widths up to 128 (below),
+// k_chol_tp for widths up to 192 (the same steps on the lower tiles only,
+// further down).
 //
 // The whole matrix sits in LDS as a 128 x 128 square of doubles whose rows are
 // XOR-swizzled in groups of 16 (element (i, c) at i * 128 + (c ^ (i & 15))),
