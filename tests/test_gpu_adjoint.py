@@ -92,7 +92,8 @@ def test_backward_matches_torch_full_svd_autograd():
     assert rel(gA.cpu().double().numpy(), ref_grad) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("m,n,k,p,q", [(4096, 2048, 64, 16, 3), (3000, 1200, 40, 24, 2)])
+@pytest.mark.parametrize("m,n,k,p,q", [(4096, 2048, 64, 16, 3), (3000, 1200, 40, 24, 2),
+                                       (140000, 256, 32, 16, 1)])   # tall: staged m-side products
 def test_autograd_function_closed_form_of_sigma_plus_residual_loss(m, n, k, p, q):
     # L = sum w_i s_i + ||A - U S V^T||_F^2 through torch autograd; because
     # U^T A = S V^T, dL/dA = U diag(w) V^T + 2 A (I - V V^T)
