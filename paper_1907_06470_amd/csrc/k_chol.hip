@@ -273,8 +273,8 @@ __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ 
     }
   }
   if (tid == 0) {
-    status[kStDropped] += ndrop;
-    status[kStNonFinite] += nbad;
+    if (ndrop) atomicAdd(status + kStDropped, ndrop);
+    if (nbad) atomicAdd(status + kStNonFinite, nbad);
   }
 }
 
@@ -491,8 +491,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_tp(const double* __restrict__
     st4(W + (int64_t)a * n + c0, make_float4(v[0], v[1], v[2], v[3]));
   }
   if (tid == 0) {
-    status[kStDropped] += ndrop;
-    status[kStNonFinite] += nbad;
+    if (ndrop) atomicAdd(status + kStDropped, ndrop);
+    if (nbad) atomicAdd(status + kStNonFinite, nbad);
   }
 }
 

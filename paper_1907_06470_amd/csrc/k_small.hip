@@ -18,6 +18,7 @@
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
+#include "rank.h"
 
 namespace rsvd {
 
@@ -36,7 +37,6 @@ __device__ inline void tri_decode(int e, int& i, int& c) {
   c = e - ii * (ii + 1) / 2;
 }
 
-__device__ inline double nan_low(double x) { return x == x ? x : -__builtin_inf(); }
 
 __device__ inline f64x4 mfma64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
       Lout[e] = (i < l && c <= i) ? T[tidx(i, c)] : 0.0;
     }
     if (tid == 0) {
-      status[kStDropped] += ndrop;
-      status[kStNonFinite] += nbad;
+      if (ndrop) atomicAdd(status + kStDropped, ndrop);
+      if (nbad) atomicAdd(status + kStNonFinite, nbad);
     }
     return;
   }
@@ -537,8 +537,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
     W[e] = (c < l && a <= c) ? (float)T[tidx(c, a)] : 0.f;
   }
   if (tid == 0) {
-    status[kStDropped] += ndrop;
-    status[kStNonFinite] += nbad;
+    if (ndrop) atomicAdd(status + kStDropped, ndrop);
+    if (nbad) atomicAdd(status + kStNonFinite, nbad);
   }
 }
 
@@ -1211,19 +1211,11 @@ __global__ __launch_bounds__(1024) void k_finish_small(const double* __restrict_
   __shared__ int nzero;
   const int tid = threadIdx.x;
   if (tid == 0) nzero = 0;
-  for (int i = tid; i < l; i += blockDim.x) lv[i] = nan_low(lam[i]);
+  for (int i = tid; i < l; i += blockDim.x) lv[i] = nan_as_low(lam[i]);
   __syncthreads();
   // Rank by a strict total order: NaN counts as -inf and ties go by index,
   // so the ranks are a permutation of [0, l) whatever the values are.
-  for (int i = tid; i < l; i += blockDim.x) {
-    const double li = lv[i];
-    int rank = 0;
-    for (int j = 0; j < l; ++j) {
-      const double lj = lv[j];
-      rank += (lj > li) || (lj == li && j < i);
-    }
-    order[rank] = i;
-  }
+  for (int i = tid; i < l; i += blockDim.x) order[desc_rank(lv, l, i)] = i;
   if (tid == 0) {
     double mx = 0.0;
     for (int j = 0; j < l; ++j) mx = fmax(mx, lv[j]);

@@ -16,6 +16,7 @@
 //     does not depend on scheduling: runs are bitwise reproducible.
 //   * The result is written row-major and transposed into the column-major
 //     panel the orthonormalisation uses; empty rows become zero there.
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -29,7 +30,7 @@ namespace rsvd {
 namespace {
 
 constexpr int kChunk = (int)kSpmmChunk;   // nonzeros per wave
-constexpr int kMaxCW = 3;        // columns per lane: lp <= 192 = 3 x 64
+constexpr int kMaxCW = 3;        // columns per lane: slices of up to 192 = 3 x 64 columns
 constexpr int kGather = 8;       // nonzeros whose rows of X are loaded together
 
 // first row of each chunk: largest r with ptr[r] <= c C
@@ -446,38 +447,48 @@ hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val,
                        int64_t parts, int64_t nnz, const float* X, int64_t ldx, int64_t xrows,
                        int64_t lp, float* Xr, float* Yr, float* carry, int32_t* first,
                        float* out, int64_t ldo, hipStream_t s) {
-  if (lp > 64 * kMaxCW || parts < 1) return hipErrorInvalidValue;
+  if (parts < 1) return hipErrorInvalidValue;
   const int64_t out_rows = rows;
   rows *= parts;   // the compressed rows the product walks
   const int64_t chunks = spmm_chunk_count(nnz);
-  const int64_t ldr = lp;
   // the layout kernels move 16-byte pieces
   if (lp % 4 || ldx % 4 || ldo % 4 || (((uintptr_t)X | (uintptr_t)Xr | (uintptr_t)Yr |
                                          (uintptr_t)out) & 15))
     return hipErrorInvalidValue;
-  dim3 gx((unsigned)ceil_div_dev(xrows, kTT), (unsigned)ceil_div_dev(lp, kTT));
-  hipLaunchKernelGGL(k_to_rows, gx, dim3(256), 0, s, X, ldx, xrows, (int)lp, Xr, ldr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)ceil_div_dev(chunks, 256)), dim3(256), 0, s,
                        ptr, rows, nnz, chunks, first);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dim3 g((unsigned)ceil_div_dev(chunks, 4));
-    switch ((lp + 63) / 64) {
-      case 1: hipLaunchKernelGGL(k_spmm_chunk<1>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
-      case 2: hipLaunchKernelGGL(k_spmm_chunk<2>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
-      default: hipLaunchKernelGGL(k_spmm_chunk<3>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)lp, Yr, ldr, carry); break;
-    }
+  }
+  // Panels wider than a lane's kMaxCW columns go in column slices: each slice
+  // gathers only its own columns of X, so the gathered bytes do not grow;
+  // only the compressed arrays are read once more per slice.
+  constexpr int64_t kSlice = 64 * kMaxCW;
+  for (int64_t c0 = 0; c0 < lp; c0 += kSlice) {
+    const int64_t cw = std::min<int64_t>(kSlice, lp - c0);
+    const int64_t ldr = cw;
+    dim3 gx((unsigned)ceil_div_dev(xrows, kTT), (unsigned)ceil_div_dev(cw, kTT));
+    hipLaunchKernelGGL(k_to_rows, gx, dim3(256), 0, s, X + c0 * ldx, ldx, xrows, (int)cw, Xr, ldr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spmm_fixup, g, dim3(256), 0, s, ptr, rows, first, chunks, carry, (int)lp,
-                       Yr, ldr);
+    if (nnz > 0) {
+      dim3 g((unsigned)ceil_div_dev(chunks, 4));
+      switch ((cw + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_spmm_chunk<1>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)cw, Yr, ldr, carry); break;
+        case 2: hipLaunchKernelGGL(k_spmm_chunk<2>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)cw, Yr, ldr, carry); break;
+        default: hipLaunchKernelGGL(k_spmm_chunk<3>, g, dim3(256), 0, s, ptr, idx, val, rows, nnz, first, chunks, Xr, ldr, xrows, (int)cw, Yr, ldr, carry); break;
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_spmm_fixup, g, dim3(256), 0, s, ptr, rows, first, chunks, carry,
+                         (int)cw, Yr, ldr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    dim3 gy((unsigned)ceil_div_dev(ldo, kTT), (unsigned)ceil_div_dev(cw, kTT));
+    hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, out_rows, parts, (int)cw,
+                       out + c0 * ldo, ldo);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  dim3 gy((unsigned)ceil_div_dev(ldo, kTT), (unsigned)ceil_div_dev(lp, kTT));
-  hipLaunchKernelGGL(k_from_rows, gy, dim3(256), 0, s, Yr, ldr, ptr, out_rows, parts, (int)lp,
-                     out, ldo);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace rsvd

@@ -32,7 +32,9 @@ int64_t csc_part_count(int64_t m, int64_t n, int64_t lp) {
   constexpr int64_t kMaxParts = 16;
   int64_t parts = std::max<int64_t>(1, ceil_div(m * lp * 4, kCscSliceBytes));
   parts = std::min(parts, kMaxParts);
-  while (parts > 1 && parts * n > (int64_t)UINT32_MAX - 1) --parts;   // 32-bit sort keys
+  // compressed rows b n + j are 32-bit sort keys and int32 row indices of the
+  // product's chunk table
+  while (parts > 1 && parts * n > (int64_t)INT32_MAX - 1) --parts;
   return parts;
 }
 
@@ -68,8 +70,8 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     return fail(p, RSVD_E_INVALID_ARG, "unknown format %lld", prob.format);
   p.coo = prob.format == RSVD_COO;
   p.csr = prob.format == RSVD_CSR || p.coo;
-  if (p.coo && (m > 2147483647ll || n > 2147483647ll))
-    return fail(p, RSVD_E_UNSUPPORTED, "COO input needs m, n < 2^31 (internal int32 CSR)");
+  if (p.csr && (m >= 2147483647ll || n >= 2147483647ll))
+    return fail(p, RSVD_E_UNSUPPORTED, "sparse input needs m, n < 2^31 - 1 (int32 CSR indices)");
   if (p.csr) {
     if (prob.nnz < 0 || prob.nnz > 2147483647ll)
       return fail(p, RSVD_E_INVALID_ARG, "nnz=%lld must be in [0, 2^31) (int32 indices)", prob.nnz);
@@ -287,7 +289,10 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     p.chunks = spmm_chunk_count(prob.nnz);
     p.csc_parts = csc_part_count(m, n, p.lp);
     const size_t nnz = (size_t)prob.nnz;
-    const size_t rows = (size_t)std::max<int64_t>(m, std::max<int64_t>(n, p.csc_parts * n));
+    // Xr: the row-major operand (n rows for A X, m for A^T Q); Yr: the
+    // compressed rows of the result (m, or n per CSC row block)
+    const size_t xrows = (size_t)std::max<int64_t>(m, n);
+    const size_t yrows = (size_t)std::max<int64_t>(m, p.csc_parts * n);
     w.colptr = take((size_t)(p.csc_parts * n + 1) * 4);
     w.rowind = take(nnz * 4);
     w.cval = take(nnz * 4);
@@ -297,8 +302,8 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.pay1 = take(nnz * 8);
     p.sort_temp = csc_sort_scratch(prob.nnz);
     w.sort_temp = take(p.sort_temp);
-    w.Xr = take(rows * lp * 4);
-    w.Yr = take(rows * lp * 4);
+    w.Xr = take(xrows * lp * 4);
+    w.Yr = take(yrows * lp * 4);
     w.carry = take((size_t)p.chunks * lp * 4);
     w.first = take((size_t)p.chunks * 4);
   } else {

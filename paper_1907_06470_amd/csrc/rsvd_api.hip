@@ -330,6 +330,7 @@ struct Runner {
   // factor W2 W1, the final small factors W2 U_B), so W2 never touches a
   // tall panel.  pend[0] / pend[1]: the m- / n-side basis has one.
   Side* side = nullptr;
+  bool allow_defer = true;     // false: both passes on the caller's stream (no side stream)
   bool pend[2] = {false, false};
   bool side_busy = false;
   double* gsmall = nullptr;    // the l x l Gram the small SVD factors (B.G, or its congruence)
@@ -668,7 +669,7 @@ struct Runner {
                    int sd = -1, bool defer = false) {
     const int pside = sd < 0 ? -1 : 1 - sd;
     if (!twice) return cholqr_pass(in, out, rows, ld, pside);
-    if (defer && sd >= 0) {
+    if (defer && allow_defer && sd >= 0) {
       rsvd_status st = cholqr_pass(in, out, rows, ld, pside);
       if (st != RSVD_OK) return st;
       return defer_second(out, rows, ld, sd);
@@ -833,7 +834,12 @@ struct Runner {
       c.panel_hash = ckpt_hash(ck->out_panel, (size_t)rows * (size_t)P.lp);
       *ck->out = c;
     }
-    if (ck->stop_after == t) return RSVD_STOPPED;
+    if (ck->stop_after == t) {
+      // a deferred CholeskyQR pass may still run on the side stream: order it
+      // before whatever the caller enqueues next on its stream
+      if (rsvd_status st = join_side()) return st;
+      return RSVD_STOPPED;
+    }
     return RSVD_OK;
   }
 
@@ -973,12 +979,14 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   std::memset(report, 0, sizeof *report);
   RSVD_HIP(hipStreamSynchronize(R.s));
   float ms = 0.f;
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; ev && i < 8; ++i) {
     RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[i], ev->ev[i + 1]));
     report->stage_ms[i] = ms;
   }
-  RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
-  report->total_ms = ms;
+  if (ev) {
+    RSVD_HIP(hipEventElapsedTime(&ms, ev->ev[0], ev->ev[8]));
+    report->total_ms = ms;
+  }
   for (size_t x = 0; x < R.nn_idx.size(); ++x) {
     const int i = R.nn_idx[x];
     RSVD_HIP(hipEventElapsedTime(&ms, ev->kern[2 * i], ev->kern[2 * i + 1]));
@@ -992,7 +1000,8 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
   report->gemm_nn_launches = (int32_t)R.nn_idx.size();
   report->gemm_tn_launches = (int32_t)R.tn_idx.size();
   int32_t stw[rsvd::kStatusWords];
-  RSVD_HIP(hipMemcpy(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost));
+  RSVD_HIP(hipMemcpyAsync(stw, R.B.status, sizeof stw, hipMemcpyDeviceToHost, R.s));
+  RSVD_HIP(hipStreamSynchronize(R.s));
   const double passes = 2.0 * (double)P.prob.q + 2.0;
   report->flops_alg = passes * 2.0 * (double)m * (double)n * (double)P.l;
   auto pass_bytes = [&](int32_t prec) {
@@ -1033,7 +1042,7 @@ namespace {
 template <typename Bind>
 rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t ldu, double* S,
                           float* V, int64_t ldv, void* stream, rsvd_report* report,
-                          const Runner::Ckpt* ck = nullptr) {
+                          const Runner::Ckpt* ck = nullptr, bool no_alloc = false) {
   const rsvd::Plan& P = h->p;
   const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k;
   if (!U || !S || !V) return set_err(h, RSVD_E_INVALID_ARG, "U, S and V must be non-NULL");
@@ -1042,8 +1051,10 @@ rsvd_status factor_common(rsvd_plan_t h, Bind bind, void* ws, float* U, int64_t 
   hipStream_t s = (hipStream_t)stream;
   Runner R(h, ws, s);
   R.ck = ck;
+  // no_alloc: nothing is created (no timing events, no side stream)
+  R.allow_defer = !no_alloc;
   Events* ev = nullptr;
-  if (report) {
+  if (report && !no_alloc) {
     rsvd_status est;
     if (!(ev = plan_events(h, est))) return est;
     R.ev = ev;
