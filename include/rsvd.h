@@ -140,7 +140,7 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  * *device_ws_bytes the workspace rsvd_factor needs (256-byte aligned).
  * Errors: RSVD_E_INVALID_ARG (k < 1, p < 0, q < 0, k + p > min(m, n),
  * bad enum, tile sizes), RSVD_E_UNSUPPORTED (format/dtype/location not
- * implemented), RSVD_E_BUDGET (workspace above hbm_budget_bytes; the message
+ * implemented, or k + p above 512), RSVD_E_BUDGET (workspace above hbm_budget_bytes; the message
  * states the bytes needed).  opt may be NULL (defaults: FP32 everywhere,
  * ortho EACH, automatic tiles, no budget). */
 rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_plan_t* out,

@@ -2,7 +2,8 @@
 // CholeskyQR pass (steps 1-3 of the orthonormalisation: G = Y^T Y = L L^T,
 // Q = Y L^-T), in one workgroup: k_chol16 for sketch widths up to 128 (below),
 // k_chol_tp for widths up to 192 (the same steps on the lower tiles only,
-// further down).
+// further down), k_chol_gm for widths up to 512 (the same steps on a square
+// in global memory, at the end).
 //
 // The whole matrix sits in LDS as a 128 x 128 square of doubles whose rows are
 // XOR-swizzled in groups of 16 (element (i, c) at i * 128 + (c ^ (i & 15))),
@@ -496,6 +497,161 @@ __global__ __launch_bounds__(kThreads) void k_chol_tp(const double* __restrict__
   }
 }
 
+
+// ---- widths 193 .. 512: the square in global memory ----------------------
+// The steps of k_chol16 on an lp x lp FP64 square in a global scratch buffer
+// (row-major, element (i, c) at S[i * lp + c]; at most 2 MiB, so it stays in
+// the L2 cache), with more waves for the many trailing tiles of a wide matrix.
+// Only the diagonal inverses X_kk (and the pivots) are in LDS.  The
+// off-diagonal blocks of X are stored transposed in the upper triangle, as in
+// k_chol16.  Waves exchange data through global memory, so every phase ends
+// with a full workgroup barrier (__syncthreads orders global memory within a
+// workgroup); wave 0 reads the diagonal tile it has just updated after a
+// fence on its own stores.
+constexpr int kGmThreads = 256;
+constexpr int kGmWaves = kGmThreads / 64;
+constexpr int kGmMaxNb = 32;   // widths up to 512
+
+__device__ inline int64_t gidx(int64_t ld, int i, int c) { return (int64_t)i * ld + c; }
+
+__device__ void gm_diag_block(double* S, int64_t ld, double* Xd, double* dinv, const double* d0,
+                              int kb, int l, double tau, int& ndrop, int& nbad) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int g0 = kb * kB;
+  double d[kB], x[kB], dv;
+#pragma unroll
+  for (int p = 0; p < kB; ++p) {
+    const double v = S[gidx(ld, g0 + r, g0 + p)];
+    d[p] = p <= r ? v : 0.0;
+  }
+  diag_factor(d, d0[g0 + r], g0, l, tau, ndrop, nbad, dv, x);
+  if (lane < kB) {
+#pragma unroll
+    for (int p = 0; p < kB; ++p) S[gidx(ld, g0 + r, g0 + p)] = d[p];
+    dinv[g0 + r] = dv;
+#pragma unroll
+    for (int i = 0; i < kB; ++i) Xd[kb * kB * kB + xq(i, r)] = x[i];
+  }
+}
+
+__device__ void gm_panel_tile(double* S, int64_t ld, const double* Xd, int kb, int I) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + q;
+    acc = mma(S[gidx(ld, I * kB + l16, kb * kB + k)], Xd[kb * kB * kB + xq(l16, k)], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[gidx(ld, I * kB + 4 * r + q, kb * kB + l16)] = acc[r];
+}
+
+__device__ void gm_update_tile(double* S, int64_t ld, int kb, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = S[gidx(ld, I * kB + 4 * r + q, J * kB + l16)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kb * kB + 4 * s + q;
+    acc = mma(-S[gidx(ld, I * kB + l16, k)], S[gidx(ld, J * kB + l16, k)], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[gidx(ld, I * kB + 4 * r + q, J * kB + l16)] = acc[r];
+}
+
+__device__ void gm_inverse_tile(double* S, int64_t ld, const double* Xd, int I, int J) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  f64x4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
+  for (int K = J; K < I; ++K) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const double b =
+          (K == J) ? Xd[J * kB * kB + xq(k, l16)] : S[gidx(ld, J * kB + l16, K * kB + k)];
+      if (s < 2)
+        t0 = mma(S[gidx(ld, I * kB + l16, K * kB + k)], b, t0);
+      else
+        t1 = mma(S[gidx(ld, I * kB + l16, K * kB + k)], b, t1);
+    }
+  }
+  f64x4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = t0[r] + t1[r];
+  f64x4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) x = mma(-Xd[I * kB * kB + xq(l16, 4 * s + q)], t[s], x);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[gidx(ld, J * kB + l16, I * kB + 4 * r + q)] = x[r];
+}
+
+// G (lp x lp FP64, leading l x l used) -> L in S (and Lout) or W = L^-T.
+// S must not alias G; it may be Lout.
+__global__ __launch_bounds__(kGmThreads) void k_chol_gm(const double* __restrict__ G, int64_t lp,
+                                                        int l, double* S, float* __restrict__ W,
+                                                        double* Lout, int32_t* status,
+                                                        double tau) {
+  __shared__ double Xd[kGmMaxNb * kB * kB];
+  __shared__ double dinv[kGmMaxNb * kB];
+  __shared__ double d0[kGmMaxNb * kB];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int n = (int)lp;
+  const int nb = (l + kB - 1) / kB;
+  for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    S[e] = (i < l && c < l) ? G[e] : 0.0;
+  }
+  for (int i = tid; i < kGmMaxNb * kB; i += kGmThreads) d0[i] = i < l ? G[(int64_t)i * n + i] : 0.0;
+  __syncthreads();
+
+  int ndrop = 0, nbad = 0;
+  if (wave == 0) gm_diag_block(S, n, Xd, dinv, d0, 0, l, tau, ndrop, nbad);
+  __syncthreads();
+  for (int kb = 0; kb < nb; ++kb) {
+    for (int I = kb + 1 + wave; I < nb; I += kGmWaves) gm_panel_tile(S, n, Xd, kb, I);
+    __syncthreads();
+    if (kb + 1 < nb) {
+      const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
+      if (wave == 0) {
+        gm_update_tile(S, n, kb, kb + 1, kb + 1);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        gm_diag_block(S, n, Xd, dinv, d0, kb + 1, l, tau, ndrop, nbad);
+      } else {
+        for (int e = wave; e < ntile; e += kGmWaves - 1) {
+          int i = 0;
+          while ((i + 1) * (i + 2) / 2 <= e) ++i;
+          const int c = e - i * (i + 1) / 2;
+          gm_update_tile(S, n, kb, kb + 1 + i, kb + 1 + c);
+        }
+        if (W)
+          for (int J = wave - 1; J < kb; J += kGmWaves - 1) gm_inverse_tile(S, n, Xd, kb, J);
+      }
+      __syncthreads();
+    }
+  }
+
+  if (Lout) {
+    for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
+      const int i = (int)(e / n), c = (int)(e % n);
+      Lout[e] = (i < l && c <= i) ? S[e] : 0.0;
+    }
+  }
+  if (W) {
+    for (int J = wave; J < nb - 1; J += kGmWaves) gm_inverse_tile(S, n, Xd, nb - 1, J);
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
+      const int a = (int)(e / n), c = (int)(e % n);
+      double xv = 0.0;
+      if (c < l && a <= c)
+        xv = (a >> 4) == (c >> 4) ? Xd[(c >> 4) * kB * kB + xq(c & 15, a & 15)] : S[e];
+      W[e] = (float)xv;
+    }
+  }
+  if (tid == 0) {
+    if (ndrop) atomicAdd(status + kStDropped, ndrop);
+    if (nbad) atomicAdd(status + kStNonFinite, nbad);
+  }
+}
 }  // namespace
 
 bool chol16_fits(int64_t lp) { return lp <= kSq; }
@@ -513,6 +669,17 @@ hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int3
                           double tau, hipStream_t s) {
   if (!chol_tp_fits(lp) || l > lp || l < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol_tp, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, status, tau);
+  return hipGetLastError();
+}
+
+bool chol_gm_fits(int64_t lp) { return lp > kTpMax && lp <= kGmMaxNb * kB && lp % kB == 0; }
+
+hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, float* W, double* L,
+                          int32_t* status, double tau, hipStream_t s) {
+  if (!chol_gm_fits(lp) || l > lp || l < 1 || !S || S == G || (!W && !L) || (L && L != S))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_gm, dim3(1), dim3(kGmThreads), 0, s, G, lp, (int)l, S, W, L, status,
+                     tau);
   return hipGetLastError();
 }
 

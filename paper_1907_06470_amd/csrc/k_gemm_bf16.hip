@@ -9,8 +9,11 @@
 // aligned); panels column-major BF16 (element (i, c) at P[c * ld + i]).
 // Like the FP32 kernels, grid.y runs over the block-cyclic tiles of the
 // reduced dimension and each tile writes its own FP32 partial panel.
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
+#include "plan.h"
 
 namespace rsvd {
 
@@ -1003,7 +1006,7 @@ __global__ void k_panel_to_bf16(const float* __restrict__ P, u16* __restrict__ P
 
 }  // namespace
 
-hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
+static hipError_t launch_nn_bf16_slice(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
                           int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
                           int64_t ldy, int64_t part_stride, hipStream_t s) {
   const int nt = (int)(lp / 32);
@@ -1059,7 +1062,7 @@ hipError_t launch_nn_bf16_cast(const float* A32, int64_t lda, int64_t m, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
+static hipError_t launch_tn_bf16_slice(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
                           int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
                           int64_t ldz, int64_t part_stride, hipStream_t s) {
   // direct-to-LDS form: whole 16-byte chunks at both ends of every row and
@@ -1111,6 +1114,35 @@ hipError_t launch_panel_to_bf16(const float* P, uint16_t* P16, int64_t count, hi
   hipLaunchKernelGGL(k_panel_to_bf16, dim3((unsigned)ceil_div_dev(c4, 256)), dim3(256), 0, s, P,
                      P16, c4);
   return hipGetLastError();
+}
+
+// Panels wider than kSliceMax columns are multiplied in column slices
+// (plan.h, slice_width): one launch per slice, each reading A once more;
+// the slices' columns are independent, so results equal a single launch.
+hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tn,
+                          int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
+                          int64_t ldy, int64_t part_stride, hipStream_t s) {
+  const int64_t cw = slice_width(lp);
+  for (int64_t c0 = 0; c0 < lp; c0 += cw) {
+    const hipError_t e = launch_nn_bf16_slice(A, lda, m, n, tn, TJ, X + c0 * ldx, ldx,
+                                              std::min(cw, lp - c0), Y + c0 * ldy, ldy,
+                                              part_stride, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_tn_bf16(const uint16_t* A, int64_t lda, int64_t m, int64_t n, int64_t tm,
+                          int64_t TI, const uint16_t* Q, int64_t ldq, int64_t lp, float* Z,
+                          int64_t ldz, int64_t part_stride, hipStream_t s) {
+  const int64_t cw = slice_width(lp);
+  for (int64_t c0 = 0; c0 < lp; c0 += cw) {
+    const hipError_t e = launch_tn_bf16_slice(A, lda, m, n, tm, TI, Q + c0 * ldq, ldq,
+                                              std::min(cw, lp - c0), Z + c0 * ldz, ldz,
+                                              part_stride, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rsvd

@@ -11,8 +11,11 @@
 // P[c * ld + i]); the sketch width is padded to a multiple of 32 with zero
 // columns, so one workgroup owns all lp columns of its rows and A is read
 // from HBM exactly once per pass.
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
+#include "plan.h"
 
 namespace rsvd {
 
@@ -240,7 +243,7 @@ __global__ void k_cast_f64_f32(const double* __restrict__ A, int64_t lda, int64_
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_nn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tn, int64_t TJ,
+static hipError_t launch_nn_f32_slice(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tn, int64_t TJ,
                          const float* X, int64_t ldx, int64_t lp, float* Y, int64_t ldy,
                          int64_t part_stride, hipStream_t s) {
   dim3 grid((unsigned)ceil_div_dev(m, BM), (unsigned)TJ);
@@ -259,7 +262,7 @@ hipError_t launch_nn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int6
   return hipGetLastError();
 }
 
-hipError_t launch_tn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tm, int64_t TI,
+static hipError_t launch_tn_f32_slice(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tm, int64_t TI,
                          const float* Q, int64_t ldq, int64_t lp, float* Z, int64_t ldz,
                          int64_t part_stride, hipStream_t s) {
   dim3 grid((unsigned)ceil_div_dev(n, BM), (unsigned)TI);
@@ -308,6 +311,35 @@ hipError_t launch_panel_copy(const float* src, int64_t lds, int64_t rows, int64_
   hipLaunchKernelGGL(k_panel_copy, dim3((unsigned)ceil_div_dev(total, 256)), dim3(256), 0, s, src,
                      lds, rows, cols, dst, ldd, dst_rows, dst_cols);
   return hipGetLastError();
+}
+
+// Panels wider than kSliceMax columns are multiplied in column slices
+// (plan.h, slice_width): one launch per slice, each reading A once more;
+// the slices' columns are independent, so results equal a single launch.
+hipError_t launch_nn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tn, int64_t TJ,
+                         const float* X, int64_t ldx, int64_t lp, float* Y, int64_t ldy,
+                         int64_t part_stride, hipStream_t s) {
+  const int64_t cw = slice_width(lp);
+  for (int64_t c0 = 0; c0 < lp; c0 += cw) {
+    const hipError_t e = launch_nn_f32_slice(A, lda, m, n, tn, TJ, X + c0 * ldx, ldx,
+                                             std::min(cw, lp - c0), Y + c0 * ldy, ldy,
+                                             part_stride, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_tn_f32(const float* A, int64_t lda, int64_t m, int64_t n, int64_t tm, int64_t TI,
+                         const float* Q, int64_t ldq, int64_t lp, float* Z, int64_t ldz,
+                         int64_t part_stride, hipStream_t s) {
+  const int64_t cw = slice_width(lp);
+  for (int64_t c0 = 0; c0 < lp; c0 += cw) {
+    const hipError_t e = launch_tn_f32_slice(A, lda, m, n, tm, TI, Q + c0 * ldq, ldq,
+                                             std::min(cw, lp - c0), Z + c0 * ldz, ldz,
+                                             part_stride, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rsvd

@@ -13,6 +13,8 @@
 //   s = 2^ceil(log2(amax / 448)) over the value's block (s = 1 for an all-zero
 //   block), q = round-to-nearest-even(x / s) in e4m3 (|x / s| <= 448, so the
 //   conversion never overflows).
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
@@ -675,7 +677,7 @@ hipError_t launch_panel_to_fp8(const float* P, int64_t ld, int64_t rows, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,
+static hipError_t launch_nn_fp8_slice(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,
                          int64_t TK, const float* sA, int64_t sc_r, int64_t sc_k,
                          const uint8_t* X8, int64_t ldx8, const float* sx, int64_t lp, float* Y,
                          int64_t ldy, int64_t part_stride, hipStream_t s) {
@@ -704,6 +706,24 @@ hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t 
   }
 #undef NN8
   return hipGetLastError();
+}
+
+// Panels wider than kSliceMax columns are multiplied in column slices
+// (plan.h, slice_width): one launch per slice, each reading A once more;
+// the slices' columns are independent, so results equal a single launch.
+hipError_t launch_nn_fp8(const uint8_t* A8, int64_t lda8, int64_t rows, int64_t kdim, int64_t tk,
+                         int64_t TK, const float* sA, int64_t sc_r, int64_t sc_k,
+                         const uint8_t* X8, int64_t ldx8, const float* sx, int64_t lp, float* Y,
+                         int64_t ldy, int64_t part_stride, hipStream_t s) {
+  const int64_t cw = slice_width(lp);
+  for (int64_t c0 = 0; c0 < lp; c0 += cw) {
+    const hipError_t e = launch_nn_fp8_slice(A8, lda8, rows, kdim, tk, TK, sA, sc_r, sc_k,
+                                             X8 + c0 * ldx8, ldx8, sx + c0,
+                                             std::min(cw, lp - c0), Y + c0 * ldy, ldy,
+                                             part_stride, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rsvd

@@ -543,13 +543,33 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double*
 }
 
 // ------------------------------------------------------ panel x matrix ----
+// Accumulator tile of output column c for rows rbase .. rbase + 31 in the
+// 32 x 32 matrix-core layout (register 4 g + e holds row rbase + 8 g +
+// 4 half + e): zero, or (accum) the values already in out, so that a product
+// split over row ranges of W adds its parts in a fixed order.
+__device__ inline f32x16 apply_acc_init(const float* out, int64_t ldo, int64_t out_rows,
+                                        int64_t rbase, int c, int half, int ncols, int accum) {
+  f32x16 a = f32x16{};
+  if (accum && c < ncols) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = rbase + 8 * g + 4 * half + e;
+        if (r < out_rows) a[4 * g + e] = out[(int64_t)c * ldo + r];
+      }
+  }
+  return a;
+}
+
 // out(i, c) = sum_a P(i, a) W(a, c) for c < ncols; rows [rows, out_rows)
 // receive zeros.  One wave per 32 rows, all lp output columns.
 template <int NT, bool TRI>
 __global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int64_t ldp,
                                                int64_t rows, int kdim, const float* __restrict__ W,
                                                int64_t ldw, int ncols, float* __restrict__ out,
-                                               int64_t ldo, int64_t out_rows, int vec_ok) {
+                                               int64_t ldo, int64_t out_rows, int vec_ok,
+                                               int accum) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, half = lane >> 5;
   const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
@@ -557,7 +577,8 @@ __global__ __launch_bounds__(256) void k_apply(const float* __restrict__ P, int6
   const bool iok = i < rows;
   f32x16 acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+  for (int t = 0; t < NT; ++t) acc[t] = apply_acc_init(out, ldo, out_rows, rbase, t * 32 + l32, half,
+                                                       ncols, accum);
   const int kd2 = (kdim + 1) & ~1;
   for (int a0 = 0; a0 < kd2; a0 += 16) {
     float av[8];
@@ -612,7 +633,8 @@ __global__ __launch_bounds__(kApThreads) void k_apply_staged(const float* __rest
                                                              const float* __restrict__ W,
                                                              int64_t ldw, int ncols,
                                                              float* __restrict__ out, int64_t ldo,
-                                                             int64_t out_rows, int vec_ok) {
+                                                             int64_t out_rows, int vec_ok,
+                                                             int accum) {
   constexpr int WC = NT * 32;
   __shared__ __attribute__((aligned(16))) float Ws[KR * WC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -644,7 +666,8 @@ __global__ __launch_bounds__(kApThreads) void k_apply_staged(const float* __rest
     const bool iok = i < rows;
     f32x16 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+    for (int t = 0; t < NT; ++t)
+      acc[t] = apply_acc_init(out, ldo, out_rows, rbase, t * 32 + l32, half, ncols, accum);
     float av[8], an[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -1205,8 +1228,8 @@ __global__ __launch_bounds__(1024) void k_finish_small(const double* __restrict_
                                                        float* __restrict__ Wv,
                                                        int32_t* __restrict__ order_out,
                                                        int32_t* status) {
-  __shared__ int order[kMaxLp];
-  __shared__ double lv[kMaxLp], sig[kMaxLp], inv[kMaxLp];
+  __shared__ int order[kWideMax];
+  __shared__ double lv[kWideMax], sig[kWideMax], inv[kWideMax];
   __shared__ double smax_s;
   __shared__ int nzero;
   const int tid = threadIdx.x;
@@ -1319,15 +1342,15 @@ __global__ void k_gather_cols(const double* __restrict__ Ev, int64_t lp, int l,
 }
 
 // C = op(A) B for lp x lp row-major matrices (lp a multiple of 16, at most
-// 192), FP64 accumulation in index order: one 16 x 16 tile of C per
+// KM), FP64 accumulation in index order: one 16 x 16 tile of C per
 // workgroup; the tile's 16 rows of op(A) and 16 columns of B are loaded to
 // LDS in one batch (every load in flight at once), then each thread sums
 // its element.
-constexpr int kLpMax = 192;
-template <typename TA, typename TB, typename TC, bool TRANS_A>
+constexpr int kLpMax = (int)kWideMax;
+template <typename TA, typename TB, typename TC, bool TRANS_A, int KM>
 __global__ __launch_bounds__(256) void k_lp_gemm(const TA* __restrict__ A, const TB* __restrict__ B,
                                                  TC* __restrict__ C, int lp) {
-  __shared__ double As[16][kLpMax + 1], Bs[kLpMax][17];
+  __shared__ double As[16][KM + 1], Bs[KM][17];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
 #pragma unroll 12
@@ -1388,7 +1411,8 @@ hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int
 }
 
 hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
-                           double tau, hipStream_t s) {
+                           double tau, double* scratch, hipStream_t s) {
+  if (chol_gm_fits(lp)) return launch_chol_gm(G, lp, l, scratch, W, nullptr, status, tau, s);
   if (lp > kMaxLp) return hipErrorInvalidValue;
   if (chol16_fits(lp)) return launch_chol16(G, lp, l, W, nullptr, status, tau, s);
   if (chol_tp_fits(lp)) return launch_chol_tp(G, lp, l, W, status, tau, s);
@@ -1397,9 +1421,10 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
   return hipGetLastError();
 }
 
-hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
-                        int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out, int64_t ldo,
-                        int64_t out_rows_total, hipStream_t s) {
+namespace {
+hipError_t apply_one(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
+                     int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out, int64_t ldo,
+                     int64_t out_rows_total, int accum, hipStream_t s) {
   if (kdim < 0 || kdim > kMaxLp) return hipErrorInvalidValue;
   const int vec_ok = ((ldo % 4) == 0 && (((uintptr_t)out) & 15) == 0) ? 1 : 0;
   const int64_t nblk = ceil_div_dev(out_rows_total, 32);
@@ -1411,7 +1436,7 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
   const dim3 grid((unsigned)ceil_div_dev(out_rows_total, 128));
 #define AP_ST(NT, TRI, KR)                                                                  \
   hipLaunchKernelGGL((k_apply_staged<NT, TRI, KR>), grid_s, dim3(kApThreads), 0, s, P, ldp, \
-                     rows, (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok)
+                     rows, (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok, accum)
 #define AP_CALL(NT)                                                                         \
   do {                                                                                      \
     if (tall && tri && !wide)                                                               \
@@ -1422,10 +1447,11 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
       AP_ST(NT, false, kMaxLp);                                                             \
     else if (tri)                                                                           \
       hipLaunchKernelGGL((k_apply<NT, true>), grid, dim3(256), 0, s, P, ldp, rows, (int)kdim, \
-                         W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);             \
+                         W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok, accum);      \
     else                                                                                    \
       hipLaunchKernelGGL((k_apply<NT, false>), grid, dim3(256), 0, s, P, ldp, rows,         \
-                         (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok);  \
+                         (int)kdim, W, ldw, (int)ncols, out, ldo, out_rows_total, vec_ok,   \
+                         accum);                                                            \
   } while (0)
   switch (lp / 32) {
     case 1: AP_CALL(1); break;
@@ -1440,11 +1466,44 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
 #undef AP_ST
   return hipGetLastError();
 }
+}  // namespace
+
+// Widths above kMaxLp: W (kdim x lp) is taken in sub-blocks of at most
+// kMaxLp x kMaxLp, column slices of equal width (a multiple of 32) and row
+// slices on the same boundaries, so that every sub-block fits the kernels
+// above (W staged in LDS on tall panels).  The row slices of one column slice
+// add into the output in increasing order (the first writes, the others
+// accumulate); with triangular W the slices below the diagonal are skipped.
+hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim, const float* W,
+                        int64_t ldw, int64_t lp, int64_t ncols, bool tri, float* out, int64_t ldo,
+                        int64_t out_rows_total, hipStream_t s) {
+  if (kdim < 0 || lp < 32 || lp % 32) return hipErrorInvalidValue;
+  if (lp <= kMaxLp && kdim <= kMaxLp)
+    return apply_one(P, ldp, rows, kdim, W, ldw, lp, ncols, tri, out, ldo, out_rows_total, 0, s);
+  if (lp > kWideMax || kdim > kWideMax) return hipErrorInvalidValue;
+  const int64_t nslice = ceil_div_dev(std::max(lp, kdim), kMaxLp);
+  const int64_t cw = ceil_div_dev(ceil_div_dev(std::max(lp, kdim), nslice), 32) * 32;
+  for (int64_t c0 = 0; c0 < lp && c0 < ncols; c0 += cw) {
+    const int64_t wc = std::min(cw, lp - c0), nc = std::min(wc, ncols - c0);
+    const int64_t kend = tri ? std::min(kdim, c0 + wc) : kdim;
+    int accum = 0;
+    for (int64_t k0 = 0; k0 < kend || (k0 == 0 && kend == 0); k0 += cw) {
+      const int64_t kw = std::min(cw, kend - k0);
+      hipError_t e = apply_one(P + k0 * ldp, ldp, rows, kw, W + k0 * ldw + c0, ldw, wc, nc,
+                               tri && k0 == c0, out + c0 * ldo, ldo, out_rows_total, accum, s);
+      if (e != hipSuccess) return e;
+      accum = 1;
+      if (kend == 0) break;
+    }
+  }
+  return hipSuccess;
+}
 
 bool small_svd_one_sided(int64_t lp) { return lp <= kOjMaxLp; }
 
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
                               double tau, hipStream_t s) {
+  if (chol_gm_fits(lp)) return launch_chol_gm(G, lp, l, L, nullptr, L, status, tau, s);
   if (lp > kBlkMaxLp) return hipErrorInvalidValue;
   if (chol16_fits(lp)) return launch_chol16(G, lp, l, nullptr, L, status, tau, s);
   hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l,
@@ -1476,32 +1535,46 @@ hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t 
   return hipGetLastError();
 }
 
+// The LDS tiles are sized for the plan's width class: kMaxLp, or kLpMax for
+// wide sketches (135 KB, one workgroup per CU).
 hipError_t launch_congruence(const double* G, const float* W, double* T, double* out, int64_t lp,
                              hipStream_t s) {
   if (lp % 16 || lp > kLpMax) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(lp / 16), (unsigned)(lp / 16));
   if (T == G || T == out) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_lp_gemm<double, float, double, false>), grid, dim3(256), 0, s, G, W, T,
-                     (int)lp);
+  if (lp <= kMaxLp)
+    hipLaunchKernelGGL((k_lp_gemm<double, float, double, false, kMaxLp>), grid, dim3(256), 0, s, G,
+                       W, T, (int)lp);
+  else
+    hipLaunchKernelGGL((k_lp_gemm<double, float, double, false, kLpMax>), grid, dim3(256), 0, s, G,
+                       W, T, (int)lp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_lp_gemm<float, double, double, true>), grid, dim3(256), 0, s, W, T, out,
-                     (int)lp);
+  if (lp <= kMaxLp)
+    hipLaunchKernelGGL((k_lp_gemm<float, double, double, true, kMaxLp>), grid, dim3(256), 0, s, W,
+                       T, out, (int)lp);
+  else
+    hipLaunchKernelGGL((k_lp_gemm<float, double, double, true, kLpMax>), grid, dim3(256), 0, s, W,
+                       T, out, (int)lp);
   return hipGetLastError();
 }
 
 hipError_t launch_lp_product(const float* A, const float* B, float* C, int64_t lp, hipStream_t s) {
   if (lp % 16 || lp > kLpMax) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(lp / 16), (unsigned)(lp / 16));
-  hipLaunchKernelGGL((k_lp_gemm<float, float, float, false>), grid, dim3(256), 0, s, A, B, C,
-                     (int)lp);
+  if (lp <= kMaxLp)
+    hipLaunchKernelGGL((k_lp_gemm<float, float, float, false, kMaxLp>), grid, dim3(256), 0, s, A, B,
+                       C, (int)lp);
+  else
+    hipLaunchKernelGGL((k_lp_gemm<float, float, float, false, kLpMax>), grid, dim3(256), 0, s, A, B,
+                       C, (int)lp);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, int64_t l,
                                int64_t k, double* S, float* Wu, float* Wv, int32_t* order,
                                int32_t* status, hipStream_t s) {
-  if (lp > kMaxLp) return hipErrorInvalidValue;
+  if (lp > kWideMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finish_small, dim3(1), dim3(1024), 0, s, lam, Ev, lp, (int)l, (int)k, S, Wu,
                      Wv, order, status);
   return hipGetLastError();

@@ -102,8 +102,9 @@ hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val,
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
                        int64_t chunks, double* gpart, double* G, hipStream_t s);
 // W = L^-T (FP32, upper triangular) with G = L L^T; dropped directions zero.
+// scratch: lp x lp FP64, distinct from G, used for widths above 192 only.
 hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
-                           double tau, hipStream_t s);
+                           double tau, double* scratch, hipStream_t s);
 // out(:, 0:ncols) = P(:, 0:kdim) * W(0:kdim, 0:ncols); W row-major with ldw;
 // `tri`: W upper triangular (skip zero blocks).  Rows [rows, ld) written as 0.
 // out = W^T G W (G FP64 symmetric, W FP32, both lp x lp row-major; T is
@@ -126,10 +127,23 @@ hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, doubl
 bool chol_tp_fits(int64_t lp);
 hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
                           double tau, hipStream_t s);
+// Cholesky factor (into L = S) or W = L^-T for 192 < lp <= 512, the square in
+// the global scratch S (lp x lp FP64, not aliasing G; k_chol.hip).
+bool chol_gm_fits(int64_t lp);
+hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, float* W, double* L,
+                          int32_t* status, double tau, hipStream_t s);
+// Small SVD of wide sketches (lp <= 512): block one-sided Jacobi on the
+// Cholesky factor L (FP64 row-major lp x lp) of C; M (lp x lp FP64) and ctl
+// (kBjMaxSweeps int32) are scratch.  Writes lam (|m_c|^2) and Ev (row-major)
+// as launch_ojacobi does (k_bjacobi.hip).
+bool bjacobi_fits(int64_t lp);
+hipError_t launch_bjacobi(const double* L, int64_t lp, int64_t l, double* M, int32_t* ctl,
+                          double* lam, double* Ev, int32_t* status, double tol, hipStream_t s);
 // Automatic q: prev[k] = max_i<k |S_i - prev_i| / S_i (+inf if first), prev = S.
 hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* prev, hipStream_t s);
 // Small SVD through the Cholesky factor of C and one-sided Jacobi (lp <= 128).
 bool small_svd_one_sided(int64_t lp);
+// L (lp x lp FP64 row-major, distinct from G) with G = L L^T.
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
                               double tau, hipStream_t s);
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,

@@ -143,9 +143,9 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
 
   p.l = k + pp;
   p.lp = round_up(p.l, kColAlign);
-  if (p.lp > 192)
-    return fail(p, RSVD_E_UNSUPPORTED, "k + p = %lld: sketch widths above 192 are not implemented",
-                p.l);
+  if (p.lp > kWideMax)
+    return fail(p, RSVD_E_UNSUPPORTED, "k + p = %lld: sketch widths above %lld are not implemented",
+                p.l, kWideMax);
   p.ldm = round_up(m, kPanelAlign);
   p.ldn = round_up(n, kPanelAlign);
 
@@ -224,9 +224,15 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.W = take(lp * lp * 4);
   w.W2 = take(lp * lp * 4);
   w.Ev = take(lp * lp * 8);
+  const bool wide = p.lp > kSliceMax;
+  w.Mj = wide ? take(lp * lp * 8) : off;
+  w.bjctl = wide ? take((size_t)kBjMaxSweeps * 4) : off;
+  w.Ls2 = wide ? take(lp * lp * 8) : off;
   w.lam = take(lp * 8);
   w.order = take(lp * 4);
-  w.rot = take((size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8);
+  // the rotation log of the two-sided Jacobi (widths 129 .. 192 only)
+  const bool two_sided = p.lp > 128 && p.lp <= kSliceMax;
+  w.rot = take(two_sided ? (size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8 : 8);
   w.signs = take(lp * 4);
   w.status = take(kStatusWords * 4);
   w.prevS = take((size_t)k * 8 + 8);

@@ -14,8 +14,19 @@ namespace rsvd {
 
 constexpr int64_t kPanelAlign = 256;   // panel leading dimensions (elements)
 constexpr int64_t kColAlign = 32;      // sketch width is padded to this
+constexpr int64_t kWideMax = 512;      // largest padded sketch width
+constexpr int64_t kSliceMax = 192;     // widest panel slice of one product launch
+// Column slices of a panel of width lp for kernels that take at most
+// kSliceMax columns: as few as possible, of equal width (a multiple of 32);
+// slice_width() is the width of all but possibly the last.
+inline int64_t slice_count(int64_t lp) { return (lp + kSliceMax - 1) / kSliceMax; }
+inline int64_t slice_width(int64_t lp) {
+  const int64_t ns = slice_count(lp);
+  return ((lp + ns - 1) / ns + 31) / 32 * 32;
+}
 constexpr int kGramBlock = 64;         // Gram output block edge
 constexpr int kJacobiMaxSweeps = 40;
+constexpr int kBjMaxSweeps = 20;     // sweeps enqueued by the block Jacobi of wide sketches
 constexpr int64_t kPanelFp8Chunks = 32;   // row chunks per column of the panel FP8 conversion
 constexpr int kStatusWords = 64;
 constexpr int64_t kSpmmChunk = 2048;   // nonzeros per wave in the sparse products
@@ -50,6 +61,9 @@ struct Workspace {
   size_t Wpm, Wpn;        // lp x lp FP32 pending right factors of the m- and n-side bases
   size_t Wc;              // lp x lp FP32 product of a pending factor and a first-pass factor
   size_t Ev;              // lp x lp FP64 eigenvectors
+  size_t Mj;              // lp x lp FP64 columns of the block Jacobi (widths > 192)
+  size_t bjctl;           // kBjMaxSweeps int32 sweep flags of the block Jacobi
+  size_t Ls2;             // lp x lp FP64 Cholesky scratch of the side stream (widths > 192)
   size_t lam;             // lp FP64 eigenvalues / singular values
   size_t order;           // lp int32 sort order
   size_t rot;             // Jacobi rotation log (FP64 pairs)

@@ -158,7 +158,8 @@ struct Buffers {
   float* coo_val;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
-  double *gpart, *G, *L, *Ev, *lam, *rot;
+  double *gpart, *G, *L, *Ev, *lam, *rot, *Mj, *Ls2;
+  int32_t* bjctl;
   double *gpart2, *G2, *Tc;
   float *Wpm, *Wpn, *Wc;
   int32_t *order, *signs, *status;
@@ -227,6 +228,9 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.Wc = (float*)(b + w.Wc);
   B.L = (double*)(b + w.L);
   B.Ev = (double*)(b + w.Ev);
+  B.Mj = (double*)(b + w.Mj);
+  B.Ls2 = (double*)(b + w.Ls2);
+  B.bjctl = (int32_t*)(b + w.bjctl);
   B.lam = (double*)(b + w.lam);
   B.rot = (double*)(b + w.rot);
   B.order = (int32_t*)(b + w.order);
@@ -633,12 +637,12 @@ struct Runner {
     if (pside >= 0 && pend[pside]) {
       if ((st = join_side())) return st;
       RSVD_HIP(rsvd::launch_congruence(B.G, Wpend(pside), B.L, B.Tc, P.lp, s));
-      RSVD_HIP(rsvd::launch_chol_inv(B.Tc, P.lp, P.l, B.W, B.status, kCholTau, s));
+      RSVD_HIP(rsvd::launch_chol_inv(B.Tc, P.lp, P.l, B.W, B.status, kCholTau, B.L, s));
       RSVD_HIP(rsvd::launch_lp_product(Wpend(pside), B.W, B.Wc, P.lp, s));
       Wuse = B.Wc;
       pend[pside] = false;
     } else {
-      RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, s));
+      RSVD_HIP(rsvd::launch_chol_inv(B.G, P.lp, P.l, B.W, B.status, kCholTau, B.L, s));
     }
     RSVD_HIP(rsvd::launch_apply(in, ld, rows, P.l, Wuse, P.lp, P.lp, P.lp, true, out, ld, ld, s));
     return RSVD_OK;
@@ -653,7 +657,8 @@ struct Runner {
     RSVD_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
     const int64_t chunks = rsvd::gram_chunks_for(P, rows);
     RSVD_HIP(rsvd::launch_gram(q1, ld, rows, P.lp, P.gram_rows, chunks, B.gpart2, B.G2, side->s));
-    RSVD_HIP(rsvd::launch_chol_inv(B.G2, P.lp, P.l, Wpend(sd), B.status, kCholTau, side->s));
+    RSVD_HIP(rsvd::launch_chol_inv(B.G2, P.lp, P.l, Wpend(sd), B.status, kCholTau, B.Ls2,
+                                   side->s));
     RSVD_HIP(hipEventRecord(side->join, side->s));
     side_busy = true;
     pend[sd] = true;
@@ -896,7 +901,13 @@ struct Runner {
     return RSVD_OK;
   }
   rsvd_status small_svd_solve(double* S, int64_t kout) {
-    if (rsvd::small_svd_one_sided(P.lp)) {
+    if (P.lp > rsvd::kSliceMax) {
+      // wide sketches: C = L L^T, then block one-sided Jacobi on L over
+      // several workgroups (no drop, as below)
+      RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
+      RSVD_HIP(rsvd::launch_bjacobi(B.L, P.lp, P.l, B.Mj, B.bjctl, B.lam, B.Ev, B.status,
+                                    kJacobiTol, s));
+    } else if (rsvd::small_svd_one_sided(P.lp)) {
       // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
       // positive pivot; exactly dependent directions give zero columns)
       RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));

@@ -29,6 +29,8 @@ def bf16_round(x):
     (1000, 1024, 120, (256, 320)),
     (520, 2080, 128, (224, 416)),
     (33, 5000, 3, (32, 4096)),
+    (700, 800, 230, (256, 256)),    # lp = 256: two slices of the direct-to-LDS width 128
+    (500, 640, 330, (0, 0)),        # lp = 352
 ])
 def test_bf16_products_within_rounding_bound(m, n, l, tile):
     dev = need_gpu()

@@ -29,6 +29,8 @@ SLAB_REL = 2.0 ** -8
     (513, 2049, 100, (512, 1024)),
     (65, 5000, 3, (64, 4096)),
     (136, 224, 120, (64, 128)),
+    (640, 768, 230, (256, 256)),
+    (512, 448, 330, (0, 0)),
 ])
 def test_fp8_products_match_quantised_operands(m, n, l, tile):
     dev = need_gpu()

@@ -57,6 +57,9 @@ PRODUCT_CASES = [
     (300, 260, 190, (96, 64)),       # widest sketch, lp = 192
     (128, 64, 32, (128, 64)),        # one tile
     (33, 5000, 3, (32, 4096)),       # short and wide
+    (600, 450, 230, (256, 160)),     # wide sketch, lp = 256: two 128-column slices
+    (420, 700, 330, (0, 0)),         # lp = 352: slices of 192 and 160
+    (530, 512, 500, (256, 256)),     # widest sketch, lp = 512
 ]
 
 
@@ -94,7 +97,8 @@ def test_products_with_fp64_input_use_the_fp32_rounding():
 
 
 @pytest.mark.parametrize("rows,l,side", [(3000, 40, 0), (2500, 120, 1), (777, 190, 0), (100, 1, 0),
-                                         (70000, 64, 0), (20000, 150, 1), (70001, 190, 0)])
+                                         (70000, 64, 0), (20000, 150, 1), (70001, 190, 0),
+                                         (5000, 230, 1), (9001, 330, 0), (2000, 500, 0)])
 def test_gram_is_the_fp64_product(rows, l, side):
     dev = need_gpu()
     say("gram", rows, l)
@@ -113,7 +117,9 @@ def test_gram_is_the_fp64_product(rows, l, side):
 
 @pytest.mark.parametrize("rows,l,cond,side", [(3000, 40, 10.0, 0), (2500, 120, 1e4, 1), (777, 190, 1e3, 0),
                                               (64, 64, 1.0, 0), (3000, 150, 1e3, 1), (5000, 176, 1e5, 0),
-                                              (140001, 190, 1e3, 0), (133000, 96, 10.0, 1)])
+                                              (140001, 190, 1e3, 0), (133000, 96, 10.0, 1),
+                                              (6000, 230, 1e4, 1), (8000, 330, 1e3, 0),
+                                              (150001, 330, 1e2, 0), (3000, 500, 1e2, 0)])
 def test_cholqr2_orthonormal_basis_of_the_span(rows, l, cond, side):
     dev = need_gpu()
     say("orth", rows, l, cond)
@@ -123,12 +129,13 @@ def test_cholqr2_orthonormal_basis_of_the_span(rows, l, cond, side):
     scale = np.logspace(0, -np.log10(cond), l)
     Y = rand_panel(rows, l, 5, scale)
     Q = plan.step_orth(side, col_major_from_numpy(Y, dev)).cpu().numpy().astype(np.float64)
+    say(f"orth err {metrics.orth_err(Q):.3e}")
     assert metrics.orth_err(Q) < 2e-6 * max(1.0, l / 32)
     Qref, _ = householder_qr(Y.astype(np.float64))
     assert metrics.sin_theta(Qref, Q) < 1e-6 * cond * 10
 
 
-@pytest.mark.parametrize("rows,l,r", [(2000, 24, 9), (3000, 170, 40)])
+@pytest.mark.parametrize("rows,l,r", [(2000, 24, 9), (3000, 170, 40), (4000, 330, 70)])
 def test_cholqr2_drops_dependent_directions(rows, l, r):
     dev = need_gpu()
     say("orth drop", rows, l, r)
@@ -138,13 +145,20 @@ def test_cholqr2_drops_dependent_directions(rows, l, r):
     Q = plan.step_orth(0, col_major_from_numpy(Y, dev)).cpu().numpy().astype(np.float64)
     norms = np.linalg.norm(Q, axis=0)
     live = norms > 0.5
+    oe = metrics.orth_err(Q[:, live])
+    say(f"orth drop: live {live.sum()}, orth err {oe:.3e}")
     assert live.sum() == r
     assert np.all(norms[~live] == 0.0)
-    assert metrics.orth_err(Q[:, live]) < 1e-5
-    assert metrics.sin_theta(Y.astype(np.float64), Q[:, live]) < 1e-5
+    assert oe < 1e-5
+    # Q = Y W is formed in FP32: its columns leave span(Y) by the rounding of
+    # the product, about u32 * cond(Y_kept) relative (u32 = 2^-24)
+    kappa = np.linalg.cond(Y[:, live].astype(np.float64))
+    assert metrics.sin_theta(Y.astype(np.float64), Q[:, live]) < 4 * 2.0 ** -24 * max(kappa, 10.0)
 
 
-@pytest.mark.parametrize("n,l,decay", [(5000, 30, 1.0), (20000, 120, 2.0), (700, 190, 0.5), (64, 1, 0.0)])
+@pytest.mark.parametrize("n,l,decay", [(5000, 30, 1.0), (20000, 120, 2.0), (700, 190, 0.5), (64, 1, 0.0),
+                                        (5000, 230, 1.0), (3000, 330, 0.5), (2000, 500, 1.0),
+                                        (900, 17, 0.5)])
 def test_small_svd_matches_oracle(n, l, decay):
     dev = need_gpu()
     say("small svd", n, l)
