@@ -68,3 +68,42 @@ def test_chain_of_stops_and_a_tampered_panel(tmp_path):
     other = Plan(m, n, k, p, q, seed=10, tile=(1024, 768))
     with pytest.raises(L.RsvdError):
         other.factor_resumable(A, resume=c4)
+
+
+def test_stop_without_saving_then_factor_on_the_same_workspace():
+    """A call that stops after pass 1 with no checkpoint leaves no deferred
+    work running behind it: an immediate factorisation on the same workspace
+    and stream reports no dropped direction and is bitwise the fresh result."""
+    dev = need_gpu()
+    m, n, k, p, q = 3000, 2000, 40, 24, 2
+    A = _A(m, n, 23).to(dev)
+    plan = Plan(m, n, k, p, q, seed=3, tile=(1024, 1024))
+    U0, S0, V0, info0 = plan.factor(A)
+    ws = plan.workspace(dev)
+    for _ in range(3):
+        _, _, _, info, ck = plan.factor_resumable(A, stop_after=1, save=False, ws=ws)
+        assert info["status"] == L.STOPPED and ck is None
+        U1, S1, V1, info1 = plan.factor(A, ws=ws)
+        assert info1["status"] == L.OK and info1["dropped"] == 0
+        assert torch.equal(S0, S1) and torch.equal(U0, U1) and torch.equal(V0, V1)
+
+
+def test_resumed_run_matches_the_oracle():
+    """The resumed factorisation is checked against the FP64 oracle on the
+    same input (sigma within the FP32 target), not only against the GPU's own
+    uninterrupted run."""
+    from oracle import metrics
+    from oracle.rsvd import rsvd as oracle_rsvd
+    dev = need_gpu()
+    m, n, k, p, q = 2400, 1500, 30, 10, 2
+    A = _A(m, n, 24)
+    plan = Plan(m, n, k, p, q, seed=4, tile=(1024, 512))
+    ref = oracle_rsvd(A.double().numpy(), k, p, q, seed=4)
+    Ad = A.to(dev)
+    for t in (1, 3, 2 * q + 2):
+        _, _, _, _, ck = plan.factor_resumable(Ad, stop_after=t)
+        U, S, V, _, _ = plan.factor_resumable(Ad, resume=ck)
+        err = metrics.sigma_err(S.cpu().numpy(), ref["S"])
+        su = metrics.sin_theta(ref["U"], U.cpu().double().numpy())
+        say(f"resumed after pass {t}: sigma err {err:.2e}, sin U {su:.1e}")
+        assert err <= 1e-5 and su <= 1e-3
