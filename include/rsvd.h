@@ -163,6 +163,27 @@ rsvd_status rsvd_factor(rsvd_plan_t plan, const void* A, int64_t lda, void* ws,
                         float* U, int64_t ldu, double* S, float* V, int64_t ldv,
                         void* stream, rsvd_report* report);
 
+/* rsvd_factor for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation on a dense, device-resident A, with the workspace
+ * taken from a static device array of RSVD_NOALLOC_WS_BYTES inside the
+ * library (one per device, held until the process ends) instead of a caller
+ * buffer.  The call allocates nothing: no device memory, no streams, no
+ * events.  Both CholeskyQR passes of every basis run on `stream` (no side
+ * stream), so results agree with rsvd_factor to rounding, not bit for bit.
+ * No report: the call only enqueues work; device-side warnings (dropped
+ * directions, non-finite values) are not returned.
+ *   A, lda, U, ldu, S, V, ldv, stream   as for rsvd_factor.
+ * Errors: RSVD_E_BUDGET when the plan's workspace exceeds
+ * RSVD_NOALLOC_WS_BYTES (the message states both sizes); RSVD_E_UNSUPPORTED
+ * for CSR/COO or host-resident plans; RSVD_E_INVALID_ARG as rsvd_factor.
+ * All calls on one device share its array and it keeps the last call's
+ * contents (every call initialises what it reads): calls that overlap on
+ * one device, on any streams, race and must be serialised by the caller. */
+#define RSVD_NOALLOC_WS_BYTES (64ull << 20)
+rsvd_status rsvd_factor_noalloc(rsvd_plan_t plan, const void* A, int64_t lda, float* U,
+                                int64_t ldu, double* S, float* V, int64_t ldv, void* stream);
+
 /* Reverse-mode derivative (adjoint) of rsvd_factor.  The paper has no
  * derivative; this treats the l = k + p Ritz triplets (U_l, S_l, V_l) of the
  * randomized SVD as exact singular triplets of A and applies the real-SVD

@@ -57,6 +57,7 @@ class Report(ctypes.Structure):
 
 
 CKPT_MAGIC = 0x31504B4344565352   # "RSVDCKP1" little-endian
+NOALLOC_WS_BYTES = 64 << 20      # static workspace of rsvd_factor_noalloc (rsvd.h)
 
 
 class Checkpoint(ctypes.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "rsvd_plan": (c_i32, [_P(Problem), _P(Options), _P(c_vp), _P(c_sz)]),
     "rsvd_factor": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
                             _P(Report)]),
+    "rsvd_factor_noalloc": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp]),
     "rsvd_backward": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
                               c_vp, c_vp, _P(Report)]),
     "rsvd_factor_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,

@@ -201,6 +201,24 @@ class Plan:
                         q_used=rep.q_used, q_delta=rep.q_delta, sketch_ms=rep.sketch_ms)
         return U, S, V, info
 
+    def factor_noalloc(self, A, out=None, stream=None):
+        """rsvd_factor_noalloc: the library's static device workspace instead of
+        a caller buffer (dense A in device memory).  Returns (U, S, V, status);
+        no report."""
+        lda = _ld_row_major(A)
+        if A.dtype != self.dtype or tuple(A.shape) != (self.m, self.n) or not A.is_cuda:
+            raise ValueError("A must be a cuda tensor that matches the plan")
+        if out is None:
+            U = col_major(self.m, self.k, device=A.device)
+            S = torch.empty(self.k, dtype=torch.float64, device=A.device)
+            V = col_major(self.n, self.k, device=A.device)
+        else:
+            U, S, V = out
+        st = L.lib().rsvd_factor_noalloc(self.handle, _ptr(A), lda, _ptr(U), _ld_col_major(U),
+                                         _ptr(S), _ptr(V), _ld_col_major(V), _stream_ptr(stream))
+        L.check(st, self.handle)
+        return U, S, V, st
+
     def factor_resumable(self, A, stop_after=0, resume=None, save=True, ws=None, stream=None,
                          report=True):
         """rsvd_factor_resumable: returns (U, S, V, info, ckpt).  ``stop_after``

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -930,6 +931,32 @@ struct Runner {
   }
 };
 
+// Static workspace of rsvd_factor_noalloc (one copy per device, held until
+// the process ends).  Its device address per device, from
+// hipGetSymbolAddress; kMaxDevices bounds the device ordinals served.
+__device__ __align__(256) static char scratch[RSVD_NOALLOC_WS_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+rsvd_status scratch_ptr(rsvd_plan_t h, void** out) {
+  int dev = -1;
+  RSVD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_err(h, RSVD_E_UNSUPPORTED, "device ordinal " + std::to_string(dev) +
+                                              " is beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    RSVD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (((uintptr_t)p) & 255))
+      return set_err(h, RSVD_E_HIP, "static workspace address is NULL or not 256-byte aligned");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return RSVD_OK;
+}
+
 rsvd_status check_plan(rsvd_plan_t h) {
   if (!h) return set_err(nullptr, RSVD_E_INVALID_ARG, "plan is NULL");
   return RSVD_OK;
@@ -1210,6 +1237,30 @@ rsvd_status rsvd_factor(rsvd_plan_t h, const void* A, int64_t lda, void* ws, flo
   if (rsvd_status st = check_ws(h, ws)) return st;
   return factor_common(h, [&](Runner& R) { return R.bind_A(A, lda); }, ws, U, ldu, S, V, ldv,
                        stream, report);
+}
+
+// rsvd_factor_noalloc: the workspace is the library's own device array
+// `scratch` instead of a caller buffer.  Host code never passes the array's
+// name to a kernel (that is a host-side stand-in); the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current
+// and kept per device.  Every call on a device shares its array.
+rsvd_status rsvd_factor_noalloc(rsvd_plan_t h, const void* A, int64_t lda, float* U, int64_t ldu,
+                                double* S, float* V, int64_t ldv, void* stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  const rsvd::Plan& P = h->p;
+  if (P.csr) return set_err(h, RSVD_E_UNSUPPORTED, "rsvd_factor_noalloc takes dense A only");
+  if (P.host)
+    return set_err(h, RSVD_E_UNSUPPORTED, "rsvd_factor_noalloc needs A in device memory");
+  if (P.ws.total > RSVD_NOALLOC_WS_BYTES)
+    return set_err(h, RSVD_E_BUDGET,
+                   "the plan needs " + std::to_string(P.ws.total) +
+                       " bytes of workspace; the static workspace of rsvd_factor_noalloc holds " +
+                       std::to_string((unsigned long long)RSVD_NOALLOC_WS_BYTES));
+  if (rsvd_status st = check_A(h, A, lda)) return st;
+  void* ws = nullptr;
+  if (rsvd_status st = scratch_ptr(h, &ws)) return st;
+  return factor_common(h, [&](Runner& R) { return R.bind_A(A, lda); }, ws, U, ldu, S, V, ldv,
+                       stream, nullptr, nullptr, /*no_alloc=*/true);
 }
 
 rsvd_status rsvd_factor_csr(rsvd_plan_t h, const int32_t* rowptr, const int32_t* colind,

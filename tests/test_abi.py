@@ -182,3 +182,17 @@ def test_host_resident_plans_size_their_tile_slots_from_the_budget():
 def test_host_resident_plans_reject_other_precisions_and_the_adjoint():
     assert _host_plan_ws(0, prec=L.BF16)[0] == L.E_UNSUPPORTED
     assert _host_plan_ws(0, flags=L.FLAG_BACKWARD)[0] == L.E_UNSUPPORTED
+
+
+def test_noalloc_entry_point_refuses_plans_beyond_its_static_workspace():
+    # checked on the host before any device call: stand-in pointers are never touched
+    plan = Plan(50000, 20000, 100, 20, 2)
+    assert plan.ws_bytes > L.NOALLOC_WS_BYTES
+    fake = ctypes.c_void_p(256)
+    st = L.lib().rsvd_factor_noalloc(plan.handle, fake, 20000, fake, 50000, fake, fake, 20000, None)
+    assert st == L.E_BUDGET
+    msg = L.lib().rsvd_last_error(plan.handle).decode()
+    assert str(plan.ws_bytes) in msg and str(L.NOALLOC_WS_BYTES) in msg
+    sparse = Plan(1000, 800, 10, 6, 1, nnz=5000)
+    st = L.lib().rsvd_factor_noalloc(sparse.handle, fake, 800, fake, 1000, fake, fake, 800, None)
+    assert st == L.E_UNSUPPORTED
