@@ -30,6 +30,8 @@ sigma(A_q) = sigma(A)^(2q+1) with the same singular vectors (Section 2.2), and
 agreement of the "each" and "final_only" schedules on well-conditioned cases.
 """
 
+import time
+
 import numpy as np
 
 from . import philox
@@ -49,26 +51,51 @@ def _orth(Y):
     return Q
 
 
-def range_finder(A, l, q, seed, ortho="each"):
+class _Clock:
+    """Wall time per stage, recorded into `times` (a dict) when one is given;
+    it only reads the clock between the steps."""
+
+    def __init__(self, times):
+        self.times = times
+        self.t = time.perf_counter()
+
+    def lap(self, name):
+        if self.times is None:
+            return
+        now = time.perf_counter()
+        self.times[name] = self.times.get(name, 0.0) + (now - self.t)
+        self.t = now
+
+
+def range_finder(A, l, q, seed, ortho="each", times=None):
     """Orthonormal basis Q (m x l) of the range of (A A^T)^q A O.
 
     Section 2.1 steps 1-4 on the power matrix of Section 2.2 Eq. (2).
     A may be a dense FP64 array or any object with @ and .T (scipy sparse).
+    times: optional dict receiving the wall time of the stages (omega,
+    sketch, orth, power).
     """
     m, n = A.shape
+    clk = _Clock(times)
     O = philox.omega(seed, n, l)                 # step 1
+    clk.lap("omega")
     Y = np.asarray(A @ O, dtype=np.float64)      # step 2 (right-most product)
+    clk.lap("sketch")
     if ortho == "each":
         Q = _orth(Y)                             # steps 3-4
+        clk.lap("orth")
         for _ in range(q):                       # Eq. (2), right to left
             W = np.asarray(A.T @ Q, dtype=np.float64)
             Qw = _orth(W)
             Y = np.asarray(A @ Qw, dtype=np.float64)
             Q = _orth(Y)
+        clk.lap("power")
     elif ortho == "final_only":
         for _ in range(q):
             Y = np.asarray(A @ np.asarray(A.T @ Y, dtype=np.float64), dtype=np.float64)
+        clk.lap("power")
         Q = _orth(Y)
+        clk.lap("orth")
     else:
         raise ValueError("ortho must be 'each' or 'final_only'")
     return Q
@@ -97,22 +124,27 @@ def sign_fix(U, V):
     return U, V
 
 
-def rsvd(A, k, p, q, seed=0, ortho="each", signs=True, full=False):
+def rsvd(A, k, p, q, seed=0, ortho="each", signs=True, full=False, times=None):
     """Rank-k randomized SVD of A with oversampling p and q power steps.
 
     Returns dict with U (m x k), S (k,), V (n x k); with full=True also the
     range basis Q (m x l), B^T (n x l) and all l Ritz triplets
-    (Ul, Sl, Vl).
+    (Ul, Sl, Vl).  times: optional dict that receives the wall time of each
+    stage (omega, sketch, orth, power, projection, svd0, post), in seconds.
     """
     m, n = A.shape
     _check(m, n, k, p, q)
     l = k + p
-    Q = range_finder(A, l, q, seed, ortho=ortho)
+    Q = range_finder(A, l, q, seed, ortho=ortho, times=times)
+    clk = _Clock(times)
     Bt = np.asarray(A.T @ Q, dtype=np.float64)   # step 5 as B^T = A^T Q
+    clk.lap("projection")
     Ub, s, Vf = small_svd(Bt)                    # step 6
+    clk.lap("svd0")
     Ul = Q @ Ub                                  # step 7
     if signs:
         Ul, Vf = sign_fix(Ul, Vf)
+    clk.lap("post")
     out = {"U": Ul[:, :k].copy(), "S": s[:k].copy(), "V": Vf[:, :k].copy()}
     if full:
         out.update({"Q": Q, "Bt": Bt, "Ul": Ul, "Sl": s, "Vl": Vf})

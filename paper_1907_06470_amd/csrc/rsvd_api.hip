@@ -1479,7 +1479,6 @@ rsvd_status rsvd_backward(rsvd_plan_t h, const void* A, int64_t lda, const float
   const rsvd::Plan& P = h->p;
   const int64_t m = P.prob.m, n = P.prob.n, k = P.prob.k, l = P.l, lp = P.lp, kp = P.kp;
   if (!P.backward) return set_err(h, RSVD_E_INVALID_ARG, "plan was made without RSVD_FLAG_BACKWARD");
-  if (kp > 192) return set_err(h, RSVD_E_UNSUPPORTED, "backward needs k <= 192");
   if (!gA || ldga < n) return set_err(h, RSVD_E_INVALID_ARG, "gA is NULL or ldga < n");
   if ((gU && ldgu < m) || (gV && ldgv < n))
     return set_err(h, RSVD_E_INVALID_ARG, "ldgu < m or ldgv < n");

@@ -132,3 +132,35 @@ def test_residual_matches_direct_fp64():
     ref = metrics.residual_fro(A.double().numpy(), U.cpu().double().numpy(), S.cpu().numpy(),
                                V.cpu().double().numpy())
     assert abs(r - ref) <= 1e-5 * ref
+
+
+@pytest.mark.parametrize("precision,m,n,k,p,q", [
+    ("fp32", 8192, 4096, 128, 32, 3),   # widths of the mixed-precision workload (l = 160)
+    ("bf16", 8192, 4096, 128, 32, 3),
+    ("fp8", 8192, 4096, 128, 32, 3),
+    ("fp32", 3000, 2000, 200, 30, 2),   # wide sketch, l = 230
+])
+def test_closed_form_after_each_forward_form(precision, m, n, k, p, q):
+    """The closed form of sum(w s) + ||A - U S V^T||^2 holds exactly when
+    U^T A = S V^T.  The FP32 form meets that to rounding; the BF16 and FP8
+    forms only to their operand rounding (their Ritz triplets are those of
+    the rounded projection).  So the gradient is held to 1e-4 plus twice the
+    measured relative departure of U^T A from S V^T."""
+    dev = need_gpu()
+    sigma = workloads.spectrum_pow(min(m, n), 0.5)
+    A0 = workloads.dense_lowrank(m, n, sigma, 1e-4, seed=5, out_dtype=torch.float32)
+    w = torch.as_tensor(np.random.default_rng(7).uniform(0, 1, k), device=dev)
+    A = A0.to(dev).requires_grad_(True)
+    U, S, V = RSVD.apply(A, k, p, q, 0, precision)
+    R = A - (U * S.float()) @ V.T
+    L = (w * S).sum() + (R.double() ** 2).sum()
+    L.backward()
+    Un, Vn, An = U.detach().double().cpu().numpy(), V.detach().double().cpu().numpy(), A0.double().numpy()
+    Sn = S.detach().cpu().numpy()
+    ref = (Un * w.cpu().numpy()) @ Vn.T + 2.0 * (An - (An @ Vn) @ Vn.T)
+    err = rel(A.grad.double().cpu().numpy(), ref)
+    dep = float(np.linalg.norm(Un.T @ An - Sn[:, None] * Vn.T) / np.linalg.norm(Sn))
+    say(f"closed form {precision} {m}x{n} l={k + p}: rel err {err:.2e}, |U^T A - S V^T| / |S| {dep:.1e}")
+    assert err <= GRAD_TOL + 2.0 * dep
+    if precision == "fp32":
+        assert err <= GRAD_TOL
