@@ -352,15 +352,19 @@ def bench_backward(A, m, n, k, p, q, seed, tile, dev, args):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     ms = float(np.median(ts))
-    log(f"backward ({form} forward recomputed): {ms:.2f} ms, gA write {m * n * 4 / (ms * 1e-3) / 1e9:.0f} GB/s")
-    return {"form": form, "ms_median": ms, "gA_write_GBs": m * n * 4 / (ms * 1e-3) / 1e9,
+    lp, kp = -(-(k + p) // 32) * 32, -(-k // 32) * 32
+    outer_flops = 2.0 * m * n * (lp + 2 * kp)      # gA = [U_l | P2 | P3] [R1 | V_k | R3]^T
+    log(f"backward ({form} forward recomputed): {ms:.2f} ms; the gA outer product is "
+        f"{outer_flops:.3g} flop and {m * n * 4 / 1e9:.2f} GB written")
+    return {"form": form, "ms_median": ms, "gA_bytes": m * n * 4, "outer_flops": outer_flops,
             "_factors": (U, S, V), "_gA": gA, "_w": w}
 
 
 def closed_form_check(A, Ah, factors, gA, w, rows=256):
-    """The composed gradient of the loss above is exactly
-    gA = U diag(w) V^T + 2 A (I - V V^T) for rSVD factors (U^T A = S V^T); it
-    is checked on a seeded sample of rows in FP64 on the host."""
+    """The gradient of the loss above is the direct term 2 (A - U S V^T) plus
+    the adjoint's gA; for rSVD factors (U^T A = S V^T) the sum is exactly
+    U diag(w) V^T + 2 A (I - V V^T).  Checked on a seeded sample of rows in
+    FP64 on the host."""
     U, S, V = (x.cpu().double().numpy() for x in factors)
     wn = w.cpu().numpy()
     rng = np.random.default_rng(11)
@@ -368,6 +372,7 @@ def closed_form_check(A, Ah, factors, gA, w, rows=256):
     Ar = Ah[idx]
     ref = (U[idx] * wn) @ V.T + 2.0 * (Ar - (Ar @ V) @ V.T)
     got = gA[torch.as_tensor(idx, device=gA.device)].cpu().double().numpy()
+    got = got + 2.0 * (Ar - (U[idx] * S) @ V.T)
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     log(f"backward closed form on {len(idx)} rows: relative error {err:.2e}")
     return {"closed_form_rel_err": err, "closed_form_rows": int(len(idx))}

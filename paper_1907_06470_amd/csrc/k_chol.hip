@@ -676,7 +676,10 @@ bool chol_gm_fits(int64_t lp) { return lp > kTpMax && lp <= kGmMaxNb * kB && lp 
 
 hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, float* W, double* L,
                           int32_t* status, double tau, hipStream_t s) {
-  if (!chol_gm_fits(lp) || l > lp || l < 1 || !S || S == G || (!W && !L) || (L && L != S))
+  // the inverse is taken here only above the widths of the LDS kernels; the
+  // factor alone also for 128 < lp (the small SVD of widths 129 .. 192)
+  const bool fits = W ? chol_gm_fits(lp) : (lp > kSq && lp <= kGmMaxNb * kB && lp % kB == 0);
+  if (!fits || l > lp || l < 1 || !S || S == G || (!W && !L) || (L && L != S))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol_gm, dim3(1), dim3(kGmThreads), 0, s, G, lp, (int)l, S, W, L, status,
                      tau);

@@ -4,17 +4,14 @@
 //    (v_mfma_f64_16x16x4_f64), split over row chunks and summed in chunk
 //    order (deterministic).  Used by the QR of steps 3-4 (Section 2.1) as
 //    CholeskyQR, and for B B^T of step 6 ("SVD0 preparation", Section 4.1).
-//  * Cholesky G = L L^T (right-looking, one workgroup, packed triangle in
-//    LDS).  A pivot at or below tau times its original diagonal marks the
-//    direction as linearly dependent: its column is dropped (the basis gets a
-//    zero column and the direction is excluded from all later ones).
-//  * X = L^-1 column by column (one workgroup per column) and W = X^T, so that
-//    Q = Y W has orthonormal columns (R = L^T is the triangular QR factor).
+//  * Routing of the Cholesky factor and W = L^-T to the kernels of
+//    k_chol.hip (a pivot at or below tau times its original diagonal drops
+//    the direction: the basis gets a zero column).
 //  * Panel times small matrix on the FP32 matrix cores (Q = Y W, U = Q U_B,
 //    V = B^T U_B S^-1; step 7 of Section 2.1).
-//  * Cyclic Jacobi eigensolver for the symmetric B B^T (step 6), one
-//    workgroup, round-robin ordering of disjoint pairs, rotations logged and
-//    applied to the identity afterwards by a row-parallel kernel.
+//  * One-sided Jacobi on the Cholesky factor of B B^T (step 6) in one
+//    workgroup for sketch widths up to 128 (wider ones: k_bjacobi.hip), and
+//    the sort, scaling and sign convention that finish the small SVD.
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
@@ -25,17 +22,8 @@ namespace rsvd {
 namespace {
 
 constexpr int kMaxLp = 192;
-constexpr int kTri = kMaxLp * (kMaxLp + 1) / 2;
 
-__device__ inline int tidx(int i, int c) { return i * (i + 1) / 2 + c; }   // i >= c
 
-__device__ inline void tri_decode(int e, int& i, int& c) {
-  int ii = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
-  while (ii * (ii + 1) / 2 > e) --ii;
-  while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-  i = ii;
-  c = e - ii * (ii + 1) / 2;
-}
 
 
 __device__ inline f64x4 mfma64(double a, double b, f64x4 c) {
@@ -274,274 +262,6 @@ __global__ void k_gram_reduce(const double* __restrict__ gpart, int64_t chunks, 
   G[col * lp + row] = v;
 }
 
-// ------------------------------------------------------------ Cholesky ----
-// One workgroup: G = L L^T (right-looking, in LDS), X = L^-1 and W = X^T
-// written as FP32 (or L itself as FP64).  A pivot at or below tau times its
-// original diagonal (or not finite) drops the direction: its column of L and
-// its row and column of X are zero, so the basis Q = Y W gets a zero column
-// and the direction feeds no other column.  Widths up to 192 go to the
-// kernels of k_chol.hip; this one factors widths 129 .. 160 for the small SVD.
-constexpr int kCholThreads = 256;
-
-// Packed-triangle form for widths up to 160 (the packed triangle plus a
-// 32-row work panel fit in LDS).  Panels of 32
-// columns: one wave factors the diagonal block (no workgroup barriers inside),
-// all threads solve the rows below against it and update the trailing
-// triangle with register-blocked dot products.  The inverse proceeds by block
-// rows: one wave inverts the diagonal block while the others form
-// T_ij = sum_k L_ik X_kj, then X_ij = -X_ii T_ij.  Three barriers per block.
-constexpr int kCB = 32;                 // block edge
-constexpr int kBlkMaxLp = 160;
-constexpr int kBlkTri = kBlkMaxLp * (kBlkMaxLp + 1) / 2;
-
-__global__ __launch_bounds__(kCholThreads) void k_chol_inv_blocked(const double* __restrict__ G,
-                                                                   int64_t lp, int l,
-                                                                   float* __restrict__ W,
-                                                                   double* __restrict__ Lout,
-                                                                   int32_t* status, double tau) {
-  __shared__ double T[kBlkTri];
-  __shared__ double dinv[kBlkMaxLp];                 // 1 / L(j, j), 0 for dropped j
-  __shared__ double Trow[kCB * (kBlkMaxLp - kCB)];   // block-row work panel
-  __shared__ double Xd[kCB * kCB];                   // inverse of a diagonal block
-  __shared__ double d0[kBlkMaxLp];
-  __shared__ int ndrop, nbad;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tot = l * (l + 1) / 2;
-  for (int e = tid; e < tot; e += kCholThreads) {
-    int i, c;
-    tri_decode(e, i, c);
-    T[e] = G[(int64_t)i * lp + c];
-  }
-  for (int i = tid; i < l; i += kCholThreads) d0[i] = G[(int64_t)i * lp + i];
-  if (tid == 0) {
-    ndrop = 0;
-    nbad = 0;
-  }
-  lds_barrier();
-  const int nb = (l + kCB - 1) / kCB;
-
-  // ---- Cholesky, right-looking by panels
-  for (int kb = 0; kb < nb; ++kb) {
-    const int k0 = kb * kCB, k1 = min(l, k0 + kCB);
-    if (wave == 0) {
-      // diagonal block, one wave: lane r holds row k0 + r in registers; the
-      // scaled pivot column goes through LDS once per step
-      const int kw = k1 - k0;
-      double d[kCB];
-#pragma unroll
-      for (int q = 0; q < kCB; ++q)
-        d[q] = (lane < kw && q <= lane) ? T[tidx(k0 + lane, k0 + q)] : 0.0;
-#pragma unroll
-      for (int j = 0; j < kCB; ++j) {
-        if (j < kw) {
-          const double a = readlane_d(d[j], j);
-          const double o = d0[k0 + j];
-          const bool bad = !is_finite_d(a);
-          double piv = 0.0;
-          if (!bad && o > 0.0 && a > tau * o) piv = sqrt(a);
-          const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-          if (lane == j) d[j] = piv;
-          else if (lane > j) d[j] *= inv;
-          if (lane == 0) {
-            dinv[k0 + j] = inv;
-            if (bad) ++nbad;
-            else if (piv == 0.0) ++ndrop;
-          }
-          Xd[lane] = d[j];            // column j of L in this block (scratch)
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-          __builtin_amdgcn_wave_barrier();
-          if (piv > 0.0) {
-            double col[kCB];
-#pragma unroll
-            for (int c = j + 1; c < kCB; ++c) col[c] = Xd[c];
-#pragma unroll
-            for (int c = j + 1; c < kCB; ++c)
-              if (c <= lane) d[c] -= d[j] * col[c];
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kCB; ++q)
-        if (lane < kw && q <= lane) T[tidx(k0 + lane, k0 + q)] = d[q];
-    }
-    lds_barrier();
-    // rows below: L_ij = (A_ij - sum_{k0<=p<j} L_ip L_jp) / L_jj, one row per thread
-    for (int i = k1 + tid; i < l; i += kCholThreads) {
-      double r[kCB];
-#pragma unroll
-      for (int q = 0; q < kCB; ++q) r[q] = (k0 + q < k1) ? T[tidx(i, k0 + q)] : 0.0;
-#pragma unroll
-      for (int q = 0; q < kCB; ++q) {
-        const int j = k0 + q;
-        if (j < k1) {
-          double a0 = r[q], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-          const int jb = tidx(j, k0);
-#pragma unroll
-          for (int pq = 0; pq + 3 < q; pq += 4) {
-            a0 -= r[pq] * T[jb + pq];
-            a1 -= r[pq + 1] * T[jb + pq + 1];
-            a2 -= r[pq + 2] * T[jb + pq + 2];
-            a3 -= r[pq + 3] * T[jb + pq + 3];
-          }
-#pragma unroll
-          for (int pq = q & ~3; pq < q; ++pq) a0 -= r[pq] * T[jb + pq];
-          r[q] = ((a0 + a1) + (a2 + a3)) * dinv[j];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kCB; ++q)
-        if (k0 + q < k1) T[tidx(i, k0 + q)] = r[q];
-    }
-    lds_barrier();
-    // trailing update, 4 x 4 element blocks of the lower triangle
-    const int t0 = k1, nt = l - k1;
-    if (nt > 0) {
-      const int nbb = (nt + 3) / 4;
-      const int nblk = nbb * (nbb + 1) / 2;
-      for (int e = tid; e < nblk; e += kCholThreads) {
-        int bi, bc;
-        tri_decode(e, bi, bc);
-        double acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-        for (int q = k0; q < k1; ++q) {
-          double li[4], lc[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const int i = t0 + 4 * bi + a, c = t0 + 4 * bc + a;
-            li[a] = i < l ? T[tidx(i, q)] : 0.0;
-            lc[a] = c < l ? T[tidx(c, q)] : 0.0;
-          }
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += li[a] * lc[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int i = t0 + 4 * bi + a, c = t0 + 4 * bc + b;
-            if (i < l && c <= i) T[tidx(i, c)] -= acc[a][b];
-          }
-      }
-    }
-    lds_barrier();
-  }
-
-  if (Lout) {   // factor only: L (FP64, lp x lp row-major, zero above the diagonal)
-    for (int e = tid; e < lp * lp; e += kCholThreads) {
-      const int i = e / (int)lp, c = e % (int)lp;
-      Lout[e] = (i < l && c <= i) ? T[tidx(i, c)] : 0.0;
-    }
-    if (tid == 0) {
-      if (ndrop) atomicAdd(status + kStDropped, ndrop);
-      if (nbad) atomicAdd(status + kStNonFinite, nbad);
-    }
-    return;
-  }
-  // ---- X = L^-1 by block rows, in place
-  for (int ib = 0; ib < nb; ++ib) {
-    const int r0 = ib * kCB, r1 = min(l, r0 + kCB), rw = r1 - r0;
-    if (wave == 0) {
-      // X_ii = L_ii^-1: lane c < rw forward-substitutes column c
-      if (lane < rw) {
-        double x[kCB];
-#pragma unroll
-        for (int r = 0; r < kCB; ++r) {
-          double v = 0.0;
-          if (r < rw) {
-            const double ir = dinv[r0 + r];
-            if (ir > 0.0 && dinv[r0 + lane] > 0.0) {
-              double acc = (r == lane) ? 1.0 : 0.0;
-              const int rb = tidx(r0 + r, r0);
-#pragma unroll
-              for (int pq = 0; pq < r; ++pq) acc -= T[rb + pq] * x[pq];
-              v = acc * ir;
-            }
-          }
-          x[r] = v;
-        }
-#pragma unroll
-        for (int r = 0; r < kCB; ++r) Xd[r * kCB + lane] = x[r];
-      }
-    } else if (r0 > 0) {
-      // T_ij = sum_{c <= p < r0} L(r, p) X(p, c) for rows r of the block, columns
-      // c < r0; four columns per thread share the L(r, p) reads
-      const int c4n = (r0 + 3) / 4;
-      const int cnt = rw * c4n;
-      for (int e = tid - 64; e < cnt; e += kCholThreads - 64) {
-        const int rr = e / c4n, c0 = (e % c4n) * 4;
-        const int r = r0 + rr;
-        const int rb = tidx(r, 0);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int pq = c0; pq < r0; pq += 4) {
-          double lv[4], xv[4][4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int p = pq + e;
-            lv[e] = p < r0 ? T[rb + p] : 0.0;
-            const int pb = tidx(p, 0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) xv[e][u] = (p < r0 && c0 + u <= p) ? T[pb + c0 + u] : 0.0;
-          }
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += lv[e] * xv[e][u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (c0 + u < r0) Trow[rr * (kBlkMaxLp - kCB) + c0 + u] = acc[u];
-      }
-    }
-    lds_barrier();
-    // X_ij = -X_ii T_ij ; X_ii into place
-    {
-      const int c4n = (r0 + 3) / 4;
-      const int cnt = rw * c4n;
-      for (int e = tid; e < cnt; e += kCholThreads) {
-        const int rr = e / c4n, c0 = (e % c4n) * 4;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int q0 = 0; q0 <= rr; q0 += 4) {
-          double xv[4], tv[4][4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int q = q0 + e;
-            xv[e] = q <= rr ? Xd[rr * kCB + q] : 0.0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) tv[e][u] = q <= rr ? Trow[q * (kBlkMaxLp - kCB) + c0 + u] : 0.0;
-          }
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += xv[e] * tv[e][u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (c0 + u < r0) T[tidx(r0 + rr, c0 + u)] = -acc[u];
-      }
-      for (int e = tid; e < rw * kCB; e += kCholThreads) {
-        const int rr = e / kCB, c = e % kCB;
-        if (c <= rr) T[tidx(r0 + rr, r0 + c)] = Xd[rr * kCB + c];
-      }
-    }
-    lds_barrier();
-  }
-  for (int e = tid; e < lp * lp; e += kCholThreads) {
-    const int a = e / (int)lp, c = e % (int)lp;
-    W[e] = (c < l && a <= c) ? (float)T[tidx(c, a)] : 0.f;
-  }
-  if (tid == 0) {
-    if (ndrop) atomicAdd(status + kStDropped, ndrop);
-    if (nbad) atomicAdd(status + kStNonFinite, nbad);
-  }
-}
-
 // ------------------------------------------------------ panel x matrix ----
 // Accumulator tile of output column c for rows rbase .. rbase + 31 in the
 // 32 x 32 matrix-core layout (register 4 g + e holds row rbase + 8 g +
@@ -712,155 +432,6 @@ __global__ __launch_bounds__(kApThreads) void k_apply_staged(const float* __rest
         }
       }
     }
-  }
-}
-
-// --------------------------------------------------------------- Jacobi ----
-// Round-robin ("tournament") schedule: at round t, position x holds index
-// rr_pos(x, t); position 0 is fixed, the others rotate.  0 <= t < le - 1.
-__device__ inline int rr_pos(int x, int t, int le) {
-  if (x == 0) return 0;
-  int v = x - 1 + t;
-  if (v >= le - 1) v -= le - 1;
-  return 1 + v;
-}
-
-constexpr int kJacThreads = 1024;
-constexpr int kJacMaxBlocks = (kMaxLp / 2 * (kMaxLp / 2 + 1) / 2 + kJacThreads - 1) / kJacThreads;
-
-__global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int64_t lp,
-                                                        int l, double* __restrict__ rot,
-                                                        int64_t rot_rounds,
-                                                        double* __restrict__ lam, int32_t* status,
-                                                        double tol, int max_sweeps) {
-  __shared__ double T[kTri];
-  __shared__ double cc_s[kMaxLp / 2 + 1], ss_s[kMaxLp / 2 + 1];
-  __shared__ int pp_s[kMaxLp / 2 + 1], qq_s[kMaxLp / 2 + 1];
-  __shared__ int any_s, big_s;
-  const int tid = threadIdx.x;
-  const int le = l + (l & 1), np = le / 2, R = le - 1;
-  const int tot = l * (l + 1) / 2;
-  for (int e = tid; e < tot; e += kJacThreads) {
-    int i, c;
-    tri_decode(e, i, c);
-    T[e] = G[(int64_t)i * lp + c];
-  }
-  // Each thread owns the same 2 x 2 blocks (pair positions P1 >= P2) in every
-  // round; only the indices sitting at those positions change.
-  const int nb = np * (np + 1) / 2;
-  int P1[kJacMaxBlocks], P2[kJacMaxBlocks];
-#pragma unroll
-  for (int u = 0; u < kJacMaxBlocks; ++u) {
-    const int e = tid + u * kJacThreads;
-    int a = 0, b = 0;
-    if (e < nb) tri_decode(e, a, b);
-    P1[u] = a;
-    P2[u] = b;
-  }
-  lds_barrier();
-  int sweeps = 0;
-  int64_t ridx = 0;
-  for (int sw = 0; sw < max_sweeps && R > 0; ++sw) {
-    if (tid == 0) {
-      any_s = 0;
-      big_s = 0;
-    }
-    lds_barrier();
-    for (int t = 0; t < R; ++t) {
-      if (tid < np) {
-        const int a = rr_pos(tid, t, le), b = rr_pos(le - 1 - tid, t, le);
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0, s = 0.0;
-        if (q < l) {
-          const double app = T[tidx(p, p)], aqq = T[tidx(q, q)], apq = T[tidx(q, p)];
-          const double scale = sqrt(fabs(app * aqq));
-          if (apq != 0.0 && fabs(apq) > tol * scale) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-            any_s = 1;
-            if (fabs(apq) > 1e-10 * scale) big_s = 1;
-          }
-        }
-        pp_s[tid] = p;
-        qq_s[tid] = q;
-        cc_s[tid] = c;
-        ss_s[tid] = s;
-        if (ridx < rot_rounds) {   // the log stays in flight: barriers below order LDS only
-          rot[(ridx * np + tid) * 2 + 0] = c;
-          rot[(ridx * np + tid) * 2 + 1] = s;
-        }
-      }
-      lds_barrier();
-      // gather every owned block first, then rotate, then write back
-      int ax[kJacMaxBlocks], ay[kJacMaxBlocks], az[kJacMaxBlocks], aw[kJacMaxBlocks];
-      double vx[kJacMaxBlocks], vy[kJacMaxBlocks], vz[kJacMaxBlocks], vw[kJacMaxBlocks];
-#pragma unroll
-      for (int u = 0; u < kJacMaxBlocks; ++u) {
-        ax[u] = ay[u] = az[u] = aw[u] = -1;
-        if (tid + u * kJacThreads < nb) {
-          const int b1 = P1[u], b2 = P2[u];
-          const int p1 = pp_s[b1], q1 = qq_s[b1], p2 = pp_s[b2], q2 = qq_s[b2];
-          const double sa = ss_s[b1], sb = ss_s[b2];
-          const bool active = (b1 == b2) ? (q1 < l && sa != 0.0) : (sa != 0.0 || sb != 0.0);
-          if (active) {
-            auto idx = [&](int r, int cc) { return r >= cc ? tidx(r, cc) : tidx(cc, r); };
-            if (b1 == b2) {
-              ax[u] = tidx(p1, p1);
-              ay[u] = tidx(q1, p1);
-              aw[u] = tidx(q1, q1);
-            } else {
-              ax[u] = idx(p1, p2);
-              if (q2 < l) ay[u] = idx(p1, q2);
-              if (q1 < l) az[u] = idx(q1, p2);
-              if (q1 < l && q2 < l) aw[u] = idx(q1, q2);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kJacMaxBlocks; ++u) {
-        vx[u] = ax[u] >= 0 ? T[ax[u]] : 0.0;
-        vy[u] = ay[u] >= 0 ? T[ay[u]] : 0.0;
-        vz[u] = az[u] >= 0 ? T[az[u]] : 0.0;
-        vw[u] = aw[u] >= 0 ? T[aw[u]] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kJacMaxBlocks; ++u) {
-        if (ax[u] < 0) continue;
-        const double c1 = cc_s[P1[u]], s1 = ss_s[P1[u]];
-        if (P1[u] == P2[u]) {
-          // diagonal block: app, apq, aqq -> app - t apq, 0, aqq + t apq
-          const double tt = s1 / c1;
-          const double app = vx[u], apq = vy[u], aqq = vw[u];
-          T[ax[u]] = app - tt * apq;
-          T[ay[u]] = 0.0;
-          T[aw[u]] = aqq + tt * apq;
-        } else {
-          const double c2 = cc_s[P2[u]], s2 = ss_s[P2[u]];
-          const double x1 = c1 * vx[u] - s1 * vz[u], y1 = c1 * vy[u] - s1 * vw[u];
-          const double z1 = s1 * vx[u] + c1 * vz[u], w1 = s1 * vy[u] + c1 * vw[u];
-          T[ax[u]] = c2 * x1 - s2 * y1;
-          if (ay[u] >= 0) T[ay[u]] = s2 * x1 + c2 * y1;
-          if (az[u] >= 0) T[az[u]] = c2 * z1 - s2 * w1;
-          if (aw[u] >= 0) T[aw[u]] = s2 * z1 + c2 * w1;
-        }
-      }
-      lds_barrier();
-      ++ridx;
-    }
-    ++sweeps;
-    const int any = any_s, big = big_s;
-    lds_barrier();
-    // every rotation of this sweep was below 1e-10 of its pair's scale: the
-    // quadratic convergence leaves nothing above tol for another sweep
-    if (!any || !big) break;
-  }
-  for (int i = tid; i < lp; i += kJacThreads) lam[i] = i < l ? T[tidx(i, i)] : 0.0;
-  if (tid == 0) {
-    status[kStSweeps] = sweeps;
-    status[kStRounds] = (int32_t)min(ridx, rot_rounds);
   }
 }
 
@@ -1135,65 +706,6 @@ __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict
   }
 }
 
-// Ev = I J_1 J_2 ... : rows are independent, one wave per row (16 rows per
-// workgroup).  Within a round the lanes of a wave rotate disjoint pairs of
-// their row, so rounds need no workgroup barrier; the rotation log is staged
-// through LDS in chunks of rounds, the next chunk prefetched into registers.
-constexpr int kVecRows = 16;
-constexpr int kVecChunk = 64;
-constexpr int kVecPer = (kVecChunk * (kMaxLp / 2 + 1) * 2 + kVecRows * 64 - 1) / (kVecRows * 64);
-__global__ __launch_bounds__(kVecRows * 64) void k_jacobi_vecs(const double* __restrict__ rot,
-                                                              const int32_t* __restrict__ status,
-                                                              int64_t lp, int l,
-                                                              double* __restrict__ Ev) {
-  __shared__ double rowv[kVecRows][kMaxLp + 2];
-  __shared__ double cs[kVecChunk * (kMaxLp / 2 + 1) * 2];
-  const int le = l + (l & 1), np = le / 2, R = le - 1;
-  const int64_t rounds = status[kStRounds];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int r = blockIdx.x * kVecRows + w;
-  for (int x = lane; x < kMaxLp + 2; x += 64) rowv[w][x] = (x == r) ? 1.0 : 0.0;
-  double pre[kVecPer];
-  auto fetch = [&](int64_t t0) {
-    const int64_t nr = min((int64_t)kVecChunk, rounds - t0);
-    const int64_t cnt = nr * np * 2;
-#pragma unroll
-    for (int u = 0; u < kVecPer; ++u) {
-      const int64_t idx = tid + (int64_t)u * kVecRows * 64;
-      pre[u] = idx < cnt ? rot[t0 * np * 2 + idx] : 0.0;
-    }
-  };
-  if (rounds > 0) fetch(0);
-  for (int64_t t0 = 0; t0 < rounds; t0 += kVecChunk) {
-    const int nr = (int)min((int64_t)kVecChunk, rounds - t0);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kVecPer; ++u) {
-      const int idx = tid + u * kVecRows * 64;
-      if (idx < nr * np * 2) cs[idx] = pre[u];
-    }
-    __syncthreads();
-    if (t0 + kVecChunk < rounds) fetch(t0 + kVecChunk);
-    int tr = (int)(t0 % R);
-    for (int tt = 0; tt < nr; ++tt, tr = (tr + 1 == R) ? 0 : tr + 1) {
-      for (int i = lane; i < np; i += 64) {
-        const double c = cs[(tt * np + i) * 2], s = cs[(tt * np + i) * 2 + 1];
-        if (s != 0.0) {
-          const int a = rr_pos(i, tr, le), b = rr_pos(le - 1 - i, tr, le);
-          const int p = min(a, b), q = max(a, b);
-          const double vp = rowv[w][p], vq = rowv[w][q];
-          rowv[w][p] = c * vp - s * vq;
-          rowv[w][q] = s * vp + c * vq;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  if (r < lp)
-    for (int x = lane; x < lp; x += 64) Ev[(int64_t)r * lp + x] = (r < l && x < l) ? rowv[w][x] : 0.0;
-}
-
 // Automatic iteration parameter: largest relative change of the k leading
 // singular values from the previous power step (prev[k] receives it; +inf on
 // the first step), then prev = S.
@@ -1416,9 +928,7 @@ hipError_t launch_chol_inv(const double* G, int64_t lp, int64_t l, float* W, int
   if (lp > kMaxLp) return hipErrorInvalidValue;
   if (chol16_fits(lp)) return launch_chol16(G, lp, l, W, nullptr, status, tau, s);
   if (chol_tp_fits(lp)) return launch_chol_tp(G, lp, l, W, status, tau, s);
-  hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l, W,
-                     (double*)nullptr, status, tau);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 namespace {
@@ -1503,12 +1013,8 @@ bool small_svd_one_sided(int64_t lp) { return lp <= kOjMaxLp; }
 
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
                               double tau, hipStream_t s) {
-  if (chol_gm_fits(lp)) return launch_chol_gm(G, lp, l, L, nullptr, L, status, tau, s);
-  if (lp > kBlkMaxLp) return hipErrorInvalidValue;
   if (chol16_fits(lp)) return launch_chol16(G, lp, l, nullptr, L, status, tau, s);
-  hipLaunchKernelGGL(k_chol_inv_blocked, dim3(1), dim3(kCholThreads), 0, s, G, lp, (int)l,
-                     (float*)nullptr, L, status, tau);
-  return hipGetLastError();
+  return launch_chol_gm(G, lp, l, L, nullptr, L, status, tau, s);
 }
 
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
@@ -1516,22 +1022,6 @@ hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, d
   if (lp > kOjMaxLp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ojacobi, dim3(1), dim3(kOjThreads), 0, s, L, lp, (int)l, lam, Ev, status,
                      tol, max_sweeps);
-  return hipGetLastError();
-}
-
-hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
-                         double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s) {
-  if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), 0, s, G, lp, (int)l, rot, rot_rounds,
-                     lam, status, tol, max_sweeps);
-  return hipGetLastError();
-}
-
-hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
-                              double* Ev, hipStream_t s) {
-  if (lp > kMaxLp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi_vecs, dim3((unsigned)ceil_div_dev(lp, kVecRows)),
-                     dim3(kVecRows * 64), 0, s, rot, status, lp, (int)l, Ev);
   return hipGetLastError();
 }
 

@@ -127,12 +127,12 @@ hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, doubl
 bool chol_tp_fits(int64_t lp);
 hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
                           double tau, hipStream_t s);
-// Cholesky factor (into L = S) or W = L^-T for 192 < lp <= 512, the square in
-// the global scratch S (lp x lp FP64, not aliasing G; k_chol.hip).
+// Cholesky factor (into L = S; 128 < lp <= 512) or W = L^-T (192 < lp <= 512),
+// the square in the global scratch S (lp x lp FP64, not aliasing G; k_chol.hip).
 bool chol_gm_fits(int64_t lp);
 hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, float* W, double* L,
                           int32_t* status, double tau, hipStream_t s);
-// Small SVD of wide sketches (lp <= 512): block one-sided Jacobi on the
+// Small SVD of sketches wider than 128 (lp <= 512): block one-sided Jacobi on the
 // Cholesky factor L (FP64 row-major lp x lp) of C; M (lp x lp FP64) and ctl
 // (kBjMaxSweeps int32) are scratch.  Writes lam (|m_c|^2) and Ev (row-major)
 // as launch_ojacobi does (k_bjacobi.hip).
@@ -141,17 +141,14 @@ hipError_t launch_bjacobi(const double* L, int64_t lp, int64_t l, double* M, int
                           double* lam, double* Ev, int32_t* status, double tol, hipStream_t s);
 // Automatic q: prev[k] = max_i<k |S_i - prev_i| / S_i (+inf if first), prev = S.
 hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* prev, hipStream_t s);
-// Small SVD through the Cholesky factor of C and one-sided Jacobi (lp <= 128).
+// Small SVD through the Cholesky factor of C and one-sided Jacobi in one
+// workgroup (lp <= 128); wider sketches take launch_bjacobi.
 bool small_svd_one_sided(int64_t lp);
 // L (lp x lp FP64 row-major, distinct from G) with G = L L^T.
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
                               double tau, hipStream_t s);
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
                           int32_t* status, double tol, int max_sweeps, hipStream_t s);
-hipError_t launch_jacobi(const double* G, int64_t lp, int64_t l, double* rot, int64_t rot_rounds,
-                         double* lam, int32_t* status, double tol, int max_sweeps, hipStream_t s);
-hipError_t launch_jacobi_vecs(const double* rot, const int32_t* status, int64_t lp, int64_t l,
-                              double* Ev, hipStream_t s);
 // sort eigenvalues, form S (k values), Wu = Ev(:, order(0:k)), Wv = Wu / sigma
 hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, int64_t l,
                                int64_t k, double* S, float* Wu, float* Wv, int32_t* order,

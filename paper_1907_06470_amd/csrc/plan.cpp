@@ -174,12 +174,6 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     p.gram_rows = std::max<int64_t>(256, round_up(ceil_div(rows, chunks), 64));
     p.gram_chunks = gram_chunks_for(p, rows);
   }
-  // Jacobi rotation log: rounds per sweep = (even width) - 1
-  {
-    int64_t le = p.l + (p.l & 1);
-    p.rot_rounds = (int64_t)kJacobiMaxSweeps * std::max<int64_t>(1, le - 1);
-  }
-
   // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -224,15 +218,12 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.W = take(lp * lp * 4);
   w.W2 = take(lp * lp * 4);
   w.Ev = take(lp * lp * 8);
-  const bool wide = p.lp > kSliceMax;
-  w.Mj = wide ? take(lp * lp * 8) : off;
-  w.bjctl = wide ? take((size_t)kBjMaxSweeps * 4) : off;
+  const bool bj = p.lp > 128, wide = p.lp > kSliceMax;   // block Jacobi; Cholesky in global memory
+  w.Mj = bj ? take(lp * lp * 8) : off;
+  w.bjctl = bj ? take((size_t)kBjMaxSweeps * 4) : off;
   w.Ls2 = wide ? take(lp * lp * 8) : off;
   w.lam = take(lp * 8);
   w.order = take(lp * 4);
-  // the rotation log of the two-sided Jacobi (widths 129 .. 192 only)
-  const bool two_sided = p.lp > 128 && p.lp <= kSliceMax;
-  w.rot = take(two_sided ? (size_t)p.rot_rounds * (lp / 2 + 1) * 2 * 8 : 8);
   w.signs = take(lp * 4);
   w.status = take(kStatusWords * 4);
   w.prevS = take((size_t)k * 8 + 8);

@@ -61,12 +61,11 @@ struct Workspace {
   size_t Wpm, Wpn;        // lp x lp FP32 pending right factors of the m- and n-side bases
   size_t Wc;              // lp x lp FP32 product of a pending factor and a first-pass factor
   size_t Ev;              // lp x lp FP64 eigenvectors
-  size_t Mj;              // lp x lp FP64 columns of the block Jacobi (widths > 192)
+  size_t Mj;              // lp x lp FP64 columns of the block Jacobi (widths > 128)
   size_t bjctl;           // kBjMaxSweeps int32 sweep flags of the block Jacobi
   size_t Ls2;             // lp x lp FP64 Cholesky scratch of the side stream (widths > 192)
   size_t lam;             // lp FP64 eigenvalues / singular values
   size_t order;           // lp int32 sort order
-  size_t rot;             // Jacobi rotation log (FP64 pairs)
   size_t signs;           // k int32 sign-fix argmax
   size_t status;          // kStatusWords int32
   size_t prevS;           // automatic q: previous k singular values + change
@@ -106,7 +105,6 @@ struct Plan {
   bool any_f32 = false;         // some product runs in FP32
   int64_t gram_rows = 0;        // rows per Gram chunk
   int64_t gram_chunks = 0;      // max chunks over the m- and n-side panels
-  int64_t rot_rounds = 0;       // capacity of the rotation log (rounds)
   int64_t kp = 0;               // k rounded up to 32 (backward)
   int64_t rcat = 0;             // columns of the outer-product factors
   bool backward = false;

@@ -159,7 +159,7 @@ struct Buffers {
   float* coo_val;
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
-  double *gpart, *G, *L, *Ev, *lam, *rot, *Mj, *Ls2;
+  double *gpart, *G, *L, *Ev, *lam, *Mj, *Ls2;
   int32_t* bjctl;
   double *gpart2, *G2, *Tc;
   float *Wpm, *Wpn, *Wc;
@@ -233,7 +233,6 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.Ls2 = (double*)(b + w.Ls2);
   B.bjctl = (int32_t*)(b + w.bjctl);
   B.lam = (double*)(b + w.lam);
-  B.rot = (double*)(b + w.rot);
   B.order = (int32_t*)(b + w.order);
   B.signs = (int32_t*)(b + w.signs);
   B.status = (int32_t*)(b + w.status);
@@ -902,23 +901,16 @@ struct Runner {
     return RSVD_OK;
   }
   rsvd_status small_svd_solve(double* S, int64_t kout) {
-    if (P.lp > rsvd::kSliceMax) {
-      // wide sketches: C = L L^T, then block one-sided Jacobi on L over
-      // several workgroups (no drop, as below)
-      RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
-      RSVD_HIP(rsvd::launch_bjacobi(B.L, P.lp, P.l, B.Mj, B.bjctl, B.lam, B.Ev, B.status,
-                                    kJacobiTol, s));
-    } else if (rsvd::small_svd_one_sided(P.lp)) {
-      // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
-      // positive pivot; exactly dependent directions give zero columns)
-      RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
+    // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
+    // positive pivot; exactly dependent directions give zero columns): in one
+    // workgroup up to width 128, over many workgroups (block Jacobi) beyond
+    RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
+    if (rsvd::small_svd_one_sided(P.lp))
       RSVD_HIP(rsvd::launch_ojacobi(B.L, P.lp, P.l, B.lam, B.Ev, B.status, kJacobiTol,
                                     rsvd::kJacobiMaxSweeps, s));
-    } else {
-      RSVD_HIP(rsvd::launch_jacobi(gsmall, P.lp, P.l, B.rot, P.rot_rounds, B.lam, B.status,
-                                   kJacobiTol, rsvd::kJacobiMaxSweeps, s));
-      RSVD_HIP(rsvd::launch_jacobi_vecs(B.rot, B.status, P.lp, P.l, B.Ev, s));
-    }
+    else
+      RSVD_HIP(rsvd::launch_bjacobi(B.L, P.lp, P.l, B.Mj, B.bjctl, B.lam, B.Ev, B.status,
+                                    kJacobiTol, s));
     RSVD_HIP(rsvd::launch_finish_small(B.lam, B.Ev, P.lp, P.l, kout, S, B.W, B.W2, B.order,
                                        B.status, s));
     if (pend[0]) {   // U = Q1 (Wp U_B), V = Bt (Wp U_B S^-1)
