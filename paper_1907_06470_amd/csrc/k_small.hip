@@ -201,6 +201,118 @@ __global__ __launch_bounds__(256) void k_gram_tri(const float* __restrict__ P, i
   }
 }
 
+// Lower-triangle Gram for wider panels (lp > 192): the lp columns are cut
+// into slices of 128 (8 blocks of 16; the last may have 2, 4 or 6), and one
+// launch forms the tiles of one slice pair (s, t), s >= t: the lower
+// triangle of slice s with itself (DIAG) or the NA x NB rectangle of slice s
+// against slice t.  The inner loop is that of k_gram_tri, with the two
+// slices' columns staged side by side; tiles are stored at their places in
+// the whole lower triangle, so k_gram_tri_reduce sums them as for k_gram_tri.
+// Each slice pair reads its slices of the panel once: nS slice pairs per
+// slice, i.e. the panel nS times for nS slices (3 at width 352).
+template <int NA, int NB, bool DIAG, int W>
+__device__ inline void gram_grp_wave(const float* __restrict__ P, int64_t ld, int64_t r0,
+                                     int64_t r1, int ca, int cb, int ia, int ib,
+                                     double* __restrict__ out, float* T) {
+  constexpr int NC = DIAG ? NA : NA + NB;              // staged 16-column blocks
+  constexpr int NT = DIAG ? NA * (NA + 1) / 2 : NA * NB;
+  constexpr int NACC = (NT + 3 - W) / 4 > 0 ? (NT + 3 - W) / 4 : 1;
+  constexpr int NQ = 16 * NC * (kGtSlab / 4) / 256;    // float4 loads per thread per slab
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i16 = lane & 15, kq = lane >> 4;
+  f64x4 acc[NACC];
+#pragma unroll
+  for (int a = 0; a < NACC; ++a) acc[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+  float4 pre[NQ];
+  auto gload = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int idx = tid + 256 * u, c = idx / (kGtSlab / 4), q = idx % (kGtSlab / 4);
+      const int gc = c < 16 * NA ? ca + c : cb + (c - 16 * NA);
+      const int64_t i = rb + 4 * q;
+      pre[u] = i < r1 ? ld4_masked(P + (int64_t)gc * ld, i, r1) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  if (r0 < r1) gload(r0);
+  for (int64_t rb = r0; rb < r1; rb += kGtSlab) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int idx = tid + 256 * u, c = idx / (kGtSlab / 4), q = idx % (kGtSlab / 4);
+      *reinterpret_cast<float4*>(&T[c * kGtLd + 4 * q]) = pre[u];
+    }
+    __syncthreads();
+    if (rb + kGtSlab < r1) gload(rb + kGtSlab);
+    const int ng = (int)min<int64_t>(kGtSlab / 16, (r1 - rb + 15) / 16);
+#pragma unroll
+    for (int g = 0; g < kGtSlab / 16; ++g) {
+      if (g < ng) {
+        float4 v[NC];
+#pragma unroll
+        for (int b = 0; b < NC; ++b)
+          v[b] = *reinterpret_cast<const float4*>(&T[(b * 16 + i16) * kGtLd + g * 16 + 4 * kq]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          double d[NC];
+#pragma unroll
+          for (int b = 0; b < NC; ++b) d[b] = (double)v[b][s];
+          if constexpr (DIAG) {
+#pragma unroll
+            for (int I = 0, t = 0; I < NA; ++I)
+#pragma unroll
+              for (int J = 0; J <= I; ++J, ++t)
+                if ((t & 3) == W) acc[t >> 2] = mfma64(d[I], d[J], acc[t >> 2]);
+          } else {
+#pragma unroll
+            for (int I = 0, t = 0; I < NA; ++I)
+#pragma unroll
+              for (int J = 0; J < NB; ++J, ++t)
+                if ((t & 3) == W) acc[t >> 2] = mfma64(d[I], d[NA + J], acc[t >> 2]);
+          }
+        }
+      }
+    }
+  }
+  // local tile t -> its place I (I + 1) / 2 + J in the whole lower triangle
+#pragma unroll
+  for (int t = W; t < NT; t += 4) {
+    int I, J;
+    if constexpr (DIAG) {
+      I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      J = t - I * (I + 1) / 2;
+      I += ia;
+      J += ia;
+    } else {
+      I = ia + t / NB;
+      J = ib + t % NB;
+    }
+    const int tg = I * (I + 1) / 2 + J;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[tg * 256 + (kq + 4 * r) * 16 + i16] = acc[t >> 2][r];
+  }
+}
+
+// One slice pair over one row chunk per workgroup; gpart as for k_gram_tri
+// (ntile = the tiles of the whole lower triangle).
+template <int NA, int NB, bool DIAG>
+__global__ __launch_bounds__(256) void k_gram_grp(const float* __restrict__ P, int64_t ld,
+                                                  int64_t rows, int64_t chunk_rows, int ca, int cb,
+                                                  int ia, int ib, int ntile,
+                                                  double* __restrict__ gpart) {
+  constexpr int NC = DIAG ? NA : NA + NB;
+  __shared__ __attribute__((aligned(16))) float T[16 * NC * kGtLd];
+  const int64_t r0 = (int64_t)blockIdx.x * chunk_rows;
+  const int64_t r1 = min(rows, r0 + chunk_rows);
+  double* out = gpart + (int64_t)blockIdx.x * ntile * 256;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: gram_grp_wave<NA, NB, DIAG, 0>(P, ld, r0, r1, ca, cb, ia, ib, out, T); break;
+    case 1: gram_grp_wave<NA, NB, DIAG, 1>(P, ld, r0, r1, ca, cb, ia, ib, out, T); break;
+    case 2: gram_grp_wave<NA, NB, DIAG, 2>(P, ld, r0, r1, ca, cb, ia, ib, out, T); break;
+    default: gram_grp_wave<NA, NB, DIAG, 3>(P, ld, r0, r1, ca, cb, ia, ib, out, T); break;
+  }
+}
+
 // G (lp x lp, full symmetric) from the k_gram_tri partials: 16 threads per
 // element, thread j summing chunks j, j + 16, ... in order, then the 16
 // partial sums in a fixed tree (deterministic).
@@ -888,6 +1000,42 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
 
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,
                        int64_t chunks, double* gpart, double* G, hipStream_t s) {
+  if (gram_grp_fits(lp) && (ld % 4) == 0 && (((uintptr_t)P) & 15) == 0) {
+    const int64_t crow = gram_tri_chunk_rows(rows);
+    const int64_t nch = ceil_div_dev(rows, crow);
+    const int nbk = (int)(lp / 16), ntile = nbk * (nbk + 1) / 2;
+    const int nsl = (nbk + 7) / 8;
+    for (int sa = 0; sa < nsl; ++sa) {
+      const int na = min(8, nbk - 8 * sa);
+      for (int sb = 0; sb <= sa; ++sb) {
+        const int ia = 8 * sa, ib = 8 * sb;
+#define GG(A, B, D)                                                                          \
+  hipLaunchKernelGGL((k_gram_grp<A, B, D>), dim3((unsigned)nch), dim3(256), 0, s, P, ld, rows, \
+                     crow, 16 * ia, 16 * ib, ia, ib, ntile, gpart)
+        if (sa == sb) {
+          switch (na) {
+            case 2: GG(2, 1, true); break;
+            case 4: GG(4, 1, true); break;
+            case 6: GG(6, 1, true); break;
+            default: GG(8, 1, true); break;
+          }
+        } else {
+          switch (na) {
+            case 2: GG(2, 8, false); break;
+            case 4: GG(4, 8, false); break;
+            case 6: GG(6, 8, false); break;
+            default: GG(8, 8, false); break;
+          }
+        }
+#undef GG
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
+    hipLaunchKernelGGL(k_gram_tri_reduce, dim3((unsigned)ceil_div_dev((int64_t)ntile * 256, 16)),
+                       dim3(256), 0, s, gpart, nch, ntile, lp, G);
+    return hipGetLastError();
+  }
   if (gram_tri_fits(lp) && (ld % 4) == 0 && (((uintptr_t)P) & 15) == 0) {
     const int64_t crow = gram_tri_chunk_rows(rows);
     const int64_t nch = ceil_div_dev(rows, crow);

@@ -204,7 +204,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     // also holds the 2048 partial sums of the accuracy pass
     size_t gbytes = std::max<size_t>((size_t)p.gram_chunks * blocks * kGramBlock * kGramBlock * 8,
                                      2048 * 8);
-    if (gram_tri_fits(p.lp)) gbytes = std::max(gbytes, gram_tri_bytes(p.lp));
+    if (gram_tri_fits(p.lp) || gram_grp_fits(p.lp)) gbytes = std::max(gbytes, gram_tri_bytes(p.lp));
     w.gpart = take(gbytes);
     w.gpart2 = take(gbytes);
   }

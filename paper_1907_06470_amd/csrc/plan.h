@@ -141,6 +141,8 @@ inline bool gram_tri_fits(int64_t lp) { return lp <= 192 && lp % 32 == 0; }
 inline int64_t gram_tri_chunk_rows(int64_t rows) {
   return round_up(ceil_div(rows < 1 ? 1 : rows, kGramTriChunks), 4);
 }
+// Wider panels: the same partial tiles, formed per pair of 128-column slices.
+inline bool gram_grp_fits(int64_t lp) { return lp > 192 && lp <= kWideMax && lp % 32 == 0; }
 inline size_t gram_tri_bytes(int64_t lp) {
   const int64_t nbk = lp / 16;
   return (size_t)kGramTriChunks * (size_t)(nbk * (nbk + 1) / 2) * 256 * 8;
