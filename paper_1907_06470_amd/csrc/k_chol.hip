@@ -2,8 +2,8 @@
 // CholeskyQR pass (steps 1-3 of the orthonormalisation: G = Y^T Y = L L^T,
 // Q = Y L^-T), in one workgroup: k_chol16 for sketch widths up to 128 (below),
 // k_chol_tp for widths up to 192 (the same steps on the lower tiles only,
-// further down), k_chol_gm for widths up to 512 (the same steps on a square
-// in global memory, at the end).
+// further down), and for widths up to 512 the same steps on a square in
+// global memory over several launches (at the end).
 //
 // The whole matrix sits in LDS as a 128 x 128 square of doubles whose rows are
 // XOR-swizzled in groups of 16 (element (i, c) at i * 128 + (c ^ (i & 15))),
@@ -29,6 +29,8 @@
 // A pivot a_jj <= tau * G_jj (or a non-positive original diagonal) drops the
 // direction: column j of L and row and column j of X become zero, so the
 // matching column of Q is zero; non-finite pivots are counted separately.
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
@@ -498,160 +500,185 @@ __global__ __launch_bounds__(kThreads) void k_chol_tp(const double* __restrict__
 }
 
 
-// ---- widths 193 .. 512: the square in global memory ----------------------
+// ---- widths 129 .. 512: blocked factorisation over several launches -------
 // The steps of k_chol16 on an lp x lp FP64 square in a global scratch buffer
 // (row-major, element (i, c) at S[i * lp + c]; at most 2 MiB, so it stays in
-// the L2 cache), with more waves for the many trailing tiles of a wide matrix.
-// Only the diagonal inverses X_kk (and the pivots) are in LDS.  The
-// off-diagonal blocks of X are stored transposed in the upper triangle, as in
-// k_chol16.  Waves exchange data through global memory, so every phase ends
-// with a full workgroup barrier (__syncthreads orders global memory within a
-// workgroup); wave 0 reads the diagonal tile it has just updated after a
-// fence on its own stores.
-constexpr int kGmThreads = 256;
-constexpr int kGmWaves = kGmThreads / 64;
-constexpr int kGmMaxNb = 32;   // widths up to 512
+// the L2 cache), one launch per phase so that the many trailing tiles of a
+// wide matrix are spread over the device:
+//   * k_cg_panel(kb): every workgroup factors diagonal block kb (one wave,
+//     registers; the same values in each) and forms up to four panel tiles
+//     L_Ik = A_Ik X_kk^T; workgroup 0 keeps L_kk and X_kk in the side area;
+//   * k_cg_update(kb): one wave per trailing tile, A_IJ -= L_Ik L_Jk^T;
+//   * k_cg_inverse: workgroup J forms block column J of X = L^-1 in LDS,
+//     X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ for I = J + 1, ... (the sum
+//     split over four waves and added in wave order), and writes rows
+//     16 J .. 16 J + 15 of W = X^T;
+//   * k_cg_lout (factor only): L with its diagonal blocks and zeros above.
+// Scratch: S (lp x lp), then the side area: X_kk and L_kk of every diagonal
+// block and the original diagonal (chol_gm_scratch_doubles).
+constexpr int kGmMaxNb = (int)(kWideMax / 16);   // diagonal blocks: widths up to 512
+constexpr int kCgThreads = 256;
 
 __device__ inline int64_t gidx(int64_t ld, int i, int c) { return (int64_t)i * ld + c; }
 
-__device__ void gm_diag_block(double* S, int64_t ld, double* Xd, double* dinv, const double* d0,
-                              int kb, int l, double tau, int& ndrop, int& nbad) {
-  const int lane = threadIdx.x & 63, r = lane & 15;
+struct CgSide {
+  double* xd;   // X_kk of block kb at xd[kb * 256 + xq(i, r)]
+  double* ld;   // L_kk of block kb at ld[kb * 256 + r * 16 + p], p <= r
+  double* d0;   // original diagonal
+};
+__device__ inline CgSide cg_side(double* S, int64_t lp) {
+  double* b = S + lp * lp;
+  return {b, b + kGmMaxNb * kB * kB, b + 2 * kGmMaxNb * kB * kB};
+}
+
+__global__ void k_cg_init(const double* __restrict__ G, int64_t lp, int l, double* __restrict__ S) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const CgSide sd = cg_side(S, lp);
+  if (t < lp * lp) {
+    const int i = (int)(t / lp), c = (int)(t % lp);
+    S[t] = (i < l && c < l) ? G[t] : 0.0;
+  }
+  if (t < kGmMaxNb * kB) sd.d0[t] = t < l ? G[t * lp + t] : 0.0;
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_panel(double* __restrict__ S, int64_t lp,
+                                                         int kb, int nb, int l,
+                                                         int32_t* __restrict__ status, double tau) {
+  __shared__ double Xs[kB * kB];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15;
+  const CgSide sd = cg_side(S, lp);
   const int g0 = kb * kB;
-  double d[kB], x[kB], dv;
+  if (wave == 0) {
+    double d[kB], x[kB], dv;
 #pragma unroll
-  for (int p = 0; p < kB; ++p) {
-    const double v = S[gidx(ld, g0 + r, g0 + p)];
-    d[p] = p <= r ? v : 0.0;
+    for (int p = 0; p < kB; ++p) {
+      const double v = S[gidx(lp, g0 + r, g0 + p)];
+      d[p] = p <= r ? v : 0.0;
+    }
+    int ndrop = 0, nbad = 0;
+    diag_factor(d, sd.d0[g0 + r], g0, l, tau, ndrop, nbad, dv, x);
+    if (lane < kB) {
+#pragma unroll
+      for (int i = 0; i < kB; ++i) Xs[xq(i, r)] = x[i];
+      if (blockIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kB; ++i) sd.xd[kb * kB * kB + xq(i, r)] = x[i];
+#pragma unroll
+        for (int p = 0; p < kB; ++p) sd.ld[kb * kB * kB + r * kB + p] = d[p];
+      }
+    }
+    if (blockIdx.x == 0 && lane == 0) {
+      if (ndrop) atomicAdd(status + kStDropped, ndrop);
+      if (nbad) atomicAdd(status + kStNonFinite, nbad);
+    }
   }
-  diag_factor(d, d0[g0 + r], g0, l, tau, ndrop, nbad, dv, x);
-  if (lane < kB) {
-#pragma unroll
-    for (int p = 0; p < kB; ++p) S[gidx(ld, g0 + r, g0 + p)] = d[p];
-    dinv[g0 + r] = dv;
-#pragma unroll
-    for (int i = 0; i < kB; ++i) Xd[kb * kB * kB + xq(i, r)] = x[i];
-  }
-}
-
-__device__ void gm_panel_tile(double* S, int64_t ld, const double* Xd, int kb, int I) {
-  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = 4 * s + q;
-    acc = mma(S[gidx(ld, I * kB + l16, kb * kB + k)], Xd[kb * kB * kB + xq(l16, k)], acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) S[gidx(ld, I * kB + 4 * r + q, kb * kB + l16)] = acc[r];
-}
-
-__device__ void gm_update_tile(double* S, int64_t ld, int kb, int I, int J) {
-  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
-  f64x4 acc;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = S[gidx(ld, I * kB + 4 * r + q, J * kB + l16)];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = kb * kB + 4 * s + q;
-    acc = mma(-S[gidx(ld, I * kB + l16, k)], S[gidx(ld, J * kB + l16, k)], acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) S[gidx(ld, I * kB + 4 * r + q, J * kB + l16)] = acc[r];
-}
-
-__device__ void gm_inverse_tile(double* S, int64_t ld, const double* Xd, int I, int J) {
-  const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
-  f64x4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
-  for (int K = J; K < I; ++K) {
+  __syncthreads();
+  // L_Ik = A_Ik X_kk^T, one tile per wave
+  const int I = kb + 1 + (int)blockIdx.x * 4 + wave;
+  if (I < nb) {
+    const int l16 = lane & 15, q = lane >> 4;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 4 * s + q;
-      const double b =
-          (K == J) ? Xd[J * kB * kB + xq(k, l16)] : S[gidx(ld, J * kB + l16, K * kB + k)];
-      if (s < 2)
-        t0 = mma(S[gidx(ld, I * kB + l16, K * kB + k)], b, t0);
-      else
-        t1 = mma(S[gidx(ld, I * kB + l16, K * kB + k)], b, t1);
+      acc = mma(S[gidx(lp, I * kB + l16, g0 + k)], Xs[xq(l16, k)], acc);
     }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) S[gidx(lp, I * kB + 4 * rr + q, g0 + l16)] = acc[rr];
   }
-  f64x4 t;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) t[r] = t0[r] + t1[r];
-  f64x4 x = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < 4; ++s) x = mma(-Xd[I * kB * kB + xq(l16, 4 * s + q)], t[s], x);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) S[gidx(ld, J * kB + l16, I * kB + 4 * r + q)] = x[r];
 }
 
-// G (lp x lp FP64, leading l x l used) -> L in S (and Lout) or W = L^-T.
-// S must not alias G; it may be Lout.
-__global__ __launch_bounds__(kGmThreads) void k_chol_gm(const double* __restrict__ G, int64_t lp,
-                                                        int l, double* S, float* __restrict__ W,
-                                                        double* Lout, int32_t* status,
-                                                        double tau) {
-  __shared__ double Xd[kGmMaxNb * kB * kB];
-  __shared__ double dinv[kGmMaxNb * kB];
-  __shared__ double d0[kGmMaxNb * kB];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int n = (int)lp;
-  const int nb = (l + kB - 1) / kB;
-  for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
-    const int i = (int)(e / n), c = (int)(e % n);
-    S[e] = (i < l && c < l) ? G[e] : 0.0;
+// A_IJ -= L_Ik L_Jk^T for the trailing tiles I >= J > kb (tile e of the
+// lower triangle after kb, one per wave).
+__global__ __launch_bounds__(kCgThreads) void k_cg_update(double* __restrict__ S, int64_t lp,
+                                                          int kb, int nb) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+  const int e = (int)blockIdx.x * 4 + wave, t = nb - kb - 1;
+  if (e >= t * (t + 1) / 2) return;
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= e) ++i;
+  const int I = kb + 1 + i, J = kb + 1 + (e - i * (i + 1) / 2);
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = S[gidx(lp, I * kB + 4 * r + q, J * kB + l16)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kb * kB + 4 * s + q;
+    acc = mma(-S[gidx(lp, I * kB + l16, k)], S[gidx(lp, J * kB + l16, k)], acc);
   }
-  for (int i = tid; i < kGmMaxNb * kB; i += kGmThreads) d0[i] = i < l ? G[(int64_t)i * n + i] : 0.0;
-  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[gidx(lp, I * kB + 4 * r + q, J * kB + l16)] = acc[r];
+}
 
-  int ndrop = 0, nbad = 0;
-  if (wave == 0) gm_diag_block(S, n, Xd, dinv, d0, 0, l, tau, ndrop, nbad);
-  __syncthreads();
-  for (int kb = 0; kb < nb; ++kb) {
-    for (int I = kb + 1 + wave; I < nb; I += kGmWaves) gm_panel_tile(S, n, Xd, kb, I);
+// Block column J of X = L^-1 (workgroup J), then rows 16 J .. 16 J + 15 of
+// W = X^T (zero below the diagonal, past l and for dropped directions).
+__global__ __launch_bounds__(kCgThreads) void k_cg_inverse(const double* __restrict__ S, int64_t lp,
+                                                           int nb, int l, float* __restrict__ W) {
+  __shared__ double Xc[kGmMaxNb * kB * kB];   // Xc[I * 256 + r * 16 + c] = X_IJ(r, c)
+  __shared__ double red[4][kB * kB];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+  const int J = blockIdx.x;
+  const CgSide sd = cg_side(const_cast<double*>(S), lp);
+  if (J < nb) {
+    for (int e = tid; e < kB * kB; e += kCgThreads) {
+      const int i = e >> 4, c = e & 15;
+      Xc[J * kB * kB + e] = sd.xd[J * kB * kB + xq(i, c)];
+    }
     __syncthreads();
-    if (kb + 1 < nb) {
-      const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
-      if (wave == 0) {
-        gm_update_tile(S, n, kb, kb + 1, kb + 1);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        gm_diag_block(S, n, Xd, dinv, d0, kb + 1, l, tau, ndrop, nbad);
-      } else {
-        for (int e = wave; e < ntile; e += kGmWaves - 1) {
-          int i = 0;
-          while ((i + 1) * (i + 2) / 2 <= e) ++i;
-          const int c = e - i * (i + 1) / 2;
-          gm_update_tile(S, n, kb, kb + 1 + i, kb + 1 + c);
+    for (int I = J + 1; I < nb; ++I) {
+      f64x4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J + wave; K < I; K += 4) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * s + q;
+          t = mma(S[gidx(lp, I * kB + l16, K * kB + k)], Xc[K * kB * kB + k * kB + l16], t);
         }
-        if (W)
-          for (int J = wave - 1; J < kb; J += kGmWaves - 1) gm_inverse_tile(S, n, Xd, kb, J);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][(4 * r + q) * kB + l16] = t[r];
+      __syncthreads();
+      if (wave == 0) {
+        f64x4 tt;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = (4 * r + q) * kB + l16;
+          tt[r] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+        }
+        // register s of tt holds row 4 s + q, column l16 of T: the B operand
+        // of k-step s
+        f64x4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) x = mma(-sd.xd[I * kB * kB + xq(l16, 4 * s + q)], tt[s], x);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xc[I * kB * kB + (4 * r + q) * kB + l16] = x[r];
       }
       __syncthreads();
     }
   }
-
-  if (Lout) {
-    for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
-      const int i = (int)(e / n), c = (int)(e % n);
-      Lout[e] = (i < l && c <= i) ? S[e] : 0.0;
-    }
-  }
-  if (W) {
-    for (int J = wave; J < nb - 1; J += kGmWaves) gm_inverse_tile(S, n, Xd, nb - 1, J);
-    __syncthreads();
-    for (int64_t e = tid; e < (int64_t)n * n; e += kGmThreads) {
-      const int a = (int)(e / n), c = (int)(e % n);
-      double xv = 0.0;
-      if (c < l && a <= c)
-        xv = (a >> 4) == (c >> 4) ? Xd[(c >> 4) * kB * kB + xq(c & 15, a & 15)] : S[e];
-      W[e] = (float)xv;
-    }
-  }
-  if (tid == 0) {
-    if (ndrop) atomicAdd(status + kStDropped, ndrop);
-    if (nbad) atomicAdd(status + kStNonFinite, nbad);
+  // W(a, c) = X(c, a) for a in block J, a <= c < l
+  const int n = (int)lp;
+  for (int e = tid; e < kB * n; e += kCgThreads) {
+    const int a = e / n, c = e % n;
+    const int ga = J * kB + a, I = c >> 4;
+    double v = 0.0;
+    if (J < nb && c < l && ga <= c && I >= J) v = Xc[I * kB * kB + (c & 15) * kB + a];
+    W[(int64_t)ga * n + c] = (float)v;
   }
 }
+
+// Factor only: L in place in S, with the diagonal blocks from the side area
+// and zeros above the diagonal and past l.
+__global__ void k_cg_lout(double* __restrict__ S, int64_t lp, int l) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= lp * lp) return;
+  const CgSide sd = cg_side(S, lp);
+  const int i = (int)(t / lp), c = (int)(t % lp);
+  double v = 0.0;
+  if (i < l && c <= i)
+    v = (i >> 4) == (c >> 4) ? sd.ld[(i >> 4) * kB * kB + (i & 15) * kB + (c & 15)] : S[t];
+  S[t] = v;
+}
+
 }  // namespace
 
 bool chol16_fits(int64_t lp) { return lp <= kSq; }
@@ -681,8 +708,28 @@ hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, flo
   const bool fits = W ? chol_gm_fits(lp) : (lp > kSq && lp <= kGmMaxNb * kB && lp % kB == 0);
   if (!fits || l > lp || l < 1 || !S || S == G || (!W && !L) || (L && L != S))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_gm, dim3(1), dim3(kGmThreads), 0, s, G, lp, (int)l, S, W, L, status,
-                     tau);
+  const int nb = (int)((l + kB - 1) / kB);
+  hipLaunchKernelGGL(k_cg_init, dim3((unsigned)ceil_div_dev(lp * lp, 256)), dim3(256), 0, s, G, lp,
+                     (int)l, S);
+  hipError_t e = hipGetLastError();
+  for (int kb = 0; kb < nb && e == hipSuccess; ++kb) {
+    const int below = nb - kb - 1;
+    hipLaunchKernelGGL(k_cg_panel, dim3((unsigned)std::max(1, (below + 3) / 4)), dim3(kCgThreads), 0,
+                       s, S, lp, kb, nb, (int)l, status, tau);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if (below > 0) {
+      hipLaunchKernelGGL(k_cg_update, dim3((unsigned)((below * (below + 1) / 2 + 3) / 4)),
+                         dim3(kCgThreads), 0, s, S, lp, kb, nb);
+      e = hipGetLastError();
+    }
+  }
+  if (e != hipSuccess) return e;
+  if (W)
+    hipLaunchKernelGGL(k_cg_inverse, dim3((unsigned)(lp / kB)), dim3(kCgThreads), 0, s, S, lp, nb,
+                       (int)l, W);
+  else
+    hipLaunchKernelGGL(k_cg_lout, dim3((unsigned)ceil_div_dev(lp * lp, 256)), dim3(256), 0, s, S, lp,
+                       (int)l);
   return hipGetLastError();
 }
 

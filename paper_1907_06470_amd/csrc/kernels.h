@@ -128,7 +128,8 @@ bool chol_tp_fits(int64_t lp);
 hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
                           double tau, hipStream_t s);
 // Cholesky factor (into L = S; 128 < lp <= 512) or W = L^-T (192 < lp <= 512),
-// the square in the global scratch S (lp x lp FP64, not aliasing G; k_chol.hip).
+// the square in the global scratch S (chol_gm_scratch_doubles(lp) FP64, plan.h;
+// not aliasing G; L is its leading lp x lp; k_chol.hip).
 bool chol_gm_fits(int64_t lp);
 hipError_t launch_chol_gm(const double* G, int64_t lp, int64_t l, double* S, float* W, double* L,
                           int32_t* status, double tau, hipStream_t s);

@@ -214,14 +214,16 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.Wpn = take(lp * lp * 4);
   w.Wc = take(lp * lp * 4);
   w.G = take(lp * lp * 8);
-  w.L = take(lp * lp * 8);
+  // above 128 also the scratch of the global-memory Cholesky (the square plus
+  // its side area)
+  w.L = take((size_t)(p.lp > 128 ? chol_gm_scratch_doubles(p.lp) : p.lp * p.lp) * 8);
   w.W = take(lp * lp * 4);
   w.W2 = take(lp * lp * 4);
   w.Ev = take(lp * lp * 8);
   const bool bj = p.lp > 128, wide = p.lp > kSliceMax;   // block Jacobi; Cholesky in global memory
   w.Mj = bj ? take(lp * lp * 8) : off;
   w.bjctl = bj ? take((size_t)kBjMaxSweeps * 4) : off;
-  w.Ls2 = wide ? take(lp * lp * 8) : off;
+  w.Ls2 = wide ? take((size_t)chol_gm_scratch_doubles(p.lp) * 8) : off;
   w.lam = take(lp * 8);
   w.order = take(lp * 4);
   w.signs = take(lp * 4);

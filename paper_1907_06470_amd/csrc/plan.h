@@ -141,6 +141,12 @@ inline bool gram_tri_fits(int64_t lp) { return lp <= 192 && lp % 32 == 0; }
 inline int64_t gram_tri_chunk_rows(int64_t rows) {
   return round_up(ceil_div(rows < 1 ? 1 : rows, kGramTriChunks), 4);
 }
+// Scratch of the global-memory Cholesky (k_chol.hip): the lp x lp square, then
+// X_kk and L_kk of up to kWideMax / 16 diagonal blocks and the original
+// diagonal.
+inline int64_t chol_gm_scratch_doubles(int64_t lp) {
+  return lp * lp + (kWideMax / 16) * 16 * (2 * 16 + 1);
+}
 // Wider panels: the same partial tiles, formed per pair of 128-column slices.
 inline bool gram_grp_fits(int64_t lp) { return lp > 192 && lp <= kWideMax && lp % 32 == 0; }
 inline size_t gram_tri_bytes(int64_t lp) {
