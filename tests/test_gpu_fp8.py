@@ -4,8 +4,8 @@ accumulation.  Products are checked against the FP64 product of the same
 quantised operands (quantisation by the CPU reference encoder); the matrix
 cores sum each 64-term slab with reduced internal precision, so the bound is
 2^-8 of the product of absolute values.  End to end the FP8 form has no
-accuracy target: its sigma error against the FP64 oracle is reported and held
-to a loose sanity bound."""
+accuracy target: its singular values are held to the accuracy the FP64 oracle
+reaches against the exact ones."""
 import numpy as np
 import pytest
 import torch
@@ -70,7 +70,16 @@ def test_fp8_quantisation_error_is_the_format_error():
     assert np.max(np.abs(Y / exact - 1.0)) <= 2 * 2.0 ** -4 + SLAB_REL
 
 
-@pytest.mark.parametrize("mix", [("fp8", "fp8", "fp8"), ("fp8", "bf16", "fp32")])
+# The FP8 forms have no accuracy target.  Rounding the sketch operands to e4m3
+# (3 mantissa bits) perturbs the random start, and on a spectrum that decays
+# slowly two power steps do not erase the start: the result differs from the
+# oracle's with the same seed by ~5e-3 (CPU emulation of the same rounding
+# gives the same figures), while the oracle's results for other seeds differ
+# from it by 1e-2 to 3e-2.  What is asserted is accuracy against the exact
+# singular values (LAPACK, FP64): no worse than the oracle's own, within 2e-3,
+# for every split of the passes over the FP8 form.
+@pytest.mark.parametrize("mix", [("fp8", "fp8", "fp8"), ("fp8", "fp8", "bf16"),
+                                 ("fp8", "bf16", "fp32")])
 def test_fp8_factor_end_to_end(mix):
     dev = need_gpu()
     A, meta = workloads.make("plain_gpu", scale=0.1)
@@ -79,10 +88,16 @@ def test_fp8_factor_end_to_end(mix):
     say("fp8 end to end", m, n, mix)
     plan = Plan(m, n, k, p, q, precision=mix)
     U, S, V, info = plan.factor(A.to(dev))
-    ref = oracle_rsvd(A.double().numpy(), k, p, q, seed=0)
-    err = metrics.sigma_err(S.cpu().numpy(), ref["S"])
-    say(f"fp8 form {mix}: sigma rel err {err:.3e}")
-    assert err <= 0.1
+    Ad = A.double().numpy()
+    ref = oracle_rsvd(Ad, k, p, q, seed=0)
+    exact = np.linalg.svd(Ad, compute_uv=False)[:k]
+    err = metrics.sigma_err(S.cpu().numpy(), exact)
+    err_oracle = metrics.sigma_err(ref["S"], exact)
+    spread = metrics.sigma_err(S.cpu().numpy(), ref["S"])
+    say(f"fp8 form {mix}: sigma err vs exact {err:.3e} (oracle {err_oracle:.3e}), "
+        f"vs oracle {spread:.3e}")
+    assert err <= err_oracle + 2e-3
+    assert spread <= 1e-2
     Un, Vn = U.cpu().double().numpy(), V.cpu().double().numpy()
     assert metrics.orth_err(Un) <= 1e-5 and metrics.orth_err(Vn) <= 1e-5
     assert info["status"] == 0
