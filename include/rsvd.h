@@ -130,6 +130,11 @@ typedef struct {
   double sketch_ms;        /* device time of the first A X launch (the
                               sketch pass; in the BF16 form it also writes
                               the BF16 copy of an FP32 A)                  */
+  int64_t peak_hbm;        /* device bytes the call touches: workspace
+                              + device-resident A (m n elements; 0 for host
+                              A) or the caller's CSR (8 nnz + 4 (m + 1))
+                              or COO (nnz (2 index bytes + 4)) arrays
+                              + U, V (4 (m + n) k) + S (8 k)               */
 } rsvd_report;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;
@@ -212,6 +217,18 @@ rsvd_status rsvd_backward(rsvd_plan_t plan, const void* A, int64_t lda, const fl
 rsvd_status rsvd_residual(rsvd_plan_t plan, const void* A, int64_t lda, const float* U, int64_t ldu,
                           const double* S, const float* V, int64_t ldv, double* out, void* ws,
                           void* stream);
+
+/* Streams the plan uses beside the caller's compute stream (Section 3.5
+ * overlaps copies with computation): copy_stream carries the host-to-device
+ * tile copies of a host-resident A, side_stream the second CholeskyQR pass
+ * of each basis, which runs beside the next product.  NULL (the default)
+ * lets the plan create its own non-blocking stream of default priority when
+ * first needed.  Streams given here stay owned by the caller, who keeps them
+ * alive until the plan is destroyed or the streams are replaced.  Call it
+ * between calls on the plan, never while one is running on another host
+ * thread (the plan is not thread-safe).  Host only; RSVD_E_INVALID_ARG for a
+ * NULL plan. */
+rsvd_status rsvd_plan_set_streams(rsvd_plan_t plan, void* copy_stream, void* side_stream);
 
 /* Free a plan (NULL is ignored). */
 void rsvd_plan_destroy(rsvd_plan_t plan);

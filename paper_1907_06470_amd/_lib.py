@@ -53,7 +53,7 @@ class Report(ctypes.Structure):
                 ("dropped", c_i32), ("jacobi_sweeps", c_i32), ("nonfinite", c_i32),
                 ("slots", c_i32), ("h2d_bytes", ctypes.c_double), ("tile_loads", c_i64),
                 ("q_used", c_i32), ("reserved2", c_i32), ("q_delta", ctypes.c_double),
-                ("sketch_ms", ctypes.c_double)]
+                ("sketch_ms", ctypes.c_double), ("peak_hbm", c_i64)]
 
 
 CKPT_MAGIC = 0x31504B4344565352   # "RSVDCKP1" little-endian
@@ -88,6 +88,7 @@ _SIGS = {
     "rsvd_step_spmm": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "rsvd_residual": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "rsvd_plan_destroy": (None, [c_vp]),
+    "rsvd_plan_set_streams": (c_i32, [c_vp, c_vp, c_vp]),
     "rsvd_status_str": (ctypes.c_char_p, [c_i32]),
     "rsvd_last_error": (ctypes.c_char_p, [c_vp]),
     "rsvd_version": (ctypes.c_char_p, []),

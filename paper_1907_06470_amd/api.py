@@ -147,6 +147,15 @@ class Plan:
                 pass
             self.handle = None
 
+    def set_streams(self, copy_stream=None, side_stream=None):
+        """rsvd_plan_set_streams: caller-owned torch streams for the tile
+        copies (host-resident A) and the deferred CholeskyQR passes; None lets
+        the plan create its own.  The streams must outlive their use."""
+        cs = ctypes.c_void_p(copy_stream.cuda_stream) if copy_stream is not None else None
+        ss = ctypes.c_void_p(side_stream.cuda_stream) if side_stream is not None else None
+        L.check(L.lib().rsvd_plan_set_streams(self.handle, cs, ss), self.handle)
+        self._streams = (copy_stream, side_stream)
+
     def workspace(self, device="cuda"):
         return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
@@ -198,7 +207,8 @@ class Plan:
                         ws_bytes=rep.ws_bytes, dropped=rep.dropped,
                         jacobi_sweeps=rep.jacobi_sweeps, nonfinite=rep.nonfinite,
                         slots=rep.slots, h2d_bytes=rep.h2d_bytes, tile_loads=rep.tile_loads,
-                        q_used=rep.q_used, q_delta=rep.q_delta, sketch_ms=rep.sketch_ms)
+                        q_used=rep.q_used, q_delta=rep.q_delta, sketch_ms=rep.sketch_ms,
+                        peak_hbm=rep.peak_hbm)
         return U, S, V, info
 
     def factor_noalloc(self, A, out=None, stream=None):
@@ -330,7 +340,7 @@ class Plan:
                         gemm_nn_launches=rep.gemm_nn_launches,
                         gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
                         dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps,
-                        q_used=rep.q_used, q_delta=rep.q_delta)
+                        q_used=rep.q_used, q_delta=rep.q_delta, peak_hbm=rep.peak_hbm)
         return U, S, V, info
 
     def factor_coo(self, rowind, colind, values, ws=None, out=None, stream=None, report=True):
@@ -369,7 +379,8 @@ class Plan:
                         gemm_nn_ms=rep.gemm_nn_ms, gemm_tn_ms=rep.gemm_tn_ms,
                         gemm_nn_launches=rep.gemm_nn_launches,
                         gemm_tn_launches=rep.gemm_tn_launches, ws_bytes=rep.ws_bytes,
-                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps)
+                        dropped=rep.dropped, jacobi_sweeps=rep.jacobi_sweeps,
+                        peak_hbm=rep.peak_hbm)
         return U, S, V, info
 
     def step_spmm(self, op, rowptr, colind, values, X, ws=None, stream=None):

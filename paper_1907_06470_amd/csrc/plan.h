@@ -125,6 +125,8 @@ struct Plan {
   void* hip_events = nullptr;   // created lazily by the driver
   void* streamer = nullptr;     // copy stream, slot events, slot contents (host A)
   void* side = nullptr;         // side stream + events of the deferred CholeskyQR passes
+  void* user_copy = nullptr;    // caller-owned copy / side streams (rsvd_plan_set_streams)
+  void* user_side = nullptr;
 };
 
 // Fill `plan` or return an error status with plan.last_error set.

@@ -83,6 +83,7 @@ void destroy_events(Events* e) {
 // T + (passes - 1) (T - S + 2) - (passes - 1).
 struct Streamer {
   hipStream_t copy = nullptr;
+  bool own_copy = false;          // created here (else the caller's)
   std::vector<hipEvent_t> ready, freed;
   std::vector<int64_t> tile;       // tile held by each slot (-1: none)
   std::vector<int64_t> last_use;
@@ -95,7 +96,7 @@ void destroy_streamer(Streamer* st) {
   if (!st) return;
   for (hipEvent_t e : st->ready) (void)hipEventDestroy(e);
   for (hipEvent_t e : st->freed) (void)hipEventDestroy(e);
-  if (st->copy) (void)hipStreamDestroy(st->copy);
+  if (st->copy && st->own_copy) (void)hipStreamDestroy(st->copy);
   delete st;
 }
 
@@ -104,7 +105,13 @@ hipError_t make_streamer(rsvd::Plan& P, Streamer*& out) {
   if (out) return hipSuccess;
   Streamer* st = new (std::nothrow) Streamer;
   if (!st) return hipErrorOutOfMemory;
-  hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+  hipError_t e = hipSuccess;
+  if (P.user_copy) {
+    st->copy = static_cast<hipStream_t>(P.user_copy);
+  } else {
+    e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+    st->own_copy = e == hipSuccess;
+  }
   for (int64_t j = 0; e == hipSuccess && j < P.slots; ++j) {
     hipEvent_t a, b;
     e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
@@ -244,6 +251,7 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
 // non-blocking), with the fork and join events; owned by the plan.
 struct Side {
   hipStream_t s = nullptr;
+  bool own = false;               // created here (else the caller's)
   hipEvent_t fork = nullptr, join = nullptr;
 };
 
@@ -251,7 +259,7 @@ void destroy_side(Side* d) {
   if (!d) return;
   if (d->fork) (void)hipEventDestroy(d->fork);
   if (d->join) (void)hipEventDestroy(d->join);
-  if (d->s) (void)hipStreamDestroy(d->s);
+  if (d->s && d->own) (void)hipStreamDestroy(d->s);
   delete d;
 }
 
@@ -260,7 +268,13 @@ hipError_t make_side(rsvd::Plan& P, Side*& out) {
   if (out) return hipSuccess;
   Side* d = new (std::nothrow) Side;
   if (!d) return hipErrorOutOfMemory;
-  hipError_t e = hipStreamCreateWithFlags(&d->s, hipStreamNonBlocking);
+  hipError_t e = hipSuccess;
+  if (P.user_side) {
+    d->s = static_cast<hipStream_t>(P.user_side);
+  } else {
+    e = hipStreamCreateWithFlags(&d->s, hipStreamNonBlocking);
+    d->own = e == hipSuccess;
+  }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&d->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&d->join, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -354,6 +368,7 @@ struct Runner {
   // Operand copies of A the products need: FP32 (FP64 input is rounded once)
   // and/or BF16 (rounded to nearest even once per call).
   bool fuse_cast = true;       // allow the sketch pass to produce the BF16 copy
+  int coo_bits = 0;            // index width of the caller's COO arrays
 
   // The BF16 copy if it is still owed (a BF16 product other than the sketch
   // comes first).
@@ -436,6 +451,7 @@ struct Runner {
   // (stable: a row keeps its entries' input order), then continue as CSR.
   rsvd_status bind_coo(const void* ri, const void* ci, int bits, const float* v) {
     const int64_t m = P.prob.m, n = P.prob.n, nnz = P.prob.nnz;
+    coo_bits = bits;
     size_t need = 0;
     const hipError_t e = rsvd::launch_coo_to_csr(ri, ci, bits, v, m, n, nnz, B.keys0, B.keys1,
                                                  B.pay0, B.pay1, B.sort_temp, P.sort_temp,
@@ -1042,6 +1058,15 @@ rsvd_status finish_report(rsvd_plan_t h, const Runner& R, Events* ev, rsvd_repor
                       2.0 * (double)P.prob.q * pass_bytes(P.opt.prec_power) +
                       pass_bytes(P.opt.prec_project);
   report->ws_bytes = (int64_t)P.ws.total;
+  {
+    const int64_t eb = P.prob.dtype == RSVD_F64 ? 8 : P.prob.dtype == RSVD_BF16 ? 2 : 4;
+    // caller arrays: CSR (rowptr, colind, values) or COO (two index arrays of
+    // coo_bits, values); the CSR copy of COO input lives in the workspace
+    const int64_t a_bytes = P.coo   ? P.prob.nnz * (2 * (R.coo_bits / 8) + 4)
+                            : P.csr ? P.prob.nnz * 8 + (m + 1) * 4
+                            : P.host ? 0 : m * n * eb;
+    report->peak_hbm = (int64_t)P.ws.total + a_bytes + (m + n) * P.prob.k * 4 + P.prob.k * 8;
+  }
   report->dropped = stw[rsvd::kStDropped];
   report->jacobi_sweeps = stw[rsvd::kStSweeps];
   report->nonfinite = stw[rsvd::kStNonFinite];
@@ -1148,6 +1173,19 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, const rsvd_options* opt, rsvd_pl
   }
   *out = h;
   *device_ws_bytes = h->p.ws.total;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_plan_set_streams(rsvd_plan_t h, void* copy_stream, void* side_stream) {
+  if (rsvd_status st = check_plan(h)) return st;
+  rsvd::Plan& P = h->p;
+  // a stream already in use is released (or left to its owner) first
+  destroy_streamer(static_cast<Streamer*>(P.streamer));
+  P.streamer = nullptr;
+  destroy_side(static_cast<Side*>(P.side));
+  P.side = nullptr;
+  P.user_copy = copy_stream;
+  P.user_side = side_stream;
   return RSVD_OK;
 }
 
