@@ -101,6 +101,25 @@ typedef struct {
    * q - 1, or at prob.q.  0 means 1e-4.  Needs prec_power == prec_project;
    * each step then waits for the device once. */
   double q_tol;
+  /* Per-operand device memory, the three limits of Section 3.5 (per matrix,
+   * new matrices, global):
+   *   a_budget_bytes    HBM that the tiles of A may occupy.  Host-resident
+   *                     A gets floor(a_budget / tile slot) slots, at least
+   *                     two, at most one per tile: with a slot for every
+   *                     tile, A is copied once per call and stays resident
+   *                     for the later passes (kept in-core).  A
+   *                     device-resident dense or sparse A larger than the
+   *                     limit is RSVD_E_BUDGET (plan it host-resident).
+   *   new_budget_bytes  HBM for the matrices the plan builds (panels,
+   *                     partial products, small factors, the CSC copy of a
+   *                     sparse A): RSVD_E_BUDGET when they need more.
+   *   hbm_budget_bytes  (above) the whole workspace.
+   * A limit left at 0 takes the next one's value (a_budget from new_budget,
+   * new_budget from hbm_budget_bytes); with only hbm_budget_bytes set, the
+   * slots get what the plan's own matrices leave of it.  With none set, a
+   * host-resident A streams through four slots. */
+  uint64_t a_budget_bytes;
+  uint64_t new_budget_bytes;
 } rsvd_options;
 
 /* Stage timers follow the paper's stage list (Section 4.1): 0 Gaussian O,

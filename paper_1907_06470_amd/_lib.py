@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
     _fields_ = [("prec_sketch", c_i32), ("prec_power", c_i32), ("prec_project", c_i32),
                 ("ortho", c_i32), ("tile_m", c_i64), ("tile_n", c_i64), ("grid_p", c_i64),
                 ("grid_q", c_i64), ("hbm_budget_bytes", c_u64), ("flags", c_i32),
-                ("reserved", c_i32), ("q_tol", ctypes.c_double)]
+                ("reserved", c_i32), ("q_tol", ctypes.c_double), ("a_budget_bytes", c_u64),
+                ("new_budget_bytes", c_u64)]
 
 
 class Report(ctypes.Structure):

@@ -97,9 +97,14 @@ class Plan:
 
     def __init__(self, m, n, k, p, q, seed=0, dtype=torch.float32, precision="fp32",
                  tile=None, grid=(1, 1), hbm_budget=0, flags=0, backward=False, host=False,
-                 nnz=None, auto_q=False, q_tol=0.0, coo=False):
+                 nnz=None, auto_q=False, q_tol=0.0, coo=False, a_budget=0, new_budget=0):
         """host=True: A stays in pinned host memory and is streamed to the
         device tile by tile on every pass (hbm_budget bounds the slots).
+        a_budget / new_budget: device bytes for the tiles of A and for the
+        matrices the plan builds (Section 3.5's per-matrix and new-matrix
+        limits; 0 takes the next limit, new_budget then hbm_budget).  A
+        host-resident A whose a_budget holds every tile is copied once per
+        call and kept resident for the later passes.
         nnz: A is sparse (CSR with int32 indices, FP32 values) with nnz
         nonzeros; use factor_csr / factor with a sparse CSR tensor.  With
         coo=True the nnz entries come as COO arrays (factor_coo).
@@ -123,7 +128,8 @@ class Plan:
         opt = L.Options(prec_sketch=ps, prec_power=pw, prec_project=pj, ortho=L.ORTHO_EACH,
                         tile_m=tm, tile_n=tn, grid_p=grid[0], grid_q=grid[1],
                         hbm_budget_bytes=int(hbm_budget), flags=flags, reserved=0,
-                        q_tol=float(q_tol))
+                        q_tol=float(q_tol), a_budget_bytes=int(a_budget),
+                        new_budget_bytes=int(new_budget))
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         st = L.lib().rsvd_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h),

@@ -14,6 +14,7 @@ rsvd_options default_options() {
   o.grid_p = o.grid_q = 1;
   o.hbm_budget_bytes = 0;
   o.flags = 0;
+  o.a_budget_bytes = o.new_budget_bytes = 0;
   return o;
 }
 
@@ -261,29 +262,6 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   } else {
     w.Pcat = w.Rcat = w.gUp = w.gVp = w.Ju = w.Jv = w.Sl = w.coreT = w.JuW = w.JvW = w.sinv = off;
   }
-  if (p.host) {
-    // tile slots: as many as the budget allows (at least two, so copies and
-    // products overlap), at most one per tile; four when there is no budget
-    p.elem = prob.dtype == RSVD_BF16 ? 2 : 4;
-    p.slot_ld = round_up(p.tn, 64);
-    p.slot_bytes = (size_t)round_up((int64_t)p.tm * p.slot_ld * p.elem, 256);
-    const int64_t tiles = p.TI * p.TJ;
-    int64_t S = std::min<int64_t>(tiles, 4);
-    if (o.hbm_budget_bytes) {
-      const size_t base = off;
-      if (o.hbm_budget_bytes < base + 2 * p.slot_bytes)
-        return fail(p, RSVD_E_BUDGET,
-                    "host-resident A needs %lld bytes (workspace plus two %lld-byte tile slots), "
-                    "budget is %lld",
-                    (long long)(base + 2 * p.slot_bytes), (long long)p.slot_bytes,
-                    (long long)o.hbm_budget_bytes);
-      S = std::min<int64_t>(tiles, (int64_t)((o.hbm_budget_bytes - base) / p.slot_bytes));
-    }
-    p.slots = std::max<int64_t>(S, std::min<int64_t>(tiles, 2));
-    w.slots = take((size_t)p.slots * p.slot_bytes);
-  } else {
-    w.slots = off;
-  }
   if (p.csr) {
     p.chunks = spmm_chunk_count(prob.nnz);
     p.csc_parts = csc_part_count(m, n, p.lp);
@@ -315,6 +293,47 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.coo_val = take((size_t)prob.nnz * 4);
   } else {
     w.coo_ptr = w.coo_col = w.coo_val = off;
+  }
+  // Section 3.5's limits: per matrix (the tiles of A), new matrices (all of
+  // the above), global; an unset one takes the next one's value
+  const uint64_t lim_new = o.new_budget_bytes ? o.new_budget_bytes : o.hbm_budget_bytes;
+  const uint64_t lim_a = o.a_budget_bytes ? o.a_budget_bytes : lim_new;
+  const size_t own = off;
+  if (lim_new && own > lim_new)
+    return fail(p, RSVD_E_BUDGET, "the plan's own matrices need %lld bytes, the limit is %lld",
+                (long long)own, (long long)lim_new);
+  if (!p.host && o.a_budget_bytes) {
+    const int64_t a_bytes = p.csr ? prob.nnz * 8 + (m + 1) * 4
+                                  : m * n * (prob.dtype == RSVD_F64 ? 8 : prob.dtype == RSVD_BF16 ? 2 : 4);
+    if ((uint64_t)a_bytes > o.a_budget_bytes)
+      return fail(p, RSVD_E_BUDGET,
+                  "device-resident A holds %lld bytes, above its limit of %lld (plan it "
+                  "host-resident to stream it)",
+                  (long long)a_bytes, (long long)o.a_budget_bytes);
+  }
+  if (p.host) {
+    // tile slots: as many as the limit on A allows (at least two, so copies
+    // and products overlap), at most one per tile; four when there is no limit
+    p.elem = prob.dtype == RSVD_BF16 ? 2 : 4;
+    p.slot_ld = round_up(p.tn, 64);
+    p.slot_bytes = (size_t)round_up((int64_t)p.tm * p.slot_ld * p.elem, 256);
+    const int64_t tiles = p.TI * p.TJ;
+    int64_t S = std::min<int64_t>(tiles, 4);
+    if (lim_a) {
+      // with only the global limit set, the slots share it with the rest
+      const bool own_limit = o.a_budget_bytes || o.new_budget_bytes;
+      const uint64_t avail = own_limit ? lim_a : (lim_a > own ? lim_a - own : 0);
+      if (avail < 2 * p.slot_bytes)
+        return fail(p, RSVD_E_BUDGET,
+                    "host-resident A needs two %lld-byte tile slots (%lld bytes); its limit leaves "
+                    "%lld",
+                    (long long)p.slot_bytes, (long long)(2 * p.slot_bytes), (long long)avail);
+      S = std::min<int64_t>(tiles, (int64_t)(avail / p.slot_bytes));
+    }
+    p.slots = std::max<int64_t>(S, std::min<int64_t>(tiles, 2));
+    w.slots = take((size_t)p.slots * p.slot_bytes);
+  } else {
+    w.slots = off;
   }
   w.total = off;
 

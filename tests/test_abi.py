@@ -149,12 +149,14 @@ def test_missing_library_fails_loudly():
     assert "LOUD" in out.stdout
 
 
-def _host_plan_ws(budget, flags=0, prec=None, m=4096, n=3072, tile=(1024, 1024)):
+def _host_plan_ws(budget, flags=0, prec=None, m=4096, n=3072, tile=(1024, 1024), a_budget=0,
+                  new_budget=0, host=True):
     prob = L.Problem(m=m, n=n, k=20, p=12, q=1, format=L.DENSE, dtype=L.F32,
-                     loc=L.LOC_HOST_PINNED, seed=0)
+                     loc=L.LOC_HOST_PINNED if host else L.LOC_DEVICE, seed=0)
     pr = L.F32 if prec is None else prec
     opt = L.Options(prec_sketch=pr, prec_power=pr, prec_project=pr, ortho=0, tile_m=tile[0],
-                    tile_n=tile[1], grid_p=1, grid_q=1, hbm_budget_bytes=budget, flags=flags)
+                    tile_n=tile[1], grid_p=1, grid_q=1, hbm_budget_bytes=budget, flags=flags,
+                    a_budget_bytes=a_budget, new_budget_bytes=new_budget)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
     st = L.lib().rsvd_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h), ctypes.byref(ws))
@@ -177,6 +179,37 @@ def test_host_resident_plans_size_their_tile_slots_from_the_budget():
     assert b"bytes" in L.lib().rsvd_last_error(None)
     st, ws_all = _host_plan_ws(base + 100 * slot)  # never more slots than tiles (4 x 3)
     assert st == L.OK and ws_all == base + 12 * slot
+
+
+def test_per_operand_limits_follow_the_three_limit_chain():
+    """Section 3.5: a limit for the tiles of A, one for the matrices the plan
+    builds, one global; an unset limit takes the next one's value."""
+    slot = 1024 * 1024 * 4
+    _, ws_free = _host_plan_ws(0)
+    own = ws_free - 4 * slot                        # everything but the four default slots
+    # the limit on A alone sets the slots: 7 of the 12 tiles, all 12, at least 2
+    assert _host_plan_ws(0, a_budget=7 * slot + 5) == (L.OK, own + 7 * slot)
+    assert _host_plan_ws(0, a_budget=100 * slot) == (L.OK, own + 12 * slot)
+    st, _ = _host_plan_ws(0, a_budget=2 * slot - 1)
+    assert st == L.E_BUDGET and b"slots" in L.lib().rsvd_last_error(None)
+    # the new-matrix limit bounds the plan's own matrices ...
+    st, _ = _host_plan_ws(0, a_budget=4 * slot, new_budget=own - 1)
+    assert st == L.E_BUDGET and b"own matrices" in L.lib().rsvd_last_error(None)
+    assert _host_plan_ws(0, a_budget=4 * slot, new_budget=own) == (L.OK, own + 4 * slot)
+    # ... and stands in for the limit on A when that one is unset (A then has
+    # an allowance of its own, the same size)
+    nb = own + 3 * slot
+    assert _host_plan_ws(0, new_budget=nb) == (L.OK, own + (nb // slot) * slot)
+    assert _host_plan_ws(0, new_budget=own + 20 * slot) == (L.OK, own + 12 * slot)
+    # the global limit still caps the sum
+    st, _ = _host_plan_ws(own + 5 * slot, a_budget=6 * slot)
+    assert st == L.E_BUDGET
+    assert _host_plan_ws(own + 6 * slot, a_budget=6 * slot) == (L.OK, own + 6 * slot)
+    # a device-resident A above its limit is refused (plan it host-resident)
+    m, n = 4096, 3072
+    st, _ = _host_plan_ws(0, a_budget=m * n * 4 - 1, host=False)
+    assert st == L.E_BUDGET and b"host-resident" in L.lib().rsvd_last_error(None)
+    assert _host_plan_ws(0, a_budget=m * n * 4, host=False)[0] == L.OK
 
 
 def test_host_resident_plans_reject_other_precisions_and_the_adjoint():

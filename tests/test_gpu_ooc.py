@@ -71,6 +71,27 @@ def test_slot_count_changes_traffic_not_results():
     assert metrics.sigma_err(r_few[1].cpu().numpy(), ref["S"]) <= 1e-5
 
 
+def test_per_matrix_limit_keeps_a_in_core():
+    """Section 3.5's per-matrix limit: with room for every tile of A, A is
+    copied once per call and the later passes read it from HBM; a smaller
+    limit streams it through fewer slots.  The results do not change."""
+    dev = need_gpu()
+    m, n, tile, q = 3000, 2000, (1024, 1024), 2
+    A = _workload(m, n, seed=13).pin_memory()
+    k, p = 20, 12
+    slot = 1024 * 1024 * 4
+    ref = Plan(m, n, k, p, q, tile=tile, host=True).factor(A)
+    keep = Plan(m, n, k, p, q, tile=tile, host=True, a_budget=6 * slot).factor(A)
+    three = Plan(m, n, k, p, q, tile=tile, host=True, a_budget=3 * slot + 100).factor(A)
+    say("per-matrix limit", keep[3]["slots"], keep[3]["tile_loads"], three[3]["slots"],
+        three[3]["tile_loads"])
+    assert keep[3]["slots"] == 6 and keep[3]["tile_loads"] == 6
+    assert keep[3]["h2d_bytes"] == m * n * 4
+    assert three[3]["slots"] == 3 and three[3]["tile_loads"] > 6
+    for x, y, z in zip(ref[:3], keep[:3], three[:3]):
+        assert torch.equal(x, y) and torch.equal(x, z)
+
+
 def test_host_resident_bf16_storage():
     dev = need_gpu()
     m, n, tile = 2048, 1536, (512, 512)
