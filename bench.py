@@ -208,6 +208,16 @@ def fmt(d):
     return {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in d.items()}
 
 
+def copy_calibration(dev):
+    """One plain elementwise copy kernel of known size (reads 1 GiB, writes
+    1 GiB): the reference that scales the HBM byte counters."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def bench_dense(args, dev, recipe):
     """The headline line (recipe plain_gpu) or the mixed-precision line
     (recipe mixed, with the adjoint)."""
@@ -222,11 +232,7 @@ def bench_dense(args, dev, recipe):
     torch.cuda.synchronize()
     log(f"generated A {m}x{n} on the GPU in {time.time() - t:.1f} s")
     if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)          # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(dev)
     flops_pass = 2.0 * m * n * l
     npass = 2 * q + 2
     forms, outs = {}, {}
@@ -394,6 +400,8 @@ def bench_sparse(args, dev):
     torch.cuda.synchronize()
     nnz = int(ci.numel())
     log(f"generated CSR {m}x{n}, {nnz} nonzeros on the GPU in {time.time() - t:.1f} s")
+    if args.copy_calibration:
+        copy_calibration(dev)
     plan = Plan(m, n, k, p, q, nnz=nnz)
     ws = plan.workspace(dev)
 
@@ -426,6 +434,28 @@ def bench_sparse(args, dev):
     log(f"sparse: {ms:.2f} ms/rSVD, A X {nn_ms:.3f} ms ({nn_gbs:.0f} GB/s algorithmic), "
         f"A^T Q {tn_ms:.3f} ms ({tn_gbs:.0f} GB/s), stages "
         f"{[round(x, 3) for x in infos[-1]['stage_ms']]}, properties {props}")
+    # measured HBM traffic of one A^T Q product (committed counter summary)
+    traffic = measured_traffic("k_sparse.hip", f"counters_k_spmm_chunk_sparse_{m}x{n}.md") \
+        if dom[0].startswith("A^T Q") and l == 330 else None
+    cpu = None
+    if not args.no_cpu_baseline:
+        # bounded sample: the oracle's FP64 product A O on the first tenth of
+        # the rows (scipy CSR x dense), scaled to the 8 passes over A of one
+        # rSVD (products only: a lower bound of the oracle's time)
+        from oracle import philox
+        rows = m // 10
+        O = philox.omega(0, n, l)
+        t0 = time.perf_counter()
+        _ = M[:rows] @ O
+        t_s = time.perf_counter() - t0
+        facts = host_facts()
+        cpu = {"value": round(t_s * 10 * 8 * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "seconds": round(t_s, 3),
+               "sample": f"FP64 CSR x dense product of rows 0..{rows} (1/10 of A) with the "
+                         f"{n}x{l} Gaussian panel (scipy, one thread), scaled x10 x8 passes: "
+                         "the oracle's products alone, a lower bound of its rSVD time",
+               **{kk: facts[kk] for kk in ("cpu_model", "affinity_cpus") if kk in facts}}
+        log(f"oracle sample: {t_s:.2f} s for 1/10 of one product")
     line = {
         "metric": "sparse rSVD wall time and sparse-product GB/s (algorithmic bytes)",
         "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
@@ -436,16 +466,19 @@ def bench_sparse(args, dev):
                    "m": m, "n": n, "nnz": nnz, "k": k, "p": p, "q": q,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(dom[3], 1), "peak": PEAK["hbm_GBs"],
-                     "unit": "GB/s", "frac": round(dom[3] / PEAK["hbm_GBs"], 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(dom[3] / PEAK["hbm_GBs"], 4),
+                     "traffic": traffic,
+                     "traffic_GBs": round(traffic / (dom[1] * 1e-3) / 1e9, 1) if traffic else None,
                      "kernel": f"sparse product {dom[0]}: layout change, chunk products "
                                "and carries of every column slice",
                      "launch_ms": round(dom[1], 4),
-                     "per_launch": f"compressed arrays + X once + Y once (FP32) = {dom[2]} bytes"},
+                     "per_launch": f"compressed arrays + X once + Y once (FP32) = {dom[2]} bytes; "
+                                   "traffic: measured bytes of the same product (row gathers)"},
         "nn_ms": round(nn_ms, 4), "tn_ms": round(tn_ms, 4), "nn_GBs": round(nn_gbs, 1),
         "tn_GBs": round(tn_gbs, 1),
         "stage_ms": [round(float(x), 3) for x in np.mean([i["stage_ms"] for i in infos], axis=0)],
         "jacobi_sweeps": infos[-1]["jacobi_sweeps"], "properties": fmt(props),
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

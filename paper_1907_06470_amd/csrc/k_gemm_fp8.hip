@@ -2,10 +2,11 @@
 // power-of-two scale per 64 x 64 block, in two layouts (A8 row-major for the
 // products A X, A8T = A^T row-major for A^T Q), and each panel operand is
 // stored as FP8 with one power-of-two scale per column.  The products run on
-// the gfx950 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4 with unit
-// hardware scales, FP32 accumulation); the block scale of A is applied per
-// 64-deep slab of the reduction (acc += s_block * slab product) and the column
-// scale of the panel in the epilogue.
+// the gfx950 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4, FP32
+// accumulation).  The power-of-two block scale of A is the instruction's A
+// scale (an E8M0 exponent byte per lane, applied to that lane's 32 values of
+// the 64-deep slab), so the accumulators run across the slabs of a tile with
+// no rescaling; the column scale of the panel is applied in the epilogue.
 //
 // This extends the half-precision storage of Section 3.2 one step further:
 // A costs one byte per entry, a quarter of its FP32 size, and every pass over
@@ -29,12 +30,15 @@ typedef uint8_t u8;
 constexpr int kQB = 64;          // quantisation block edge (rows and columns)
 constexpr float kFp8Max = 448.f;
 
+// 2^ceil(log2(amax / 448)), at least 2^-126 (a normal FP32 value, so that its
+// exponent field is the E8M0 byte of the matrix-core scale; only blocks with
+// amax below 448 * 2^-126 are affected, and they still fit e4m3)
 __device__ inline float pow2_scale(float amax) {
   if (!(amax > 0.f)) return 1.f;                        // all-zero block
   const float r = amax / kFp8Max;
   int e;
   const float f = __builtin_frexpf(r, &e);              // r = f 2^e, f in [0.5, 1)
-  return __builtin_ldexpf(1.f, f == 0.5f ? e - 1 : e);  // 2^ceil(log2 r)
+  return __builtin_ldexpf(1.f, max(f == 0.5f ? e - 1 : e, -126));
 }
 
 // two FP32 values -> two e4m3 bytes (round to nearest even) in the low half
@@ -257,8 +261,23 @@ __global__ __launch_bounds__(256) void k_panel_to_fp8(const float* __restrict__ 
   }
 }
 
-__device__ inline f32x16 mfma_fp8(const v8i& a, const v8i& b, f32x16 c) {
-  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+// c + (2^(sa - 127) a) b on e4m3 operands: sa is the E8M0 scale byte of this
+// lane's A values, sb that of its B values.  Both are passed in registers
+// (a scale the compiler sees as a constant would be encoded as an FP32
+// inline constant instead of a byte).
+__device__ inline f32x16 mfma_fp8(const v8i& a, const v8i& b, f32x16 c, int sa, int sb) {
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
+}
+
+// E8M0 byte of a power-of-two FP32 scale (its exponent field; NaN gives 0xFF,
+// the E8M0 NaN, so a non-finite block still poisons its products)
+__device__ inline int e8m0_of(float s) { return (int)((__builtin_bit_cast(uint32_t, s) >> 23) & 0xffu); }
+
+// 127 (scale 1) in a register the compiler cannot fold
+__device__ inline int e8m0_one() {
+  int v = 127;
+  asm volatile("" : "+v"(v));
+  return v;
 }
 
 // 16 consecutive bytes of a row from index k, zero past kend.
@@ -320,6 +339,7 @@ __global__ __launch_bounds__(256) void k_nn_fp8(const u8* __restrict__ A, int64_
     for (int s = 0; s < NT; ++s) *reinterpret_cast<uint4*>(&Xs[buf][lr + 32 * s][lc]) = rx[s];
   };
 
+  const int one = e8m0_one();
   f32x16 acc[MT][NT];
 #pragma unroll
   for (int a = 0; a < MT; ++a)
@@ -358,13 +378,9 @@ __global__ __launch_bounds__(256) void k_nn_fp8(const u8* __restrict__ A, int64_
       }
 #pragma unroll
       for (int a = 0; a < MT; ++a) {
-        const float sb = sA[rblk[a] * sc_r + kb * sc_k];
+        const int sa = e8m0_of(sA[rblk[a] * sc_r + kb * sc_k]);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const f32x16 part = mfma_fp8(av[a], bv[t], f32x16{});
-#pragma unroll
-          for (int e = 0; e < 16; ++e) acc[a][t][e] += sb * part[e];
-        }
+        for (int t = 0; t < NT; ++t) acc[a][t] = mfma_fp8(av[a], bv[t], acc[a][t], sa, one);
       }
     }
     if (more) sstore(buf ^ 1);
@@ -457,6 +473,7 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
     *reinterpret_cast<v4u*>(st + (wave * F8_XRUN + 1) * 1024 + lane * 16) = x1;
   };
 
+  const int one = e8m0_one();
   f32x16 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -484,15 +501,11 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
         const v4u hi = *reinterpret_cast<const v4u*>(xs + c * 128 + 16 * ((q + 1) ^ (c & 7)));
         bv[t] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       }
-      const float sb = sA[rblk * sc_r + (kb / kQB + s2) * sc_k];
+      const int sa = e8m0_of(sA[rblk * sc_r + (kb / kQB + s2) * sc_k]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const f32x16 part = mfma_fp8(av[a], bv[t], f32x16{});
-#pragma unroll
-          for (int e = 0; e < 16; ++e) acc[a][t][e] += sb * part[e];
-        }
+        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_fp8(av[a], bv[t], acc[a][t], sa, one);
     }
   };
 

@@ -28,10 +28,13 @@ def round_e4m3(x):
 
 
 def pow2_scale(amax):
-    """2^ceil(log2(amax / 448)); 1 for amax == 0."""
+    """2^ceil(log2(amax / 448)), at least 2^-126 (the smallest scale the FP8
+    matrix-core instruction's E8M0 byte takes from a normal FP32 value); 1 for
+    amax == 0."""
     amax = np.asarray(amax, dtype=np.float64)
     r = np.where(amax > 0, amax / 448.0, 1.0)
-    return np.where(amax > 0, np.ldexp(1.0, np.ceil(np.log2(r)).astype(np.int64)), 1.0)
+    e = np.maximum(np.ceil(np.log2(r)), -126.0).astype(np.int64)
+    return np.where(amax > 0, np.ldexp(1.0, e), 1.0)
 
 
 def quantize_blocks(A, b=64):

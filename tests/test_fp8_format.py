@@ -42,3 +42,8 @@ def test_scales_are_minimal_powers_of_two():
     assert np.all(amax / s <= 448.0)
     assert np.all(amax / (s / 2) > 448.0)
     assert f8.pow2_scale(0.0) == 1.0
+    # the floor: blocks below 448 * 2^-126 keep the scale 2^-126 and still fit
+    tiny = np.array([1e-40, 448.0 * 2.0 ** -126, 448.0 * 2.0 ** -125])
+    st = f8.pow2_scale(tiny)
+    assert list(st) == [2.0 ** -126, 2.0 ** -126, 2.0 ** -125]
+    assert np.all(tiny / st <= 448.0)
