@@ -140,9 +140,10 @@ def kernel_rows(form, m, n, l, lp, infos):
     tn_bytes = m * n * eb + m * l * eb + n * l * 4
     sk_bytes = (m * n * 4 + m * n * 2 + n * l * 2 + m * l * 4) if fused else nn_bytes
     names = {"fp32": ("k_nn_f32", "k_nn_f32", "k_tn_f32"),
-             "bf16": ("k_nn_bf16_dl_cast" if fused else "k_nn_bf16",
-                      "k_nn_bf16_dl" if lp == 128 else "k_nn_bf16",
-                      "k_tn_bf16_dl" if lp == 128 else "k_tn_bf16"),
+             "bf16": ("k_nn_bf16_dl_cast" if fused else
+                      "k_nn_bf16_dl" if lp in (128, 160) else "k_nn_bf16",
+                      "k_nn_bf16_dl" if lp in (128, 160) else "k_nn_bf16",
+                      "k_tn_bf16_dl" if lp in (128, 160) else "k_tn_bf16"),
              "fp8": ("k_nn_fp8_dl" if lp == 128 else "k_nn_fp8",) * 2 +
                     ("k_nn_fp8_dl on the transposed copy" if lp == 128 else "k_nn_fp8 on the transposed copy",)}[form]
     rows = [dict(role="sketch Y = A O", kernel=names[0], launches=1, ms=sk_ms, bytes=sk_bytes,

@@ -89,28 +89,42 @@ __device__ inline void store_acc16_rows(float* out, int64_t ld, int64_t row_base
 // counts them in order too, so its own waits stay at that depth.  One
 // workgroup barrier per slab.  A partial last slab (k1 not a multiple of 64)
 // goes through registers with masked loads, so padding beyond n is never
-// read.  Needs 256 * lda and 128 * ldx BF16 elements to fit a 31-bit byte
+// read.  Needs 256 * lda and LP * ldx BF16 elements to fit a 31-bit byte
 // offset (the launcher checks).  CP: cache-policy bits of the A loads (2 =
 // non-temporal: A is streamed once per pass).
-constexpr int DL_BM = 256, DL_LP = 128, DL_ARUN = DL_BM / 8 / 8, DL_XRUN = DL_LP / 8 / 8;
+//
+// NT = 5 (panel width 160): each of the 8 waves takes 32 rows and all five
+// 32-column tiles (one A operand read and five panel reads per step).  The
+// panel slab is 20 KB, so the A ring has three stages (3 x 32 + 2 x 20 KB of
+// LDS): two A slabs in flight while one is multiplied.  The 20 panel runs of
+// a slab go to waves w, w + 8, w + 16; waves 4-7 issue a third, unused load
+// of their second run, so every wave's wait counts are the same.
+constexpr int DL_BM = 256, DL_ARUN = DL_BM / 8 / 8;
 
-template <int CP>
+template <int CP, int NT>
 __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, int64_t lda,
                                                     int64_t m, int64_t n, int64_t tn,
                                                     const u16* __restrict__ X, int64_t ldx,
                                                     float* __restrict__ Y, int64_t ldy,
                                                     int64_t part_stride) {
-  static_assert(DL_XRUN == 2, "two panel loads per lane and slab");
+  static_assert(NT == 4 || NT == 5, "panel widths 128 and 160");
+  constexpr int LP = 32 * NT;
+  constexpr int NS = NT == 4 ? 4 : 3;           // A ring stages
+  constexpr int XR = NT == 4 ? 2 : 3;           // panel loads per lane and slab
+  constexpr int MT = NT == 4 ? 2 : 1;           // 32-row tiles per wave
+  constexpr int NW = NT == 4 ? 2 : 5;           // 32-column tiles per wave
   // one LDS object per stage: the compiler then sees that reading one stage
   // does not depend on the loads still landing in the others
   __shared__ __attribute__((aligned(1024))) u16 As0[DL_BM * 64], As1[DL_BM * 64];
-  __shared__ __attribute__((aligned(1024))) u16 As2[DL_BM * 64], As3[DL_BM * 64];
-  __shared__ __attribute__((aligned(1024))) u16 Xs0[DL_LP * 64], Xs1[DL_LP * 64];
+  __shared__ __attribute__((aligned(1024))) u16 As2[DL_BM * 64], As3[NS == 4 ? DL_BM * 64 : 1];
+  __shared__ __attribute__((aligned(1024))) u16 Xs0[LP * 64], Xs1[LP * 64];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l32 = lane & 31, half = lane >> 5;
-  const int wr = wave & 3, wc = wave >> 2;
+  // this wave's first row and column within the block
+  const int wrow = NT == 4 ? (wave & 3) * 64 : wave * 32;
+  const int wcol = NT == 4 ? (wave >> 2) * 64 : 0;
   const int64_t i0 = (int64_t)blockIdx.x * DL_BM;
   const int64_t k0 = (int64_t)blockIdx.y * tn;
   const int64_t k1 = min(n, k0 + tn);
@@ -126,7 +140,7 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
   const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(A + i0 * lda), (short)0, (int)(((int64_t)(rows - 1) * lda + n) * 2), 0x00020000);
   const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)X, (short)0, (int)(((int64_t)(DL_LP - 1) * ldx + n) * 2), 0x00020000);
+      (void*)X, (short)0, (int)(((int64_t)(LP - 1) * ldx + n) * 2), 0x00020000);
 
   // A slab t into LDS stage st, or past the last slab a re-read of panel
   // slab 0 (from the caches) so that every slab issues the same loads.  One
@@ -139,105 +153,133 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
     for (int j = 0; j < DL_ARUN; ++j) {
       const int r = (wave * DL_ARUN + j) * 8 + rr;   // row within the block
       const int rc = min(r, rows - 1);                // rows past m: any valid row
-      const int c = r & (DL_LP - 1);
+      const int c = r % LP;
       const int off = real ? (rc * (int)lda + kk + 8 * (sl ^ (r & 7))) * 2
                            : (c * (int)ldx + (int)k0 + 8 * sl) * 2;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + (wave * DL_ARUN + j) * 512, 16, off, 0, 0, CP);
     }
   };
-  // panel slab t (slab 0 past the last) into registers, and registers -> LDS
-  const int xc0 = (wave * DL_XRUN) * 8 + rr, xc1 = xc0 + 8;   // this lane's panel columns
-  auto load_x = [&](v4u& x0, v4u& x1, int64_t t) {
-    const int kk = (int)(k0 + (t < nfull ? t : 0) * 64);
-    x0 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc0 * (int)ldx + kk + 8 * (sl ^ (xc0 & 7))) * 2, 0, 0);
-    x1 = __builtin_amdgcn_raw_buffer_load_b128(rx, (xc1 * (int)ldx + kk + 8 * (sl ^ (xc1 & 7))) * 2, 0, 0);
+  // panel runs of this wave (8 panel columns each): 2 w, 2 w + 1 (width 128)
+  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8)
+  auto xrun = [&](int u) { return NT == 4 ? wave * 2 + u : wave + 8 * u; };
+  auto xrun_ld = [&](int u) {
+    const int j = xrun(u);
+    return j < LP / 8 ? j : xrun(1);
   };
-  auto store_x = [&](u16* st, const v4u& x0, const v4u& x1) {
-    *reinterpret_cast<v4u*>(st + (wave * DL_XRUN) * 512 + lane * 8) = x0;
-    *reinterpret_cast<v4u*>(st + (wave * DL_XRUN + 1) * 512 + lane * 8) = x1;
+  // panel slab t (slab 0 past the last) into registers, and registers -> LDS
+  auto load_x = [&](v4u (&x)[XR], int64_t t) {
+    const int kk = (int)(k0 + (t < nfull ? t : 0) * 64);
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int c = xrun_ld(u) * 8 + rr;
+      x[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, (c * (int)ldx + kk + 8 * (sl ^ (c & 7))) * 2, 0, 0);
+    }
+  };
+  auto store_x = [&](u16* st, const v4u (&x)[XR]) {
+#pragma unroll
+    for (int u = 0; u < XR; ++u)
+      if (xrun(u) < LP / 8) *reinterpret_cast<v4u*>(st + xrun(u) * 512 + lane * 8) = x[u];
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[MT][NW];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+    for (int t = 0; t < NW; ++t) acc[a][t] = f32x16{};
 
   auto compute = [&](const u16* as, const u16* xs) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int q = half * 4 + s;                    // 16-byte chunk of the 64-deep slab
-      bf16x8 av[2], bv[2];
+      bf16x8 av[MT], bv[NW];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int r = wr * 64 + a * 32 + l32;
+      for (int a = 0; a < MT; ++a) {
+        const int r = wrow + a * 32 + l32;
         av[a] = *reinterpret_cast<const bf16x8*>(as + r * 64 + 8 * (q ^ (r & 7)));
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int c = wc * 64 + t * 32 + l32;
+      for (int t = 0; t < NW; ++t) {
+        const int c = wcol + t * 32 + l32;
         bv[t] = *reinterpret_cast<const bf16x8*>(xs + c * 64 + 8 * (q ^ (c & 7)));
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+        for (int t = 0; t < NW; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
     }
   };
 
-  // Slab t: A stage t % 4, panel buffer t % 2.  Every slab issues the same
+  // Slab t: A stage t % NS, panel buffer t % 2.  Every slab issues the same
   // loads (dummies past the end), so the wait counts are constants.  Issue
-  // order of slab t: panel registers of slab t + 2 (DL_XRUN loads), then A
-  // slab t + 3 (DL_ARUN loads).  One step, entered after a barrier that
+  // order of slab t: panel registers of slab t + 2 (XR loads), then A slab
+  // t + NS - 1 (DL_ARUN loads).  One step, entered after a barrier that
   // follows every wave's A slab t and panel slab t landing in LDS:
-  //   issue panel slab t + 2 -> registers xn, A slab t + 3 -> the stage slab
-  //   t - 1 used; compute slab t; wait for the panel registers xp of slab
-  //   t + 1 (issued before A slab t + 2 and t + 3: vmcnt(2 * DL_ARUN +
-  //   DL_XRUN)), which also means this wave's A slab t + 1 has landed; write
-  //   them to the panel buffer slab t - 1 used; barrier.
+  //   issue panel slab t + 2 -> registers xn, A slab t + NS - 1 -> the stage
+  //   slab t - 1 used; compute slab t; wait for the panel registers xp of
+  //   slab t + 1 (the loads issued since: this step's, and with four stages
+  //   also the previous step's A slab), which also means this wave's A slab
+  //   t + 1 has landed; write them to the panel buffer slab t - 1 used;
+  //   barrier.
   // s_waitcnt immediates: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and
   // lgkmcnt 11:8 (0xc07f: lgkmcnt(0) only).
-  constexpr int kWaitStep = 0x0f70 | (2 * DL_ARUN + DL_XRUN);
-  auto step = [&](int64_t t, u16* as, u16* xs, u16* xs_next, u16* as_refill, v4u& xp0, v4u& xp1,
-                  v4u& xn0, v4u& xn1) {
-    load_x(xn0, xn1, t + 2);
-    issue_a(as_refill, t + 3);
+  constexpr int kWaitStep = 0x0f70 | ((NS - 2) * DL_ARUN + XR);
+  auto step = [&](int64_t t, u16* as, u16* xs, u16* xs_next, u16* as_refill, v4u (&xp)[XR],
+                  v4u (&xn)[XR]) {
+    load_x(xn, t + 2);
+    issue_a(as_refill, t + NS - 1);
     __builtin_amdgcn_sched_barrier(0);          // loads go out before the compute
     compute(as, xs);
     __builtin_amdgcn_s_waitcnt(kWaitStep);
-    store_x(xs_next, xp0, xp1);
+    store_x(xs_next, xp);
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_s_barrier();
   };
 
-  v4u xa0, xa1, xb0, xb1;                       // panel registers, two slabs
+  v4u xa[XR], xb[XR];                           // panel registers, two slabs
   if (nfull > 0) {
-    load_x(xa0, xa1, 0);
+    load_x(xa, 0);
     __builtin_amdgcn_s_waitcnt(0x0f70);
-    store_x(Xs0, xa0, xa1);
-    load_x(xb0, xb1, 1);
+    store_x(Xs0, xa);
+    load_x(xb, 1);
     issue_a(As0, 0);
     issue_a(As1, 1);
-    issue_a(As2, 2);
-    // A slab 0 (and the panel registers of slab 1) are older than A slabs 1, 2
-    __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * DL_ARUN));
+    if (NS == 4) issue_a(As2, 2);
+    // A slab 0 (and the panel registers of slab 1) are older than A slabs
+    // 1 .. NS - 2
+    __builtin_amdgcn_s_waitcnt(0x0f70 | ((NS - 2) * DL_ARUN));
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_s_barrier();
   }
   // slab t holds its panel registers: slab t + 1 in xb when t is even, else xa
   int64_t tb = 0;
-  for (; tb + 3 < nfull; tb += 4) {     // four whole steps: no branch between them
-    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
-    step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
-    step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
-    step(tb + 3, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1);
-  }
-  if (tb < nfull) {                     // up to three remaining slabs
-    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
-    if (tb + 1 < nfull) {
-      step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
-      if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+  if constexpr (NS == 4) {
+    for (; tb + 3 < nfull; tb += 4) {   // four whole steps: no branch between them
+      step(tb, As0, Xs0, Xs1, As3, xb, xa);
+      step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+      step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      step(tb + 3, As3, Xs1, Xs0, As2, xa, xb);
     }
+    if (tb < nfull) {                     // up to three remaining slabs
+      step(tb, As0, Xs0, Xs1, As3, xb, xa);
+      if (tb + 1 < nfull) {
+        step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+        if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      }
+    }
+  } else {
+    for (; tb + 5 < nfull; tb += 6) {   // six whole steps: stages and buffers realign
+      step(tb, As0, Xs0, Xs1, As2, xb, xa);
+      step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+      step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      step(tb + 3, As0, Xs1, Xs0, As2, xa, xb);
+      step(tb + 4, As1, Xs0, Xs1, As0, xb, xa);
+      step(tb + 5, As2, Xs1, Xs0, As1, xa, xb);
+    }
+    if (tb < nfull) step(tb, As0, Xs0, Xs1, As2, xb, xa);   // up to five remaining slabs
+    if (tb + 1 < nfull) step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+    if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+    if (tb + 3 < nfull) step(tb + 3, As0, Xs1, Xs0, As2, xa, xb);
+    if (tb + 4 < nfull) step(tb + 4, As1, Xs0, Xs1, As0, xb, xa);
   }
   __builtin_amdgcn_s_waitcnt(0x0f70);   // the last (dummy) loads land before LDS is reused or freed
   if (tail) {   // last, partial slab: masked loads through registers
@@ -249,7 +291,7 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
       *reinterpret_cast<uint4*>(As0 + r * 64 + 8 * (c ^ (r & 7))) =
           ld8_masked(A + gi * lda, kk + 8 * c, k1);
     }
-    for (int e = tid; e < DL_LP * 8; e += 512) {
+    for (int e = tid; e < LP * 8; e += 512) {
       const int r = e >> 3, c = e & 7;
       *reinterpret_cast<uint4*>(Xs0 + r * 64 + 8 * (c ^ (r & 7))) =
           ld8_masked(X + (int64_t)r * ldx, kk + 8 * c, k1);
@@ -262,11 +304,11 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
   // row m - 1)
   const int64_t mz = (m + 127) / 128 * 128;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t rb = i0 + wr * 64 + a * 32;
-      if (rb < mz) store_acc16_rows(Yp, ldy, rb, wc * 64 + t * 32 + l32, acc[a][t], half, m);
+    for (int t = 0; t < NW; ++t) {
+      const int64_t rb = i0 + wrow + a * 32;
+      if (rb < mz) store_acc16_rows(Yp, ldy, rb, wcol + t * 32 + l32, acc[a][t], half, m);
     }
 }
 
@@ -781,25 +823,37 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
 // path; panel rows past the tile are zeroed the same way.  Columns past n
 // re-read the block's last chunk: with n a multiple of 32 their sums fill
 // only whole 32-row groups of the output past n, which are stored as zeros.
-// Needs n a multiple of 32, m a multiple of 8, tm * lda and 128 * ldq BF16
+// Needs n a multiple of 32, m a multiple of 8, tm * lda and LP * ldq BF16
 // elements within a 31-bit byte offset (the launcher checks).
-constexpr int DT_BN = 256, DT_LP = 128, DT_ARUN = 64 * DT_BN / 512 / 8, DT_XRUN = 2;
+//
+// NT = 5 (panel width 160), as for the A X form: each of the 8 waves takes 32
+// output rows and all five 32-column tiles, the A ring has three stages, and
+// the 20 panel runs of a slab go to waves w, w + 8, w + 16 (waves 4-7 issue a
+// third, unused load).
+constexpr int DT_BN = 256, DT_ARUN = 64 * DT_BN / 512 / 8;
 
-template <int CP>
+template <int CP, int NT>
 __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, int64_t lda,
                                                     int64_t m, int64_t n, int64_t tm,
                                                     const u16* __restrict__ Q, int64_t ldq,
                                                     float* __restrict__ Z, int64_t ldz,
                                                     int64_t part_stride) {
   static_assert(DT_ARUN == 4, "four 1 KB runs per wave and slab");
+  static_assert(NT == 4 || NT == 5, "panel widths 128 and 160");
+  constexpr int LP = 32 * NT;
+  constexpr int NS = NT == 4 ? 4 : 3;           // A ring stages
+  constexpr int XR = NT == 4 ? 2 : 3;           // panel loads per lane and slab
+  constexpr int MT = NT == 4 ? 2 : 1;           // 32-row output tiles per wave
+  constexpr int NW = NT == 4 ? 2 : 5;           // 32-column tiles per wave
   __shared__ __attribute__((aligned(1024))) u16 As0[64 * DT_BN], As1[64 * DT_BN];
-  __shared__ __attribute__((aligned(1024))) u16 As2[64 * DT_BN], As3[64 * DT_BN];
-  __shared__ __attribute__((aligned(1024))) u16 Qs0[DT_LP * 64], Qs1[DT_LP * 64];
+  __shared__ __attribute__((aligned(1024))) u16 As2[64 * DT_BN], As3[NS == 4 ? 64 * DT_BN : 1];
+  __shared__ __attribute__((aligned(1024))) u16 Qs0[LP * 64], Qs1[LP * 64];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l32 = lane & 31, half = lane >> 5;
-  const int wj = wave & 3, wc = wave >> 2;
+  const int wrow = NT == 4 ? (wave & 3) * 64 : wave * 32;   // first output row (column of A)
+  const int wcol = NT == 4 ? (wave >> 2) * 64 : 0;          // first panel column
   const int64_t j0 = (int64_t)blockIdx.x * DT_BN;
   const int64_t ib0 = (int64_t)blockIdx.y * tm;
   const int64_t ib1 = min(m, ib0 + tm);
@@ -813,7 +867,7 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
   const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(A + ib0 * lda + j0), (short)0, (int)((ib1 - ib0) * lda * 2), 0x00020000);
   const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)Q, (short)0, (int)(((int64_t)(DT_LP - 1) * ldq + m) * 2), 0x00020000);
+      (void*)Q, (short)0, (int)(((int64_t)(LP - 1) * ldq + m) * 2), 0x00020000);
 
   // A slab t: wave w fills the 1 KB runs 4 w .. 4 w + 3, run b = rows 2 b and
   // 2 b + 1; lane i writes slot i & 31 of row 2 b + (i >> 5), which holds
@@ -829,31 +883,40 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
       const int ch = slot ^ (2 * (r & 3));
       const int row = (int)(t * 64) + r;               // within the tile
       const int off = (row * (int)lda + min(8 * ch, ncol - 8)) * 2;
-      const int c = (b * 2 + (lane >> 5)) & (DT_LP - 1);
+      const int c = (b * 2 + (lane >> 5)) % LP;
       const int doff = (c * (int)ldq + (int)ib0 + 8 * (slot & 7)) * 2;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + b * 512, 16, real ? off : doff, 0, 0, CP);
     }
   };
-  // panel slab t (slab 0 past the last) into registers; rows past the tile
-  // read zero
+  // panel runs of this wave (8 panel columns each): 2 w, 2 w + 1 (width 128)
+  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8); rows
+  // past the tile read zero
   const int rr = lane >> 3, sl = lane & 7;
-  const int qc0 = (wave * DT_XRUN) * 8 + rr, qc1 = qc0 + 8;
-  auto load_q = [&](v4u& x0, v4u& x1, int64_t t) {
-    const int64_t i0 = ib0 + (t < ns ? t : 0) * 64;
-    const int64_t r0 = i0 + 8 * (sl ^ (qc0 & 7)), r1 = i0 + 8 * (sl ^ (qc1 & 7));
-    x0 = __builtin_amdgcn_raw_buffer_load_b128(rq, r0 < ib1 ? (int)((qc0 * ldq + r0) * 2) : kOob, 0, 0);
-    x1 = __builtin_amdgcn_raw_buffer_load_b128(rq, r1 < ib1 ? (int)((qc1 * ldq + r1) * 2) : kOob, 0, 0);
+  auto qrun = [&](int u) { return NT == 4 ? wave * 2 + u : wave + 8 * u; };
+  auto qrun_ld = [&](int u) {
+    const int j = qrun(u);
+    return j < LP / 8 ? j : qrun(1);
   };
-  auto store_q = [&](u16* st, const v4u& x0, const v4u& x1) {
-    *reinterpret_cast<v4u*>(st + (wave * DT_XRUN) * 512 + lane * 8) = x0;
-    *reinterpret_cast<v4u*>(st + (wave * DT_XRUN + 1) * 512 + lane * 8) = x1;
+  auto load_q = [&](v4u (&x)[XR], int64_t t) {
+    const int64_t i0 = ib0 + (t < ns ? t : 0) * 64;
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int qc = qrun_ld(u) * 8 + rr;
+      const int64_t r0 = i0 + 8 * (sl ^ (qc & 7));
+      x[u] = __builtin_amdgcn_raw_buffer_load_b128(rq, r0 < ib1 ? (int)((qc * ldq + r0) * 2) : kOob, 0, 0);
+    }
+  };
+  auto store_q = [&](u16* st, const v4u (&x)[XR]) {
+#pragma unroll
+    for (int u = 0; u < XR; ++u)
+      if (qrun(u) < LP / 8) *reinterpret_cast<v4u*>(st + qrun(u) * 512 + lane * 8) = x[u];
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[MT][NW];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+    for (int t = 0; t < NW; ++t) acc[a][t] = f32x16{};
 
   // transposed-read coordinates of this lane: 16-lane group g, row a4 of the
   // four, columns 4 b4 .. 4 b4 + 3 of the group's sixteen
@@ -861,10 +924,10 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
   auto compute = [&](const u16* as, const u16* qs) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      bf16x8 av[2], bv[2];
+      bf16x8 av[MT], bv[NW];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int col = wj * 64 + a * 32 + (g & 1) * 16 + 4 * b4;
+      for (int a = 0; a < MT; ++a) {
+        const int col = wrow + a * 32 + (g & 1) * 16 + 4 * b4;
         const int r0 = s * 16 + half * 8 + a4, r1 = r0 + 4;    // r0 & 3 == r1 & 3 == a4
         const int cs = ((col >> 3) ^ (2 * a4)) * 8 + (col & 7);
         const s16x4 lo4 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(as + r0 * DT_BN + cs));
@@ -874,68 +937,84 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
       }
       const int q = s * 2 + half;                   // 16-byte chunk of the 64-row slab
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int c = wc * 64 + t * 32 + l32;
+      for (int t = 0; t < NW; ++t) {
+        const int c = wcol + t * 32 + l32;
         bv[t] = *reinterpret_cast<const bf16x8*>(qs + c * 64 + 8 * (q ^ (c & 7)));
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
+        for (int t = 0; t < NW; ++t) acc[a][t] = mfma_bf16(av[a], bv[t], acc[a][t]);
     }
   };
 
-  // the same slab schedule as the A X form: issue panel t + 2 and A t + 3,
-  // compute t, wait for the panel registers of t + 1 (and so A t + 1), write
-  // them to LDS, barrier
-  constexpr int kWaitStep = 0x0f70 | (2 * DT_ARUN + DT_XRUN);
-  auto step = [&](int64_t t, u16* as, u16* qs, u16* qs_next, u16* as_refill, v4u& xp0, v4u& xp1,
-                  v4u& xn0, v4u& xn1) {
-    load_q(xn0, xn1, t + 2);
-    issue_a(as_refill, t + 3);
+  // the same slab schedule as the A X form: issue panel t + 2 and A
+  // t + NS - 1, compute t, wait for the panel registers of t + 1 (and so A
+  // t + 1), write them to LDS, barrier
+  constexpr int kWaitStep = 0x0f70 | ((NS - 2) * DT_ARUN + XR);
+  auto step = [&](int64_t t, u16* as, u16* qs, u16* qs_next, u16* as_refill, v4u (&xp)[XR],
+                  v4u (&xn)[XR]) {
+    load_q(xn, t + 2);
+    issue_a(as_refill, t + NS - 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(as, qs);
     __builtin_amdgcn_s_waitcnt(kWaitStep);
-    store_q(qs_next, xp0, xp1);
+    store_q(qs_next, xp);
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_s_barrier();
   };
 
-  v4u xa0, xa1, xb0, xb1;
-  load_q(xa0, xa1, 0);
+  v4u xa[XR], xb[XR];
+  load_q(xa, 0);
   __builtin_amdgcn_s_waitcnt(0x0f70);
-  store_q(Qs0, xa0, xa1);
-  load_q(xb0, xb1, 1);
+  store_q(Qs0, xa);
+  load_q(xb, 1);
   issue_a(As0, 0);
   issue_a(As1, 1);
-  issue_a(As2, 2);
-  __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * DT_ARUN));
+  if (NS == 4) issue_a(As2, 2);
+  __builtin_amdgcn_s_waitcnt(0x0f70 | ((NS - 2) * DT_ARUN));
   __builtin_amdgcn_s_waitcnt(0xc07f);
   __builtin_amdgcn_s_barrier();
   int64_t tb = 0;
-  for (; tb + 3 < ns; tb += 4) {
-    step(tb, As0, Qs0, Qs1, As3, xb0, xb1, xa0, xa1);
-    step(tb + 1, As1, Qs1, Qs0, As0, xa0, xa1, xb0, xb1);
-    step(tb + 2, As2, Qs0, Qs1, As1, xb0, xb1, xa0, xa1);
-    step(tb + 3, As3, Qs1, Qs0, As2, xa0, xa1, xb0, xb1);
-  }
-  if (tb < ns) {
-    step(tb, As0, Qs0, Qs1, As3, xb0, xb1, xa0, xa1);
-    if (tb + 1 < ns) {
-      step(tb + 1, As1, Qs1, Qs0, As0, xa0, xa1, xb0, xb1);
-      if (tb + 2 < ns) step(tb + 2, As2, Qs0, Qs1, As1, xb0, xb1, xa0, xa1);
+  if constexpr (NS == 4) {
+    for (; tb + 3 < ns; tb += 4) {
+      step(tb, As0, Qs0, Qs1, As3, xb, xa);
+      step(tb + 1, As1, Qs1, Qs0, As0, xa, xb);
+      step(tb + 2, As2, Qs0, Qs1, As1, xb, xa);
+      step(tb + 3, As3, Qs1, Qs0, As2, xa, xb);
     }
+    if (tb < ns) {
+      step(tb, As0, Qs0, Qs1, As3, xb, xa);
+      if (tb + 1 < ns) {
+        step(tb + 1, As1, Qs1, Qs0, As0, xa, xb);
+        if (tb + 2 < ns) step(tb + 2, As2, Qs0, Qs1, As1, xb, xa);
+      }
+    }
+  } else {
+    for (; tb + 5 < ns; tb += 6) {
+      step(tb, As0, Qs0, Qs1, As2, xb, xa);
+      step(tb + 1, As1, Qs1, Qs0, As0, xa, xb);
+      step(tb + 2, As2, Qs0, Qs1, As1, xb, xa);
+      step(tb + 3, As0, Qs1, Qs0, As2, xa, xb);
+      step(tb + 4, As1, Qs0, Qs1, As0, xb, xa);
+      step(tb + 5, As2, Qs1, Qs0, As1, xa, xb);
+    }
+    if (tb < ns) step(tb, As0, Qs0, Qs1, As2, xb, xa);
+    if (tb + 1 < ns) step(tb + 1, As1, Qs1, Qs0, As0, xa, xb);
+    if (tb + 2 < ns) step(tb + 2, As2, Qs0, Qs1, As1, xb, xa);
+    if (tb + 3 < ns) step(tb + 3, As0, Qs1, Qs0, As2, xa, xb);
+    if (tb + 4 < ns) step(tb + 4, As1, Qs0, Qs1, As0, xb, xa);
   }
   __builtin_amdgcn_s_waitcnt(0x0f70);   // the last (dummy) loads land before LDS is freed
   // output rows [n, n rounded up to 128) are written as zeros, as by the
   // register-staged form
   const int64_t nz = (n + 127) / 128 * 128;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t jb = j0 + wj * 64 + a * 32;
-      if (jb < nz) store_acc16_rows(Zp, ldz, jb, wc * 64 + t * 32 + l32, acc[a][t], half, n);
+    for (int t = 0; t < NW; ++t) {
+      const int64_t jb = j0 + wrow + a * 32;
+      if (jb < nz) store_acc16_rows(Zp, ldz, jb, wcol + t * 32 + l32, acc[a][t], half, n);
     }
 }
 
@@ -1010,15 +1089,19 @@ static hipError_t launch_nn_bf16_slice(const uint16_t* A, int64_t lda, int64_t m
                           int64_t TJ, const uint16_t* X, int64_t ldx, int64_t lp, float* Y,
                           int64_t ldy, int64_t part_stride, hipStream_t s) {
   const int nt = (int)(lp / 32);
-  // direct-to-LDS form: 16-byte aligned rows and 31-bit buffer offsets over
-  // 256 rows of A and the 128 panel columns
-  const bool dl = nt == 4 && (lda % 8) == 0 && (ldx % 8) == 0 && (tn % 8) == 0 &&
+  // direct-to-LDS form (widths 128 and 160): 16-byte aligned rows and 31-bit
+  // buffer offsets over 256 rows of A and the panel columns
+  const bool dl = (nt == 4 || nt == 5) && (lda % 8) == 0 && (ldx % 8) == 0 && (tn % 8) == 0 &&
                   ((uintptr_t)A & 15) == 0 && ((uintptr_t)X & 15) == 0 &&
-                  (int64_t)DL_BM * lda * 2 <= INT32_MAX && (int64_t)DL_LP * ldx * 2 <= INT32_MAX;
+                  (int64_t)DL_BM * lda * 2 <= INT32_MAX && lp * ldx * 2 <= INT32_MAX;
   if (dl) {
     dim3 grid((unsigned)ceil_div_dev(m, DL_BM), (unsigned)TJ);
-    hipLaunchKernelGGL((k_nn_bf16_dl<2>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
-                       ldy, part_stride);
+    if (nt == 4)
+      hipLaunchKernelGGL((k_nn_bf16_dl<2, 4>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
+                         ldy, part_stride);
+    else
+      hipLaunchKernelGGL((k_nn_bf16_dl<2, 5>), grid, dim3(512), 0, s, A, lda, m, n, tn, X, ldx, Y,
+                         ldy, part_stride);
     return hipGetLastError();
   }
   if (nt == 4) {   // square wave tiles, 128 rows per workgroup
@@ -1067,13 +1150,18 @@ static hipError_t launch_tn_bf16_slice(const uint16_t* A, int64_t lda, int64_t m
                           int64_t ldz, int64_t part_stride, hipStream_t s) {
   // direct-to-LDS form: whole 16-byte chunks at both ends of every row and
   // tile (n a multiple of 32, m of 8), 16-byte aligned rows, 31-bit offsets
-  const bool dl = lp == 128 && (n % 32) == 0 && (m % 8) == 0 && (tm % 8) == 0 && (lda % 8) == 0 &&
-                  (ldq % 8) == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)Q & 15) == 0 &&
-                  (tm + 64) * lda * 2 <= INT32_MAX && (int64_t)DT_LP * ldq * 2 <= INT32_MAX;
+  const bool dl = (lp == 128 || lp == 160) && (n % 32) == 0 && (m % 8) == 0 && (tm % 8) == 0 &&
+                  (lda % 8) == 0 && (ldq % 8) == 0 && ((uintptr_t)A & 15) == 0 &&
+                  ((uintptr_t)Q & 15) == 0 && (tm + 64) * lda * 2 <= INT32_MAX &&
+                  lp * ldq * 2 <= INT32_MAX;
   if (dl) {
     dim3 grid((unsigned)ceil_div_dev(n, DT_BN), (unsigned)TI);
-    hipLaunchKernelGGL((k_tn_bf16_dl<2>), grid, dim3(512), 0, s, A, lda, m, n, tm, Q, ldq, Z, ldz,
-                       part_stride);
+    if (lp == 128)
+      hipLaunchKernelGGL((k_tn_bf16_dl<2, 4>), grid, dim3(512), 0, s, A, lda, m, n, tm, Q, ldq, Z,
+                         ldz, part_stride);
+    else
+      hipLaunchKernelGGL((k_tn_bf16_dl<2, 5>), grid, dim3(512), 0, s, A, lda, m, n, tm, Q, ldq, Z,
+                         ldz, part_stride);
     return hipGetLastError();
   }
   dim3 grid((unsigned)ceil_div_dev(n, TBN), (unsigned)TI);

@@ -71,11 +71,18 @@ def test_bf16_product_from_bf16_storage():
     (257, 4096, 100, (0, 0)),        # one row past a block; m not a multiple of 8 (Aᵀ Q other form)
     (128, 160, 128, (32, 32)),       # tiles shallower than one slab
     (136, 224, 120, (64, 96)),       # one partial row block; a whole slab plus a tail per tile
+    # width 160 (three-stage ring, six-step loop and its remainders)
+    (1000, 1024, 150, (256, 320)),
+    (520, 2080, 160, (224, 416)),
+    (257, 4096, 140, (0, 0)),
+    (160, 192, 160, (32, 32)),
+    (176, 224, 150, (64, 96)),
+    (640, 3000, 160, (384, 1472)),   # 23 whole slabs per A X tile, 6 per Aᵀ Q tile
 ])
-def test_bf16_products_from_bf16_storage_width_128(m, n, l, tile):
-    """Panel width 128 with BF16-stored A (the direct-to-LDS product kernels)
-    against the FP64 product of the same operands, within the FP32 summation
-    bound."""
+def test_bf16_products_from_bf16_storage_direct_widths(m, n, l, tile):
+    """Panel widths 128 and 160 with BF16-stored A (the direct-to-LDS product
+    kernels) against the FP64 product of the same operands, within the FP32
+    summation bound."""
     dev = need_gpu()
     say("bf16 width-128 products", m, n, l, tile)
     k = max(1, l - 20)
