@@ -144,8 +144,9 @@ def kernel_rows(form, m, n, l, lp, infos):
                       "k_nn_bf16_dl" if lp in (128, 160) else "k_nn_bf16",
                       "k_nn_bf16_dl" if lp in (128, 160) else "k_nn_bf16",
                       "k_tn_bf16_dl" if lp in (128, 160) else "k_tn_bf16"),
-             "fp8": ("k_nn_fp8_dl" if lp == 128 else "k_nn_fp8",) * 2 +
-                    ("k_nn_fp8_dl on the transposed copy" if lp == 128 else "k_nn_fp8 on the transposed copy",)}[form]
+             "fp8": ("k_nn_fp8_dl" if lp in (128, 160) else "k_nn_fp8",) * 2 +
+                    ("k_nn_fp8_dl on the transposed copy" if lp in (128, 160)
+                     else "k_nn_fp8 on the transposed copy",)}[form]
     rows = [dict(role="sketch Y = A O", kernel=names[0], launches=1, ms=sk_ms, bytes=sk_bytes,
                  flops=flops)]
     if nn_ms is not None:

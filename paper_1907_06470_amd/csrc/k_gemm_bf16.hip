@@ -97,8 +97,10 @@ __device__ inline void store_acc16_rows(float* out, int64_t ld, int64_t row_base
 // 32-column tiles (one A operand read and five panel reads per step).  The
 // panel slab is 20 KB, so the A ring has three stages (3 x 32 + 2 x 20 KB of
 // LDS): two A slabs in flight while one is multiplied.  The 20 panel runs of
-// a slab go to waves w, w + 8, w + 16; waves 4-7 issue a third, unused load
-// of their second run, so every wave's wait counts are the same.
+// a slab go to waves w, w + 8, w + 16; waves 4-7 load their second run once
+// more into rows 160-191 of the panel buffer, which nothing reads, so every
+// wave issues and stores the same number of runs (same wait counts, no
+// branch).
 constexpr int DL_BM = 256, DL_ARUN = DL_BM / 8 / 8;
 
 template <int CP, int NT>
@@ -111,13 +113,15 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
   constexpr int LP = 32 * NT;
   constexpr int NS = NT == 4 ? 4 : 3;           // A ring stages
   constexpr int XR = NT == 4 ? 2 : 3;           // panel loads per lane and slab
+  constexpr int XB = 64 * XR;                   // panel buffer rows (192 at width 160: the
+                                                // unused third runs of waves 4-7 land past 160)
   constexpr int MT = NT == 4 ? 2 : 1;           // 32-row tiles per wave
   constexpr int NW = NT == 4 ? 2 : 5;           // 32-column tiles per wave
   // one LDS object per stage: the compiler then sees that reading one stage
   // does not depend on the loads still landing in the others
   __shared__ __attribute__((aligned(1024))) u16 As0[DL_BM * 64], As1[DL_BM * 64];
   __shared__ __attribute__((aligned(1024))) u16 As2[DL_BM * 64], As3[NS == 4 ? DL_BM * 64 : 1];
-  __shared__ __attribute__((aligned(1024))) u16 Xs0[LP * 64], Xs1[LP * 64];
+  __shared__ __attribute__((aligned(1024))) u16 Xs0[XB * 64], Xs1[XB * 64];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -160,7 +164,8 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
     }
   };
   // panel runs of this wave (8 panel columns each): 2 w, 2 w + 1 (width 128)
-  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8)
+  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8 and
+  // land in the unread rows 160-191)
   auto xrun = [&](int u) { return NT == 4 ? wave * 2 + u : wave + 8 * u; };
   auto xrun_ld = [&](int u) {
     const int j = xrun(u);
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(512) void k_nn_bf16_dl(const u16* __restrict__ A, i
   auto store_x = [&](u16* st, const v4u (&x)[XR]) {
 #pragma unroll
     for (int u = 0; u < XR; ++u)
-      if (xrun(u) < LP / 8) *reinterpret_cast<v4u*>(st + xrun(u) * 512 + lane * 8) = x[u];
+      *reinterpret_cast<v4u*>(st + xrun(u) * 512 + lane * 8) = x[u];
   };
 
   f32x16 acc[MT][NW];
@@ -828,8 +833,9 @@ __global__ __launch_bounds__(256) void k_tn_bf16(const u16* __restrict__ A, int6
 //
 // NT = 5 (panel width 160), as for the A X form: each of the 8 waves takes 32
 // output rows and all five 32-column tiles, the A ring has three stages, and
-// the 20 panel runs of a slab go to waves w, w + 8, w + 16 (waves 4-7 issue a
-// third, unused load).
+// the 20 panel runs of a slab go to waves w, w + 8, w + 16 (waves 4-7 load
+// their second run once more into rows 160-191 of the panel buffer, which
+// nothing reads).
 constexpr int DT_BN = 256, DT_ARUN = 64 * DT_BN / 512 / 8;
 
 template <int CP, int NT>
@@ -843,11 +849,13 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
   constexpr int LP = 32 * NT;
   constexpr int NS = NT == 4 ? 4 : 3;           // A ring stages
   constexpr int XR = NT == 4 ? 2 : 3;           // panel loads per lane and slab
+  constexpr int XB = 64 * XR;                   // panel buffer rows (192 at width 160: the
+                                                // unused third runs of waves 4-7 land past 160)
   constexpr int MT = NT == 4 ? 2 : 1;           // 32-row output tiles per wave
   constexpr int NW = NT == 4 ? 2 : 5;           // 32-column tiles per wave
   __shared__ __attribute__((aligned(1024))) u16 As0[64 * DT_BN], As1[64 * DT_BN];
   __shared__ __attribute__((aligned(1024))) u16 As2[64 * DT_BN], As3[NS == 4 ? 64 * DT_BN : 1];
-  __shared__ __attribute__((aligned(1024))) u16 Qs0[LP * 64], Qs1[LP * 64];
+  __shared__ __attribute__((aligned(1024))) u16 Qs0[XB * 64], Qs1[XB * 64];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -889,7 +897,8 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
     }
   };
   // panel runs of this wave (8 panel columns each): 2 w, 2 w + 1 (width 128)
-  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8); rows
+  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8 and
+  // land in the unread rows 160-191); rows
   // past the tile read zero
   const int rr = lane >> 3, sl = lane & 7;
   auto qrun = [&](int u) { return NT == 4 ? wave * 2 + u : wave + 8 * u; };
@@ -909,7 +918,7 @@ __global__ __launch_bounds__(512) void k_tn_bf16_dl(const u16* __restrict__ A, i
   auto store_q = [&](u16* st, const v4u (&x)[XR]) {
 #pragma unroll
     for (int u = 0; u < XR; ++u)
-      if (qrun(u) < LP / 8) *reinterpret_cast<v4u*>(st + qrun(u) * 512 + lane * 8) = x[u];
+      *reinterpret_cast<v4u*>(st + qrun(u) * 512 + lane * 8) = x[u];
   };
 
   f32x16 acc[MT][NW];

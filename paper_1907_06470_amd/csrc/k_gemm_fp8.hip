@@ -416,9 +416,16 @@ __global__ __launch_bounds__(256) void k_nn_fp8(const u8* __restrict__ A, int64_
 // block, so one block scale per wave and 64-deep slab; the per-slab products
 // and their scaling are those of the register-staged kernel, in the same
 // order.  A partial last slab goes through registers with masked loads.
-// Needs 256 * lda and 128 * ldx bytes within a 31-bit offset.
-constexpr int F8_BM = 256, F8_LP = 128, F8_ARUN = 4, F8_XRUN = 2;
+// Needs 256 * lda and LP * ldx bytes within a 31-bit offset.
+//
+// NT = 5 (panel width 160), as for the BF16 form: each of the 8 waves takes 32
+// rows (half of one quantisation row block) and all five 32-column tiles, the
+// A ring has three stages (the panel slab is 20 KB), and the 20 panel runs of
+// a slab go to waves w, w + 8, w + 16 (waves 4-7 load their second run once
+// more into rows 160-191 of the panel buffer, which nothing reads).
+constexpr int F8_BM = 256, F8_ARUN = 4;
 
+template <int NT>
 __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int64_t lda,
                                                    int64_t rows, int64_t kdim, int64_t tk,
                                                    const float* __restrict__ sA, int64_t sc_r,
@@ -426,14 +433,23 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
                                                    int64_t ldx, const float* __restrict__ sx,
                                                    float* __restrict__ Y, int64_t ldy,
                                                    int64_t part_stride) {
+  static_assert(NT == 4 || NT == 5, "panel widths 128 and 160");
+  constexpr int LP = 32 * NT;
+  constexpr int NS = NT == 4 ? 4 : 3;           // A ring stages
+  constexpr int XR = NT == 4 ? 2 : 3;           // panel loads per lane and slab
+  constexpr int XB = 64 * XR;                   // panel buffer rows (192 at width 160: the
+                                                // unused third runs of waves 4-7 land past 160)
+  constexpr int MT = NT == 4 ? 2 : 1;           // 32-row tiles per wave
+  constexpr int NW = NT == 4 ? 2 : 5;           // 32-column tiles per wave
   __shared__ __attribute__((aligned(1024))) u8 As0[F8_BM * 128], As1[F8_BM * 128];
-  __shared__ __attribute__((aligned(1024))) u8 As2[F8_BM * 128], As3[F8_BM * 128];
-  __shared__ __attribute__((aligned(1024))) u8 Xs0[F8_LP * 128], Xs1[F8_LP * 128];
+  __shared__ __attribute__((aligned(1024))) u8 As2[F8_BM * 128], As3[NS == 4 ? F8_BM * 128 : 1];
+  __shared__ __attribute__((aligned(1024))) u8 Xs0[XB * 128], Xs1[XB * 128];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l32 = lane & 31, half = lane >> 5;
-  const int wr = wave & 3, wc = wave >> 2;
+  const int wrow = NT == 4 ? (wave & 3) * 64 : wave * 32;
+  const int wcol = NT == 4 ? (wave >> 2) * 64 : 0;
   const int64_t i0 = (int64_t)blockIdx.x * F8_BM;
   const int64_t k0 = (int64_t)blockIdx.y * tk;
   const int64_t k1 = min(kdim, k0 + tk);
@@ -445,9 +461,9 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
   const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(A + i0 * lda), (short)0, (int)((int64_t)(nrow - 1) * lda + kdim), 0x00020000);
   const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)X, (short)0, (int)((int64_t)(F8_LP - 1) * ldx + kdim), 0x00020000);
-  // quantisation row block of this wave's 64 rows (rows past the end: the last)
-  const int64_t rblk = min(i0 + wr * 64, rows - 1) / kQB;
+      (void*)X, (short)0, (int)((int64_t)(LP - 1) * ldx + kdim), 0x00020000);
+  // quantisation row block of this wave's rows (rows past the end: the last)
+  const int64_t rblk = min(i0 + wrow, rows - 1) / kQB;
 
   auto issue_a = [&](u8* st, int64_t t) {   // past the last slab: panel re-reads
     const bool real = t < nfull;
@@ -457,28 +473,39 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
     for (int j = 0; j < F8_ARUN; ++j) {
       const int r = (wave * F8_ARUN + j) * 8 + rr;
       const int rc = min(r, nrow - 1);
-      const int c = r & (F8_LP - 1);
+      const int c = r % LP;
       const int off = real ? rc * (int)lda + kk + 16 * (sl ^ (r & 7)) : c * (int)ldx + (int)k0 + 16 * sl;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, st + (wave * F8_ARUN + j) * 1024, 16, off, 0, 0, 2);
     }
   };
-  const int xc0 = (wave * F8_XRUN) * 8 + rr, xc1 = xc0 + 8;
-  auto load_x = [&](v4u& x0, v4u& x1, int64_t t) {
-    const int kk = (int)(k0 + (t < nfull ? t : 0) * 128);
-    x0 = __builtin_amdgcn_raw_buffer_load_b128(rx, xc0 * (int)ldx + kk + 16 * (sl ^ (xc0 & 7)), 0, 0);
-    x1 = __builtin_amdgcn_raw_buffer_load_b128(rx, xc1 * (int)ldx + kk + 16 * (sl ^ (xc1 & 7)), 0, 0);
+  // panel runs of this wave (8 panel columns each): 2 w, 2 w + 1 (width 128)
+  // or w, w + 8, w + 16 (width 160; runs past the 20 re-read run w + 8 and
+  // land in the unread rows 160-191)
+  auto xrun = [&](int u) { return NT == 4 ? wave * 2 + u : wave + 8 * u; };
+  auto xrun_ld = [&](int u) {
+    const int j = xrun(u);
+    return j < LP / 8 ? j : xrun(1);
   };
-  auto store_x = [&](u8* st, const v4u& x0, const v4u& x1) {
-    *reinterpret_cast<v4u*>(st + (wave * F8_XRUN) * 1024 + lane * 16) = x0;
-    *reinterpret_cast<v4u*>(st + (wave * F8_XRUN + 1) * 1024 + lane * 16) = x1;
+  auto load_x = [&](v4u (&x)[XR], int64_t t) {
+    const int kk = (int)(k0 + (t < nfull ? t : 0) * 128);
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int c = xrun_ld(u) * 8 + rr;
+      x[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, c * (int)ldx + kk + 16 * (sl ^ (c & 7)), 0, 0);
+    }
+  };
+  auto store_x = [&](u8* st, const v4u (&x)[XR]) {
+#pragma unroll
+    for (int u = 0; u < XR; ++u)
+      *reinterpret_cast<v4u*>(st + xrun(u) * 1024 + lane * 16) = x[u];
   };
 
   const int one = e8m0_one();
-  f32x16 acc[2][2];
+  f32x16 acc[MT][NW];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) acc[a][t] = f32x16{};
+    for (int t = 0; t < NW; ++t) acc[a][t] = f32x16{};
 
   // 64-deep quantisation slabs nq (1 or 2) of a 128-deep slab from column kb
   auto compute = [&](const u8* as, const u8* xs, int64_t kb, int nq) {
@@ -486,68 +513,85 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
     for (int s2 = 0; s2 < 2; ++s2) {
       if (s2 >= nq) break;
       const int q = 4 * s2 + 2 * half;             // this lane's two 16-byte chunks
-      v8i av[2], bv[2];
+      v8i av[MT], bv[NW];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int r = wr * 64 + a * 32 + l32;
+      for (int a = 0; a < MT; ++a) {
+        const int r = wrow + a * 32 + l32;
         const v4u lo = *reinterpret_cast<const v4u*>(as + r * 128 + 16 * (q ^ (r & 7)));
         const v4u hi = *reinterpret_cast<const v4u*>(as + r * 128 + 16 * ((q + 1) ^ (r & 7)));
         av[a] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int c = wc * 64 + t * 32 + l32;
+      for (int t = 0; t < NW; ++t) {
+        const int c = wcol + t * 32 + l32;
         const v4u lo = *reinterpret_cast<const v4u*>(xs + c * 128 + 16 * (q ^ (c & 7)));
         const v4u hi = *reinterpret_cast<const v4u*>(xs + c * 128 + 16 * ((q + 1) ^ (c & 7)));
         bv[t] = v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       }
       const int sa = e8m0_of(sA[rblk * sc_r + (kb / kQB + s2) * sc_k]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[a][t] = mfma_fp8(av[a], bv[t], acc[a][t], sa, one);
+        for (int t = 0; t < NW; ++t) acc[a][t] = mfma_fp8(av[a], bv[t], acc[a][t], sa, one);
     }
   };
 
-  constexpr int kWaitStep = 0x0f70 | (2 * F8_ARUN + F8_XRUN);
-  auto step = [&](int64_t t, u8* as, u8* xs, u8* xs_next, u8* as_refill, v4u& xp0, v4u& xp1,
-                  v4u& xn0, v4u& xn1) {
-    load_x(xn0, xn1, t + 2);
-    issue_a(as_refill, t + 3);
+  // the slab schedule of the BF16 direct-to-LDS kernel
+  constexpr int kWaitStep = 0x0f70 | ((NS - 2) * F8_ARUN + XR);
+  auto step = [&](int64_t t, u8* as, u8* xs, u8* xs_next, u8* as_refill, v4u (&xp)[XR],
+                  v4u (&xn)[XR]) {
+    load_x(xn, t + 2);
+    issue_a(as_refill, t + NS - 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(as, xs, k0 + t * 128, 2);
     __builtin_amdgcn_s_waitcnt(kWaitStep);
-    store_x(xs_next, xp0, xp1);
+    store_x(xs_next, xp);
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_s_barrier();
   };
 
-  v4u xa0, xa1, xb0, xb1;
+  v4u xa[XR], xb[XR];
   if (nfull > 0) {
-    load_x(xa0, xa1, 0);
+    load_x(xa, 0);
     __builtin_amdgcn_s_waitcnt(0x0f70);
-    store_x(Xs0, xa0, xa1);
-    load_x(xb0, xb1, 1);
+    store_x(Xs0, xa);
+    load_x(xb, 1);
     issue_a(As0, 0);
     issue_a(As1, 1);
-    issue_a(As2, 2);
-    __builtin_amdgcn_s_waitcnt(0x0f70 | (2 * F8_ARUN));
+    if (NS == 4) issue_a(As2, 2);
+    __builtin_amdgcn_s_waitcnt(0x0f70 | ((NS - 2) * F8_ARUN));
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_s_barrier();
   }
   int64_t tb = 0;
-  for (; tb + 3 < nfull; tb += 4) {
-    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
-    step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
-    step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
-    step(tb + 3, As3, Xs1, Xs0, As2, xa0, xa1, xb0, xb1);
-  }
-  if (tb < nfull) {
-    step(tb, As0, Xs0, Xs1, As3, xb0, xb1, xa0, xa1);
-    if (tb + 1 < nfull) {
-      step(tb + 1, As1, Xs1, Xs0, As0, xa0, xa1, xb0, xb1);
-      if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb0, xb1, xa0, xa1);
+  if constexpr (NS == 4) {
+    for (; tb + 3 < nfull; tb += 4) {
+      step(tb, As0, Xs0, Xs1, As3, xb, xa);
+      step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+      step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      step(tb + 3, As3, Xs1, Xs0, As2, xa, xb);
     }
+    if (tb < nfull) {
+      step(tb, As0, Xs0, Xs1, As3, xb, xa);
+      if (tb + 1 < nfull) {
+        step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+        if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      }
+    }
+  } else {
+    for (; tb + 5 < nfull; tb += 6) {
+      step(tb, As0, Xs0, Xs1, As2, xb, xa);
+      step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+      step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+      step(tb + 3, As0, Xs1, Xs0, As2, xa, xb);
+      step(tb + 4, As1, Xs0, Xs1, As0, xb, xa);
+      step(tb + 5, As2, Xs1, Xs0, As1, xa, xb);
+    }
+    if (tb < nfull) step(tb, As0, Xs0, Xs1, As2, xb, xa);
+    if (tb + 1 < nfull) step(tb + 1, As1, Xs1, Xs0, As0, xa, xb);
+    if (tb + 2 < nfull) step(tb + 2, As2, Xs0, Xs1, As1, xb, xa);
+    if (tb + 3 < nfull) step(tb + 3, As0, Xs1, Xs0, As2, xa, xb);
+    if (tb + 4 < nfull) step(tb + 4, As1, Xs0, Xs1, As0, xb, xa);
   }
   __builtin_amdgcn_s_waitcnt(0x0f70);
   if (tail) {   // last, partial slab: masked loads through registers
@@ -559,7 +603,7 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
       *reinterpret_cast<uint4*>(As0 + r * 128 + 16 * (c ^ (r & 7))) =
           ld16_masked(A + gi * lda, kk + 16 * c, k1);
     }
-    for (int e = tid; e < F8_LP * 8; e += 512) {
+    for (int e = tid; e < LP * 8; e += 512) {
       const int r = e >> 3, c = e & 7;
       *reinterpret_cast<uint4*>(Xs0 + r * 128 + 16 * (c ^ (r & 7))) =
           ld16_masked(X + (int64_t)r * ldx, kk + 16 * c, k1);
@@ -571,12 +615,12 @@ __global__ __launch_bounds__(512) void k_nn_fp8_dl(const u8* __restrict__ A, int
   // the register-staged kernel
   const int64_t rz = (rows + 127) / 128 * 128;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int col = wc * 64 + t * 32 + l32;
+  for (int t = 0; t < NW; ++t) {
+    const int col = wcol + t * 32 + l32;
     const float cs = sx[col];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int64_t rb = i0 + wr * 64 + a * 32;
+    for (int a = 0; a < MT; ++a) {
+      const int64_t rb = i0 + wrow + a * 32;
       if (rb >= rz) continue;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
@@ -697,13 +741,17 @@ static hipError_t launch_nn_fp8_slice(const uint8_t* A8, int64_t lda8, int64_t r
   if (tk % kQB != 0 || lda8 % 16 != 0 || ldx8 % 16 != 0 || ldy % 4 != 0)
     return hipErrorInvalidValue;
   const int nt = (int)(lp / 32);
-  // direct-to-LDS form: panel width 128, 16-byte aligned operands, 31-bit
-  // buffer offsets over 256 rows of A and the 128 panel columns
-  if (nt == 4 && ((uintptr_t)A8 & 15) == 0 && ((uintptr_t)X8 & 15) == 0 &&
-      (int64_t)F8_BM * lda8 <= INT32_MAX && (int64_t)F8_LP * ldx8 <= INT32_MAX) {
+  // direct-to-LDS form: panel widths 128 and 160, 16-byte aligned operands,
+  // 31-bit buffer offsets over 256 rows of A and the panel columns
+  if ((nt == 4 || nt == 5) && ((uintptr_t)A8 & 15) == 0 && ((uintptr_t)X8 & 15) == 0 &&
+      (int64_t)F8_BM * lda8 <= INT32_MAX && lp * ldx8 <= INT32_MAX) {
     dim3 grid((unsigned)ceil_div_dev(rows, F8_BM), (unsigned)TK);
-    hipLaunchKernelGGL(k_nn_fp8_dl, grid, dim3(512), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r, sc_k,
-                       X8, ldx8, sx, Y, ldy, part_stride);
+    if (nt == 4)
+      hipLaunchKernelGGL(k_nn_fp8_dl<4>, grid, dim3(512), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r,
+                         sc_k, X8, ldx8, sx, Y, ldy, part_stride);
+    else
+      hipLaunchKernelGGL(k_nn_fp8_dl<5>, grid, dim3(512), 0, s, A8, lda8, rows, kdim, tk, sA, sc_r,
+                         sc_k, X8, ldx8, sx, Y, ldy, part_stride);
     return hipGetLastError();
   }
   dim3 grid((unsigned)ceil_div_dev(rows, 128), (unsigned)TK);

@@ -31,6 +31,8 @@ SLAB_REL = 2.0 ** -8
     (136, 224, 120, (64, 128)),
     (640, 768, 230, (256, 256)),
     (512, 448, 330, (0, 0)),
+    (1000, 700, 150, (256, 192)),     # width 160: direct-to-LDS, three-stage ring
+    (640, 1536, 160, (128, 1408)),    # 11 whole slabs per A X tile (six-step loop + 5)
 ])
 def test_fp8_products_match_quantised_operands(m, n, l, tile):
     dev = need_gpu()
