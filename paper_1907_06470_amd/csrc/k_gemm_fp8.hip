@@ -30,6 +30,13 @@ typedef uint8_t u8;
 constexpr int kQB = 64;          // quantisation block edge (rows and columns)
 constexpr float kFp8Max = 448.f;
 
+// 16 bytes of A that is read once (non-temporal: leaves the caches to others)
+__device__ inline float4 ld4_nt(const float* p) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // 2^ceil(log2(amax / 448)), at least 2^-126 (a normal FP32 value, so that its
 // exponent field is the E8M0 byte of the matrix-core scale; only blocks with
 // amax below 448 * 2^-126 are affected, and they still fit e4m3)
@@ -148,8 +155,8 @@ __global__ __launch_bounds__(512) void k_cast_fp8_strip(const float* __restrict_
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int64_t i = i0 + 16 * wave + u;
-    if (full)
-      x[u] = ld4(A + i * lda + jc);
+    if (full)   // A is read once: a non-temporal load leaves the caches to others
+      x[u] = ld4_nt(A + i * lda + jc);
     else
       x[u] = (i < m && jc < n) ? ld4_masked(A + i * lda, jc, n) : make_float4(0.f, 0.f, 0.f, 0.f);
     amax = fmaxf(amax, fmaxf(fmaxf(fabsf(x[u].x), fabsf(x[u].y)), fmaxf(fabsf(x[u].z), fabsf(x[u].w))));
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(512) void k_cast_fp8_strip(const float* __restrict_
     w[u] = cvt2(x[u].x * inv, x[u].y * inv) | (cvt2(x[u].z * inv, x[u].w * inv) << 16);
     const int64_t i = i0 + 16 * wave + u;
     if (full) {
-      *reinterpret_cast<uint32_t*>(A8 + i * lda8 + jc) = w[u];
+      __builtin_nontemporal_store(w[u], reinterpret_cast<uint32_t*>(A8 + i * lda8 + jc));
     } else if (i < m && jc < n) {
       if (jc + 4 <= n && (lda8 & 3) == 0) {
         *reinterpret_cast<uint32_t*>(A8 + i * lda8 + jc) = w[u];
@@ -214,7 +221,8 @@ __global__ __launch_bounds__(512) void k_cast_fp8_strip(const float* __restrict_
     const int64_t j = j0 + c, i = i0 + 16 * t8;
     const uint4 v = *reinterpret_cast<const uint4*>(&Tt[p * TLD + 16 * t8]);
     if (full) {
-      *reinterpret_cast<uint4*>(A8T + j * ldat8 + i) = v;
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4*>(A8T + j * ldat8 + i));
     } else if (j < n && i < m) {
       if (i + 16 <= m && (ldat8 & 15) == 0) {
         *reinterpret_cast<uint4*>(A8T + j * ldat8 + i) = v;
