@@ -79,11 +79,23 @@ hipError_t launch_csr_check(const int32_t* ptr, const int32_t* idx, int64_t rows
 // block b.  A stable radix sort of the nonzeros by (block, column) keeps each
 // column's row order.  On a scratch shortfall returns hipErrorOutOfMemory with
 // the bytes needed in *need.
+// Head columns of the CSC copy (plan.h, kHeadCols): counts on sampled rows
+// (cnt, n entries), columns ranked by count (rk*, rv*: n-entry sort buffers),
+// headof[col] = rank (< head_k) or -1, headcol[rank] = col.
+hipError_t launch_head_select(const int32_t* rowptr, const int32_t* colind, int64_t m, int64_t n,
+                              int64_t nnz, int64_t head_k, uint32_t* cnt, int32_t* headof,
+                              int32_t* headcol, uint32_t* rk0, uint32_t* rk1, int32_t* rv0,
+                              int32_t* rv1, void* temp, size_t temp_bytes, size_t* need,
+                              hipStream_t s);
+// CSC copy with `parts` row blocks for the other columns and, when headof is
+// given, head_parts row blocks for the head_k head columns (compressed rows
+// parts n + b K + h after the others').
 hipError_t launch_build_csc(const int32_t* rowptr, const int32_t* colind, const float* values,
-                            int64_t m, int64_t n, int64_t nnz, int64_t parts, uint32_t* keys0,
-                            uint32_t* keys1, uint64_t* pay0, uint64_t* pay1, void* temp,
-                            size_t temp_bytes, int32_t* colptr, int32_t* rowind, float* cval,
-                            size_t* need, hipStream_t s);
+                            int64_t m, int64_t n, int64_t nnz, int64_t parts,
+                            const int32_t* headof, int64_t head_k, int64_t head_parts,
+                            uint32_t* keys0, uint32_t* keys1, uint64_t* pay0, uint64_t* pay1,
+                            void* temp, size_t temp_bytes, int32_t* colptr, int32_t* rowind,
+                            float* cval, size_t* need, hipStream_t s);
 hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_bits,
                              const float* values, int64_t m, int64_t n, int64_t nnz,
                              uint32_t* keys0, uint32_t* keys1, uint64_t* pay0, uint64_t* pay1,
@@ -93,10 +105,13 @@ hipError_t launch_coo_to_csr(const void* rowind, const void* colind, int index_b
 // form and X column-major (ldx); with parts > 1 the compressed rows are parts
 // blocks of `rows` rows, and row r of out sums row r of every block in block
 // order.  Xr, Yr, carry, first are scratch.
+// headcol / head_k / head_parts: the head columns of a CSC copy built with
+// them (their block results are added into out rows headcol[h]).
 hipError_t launch_spmm(const int32_t* ptr, const int32_t* idx, const float* val, int64_t rows,
                        int64_t parts, int64_t nnz, const float* X, int64_t ldx, int64_t xrows,
                        int64_t lp, float* Xr, float* Yr, float* carry, int32_t* first,
-                       float* out, int64_t ldo, hipStream_t s);
+                       float* out, int64_t ldo, hipStream_t s, const int32_t* headcol = nullptr,
+                       int64_t head_k = 0, int64_t head_parts = 0);
 
 // --- small dense FP64 steps (k_small.hip) ---
 hipError_t launch_gram(const float* P, int64_t ld, int64_t rows, int64_t lp, int64_t chunk_rows,

@@ -265,12 +265,31 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (p.csr) {
     p.chunks = spmm_chunk_count(prob.nnz);
     p.csc_parts = csc_part_count(m, n, p.lp);
+    p.head_k = std::min<int64_t>(kHeadCols, n);
+    p.head_parts = ceil_div(m, kHeadPartRows);
+    // compressed rows of the CSC copy: b n + j for the other columns, then
+    // P n + b' K + h for the head columns (32-bit sort keys, int32 rows); a
+    // matrix too tall for the head blocks goes without them
+    if (p.head_k < 1 || p.head_parts < 1 ||
+        p.csc_parts * n + p.head_parts * p.head_k > (int64_t)INT32_MAX - 1)
+      p.head_k = p.head_parts = 0;
+    if (p.csc_parts * n > (int64_t)INT32_MAX - 1)
+      return fail(p, RSVD_E_UNSUPPORTED, "sparse A with %lld columns is too wide for 32-bit keys",
+                  (long long)n);
+    const int64_t nv = p.csc_parts * n + p.head_parts * p.head_k;
     const size_t nnz = (size_t)prob.nnz;
     // Xr: the row-major operand (n rows for A X, m for A^T Q); Yr: the
-    // compressed rows of the result (m, or n per CSC row block)
+    // compressed rows of the result (m, or the CSC copy's compressed rows)
     const size_t xrows = (size_t)std::max<int64_t>(m, n);
-    const size_t yrows = (size_t)std::max<int64_t>(m, p.csc_parts * n);
-    w.colptr = take((size_t)(p.csc_parts * n + 1) * 4);
+    const size_t yrows = (size_t)std::max<int64_t>(m, nv);
+    w.colptr = take((size_t)(nv + 1) * 4);
+    w.colcnt = take((size_t)n * 4);
+    w.headof = take((size_t)n * 4);
+    w.headcol = take((size_t)p.head_k * 4);
+    w.rk0 = take((size_t)n * 4);
+    w.rk1 = take((size_t)n * 4);
+    w.rv0 = take((size_t)n * 4);
+    w.rv1 = take((size_t)n * 4);
     w.rowind = take(nnz * 4);
     w.cval = take(nnz * 4);
     w.keys0 = take(nnz * 4);
@@ -285,6 +304,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
     w.first = take((size_t)p.chunks * 4);
   } else {
     w.colptr = w.rowind = w.cval = w.keys0 = w.keys1 = w.pay0 = w.pay1 = w.sort_temp = off;
+    w.colcnt = w.headof = w.headcol = w.rk0 = w.rk1 = w.rv0 = w.rv1 = off;
     w.Xr = w.Yr = w.carry = w.first = off;
   }
   if (p.coo) {

@@ -85,6 +85,9 @@ struct Workspace {
   size_t slots;           // host-resident A: S tile slots of slot_bytes each
   // CSR input: CSC copy, sort buffers, row-major operand/result, chunk carries
   size_t colptr, rowind, cval, keys0, keys1, pay0, pay1, sort_temp;
+  // head columns of the CSC copy: sampled column counts, column -> head index,
+  // head index -> column, and the rank sort's buffers
+  size_t colcnt, headof, headcol, rk0, rk1, rv0, rv1;
   size_t coo_ptr, coo_col, coo_val;   // CSR arrays built from COO input
   size_t Xr, Yr, carry, first;
   size_t total;
@@ -115,6 +118,8 @@ struct Plan {
   double q_tol = 0.0;
   int64_t chunks = 0;           // nonzero chunks of the sparse products
   int64_t csc_parts = 1;        // row blocks of the CSC copy (A^T Q gathers within one)
+  int64_t head_k = 0;           // head columns of the CSC copy (their own small row blocks)
+  int64_t head_parts = 0;       // row blocks of the head columns
   size_t sort_temp = 0;         // scratch reserved for the CSC sort
   int64_t slots = 0;            // HBM tile slots (host-resident A)
   int64_t slot_ld = 0;          // leading dimension (elements) of a slot
@@ -164,6 +169,14 @@ int64_t spmm_chunk_count(int64_t nnz);
 // row blocks of the CSC copy: the rows of Q one block's columns gather from
 // stay within kCscSliceBytes, so that they are served from the caches
 int64_t csc_part_count(int64_t m, int64_t n, int64_t lp);
+// Head columns of A^T products: the kHeadCols columns with the most nonzeros
+// (counted on every kHeadSampleStride-th row) get compressed rows of their
+// own per block of kHeadPartRows rows of A; a product stages such a block's
+// panel rows in LDS once and runs every head column's entries of the block
+// against it.  The other columns keep the csc_part_count row blocks.
+constexpr int64_t kHeadCols = 512;
+constexpr int64_t kHeadPartRows = 512;
+constexpr int64_t kHeadSampleStride = 16;
 size_t csc_sort_scratch(int64_t nnz);
 
 }  // namespace rsvd

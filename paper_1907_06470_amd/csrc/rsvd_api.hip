@@ -157,7 +157,8 @@ struct Buffers {
   uint8_t *A8, *A8T, *Xop8, *Mop8;
   float *sA8, *sX8, *sM8, *f8part;
   char* slots;
-  int32_t *colptr, *rowind, *first;
+  int32_t *colptr, *rowind, *first, *headof, *headcol, *rv0, *rv1;
+  uint32_t *colcnt, *rk0, *rk1;
   float *cval, *Xr, *Yr, *carry;
   uint32_t *keys0, *keys1;
   uint64_t *pay0, *pay1;
@@ -201,6 +202,13 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.f8part = (float*)(b + w.f8part);
   B.slots = b + w.slots;
   B.colptr = (int32_t*)(b + w.colptr);
+  B.headof = (int32_t*)(b + w.headof);
+  B.headcol = (int32_t*)(b + w.headcol);
+  B.rv0 = (int32_t*)(b + w.rv0);
+  B.rv1 = (int32_t*)(b + w.rv1);
+  B.colcnt = (uint32_t*)(b + w.colcnt);
+  B.rk0 = (uint32_t*)(b + w.rk0);
+  B.rk1 = (uint32_t*)(b + w.rk1);
   B.rowind = (int32_t*)(b + w.rowind);
   B.first = (int32_t*)(b + w.first);
   B.cval = (float*)(b + w.cval);
@@ -435,10 +443,21 @@ struct Runner {
     const int64_t m = P.prob.m, n = P.prob.n, nnz = P.prob.nnz;
     RSVD_HIP(rsvd::launch_csr_check(rp, ci, m, n, nnz, B.status, s));
     size_t need = 0;
-    const hipError_t e = rsvd::launch_build_csc(rp, ci, v, m, n, nnz, P.csc_parts, B.keys0,
-                                                B.keys1, B.pay0, B.pay1, B.sort_temp,
-                                                P.sort_temp, B.colptr, B.rowind, B.cval, &need,
-                                                s);
+    if (P.head_k > 0) {
+      const hipError_t eh = rsvd::launch_head_select(rp, ci, m, n, nnz, P.head_k, B.colcnt,
+                                                     B.headof, B.headcol, B.rk0, B.rk1, B.rv0,
+                                                     B.rv1, B.sort_temp, P.sort_temp, &need, s);
+      if (eh == hipErrorOutOfMemory && need > P.sort_temp)
+        return set_err(h, RSVD_E_BUDGET,
+                       "the column ranking needs " + std::to_string(need) + " bytes of scratch, "
+                       "the plan reserved " + std::to_string(P.sort_temp));
+      RSVD_HIP(eh);
+    }
+    const hipError_t e = rsvd::launch_build_csc(rp, ci, v, m, n, nnz, P.csc_parts,
+                                                P.head_k > 0 ? B.headof : nullptr, P.head_k,
+                                                P.head_parts, B.keys0, B.keys1, B.pay0, B.pay1,
+                                                B.sort_temp, P.sort_temp, B.colptr, B.rowind,
+                                                B.cval, &need, s);
     if (e == hipErrorOutOfMemory && need > P.sort_temp)
       return set_err(h, RSVD_E_BUDGET,
                      "the CSC sort needs " + std::to_string(need) + " bytes of scratch, the plan "
@@ -597,7 +616,7 @@ struct Runner {
       RSVD_HIP(tick(false, true));
       RSVD_HIP(rsvd::launch_spmm(B.colptr, B.rowind, B.cval, P.prob.n, P.csc_parts, P.prob.nnz,
                                  Q, P.ldm, P.prob.m, P.lp, B.Xr, B.Yr, B.carry, B.first, out,
-                                 P.ldn, s));
+                                 P.ldn, s, B.headcol, P.head_k, P.head_parts));
       RSVD_HIP(tick(false, false));
       return RSVD_OK;
     }

@@ -65,6 +65,40 @@ def test_sparse_products_match_scipy(m, n, per_row, l, drop):
     assert np.array_equal(Z, Z2)
 
 
+def test_sparse_head_block_edges():
+    """A^T Q through the head columns' LDS blocks of 512 rows: a last block of
+    one row, a column with an entry in every row, empty columns and a column
+    whose only entry is in the last row, next to Zipf columns."""
+    dev = need_gpu()
+    m, n, l = 3 * 512 + 1, 700, 96
+    say("spmm head edges", m, n, l)
+    rp, ci, v, Z0 = _csr(m, n, 9, seed=11)
+    M = sp.lil_matrix(Z0)
+    M[:, 0:4] = 0.0                                   # empty columns
+    M[:, 5] = np.linspace(0.5, 1.5, m)[:, None]       # an entry in every row
+    M[:, 10] = 0.0
+    M[m - 1, 10] = 3.0                                # only in the last row
+    M = sp.csr_matrix(M)
+    M.eliminate_zeros()
+    M.sort_indices()
+    rp = torch.as_tensor(M.indptr.astype(np.int32))
+    ci = torch.as_tensor(M.indices.astype(np.int32))
+    v = torch.as_tensor(M.data.astype(np.float32))
+    M = sp.csr_matrix((v.numpy().astype(np.float64), ci.numpy(), rp.numpy()), shape=(m, n))
+    k = l // 2
+    plan = Plan(m, n, k, l - k, 1, nnz=int(ci.numel()))
+    args = (rp.to(dev), ci.to(dev), v.to(dev))
+    Q = rand_panel(m, l, 5)
+    Z = plan.step_spmm(1, *args, col_major_from_numpy(Q, dev)).cpu().numpy().astype(np.float64)
+    ref = M.T @ Q.astype(np.float64)
+    K = int(np.max(np.diff(M.tocsc().indptr))) + 2 + 16
+    assert np.all(np.abs(Z - ref) <= gamma_bound(K, abs(M).T @ np.abs(Q)) + 1e-30)
+    # one entry: one rounded product, then sums of exact zeros
+    assert not np.any(Z[0:4]) and np.array_equal(Z[10], (np.float32(3.0) * Q[m - 1]).astype(np.float64))
+    Z2 = plan.step_spmm(1, *args, col_major_from_numpy(Q, dev)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(Z, Z2)
+
+
 def test_sparse_factor_matches_oracle_and_is_reproducible():
     dev = need_gpu()
     m, n, per_row = 12000, 4000, 30
