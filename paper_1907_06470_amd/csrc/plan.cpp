@@ -29,7 +29,7 @@ static rsvd_status fail(Plan& p, rsvd_status s, const char* fmt, long long a = 0
 int64_t spmm_chunk_count(int64_t nnz) { return std::max<int64_t>(1, ceil_div(nnz, kSpmmChunk)); }
 
 int64_t csc_part_count(int64_t m, int64_t n, int64_t lp) {
-  constexpr int64_t kCscSliceBytes = int64_t(128) << 20;
+  constexpr int64_t kCscSliceBytes = int64_t(1024) << 20;
   constexpr int64_t kMaxParts = 16;
   int64_t parts = std::max<int64_t>(1, ceil_div(m * lp * 4, kCscSliceBytes));
   parts = std::min(parts, kMaxParts);

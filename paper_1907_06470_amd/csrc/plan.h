@@ -166,8 +166,12 @@ rsvd_options default_options();
 // sparse products: nonzero chunks and the scratch reserved for the CSC sort
 // (host-side mirrors of the constants in k_sparse.hip)
 int64_t spmm_chunk_count(int64_t nnz);
-// row blocks of the CSC copy: the rows of Q one block's columns gather from
-// stay within kCscSliceBytes, so that they are served from the caches
+// row blocks of the CSC copy (for the columns outside the head set): the
+// rows of Q one block's columns gather from stay within kCscSliceBytes.
+// Smaller blocks keep more of those gathers in the last-level cache but add
+// a partial result row per (block, column) that is written and read back;
+// 1 GiB slices (3 blocks for 2e6 x 352) measured best on a 1e8-entry Zipf
+// matrix, against 16 blocks of 128 MiB
 int64_t csc_part_count(int64_t m, int64_t n, int64_t lp);
 // Head columns of A^T products: the kHeadCols columns with the most nonzeros
 // (counted on every kHeadSampleStride-th row) get compressed rows of their

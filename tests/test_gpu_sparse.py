@@ -40,7 +40,8 @@ def _csr(m, n, per_row, seed, drop_rows=0):
     (7000, 9000, 13, 100, 3),      # empty rows, unused columns, wide panel
     (300, 200, 1, 20, 0),          # fewer nonzeros than one chunk
     (5000, 3000, 37, 190, 7),      # widest panel (three columns per lane)
-    (200000, 3000, 3, 190, 5),     # tall: the CSC copy is split into two row blocks
+    (200000, 3000, 3, 190, 5),     # tall, 391 head blocks of 512 rows
+    (1200000, 3000, 2, 230, 5),    # taller: the CSC copy is split into two row blocks
     (20000, 6000, 25, 330, 0),     # wide sketch: two column slices of 192 and 138
 ])
 def test_sparse_products_match_scipy(m, n, per_row, l, drop):
