@@ -48,15 +48,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_file, summary):
-    """HBM bytes per launch from a committed counter summary, or None when the
-    kernel source changed after the counters were taken."""
+def measured_traffic(kernel_files, summary):
+    """HBM bytes per launch from a committed counter summary, or None when a
+    source the traffic depends on changed after the counters were taken (the
+    summary's source_sha256 is the SHA-256 of those files, concatenated in the
+    order given)."""
     import hashlib
+    if isinstance(kernel_files, str):
+        kernel_files = (kernel_files,)
     path = os.path.join(PROFILES, summary)
-    src = os.path.join(ROOT, "paper_1907_06470_amd", "csrc", kernel_file)
-    if not (os.path.exists(path) and os.path.exists(src)):
+    srcs = [os.path.join(ROOT, "paper_1907_06470_amd", "csrc", f) for f in kernel_files]
+    if not (os.path.exists(path) and all(os.path.exists(f) for f in srcs)):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
     fields = {}
     for line in open(path):
         if ":" in line and line.lstrip().startswith("- "):
@@ -437,7 +441,8 @@ def bench_sparse(args, dev):
         f"A^T Q {tn_ms:.3f} ms ({tn_gbs:.0f} GB/s), stages "
         f"{[round(x, 3) for x in infos[-1]['stage_ms']]}, properties {props}")
     # measured HBM traffic of one A^T Q product (committed counter summary)
-    traffic = measured_traffic("k_sparse.hip", f"counters_k_spmm_chunk_sparse_{m}x{n}.md") \
+    traffic = measured_traffic(("k_sparse.hip", "plan.cpp"),
+                               f"counters_k_spmm_chunk_sparse_{m}x{n}.md") \
         if dom[0].startswith("A^T Q") and l == 330 else None
     cpu = None
     if not args.no_cpu_baseline:
@@ -472,8 +477,9 @@ def bench_sparse(args, dev):
                      "unit": "GB/s", "frac": round(dom[3] / PEAK["hbm_GBs"], 4),
                      "traffic": traffic,
                      "traffic_GBs": round(traffic / (dom[1] * 1e-3) / 1e9, 1) if traffic else None,
-                     "kernel": f"sparse product {dom[0]}: layout change, chunk products "
-                               "and carries of every column slice",
+                     "kernel": f"sparse product {dom[0]}: for every column slice the layout "
+                               "change, the chunk products and carries, and (A^T Q) the head "
+                               "columns' LDS blocks and their block sums",
                      "launch_ms": round(dom[1], 4),
                      "per_launch": f"compressed arrays + X once + Y once (FP32) = {dom[2]} bytes; "
                                    "traffic: measured bytes of the same product (row gathers)"},
