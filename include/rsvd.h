@@ -61,7 +61,10 @@ enum {
   RSVD_FLAG_NO_SIGN_FIX = 1,   /* skip the sign convention                          */
   RSVD_FLAG_CHOLQR1 = 2,       /* one CholeskyQR pass for intermediate bases        */
   RSVD_FLAG_BACKWARD = 4,      /* size the workspace for rsvd_backward too          */
-  RSVD_FLAG_AUTO_Q = 8         /* choose q <= prob.q automatically (q_tol)          */
+  RSVD_FLAG_AUTO_Q = 8,        /* choose q <= prob.q automatically (q_tol)          */
+  RSVD_FLAG_JACOBI_ONLY = 16   /* small SVD by Cholesky and one-sided Jacobi only,
+                                  also at widths <= 128 (where the tridiagonal
+                                  eigensolver runs first by default)              */
 };
 
 /* The problem: A is m x n, rank k, oversampling p, q power steps

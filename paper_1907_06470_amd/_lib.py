@@ -26,7 +26,7 @@ DENSE, CSR, COO = 0, 1, 2
 F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
 LOC_DEVICE, LOC_HOST_PINNED = 0, 1
 ORTHO_EACH, ORTHO_FINAL_ONLY = 0, 2
-FLAG_NO_SIGN_FIX, FLAG_CHOLQR1, FLAG_BACKWARD, FLAG_AUTO_Q = 1, 2, 4, 8
+FLAG_NO_SIGN_FIX, FLAG_CHOLQR1, FLAG_BACKWARD, FLAG_AUTO_Q, FLAG_JACOBI_ONLY = 1, 2, 4, 8, 16
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 c_vp, c_sz = ctypes.c_void_p, ctypes.c_size_t

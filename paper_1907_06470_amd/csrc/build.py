@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["plan.cpp", "k_philox.hip", "k_gemm_f32.hip", "k_gemm_bf16.hip", "k_gemm_fp8.hip", "k_small.hip", "k_chol.hip", "k_bjacobi.hip", "k_sparse.hip",
+SOURCES = ["plan.cpp", "k_philox.hip", "k_gemm_f32.hip", "k_gemm_bf16.hip", "k_gemm_fp8.hip", "k_small.hip", "k_chol.hip", "k_bjacobi.hip", "k_trieig.hip", "k_sparse.hip",
            "k_adjoint.hip", "k_resid.hip", "rsvd_api.hip"]
 LIB = os.path.join(PKG, "librsvd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -182,7 +182,9 @@ __device__ void inverse_tile(double* S, const double* Xd, int I, int J) {
 __global__ __launch_bounds__(kThreads) void k_chol16(const double* __restrict__ G, int64_t lp,
                                                      int l, float* __restrict__ W,
                                                      double* __restrict__ Lout,
-                                                     int32_t* __restrict__ status, double tau) {
+                                                     int32_t* __restrict__ status, double tau,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;   // the whole workgroup: the small SVD is already done
   __shared__ double S[kSq * kSq];
   __shared__ double Xd[kNbMax * kB * kB];
   __shared__ double dinv[kSq];
@@ -684,9 +686,10 @@ __global__ void k_cg_lout(double* __restrict__ S, int64_t lp, int l) {
 bool chol16_fits(int64_t lp) { return lp <= kSq; }
 
 hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, double* L,
-                         int32_t* status, double tau, hipStream_t s) {
+                         int32_t* status, double tau, hipStream_t s, const int32_t* skip) {
   if (lp > kSq || lp % kB != 0 || l > lp || l < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol16, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, L, status, tau);
+  hipLaunchKernelGGL(k_chol16, dim3(1), dim3(kThreads), 0, s, G, lp, (int)l, W, L, status, tau,
+                     skip);
   return hipGetLastError();
 }
 

@@ -670,7 +670,9 @@ __device__ inline bool oj_idle(int pos, int par, int nb) {
 __global__ __launch_bounds__(kOjThreads) void k_ojacobi(const double* __restrict__ L, int64_t lp,
                                                         int l, double* __restrict__ lam,
                                                         double* __restrict__ Ev, int32_t* status,
-                                                        double tol, int max_sweeps) {
+                                                        double tol, int max_sweeps,
+                                                        const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;   // the whole workgroup: the small SVD is already done
   __shared__ double M[kOjMaxLp * kOjLd];   // block at position p: columns 2p, 2p + 1
   __shared__ int blk[kOjMaxLp / 2];        // block (pair of original columns) at position p
   __shared__ double nrm[kOjMaxLp];         // squared column norms of the block at position p
@@ -1160,16 +1162,18 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
 bool small_svd_one_sided(int64_t lp) { return lp <= kOjMaxLp; }
 
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
-                              double tau, hipStream_t s) {
-  if (chol16_fits(lp)) return launch_chol16(G, lp, l, nullptr, L, status, tau, s);
+                              double tau, hipStream_t s, const int32_t* skip) {
+  if (chol16_fits(lp)) return launch_chol16(G, lp, l, nullptr, L, status, tau, s, skip);
+  if (skip) return hipErrorInvalidValue;   // the tridiagonal path covers widths <= 128 only
   return launch_chol_gm(G, lp, l, L, nullptr, L, status, tau, s);
 }
 
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
-                          int32_t* status, double tol, int max_sweeps, hipStream_t s) {
+                          int32_t* status, double tol, int max_sweeps, hipStream_t s,
+                          const int32_t* skip) {
   if (lp > kOjMaxLp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ojacobi, dim3(1), dim3(kOjThreads), 0, s, L, lp, (int)l, lam, Ev, status,
-                     tol, max_sweeps);
+                     tol, max_sweeps, skip);
   return hipGetLastError();
 }
 

@@ -1,0 +1,559 @@
+// Small SVD of Section 2.1 step 6 through the symmetric eigenproblem of the
+// FP64 Gram C = B B^T (order n = l <= 128; its two triangles are averaged,
+// since a congruence Wp^T G Wp is symmetric only to rounding), in one
+// workgroup:
+//
+//   1. Householder reduction Q^T C Q = T (tridiagonal).  C is held in
+//      registers on a 32 x 32 thread grid (thread (r, c) owns rows r + 32 i
+//      and columns c + 32 j, i, j < 4); each step forms the reflector from the
+//      column below the diagonal, p = tau A v (row sums over a half-wave),
+//      w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T.  The reflectors are
+//      kept in LDS.  Sums across lanes go through DPP permutes.
+//   2. Eigenvalues of T by bisection on the Sturm count (the number of
+//      negative pivots of T - x I), eight lanes per eigenvalue cutting the
+//      interval into nine parts per round; 17 rounds take the Gershgorin
+//      interval below FP64 resolution.
+//   3. Eigenvectors of T by inverse iteration, one lane per eigenvalue: the
+//      LU factors of T - lambda I with row interchanges (the LAPACK gttrf
+//      pattern) go to a global scratch laid out [array][row][lane], then two
+//      solves from a fixed pseudo-random start, normalising in between.
+//   4. Back-transformation W = Q Z, the reflectors applied in reverse order
+//      (column sums: partials over the thread grid in LDS, then one thread
+//      per column).
+//   5. Checks: |W^T W - I| <= 1e-12 (the accuracy the one-sided Jacobi path
+//      reaches) and, for a fixed pseudo-random y, |C (W y) - W (diag(lambda)
+//      y)| <= 1e-12 lambda_max |y|_1, with every value finite.  status[kStTriOk] says whether they held; the Cholesky
+//      and Jacobi kernels launched after this one run only when they did
+//      not (close or repeated eigenvalues, where independent inverse
+//      iterations lose orthogonality, or non-finite input).
+//
+// Outputs as the Jacobi path writes them: lam[c] = eigenvalue c (zero from n
+// on), Ev row-major lp x lp with column c the unit eigenvector (zero rows
+// and columns from n on).
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int kTeN = (int)kTriMaxLp;             // largest order
+constexpr int kTeR = 4;                          // rows (columns) per thread
+constexpr int kTeRounds = 17;                    // 9^17 > 2^52
+constexpr int kTePacked = kTeN * (kTeN - 1) / 2; // reflector store (doubles)
+constexpr double kTeTol = 1e-12;
+constexpr int kTeArrays = 6;                     // dl, dd, du, du2, pivot, x
+static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scratch layout");
+
+__device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
+
+__device__ inline double te_sel(const double (&a)[kTeR], int c) {
+  return c == 0 ? a[0] : c == 1 ? a[1] : c == 2 ? a[2] : a[3];
+}
+
+// Cross-lane sums through DPP lane permutes (no LDS round trips); every lane
+// of a row (half-wave, wave) ends with the same bits, since each step adds
+// the same two operands in every lane.
+template <int kCtrl>
+__device__ inline double te_dpp(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kCtrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ inline double te_row_sum(double x) {   // over the 16 lanes of a row
+  x += te_dpp<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += te_dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += te_dpp<0x141>(x);   // row_half_mirror
+  x += te_dpp<0x140>(x);   // row_mirror
+  return x;
+}
+
+__device__ inline double te_lane(double x, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline double te_half_sum(double x) {   // over the 32 lanes of a half-wave
+  x = te_row_sum(x);
+  const double s0 = te_lane(x, 0) + te_lane(x, 16), s1 = te_lane(x, 32) + te_lane(x, 48);
+  return (threadIdx.x & 32) ? s1 : s0;
+}
+
+__device__ inline double te_wave_sum(double x) {
+  x = te_row_sum(x);
+  return (te_lane(x, 0) + te_lane(x, 16)) + (te_lane(x, 32) + te_lane(x, 48));
+}
+
+// 1 / q: the hardware reciprocal and one Newton step
+__device__ inline double te_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  return fma(fma(-q, r, 1.0), r, r);
+}
+
+__device__ inline void te_sturm_step(double d, double e2, double x, double pivmin, double& q,
+                                     int& cnt) {
+  q = (d - x) - e2 * te_rcp(q);
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+}
+
+// number of eigenvalues of T below x (negative pivots of T - x I)
+__device__ inline int te_sturm(const double* dS, const double* e2S, int n, double x,
+                               double pivmin) {
+  double q = dS[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  int i = 1;
+  for (; i + 4 <= n; i += 4) {
+    double d[4], e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      d[u] = dS[i + u];
+      e[u] = e2S[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) te_sturm_step(d[u], e[u], x, pivmin, q, cnt);
+  }
+  for (; i < n; ++i) te_sturm_step(dS[i], e2S[i - 1], x, pivmin, q, cnt);
+  return cnt;
+}
+
+// fixed pseudo-random start vector entry in [-1, 1)
+__device__ inline double te_start(int i, int j) {
+  uint32_t h = (uint32_t)(i + 1) * 0x9E3779B1u ^ (uint32_t)(j + 1) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return (double)(h >> 8) * (2.0 / 16777216.0) - 1.0;
+}
+
+__global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, int64_t lp, int n,
+                                                  double* __restrict__ lam,
+                                                  double* __restrict__ Ev,
+                                                  double* __restrict__ scr,
+                                                  int32_t* __restrict__ status) {
+  __shared__ double big[kTeN * kTeN];   // reflectors, then W
+  __shared__ double xsb[2 * kTeN], ps[kTeN];
+  __shared__ double dS[kTeN], eS[kTeN], e2S[kTeN], tauS[kTeN], lamS[kTeN], znS[kTeN];
+  __shared__ double shv[4];
+  double* vst = big;
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, l64 = tid & 63;
+  // scratch arrays: 0 multiplier, 1 reciprocal pivot, 2 and 3 the two super
+  // diagonals of U, 4 interchange flag, 5 right-hand side / solution
+  double* const sa[kTeArrays] = {scr, scr + kTeN * kTeN, scr + 2 * kTeN * kTeN,
+                                 scr + 3 * kTeN * kTeN, scr + 4 * kTeN * kTeN,
+                                 scr + 5 * kTeN * kTeN};
+
+  double A[kTeR][kTeR];
+#pragma unroll
+  for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+    for (int c = 0; c < kTeR; ++c) {
+      const int i = tr + 32 * r, j = tc + 32 * c;
+      A[r][c] = (i < n && j < n) ? 0.5 * (G[(int64_t)i * lp + j] + G[(int64_t)j * lp + i]) : 0.0;
+    }
+  for (int i = tid; i < kTeN; i += 1024) {
+    ps[i] = 0.0;
+    eS[i] = 0.0;
+    e2S[i] = 0.0;
+    tauS[i] = 0.0;
+  }
+  __syncthreads();
+
+  // 1. tridiagonal reduction, two barriers a step: every wave forms the
+  // reflector and the scalar K itself (same bits in every wave); the column
+  // below the diagonal alternates between two buffers so that the next
+  // step's owner never overwrites one still being read
+  for (int k = 0; k + 2 < n; ++k) {
+    double* xk = xsb + (k & 1) * kTeN;
+    const int kc = k >> 5;
+    if (tc == (k & 31)) {
+#pragma unroll
+      for (int r = 0; r < kTeR; ++r) {
+        const int i = tr + 32 * r;
+        const double x = te_sel(A[r], kc);
+        if (i > k && i < n) xk[i] = x;
+        if (i == k) dS[k] = x;
+      }
+    }
+    __syncthreads();
+    double sg = 0.0;
+    {
+      const int i0 = k + 2 + l64, i1 = i0 + 64;
+      if (i0 < n) sg += xk[i0] * xk[i0];
+      if (i1 < n) sg += xk[i1] * xk[i1];
+    }
+    sg = te_wave_sum(sg);
+    const double al = xk[k + 1];
+    double tau = 0.0, beta = al, sc = 0.0;
+    if (sg > 0.0) {
+      const double mu = sqrt(al * al + sg);
+      beta = al >= 0.0 ? -mu : mu;
+      sc = 1.0 / (al - beta);
+      tau = (beta - al) / beta;
+    }
+    auto vof = [&](int i) -> double {
+      return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
+    };
+    double vi[kTeR], vj[kTeR];
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r) {
+      vi[r] = vof(tr + 32 * r);
+      vj[r] = vof(tc + 32 * r);
+    }
+    if (tid < 64) {
+      for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
+      if (tid == 0) {
+        tauS[k] = tau;
+        eS[k] = beta;
+      }
+    }
+    double pr[kTeR];
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < kTeR; ++c) s += A[r][c] * vj[c];
+      pr[r] = te_half_sum(s);
+    }
+    if (tc == 0) {
+#pragma unroll
+      for (int r = 0; r < kTeR; ++r) {
+        const int i = tr + 32 * r;
+        if (i < n) ps[i] = i > k ? tau * pr[r] : 0.0;
+      }
+    }
+    __syncthreads();
+    double kk = 0.0;
+    if (l64 < n) kk += ps[l64] * vof(l64);
+    if (l64 + 64 < n) kk += ps[l64 + 64] * vof(l64 + 64);
+    const double K = 0.5 * tau * te_wave_sum(kk);
+    double wi[kTeR], wj[kTeR];
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r) {
+      const int i = tr + 32 * r, j = tc + 32 * r;
+      wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
+      wj[r] = j < n ? ps[j] - K * vj[r] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+      for (int c = 0; c < kTeR; ++c) A[r][c] -= vi[r] * wj[c] + wi[r] * vj[c];
+  }
+  // the last 2 x 2 block (or the single entry)
+#pragma unroll
+  for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+    for (int c = 0; c < kTeR; ++c) {
+      const int i = tr + 32 * r, j = tc + 32 * c;
+      if (i == j && i >= n - 2 && i < n) dS[i] = A[r][c];
+      if (n >= 2 && i == n - 1 && j == n - 2) eS[n - 2] = A[r][c];
+    }
+  __syncthreads();
+  for (int i = tid; i + 1 < n; i += 1024) e2S[i] = eS[i] * eS[i];
+  if (tid < 64) {   // Gershgorin interval, |T| and the pivot floor
+    double lo = __builtin_inf(), hi = -__builtin_inf(), em = 0.0;
+    for (int i = tid; i < n; i += 64) {
+      const double rad = (i > 0 ? fabs(eS[i - 1]) : 0.0) + (i + 1 < n ? fabs(eS[i]) : 0.0);
+      lo = fmin(lo, dS[i] - rad);
+      hi = fmax(hi, dS[i] + rad);
+      if (i + 1 < n) em = fmax(em, eS[i] * eS[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      em = fmax(em, __shfl_xor(em, o, 64));
+    }
+    if (tid == 0) {
+      const double tn = fmax(fabs(lo), fabs(hi));
+      const double w = fmax(tn, 1e-300) * 4.0 * 2.220446049250313e-16;
+      shv[0] = lo - w;
+      shv[1] = hi + w;
+      shv[2] = 2.2250738585072014e-308 * fmax(1.0, em);
+      shv[3] = tn;
+    }
+  }
+  __syncthreads();
+
+  // 2. eigenvalues: group of 8 lanes per eigenvalue j (ascending)
+  {
+    const int j = tid >> 3, s = tid & 7;
+    double a = shv[0], b = shv[1];
+    const double pivmin = shv[2];
+    for (int round = 0; round < kTeRounds; ++round) {
+      const double x = a + (b - a) * (double)(s + 1) * (1.0 / 9.0);
+      const int cnt = j < n ? te_sturm(dS, e2S, n, x, pivmin) : 0;
+      int smax = cnt <= j ? s : -1;   // count(a) <= j < count(b)
+      for (int o = 1; o < 8; o <<= 1) smax = max(smax, __shfl_xor(smax, o, 8));
+      const double xl = __shfl(x, smax < 0 ? 0 : smax, 8);
+      const double xh = __shfl(x, smax < 7 ? smax + 1 : 7, 8);
+      if (smax >= 0) a = xl;
+      if (smax < 7) b = xh;
+    }
+    if (s == 0 && j < n) lamS[j] = 0.5 * (a + b);
+  }
+  __syncthreads();
+
+  // 3. inverse iteration, lane j = eigenvector j
+  if (tid < n) {
+    const int j = tid;
+    const double lj = lamS[j];
+    // only an exactly zero pivot is replaced (by the Sturm pivot floor):
+    // raising small pivots to eps |T| caps the growth that makes the
+    // iteration converge for eigenvalues far below |T| (their vectors lose
+    // orthogonality to ~1e-11); an overflow instead fails the checks
+    const double tiny = shv[2];
+    double* const dl = sa[0] + j;
+    double* const rp = sa[1] + j;
+    double* const u1 = sa[2] + j;
+    double* const u2 = sa[3] + j;
+    double* const pv = sa[4] + j;
+    double* const X = sa[5] + j;
+    // factor T - lj I = P L U, transforming the start vector on the way
+    double dd = dS[0] - lj, du = n > 1 ? eS[0] : 0.0, xi = te_start(0, j);
+    for (int i = 0; i + 1 < n; ++i) {
+      if (dd == 0.0) dd = tiny;
+      const double sub = eS[i], dn = dS[i + 1] - lj, un = i + 2 < n ? eS[i + 1] : 0.0;
+      const double bn = te_start(i + 1, j);
+      const int o = i * kTeN;
+      if (fabs(dd) >= fabs(sub)) {
+        const double r = te_rcp(dd), f = sub * r;
+        dl[o] = f;
+        rp[o] = r;
+        u1[o] = du;
+        u2[o] = 0.0;
+        pv[o] = 0.0;
+        X[o] = xi;
+        dd = dn - f * du;
+        du = un;
+        xi = bn - f * xi;
+      } else {
+        const double r = te_rcp(sub), f = dd * r;
+        dl[o] = f;
+        rp[o] = r;
+        u1[o] = dn;
+        u2[o] = un;
+        pv[o] = 1.0;
+        X[o] = bn;
+        const double ndd = du - f * dn;
+        du = -f * un;
+        xi = xi - f * bn;
+        dd = ndd;
+      }
+    }
+    if (dd == 0.0) dd = tiny;
+    {
+      const int o = (n - 1) * kTeN;
+      rp[o] = te_rcp(dd);
+      u1[o] = 0.0;
+      u2[o] = 0.0;
+      X[o] = xi;
+    }
+    double scale = 1.0;
+    for (int it = 0; it < 2; ++it) {
+      if (it > 0) {   // forward pass on the normalised previous solution
+        double bi = X[0] * scale;
+        for (int i = 0; i + 1 < n; ++i) {
+          const int o = i * kTeN;
+          const double f = dl[o], bn = X[o + kTeN] * scale;
+          if (pv[o] != 0.0) {
+            X[o] = bn;
+            bi = bi - f * bn;
+          } else {
+            X[o] = bi;
+            bi = bn - f * bi;
+          }
+        }
+        X[(n - 1) * kTeN] = bi;
+      }
+      // back substitution with U (reciprocal pivots, super diagonals), four
+      // rows at a time with their loads issued together
+      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+      int i = n - 1;
+      for (; i >= 3; i -= 4) {
+        double b[4], a1[4], a2[4], rr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int o = (i - u) * kTeN;
+          b[u] = X[o];
+          a1[u] = u1[o];
+          a2[u] = u2[o];
+          rr[u] = rp[o];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double x = (b[u] - a1[u] * x1 - a2[u] * x2) * rr[u];
+          X[(i - u) * kTeN] = x;
+          nrm += x * x;
+          x2 = x1;
+          x1 = x;
+        }
+      }
+      for (; i >= 0; --i) {
+        const int o = i * kTeN;
+        const double x = (X[o] - u1[o] * x1 - u2[o] * x2) * rp[o];
+        X[o] = x;
+        nrm += x * x;
+        x2 = x1;
+        x1 = x;
+      }
+      scale = 1.0 / sqrt(nrm);
+    }
+    znS[j] = scale;
+  }
+  __syncthreads();
+
+  // 4. W = Q Z, the reflectors in reverse order: per step the thread grid
+  // writes partial column sums over its rows, one thread per column adds
+  // the 32 partials (faster here than spreading the sum over lanes), and
+  // every thread updates its entries.
+  double* red = big + kTePacked;   // 32 x kTeN partial column sums
+  double Z[kTeR][kTeR];
+#pragma unroll
+  for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+    for (int c = 0; c < kTeR; ++c) {
+      const int i = tr + 32 * r, j = tc + 32 * c;
+      Z[r][c] = (i < n && j < n) ? sa[5][i * kTeN + j] * znS[j] : 0.0;
+    }
+  for (int k = n - 3; k >= 0; --k) {
+    const double tau = tauS[k];
+    if (tau == 0.0) continue;   // no reflection at this step (the same in every thread)
+    double vi[kTeR];
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r) {
+      const int i = tr + 32 * r;
+      vi[r] = (i > k && i < n) ? vst[te_off(k) + i - k - 1] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kTeR; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < kTeR; ++r) s += vi[r] * Z[r][c];
+      red[tr * kTeN + tc + 32 * c] = s;
+    }
+    __syncthreads();
+    if (tid < n) {
+      double s = 0.0;
+      for (int t = 0; t < 32; ++t) s += red[t * kTeN + tid];
+      ps[tid] = tau * s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+      for (int c = 0; c < kTeR; ++c) Z[r][c] -= vi[r] * ps[tc + 32 * c];
+  }
+  __syncthreads();   // the reflector store is read for the last time above
+
+  // 5. checks on W (in LDS), then the outputs
+#pragma unroll
+  for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+    for (int c = 0; c < kTeR; ++c) big[(tr + 32 * r) * kTeN + tc + 32 * c] = Z[r][c];
+  __syncthreads();
+  double lmax = 0.0;
+  for (int j = 0; j < n; ++j) lmax = fmax(lmax, fabs(lamS[j]));
+  auto cval = [&](int row, int i) -> double {   // C(row, i), both triangles averaged
+    return row < n ? 0.5 * (G[(int64_t)row * lp + i] + G[(int64_t)i * lp + row]) : 0.0;
+  };
+  bool bad = !(lmax < __builtin_inf());
+  {   // W^T W = I
+    double g[kTeR][kTeR];
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+      for (int c = 0; c < kTeR; ++c) g[r][c] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double wa[kTeR], wb[kTeR];
+#pragma unroll
+      for (int r = 0; r < kTeR; ++r) {
+        wa[r] = big[i * kTeN + tr + 32 * r];
+        wb[r] = big[i * kTeN + tc + 32 * r];
+      }
+#pragma unroll
+      for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+        for (int c = 0; c < kTeR; ++c) g[r][c] += wa[r] * wb[c];
+    }
+#pragma unroll
+    for (int r = 0; r < kTeR; ++r)
+#pragma unroll
+      for (int c = 0; c < kTeR; ++c) {
+        const int a = tr + 32 * r, b = tc + 32 * c;
+        if (a < n && b < n && !(fabs(g[r][c] - (a == b ? 1.0 : 0.0)) <= kTeTol)) bad = true;
+      }
+  }
+  {   // C (W y) = W (diag(lambda) y) for a fixed pseudo-random y: eight
+      // threads per row, sixteen entries each, then a sum over the eight
+    const int i = tid >> 3, s8 = tid & 7;
+    double u = 0.0, t = 0.0;
+    if (i < n)
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int j = 16 * s8 + q;
+        if (j < n) {
+          const double y = te_start(j, 4099), w = big[i * kTeN + j];
+          u += w * y;
+          t += w * (lamS[j] * y);
+        }
+      }
+    u += te_dpp<0xB1>(u);
+    u += te_dpp<0x4E>(u);
+    u += te_dpp<0x141>(u);
+    t += te_dpp<0xB1>(t);
+    t += te_dpp<0x4E>(t);
+    t += te_dpp<0x141>(t);
+    if (s8 == 0 && i < kTeN) ps[i] = i < n ? u : 0.0;
+    __syncthreads();
+    double cu = 0.0;
+    if (i < n) {
+      double cv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int m = 16 * s8 + q;
+        cv[q] = m < n ? cval(i, m) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cu += cv[q] * ps[16 * s8 + q];
+    }
+    cu += te_dpp<0xB1>(cu);
+    cu += te_dpp<0x4E>(cu);
+    cu += te_dpp<0x141>(cu);
+    double ysum = 0.0;
+    for (int j = 0; j < n; ++j) ysum += fabs(te_start(j, 4099));
+    if (i < n && s8 == 0 && !(fabs(cu - t) <= kTeTol * lmax * ysum)) bad = true;
+  }
+  const int any_bad = __syncthreads_or(bad ? 1 : 0);
+  for (int e = tid; e < lp * lp; e += 1024) {
+    const int i = e / (int)lp, j = e % (int)lp;
+    Ev[e] = (i < n && j < n) ? big[i * kTeN + j] : 0.0;
+  }
+  for (int j = tid; j < lp; j += 1024) lam[j] = j < n ? lamS[j] : 0.0;
+  if (tid == 0) {
+    status[kStTriOk] = any_bad ? 0 : 1;
+    if (!any_bad) {
+      status[kStSweeps] = 0;
+      status[kStRounds] = 0;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tri_eig(const double* G, int64_t lp, int64_t l, double* lam, double* Ev,
+                          double* scratch, int32_t* status, hipStream_t s) {
+  if (lp > kTeN || l < 1 || l > lp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(1024), 0, s, G, lp, (int)l, lam, Ev, scratch,
+                     status);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -137,7 +137,8 @@ hipError_t launch_apply(const float* P, int64_t ldp, int64_t rows, int64_t kdim,
 // route there when the width fits.
 bool chol16_fits(int64_t lp);
 hipError_t launch_chol16(const double* G, int64_t lp, int64_t l, float* W, double* L,
-                         int32_t* status, double tau, hipStream_t s);
+                         int32_t* status, double tau, hipStream_t s,
+                         const int32_t* skip = nullptr);
 // W = L^-T for 128 < lp <= 192 (k_chol.hip, lower tiles packed in LDS).
 bool chol_tp_fits(int64_t lp);
 hipError_t launch_chol_tp(const double* G, int64_t lp, int64_t l, float* W, int32_t* status,
@@ -161,10 +162,19 @@ hipError_t launch_ritz_delta(const double* S, int64_t k, bool first, double* pre
 // workgroup (lp <= 128); wider sketches take launch_bjacobi.
 bool small_svd_one_sided(int64_t lp);
 // L (lp x lp FP64 row-major, distinct from G) with G = L L^T.
+// skip (optional): a device word; the kernels return at once when it is
+// nonzero (the tridiagonal eigensolver's result passed its checks).
 hipError_t launch_chol_factor(const double* G, int64_t lp, int64_t l, double* L, int32_t* status,
-                              double tau, hipStream_t s);
+                              double tau, hipStream_t s, const int32_t* skip = nullptr);
 hipError_t launch_ojacobi(const double* L, int64_t lp, int64_t l, double* lam, double* Ev,
-                          int32_t* status, double tol, int max_sweeps, hipStream_t s);
+                          int32_t* status, double tol, int max_sweeps, hipStream_t s,
+                          const int32_t* skip = nullptr);
+// Small SVD through the tridiagonal form of C (k_trieig.hip), lp <=
+// kTriMaxLp: writes lam and Ev as launch_ojacobi does and status[kStTriOk]
+// (1 when the orthogonality and residual checks held).  scratch:
+// kTriScratchDoubles FP64.
+hipError_t launch_tri_eig(const double* G, int64_t lp, int64_t l, double* lam, double* Ev,
+                          double* scratch, int32_t* status, hipStream_t s);
 // sort eigenvalues, form S (k values), Wu = Ev(:, order(0:k)), Wv = Wu / sigma
 hipError_t launch_finish_small(const double* lam, const double* Ev, int64_t lp, int64_t l,
                                int64_t k, double* S, float* Wu, float* Wv, int32_t* order,

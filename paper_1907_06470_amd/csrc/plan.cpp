@@ -128,7 +128,8 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   if (o.tile_m < 0 || o.tile_n < 0 || o.tile_m % 32 || o.tile_n % 32)
     return fail(p, RSVD_E_INVALID_ARG, "tile sizes %lld x %lld must be >= 0 and multiples of 32",
                 o.tile_m, o.tile_n);
-  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1 | RSVD_FLAG_BACKWARD | RSVD_FLAG_AUTO_Q))
+  if (o.flags & ~(RSVD_FLAG_NO_SIGN_FIX | RSVD_FLAG_CHOLQR1 | RSVD_FLAG_BACKWARD | RSVD_FLAG_AUTO_Q |
+                  RSVD_FLAG_JACOBI_ONLY))
     return fail(p, RSVD_E_INVALID_ARG, "unknown flags 0x%llx", o.flags);
   p.auto_q = (o.flags & RSVD_FLAG_AUTO_Q) != 0;
   if (p.auto_q) {
@@ -221,6 +222,7 @@ rsvd_status make_plan(const rsvd_problem& prob, const rsvd_options* optp, Plan& 
   w.W = take(lp * lp * 4);
   w.W2 = take(lp * lp * 4);
   w.Ev = take(lp * lp * 8);
+  w.tri = small_svd_tridiagonal(p) ? take((size_t)kTriScratchDoubles * 8) : off;
   const bool bj = p.lp > 128, wide = p.lp > kSliceMax;   // block Jacobi; Cholesky in global memory
   w.Mj = bj ? take(lp * lp * 8) : off;
   w.bjctl = bj ? take((size_t)kBjMaxSweeps * 4) : off;

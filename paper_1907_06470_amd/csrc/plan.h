@@ -40,6 +40,7 @@ enum StatusWord {
   kStRankSmall = 4,    // zero singular values in the small SVD
   kStTies = 5,         // equal singular-value pairs met by the adjoint
   kStBadSparse = 6,    // malformed CSR input (pointers or column indices)
+  kStTriOk = 7,        // 1 when the tridiagonal eigensolver's small SVD passed its checks
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -58,6 +59,7 @@ struct Workspace {
   size_t W2;              // lp x lp FP32 second right factor
   size_t gpart2, G2;      // Gram partials and Gram of the deferred second CholeskyQR pass
   size_t Tc;              // lp x lp FP64 scratch of W^T G W
+  size_t tri;             // tridiagonal eigensolver scratch (FP64, widths <= 128)
   size_t Wpm, Wpn;        // lp x lp FP32 pending right factors of the m- and n-side bases
   size_t Wc;              // lp x lp FP32 product of a pending factor and a first-pass factor
   size_t Ev;              // lp x lp FP64 eigenvectors
@@ -182,5 +184,16 @@ constexpr int64_t kHeadCols = 512;
 constexpr int64_t kHeadPartRows = 512;
 constexpr int64_t kHeadSampleStride = 16;
 size_t csc_sort_scratch(int64_t nnz);
+// Tridiagonal eigensolver of the small SVD (widths up to kTriMaxLp): FP64
+// scratch of six kTriMaxLp x kTriMaxLp arrays (the LU factors of the
+// inverse iterations and their solutions).
+constexpr int64_t kTriMaxLp = 128;
+constexpr int64_t kTriScratchDoubles = 6 * kTriMaxLp * kTriMaxLp;
+
+// the small SVD runs the tridiagonal eigensolver first (widths <= kTriMaxLp
+// unless RSVD_FLAG_JACOBI_ONLY)
+inline bool small_svd_tridiagonal(const Plan& p) {
+  return p.lp <= kTriMaxLp && !(p.opt.flags & RSVD_FLAG_JACOBI_ONLY);
+}
 
 }  // namespace rsvd

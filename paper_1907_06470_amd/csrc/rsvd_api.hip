@@ -168,6 +168,7 @@ struct Buffers {
   float *Pcat, *Rcat, *gUp, *gVp, *coreT, *JuW, *JvW, *sinv;
   double *Ju, *Jv, *Sl;
   double *gpart, *G, *L, *Ev, *lam, *Mj, *Ls2;
+  double* tri;   // tridiagonal eigensolver scratch, or null (Jacobi only)
   int32_t* bjctl;
   double *gpart2, *G2, *Tc;
   float *Wpm, *Wpn, *Wc;
@@ -245,6 +246,7 @@ Buffers carve(const rsvd::Plan& P, void* ws) {
   B.L = (double*)(b + w.L);
   B.Ev = (double*)(b + w.Ev);
   B.Mj = (double*)(b + w.Mj);
+  B.tri = rsvd::small_svd_tridiagonal(P) ? (double*)(b + w.tri) : nullptr;
   B.Ls2 = (double*)(b + w.Ls2);
   B.bjctl = (int32_t*)(b + w.bjctl);
   B.lam = (double*)(b + w.lam);
@@ -939,10 +941,18 @@ struct Runner {
     // C = L L^T, then one-sided Jacobi on L (no drop: tau = 0 keeps every
     // positive pivot; exactly dependent directions give zero columns): in one
     // workgroup up to width 128, over many workgroups (block Jacobi) beyond
-    RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s));
+    // Widths <= 128: the tridiagonal eigensolver of C first; the Cholesky and
+    // Jacobi kernels then return at once unless its checks failed (close or
+    // repeated eigenvalues, non-finite input), all decided on the device.
+    const int32_t* skip = nullptr;
+    if (B.tri) {
+      RSVD_HIP(rsvd::launch_tri_eig(gsmall, P.lp, P.l, B.lam, B.Ev, B.tri, B.status, s));
+      skip = B.status + rsvd::kStTriOk;
+    }
+    RSVD_HIP(rsvd::launch_chol_factor(gsmall, P.lp, P.l, B.L, B.status, 0.0, s, skip));
     if (rsvd::small_svd_one_sided(P.lp))
       RSVD_HIP(rsvd::launch_ojacobi(B.L, P.lp, P.l, B.lam, B.Ev, B.status, kJacobiTol,
-                                    rsvd::kJacobiMaxSweeps, s));
+                                    rsvd::kJacobiMaxSweeps, s, skip));
     else
       RSVD_HIP(rsvd::launch_bjacobi(B.L, P.lp, P.l, B.Mj, B.bjctl, B.lam, B.Ev, B.status,
                                     kJacobiTol, s));

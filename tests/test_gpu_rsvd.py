@@ -103,6 +103,43 @@ def test_cholqr1_flag_same_result():
     run_and_compare(A.numpy(), 50, 10, 2, flags=L.FLAG_CHOLQR1)
 
 
+def test_small_svd_tridiagonal_matches_jacobi():
+    """Widths <= 128 solve the small eigenproblem of C = B B^T through its
+    tridiagonal form (Householder, bisection, inverse iteration) and keep the
+    result only when W^T W = I and C W = W diag(lambda) hold to 1e-12; the
+    Cholesky + one-sided Jacobi path (forced here by RSVD_FLAG_JACOBI_ONLY)
+    gives the same factors."""
+    dev = need_gpu()
+    A, _ = workloads.make("plain_gpu", scale=0.1)
+    A = A.to(dev)
+    m, n = A.shape
+    outs = []
+    for flags in (0, L.FLAG_JACOBI_ONLY):
+        plan = Plan(m, n, 100, 20, 2, tile=(1024, 1024), flags=flags)
+        outs.append(plan.factor(A))
+        torch.cuda.synchronize()
+    (U1, S1, V1, i1), (U2, S2, V2, i2) = outs
+    S1, S2 = S1.cpu().double().numpy(), S2.cpu().double().numpy()
+    su = metrics.sin_theta(U2.cpu().double().numpy(), U1.cpu().double().numpy())
+    sv = metrics.sin_theta(V2.cpu().double().numpy(), V1.cpu().double().numpy())
+    say(f"tridiagonal vs Jacobi: sigma diff {np.max(np.abs(S1 - S2)) / S2[0]:.2e}, sin U {su:.1e}, "
+        f"sin V {sv:.1e}, sweeps {i1['jacobi_sweeps']} / {i2['jacobi_sweeps']}")
+    assert i1["jacobi_sweeps"] == 0 and i2["jacobi_sweeps"] > 0
+    assert np.max(np.abs(S1 - S2)) <= 1e-6 * S2[0]
+    assert su <= 1e-4 and sv <= 1e-4
+
+
+def test_small_svd_falls_back_to_jacobi_on_repeated_eigenvalues():
+    """Rank 8 with l = 16: the dropped directions give C a repeated zero
+    eigenvalue, independent inverse iterations are not orthogonal there, and
+    the Jacobi path runs instead (on the device, no host decision)."""
+    sig = np.array([4.0, 3.0, 2.0, 1.5, 1.0, 0.7, 0.5, 0.3])
+    A = workloads.dense_lowrank(1200, 700, sig, 0.0, seed=12, out_dtype=torch.float32).numpy()
+    S, _, info = run_and_compare(A, 8, 8, 1, expect_status=L.W_RANK_DEFICIENT)
+    assert np.all(np.abs(S - sig) <= 1e-5 * sig)
+    assert info["jacobi_sweeps"] > 0
+
+
 def test_bitwise_deterministic():
     dev = need_gpu()
     A, _ = workloads.make("plain_gpu", scale=0.1)
