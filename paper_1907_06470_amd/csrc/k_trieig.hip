@@ -196,8 +196,8 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
     if (sg > 0.0) {
       const double mu = sqrt(al * al + sg);
       beta = al >= 0.0 ? -mu : mu;
-      sc = 1.0 / (al - beta);
-      tau = (beta - al) / beta;
+      sc = te_rcp(al - beta);   // al - beta and beta are nonzero here (sg > 0)
+      tau = (beta - al) * te_rcp(beta);
     }
     auto vof = [&](int i) -> double {
       return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
