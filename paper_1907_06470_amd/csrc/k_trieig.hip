@@ -10,9 +10,10 @@
 //      w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T.  The reflectors are
 //      kept in LDS.  Sums across lanes go through DPP permutes.
 //   2. Eigenvalues of T by bisection on the Sturm count (the number of
-//      negative pivots of T - x I), eight lanes per eigenvalue cutting the
-//      interval into nine parts per round; 17 rounds take the Gershgorin
-//      interval below FP64 resolution.
+//      negative pivots of T - x I), four lanes per eigenvalue cutting the
+//      interval into five parts per round; 23 rounds take the Gershgorin
+//      interval below FP64 resolution.  (The phase is bound by FP64 issue:
+//      four lanes do a third less work than eight for the same resolution.)
 //   3. Eigenvectors of T by inverse iteration, one lane per eigenvalue: the
 //      LU factors of T - lambda I with row interchanges (the LAPACK gttrf
 //      pattern) go to a global scratch laid out [array][row][lane], then two
@@ -40,7 +41,9 @@ namespace {
 
 constexpr int kTeN = (int)kTriMaxLp;             // largest order
 constexpr int kTeR = 4;                          // rows (columns) per thread
-constexpr int kTeRounds = 17;                    // 9^17 > 2^52
+constexpr int kTeG = 4;                          // lanes per eigenvalue in the bisection
+constexpr int kTeRounds = 23;                    // (kTeG + 1)^23 = 5^23 > 2^52
+static_assert(kTeG * kTeN <= 1024, "one lane group per eigenvalue");
 constexpr int kTePacked = kTeN * (kTeN - 1) / 2; // reflector store (doubles)
 constexpr double kTeTol = 1e-12;
 constexpr int kTeArrays = 6;                     // dl, dd, du, du2, pivot, x
@@ -282,20 +285,20 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   }
   __syncthreads();
 
-  // 2. eigenvalues: group of 8 lanes per eigenvalue j (ascending)
+  // 2. eigenvalues: group of kTeG lanes per eigenvalue j (ascending)
   {
-    const int j = tid >> 3, s = tid & 7;
+    const int j = tid / kTeG, s = tid % kTeG;
     double a = shv[0], b = shv[1];
     const double pivmin = shv[2];
     for (int round = 0; round < kTeRounds; ++round) {
-      const double x = a + (b - a) * (double)(s + 1) * (1.0 / 9.0);
+      const double x = a + (b - a) * (double)(s + 1) * (1.0 / (kTeG + 1));
       const int cnt = j < n ? te_sturm(dS, e2S, n, x, pivmin) : 0;
       int smax = cnt <= j ? s : -1;   // count(a) <= j < count(b)
-      for (int o = 1; o < 8; o <<= 1) smax = max(smax, __shfl_xor(smax, o, 8));
-      const double xl = __shfl(x, smax < 0 ? 0 : smax, 8);
-      const double xh = __shfl(x, smax < 7 ? smax + 1 : 7, 8);
+      for (int o = 1; o < kTeG; o <<= 1) smax = max(smax, __shfl_xor(smax, o, kTeG));
+      const double xl = __shfl(x, smax < 0 ? 0 : smax, kTeG);
+      const double xh = __shfl(x, smax < kTeG - 1 ? smax + 1 : kTeG - 1, kTeG);
       if (smax >= 0) a = xl;
-      if (smax < 7) b = xh;
+      if (smax < kTeG - 1) b = xh;
     }
     if (s == 0 && j < n) lamS[j] = 0.5 * (a + b);
   }
