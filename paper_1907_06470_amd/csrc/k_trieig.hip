@@ -22,8 +22,9 @@
 //      (column sums: partials over the thread grid in LDS, then one thread
 //      per column).
 //   5. Checks: |W^T W - I| <= 1e-12 (the accuracy the one-sided Jacobi path
-//      reaches) and, for a fixed pseudo-random y, |C (W y) - W (diag(lambda)
-//      y)| <= 1e-12 lambda_max |y|_1, with every value finite.  status[kStTriOk] says whether they held; the Cholesky
+//      reaches) and, for a fixed pseudo-random y,
+//      |C (W y) - W (diag(lambda) y)| <= 1e-12 lambda_max |y|_1, with every
+//      value finite.  status[kStTriOk] says whether they held; the Cholesky
 //      and Jacobi kernels launched after this one run only when they did
 //      not (close or repeated eigenvalues, where independent inverse
 //      iterations lose orthogonality, or non-finite input).
@@ -46,7 +47,7 @@ constexpr int kTeRounds = 23;                    // (kTeG + 1)^23 = 5^23 > 2^52
 static_assert(kTeG * kTeN <= 1024, "one lane group per eigenvalue");
 constexpr int kTePacked = kTeN * (kTeN - 1) / 2; // reflector store (doubles)
 constexpr double kTeTol = 1e-12;
-constexpr int kTeArrays = 6;                     // dl, dd, du, du2, pivot, x
+constexpr int kTeArrays = 6;                     // scratch arrays of the inverse iteration
 static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scratch layout");
 
 __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
                                                   double* __restrict__ Ev,
                                                   double* __restrict__ scr,
                                                   int32_t* __restrict__ status) {
-  __shared__ double big[kTeN * kTeN];   // reflectors, then W
+  __shared__ double big[kTeN * kTeN];   // reflectors (and column partial sums), then W
   __shared__ double xsb[2 * kTeN], ps[kTeN];
   __shared__ double dS[kTeN], eS[kTeN], e2S[kTeN], tauS[kTeN], lamS[kTeN], znS[kTeN];
   __shared__ double shv[4];
