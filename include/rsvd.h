@@ -141,7 +141,9 @@ typedef struct {
   int32_t gemm_nn_launches;
   int32_t gemm_tn_launches;
   int32_t dropped;         /* sketch directions dropped as dependent        */
-  int32_t jacobi_sweeps;   /* sweeps of the small eigensolver               */
+  int32_t jacobi_sweeps;   /* one-sided Jacobi sweeps of the small SVD; 0
+                              when the tridiagonal eigensolver's result
+                              was kept (widths <= 128, checks held)        */
   int32_t nonfinite;       /* NaN/Inf seen on the device                    */
   int32_t slots;           /* host-resident A: HBM tile slots               */
   double h2d_bytes;        /* host-resident A: bytes copied host -> device  */
