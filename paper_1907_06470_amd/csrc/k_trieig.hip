@@ -212,13 +212,6 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
       vi[r] = vof(tr + 32 * r);
       vj[r] = vof(tc + 32 * r);
     }
-    if (tid < 64) {
-      for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
-      if (tid == 0) {
-        tauS[k] = tau;
-        eS[k] = beta;
-      }
-    }
     double pr[kTeR];
 #pragma unroll
     for (int r = 0; r < kTeR; ++r) {
@@ -245,6 +238,15 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
       const int i = tr + 32 * r, j = tc + 32 * r;
       wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
       wj[r] = j < n ? ps[j] - K * vj[r] : 0.0;
+    }
+    // the reflector for the back-transformation (xk stays valid until step
+    // k + 2 writes it again), stored off the path to the second barrier
+    if (tid < 64) {
+      for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
+      if (tid == 0) {
+        tauS[k] = tau;
+        eS[k] = beta;
+      }
     }
 #pragma unroll
     for (int r = 0; r < kTeR; ++r)
