@@ -85,6 +85,16 @@ def test_tiny_matrix():
     run_and_compare(A, 3, 3, 2)
 
 
+@pytest.mark.parametrize("k,p", [(1, 0), (1, 1), (2, 0)])
+def test_sketch_widths_one_and_two(k, p):
+    """l = 1 and l = 2: the tridiagonal small SVD has no reduction step (its
+    tail block is all of C)."""
+    sig = np.array([5.0, 2.0, 1.0, 0.5, 0.25, 0.1])
+    A = workloads.dense_lowrank(400, 300, sig, 1e-3, seed=13, out_dtype=torch.float32).numpy()
+    _, _, info = run_and_compare(A, k, p, 2)
+    assert info["jacobi_sweeps"] == 0
+
+
 def test_exact_recovery_of_low_rank_input_drops_directions():
     sig = np.array([4.0, 3.0, 2.0, 1.5, 1.0, 0.7, 0.5, 0.3])
     A = workloads.dense_lowrank(1200, 700, sig, 0.0, seed=11, out_dtype=torch.float32).numpy()
