@@ -100,6 +100,29 @@ def test_sparse_head_block_edges():
     assert np.array_equal(Z, Z2)
 
 
+def test_empty_sparse_matrix():
+    """No entries: the products are zero (the head columns' output rows are
+    cleared without a product), every sketch direction is dropped and
+    S = 0 with finite U, V."""
+    dev = need_gpu()
+    m, n = 3000, 800
+    say("empty sparse", m, n)
+    rp = torch.zeros(m + 1, dtype=torch.int32, device=dev)
+    ci = torch.zeros(0, dtype=torch.int32, device=dev)
+    v = torch.zeros(0, dtype=torch.float32, device=dev)
+    plan = Plan(m, n, 5, 5, 1, nnz=0)
+    Q = rand_panel(m, 10, 3)
+    Z = plan.step_spmm(1, rp, ci, v, col_major_from_numpy(Q, dev))
+    X = rand_panel(n, 10, 4)
+    Y = plan.step_spmm(0, rp, ci, v, col_major_from_numpy(X, dev))
+    assert not bool(torch.any(Z != 0)) and not bool(torch.any(Y != 0))
+    U, S, V, info = plan.factor_csr(rp, ci, v)
+    torch.cuda.synchronize()
+    assert torch.all(S == 0)
+    assert bool(torch.isfinite(U).all()) and bool(torch.isfinite(V).all())
+    assert info["status"] in (L.OK, L.W_RANK_DEFICIENT)
+
+
 def test_sparse_factor_matches_oracle_and_is_reproducible():
     dev = need_gpu()
     m, n, per_row = 12000, 4000, 30
