@@ -441,7 +441,7 @@ def bench_sparse(args, dev):
         f"A^T Q {tn_ms:.3f} ms ({tn_gbs:.0f} GB/s), stages "
         f"{[round(x, 3) for x in infos[-1]['stage_ms']]}, properties {props}")
     # measured HBM traffic of one A^T Q product (committed counter summary)
-    traffic = measured_traffic(("k_sparse.hip", "plan.cpp"),
+    traffic = measured_traffic(("k_sparse.hip", "plan.cpp", "plan.h"),
                                f"counters_k_spmm_chunk_sparse_{m}x{n}.md") \
         if dom[0].startswith("A^T Q") and l == 330 else None
     cpu = None

@@ -179,9 +179,12 @@ int64_t csc_part_count(int64_t m, int64_t n, int64_t lp);
 // (counted on every kHeadSampleStride-th row) get compressed rows of their
 // own per block of kHeadPartRows rows of A; a product stages such a block's
 // panel rows in LDS once and runs every head column's entries of the block
-// against it.  The other columns keep the csc_part_count row blocks.
+// against it.  The other columns keep the csc_part_count row blocks.  256
+// rows (68 KB of LDS, two workgroups a compute unit) measured best on a
+// 1e8-entry Zipf matrix: 512 rows hide less latency, 128 rows double the
+// block results to add.
 constexpr int64_t kHeadCols = 512;
-constexpr int64_t kHeadPartRows = 512;
+constexpr int64_t kHeadPartRows = 256;
 constexpr int64_t kHeadSampleStride = 16;
 size_t csc_sort_scratch(int64_t nnz);
 // Tridiagonal eigensolver of the small SVD (widths up to kTriMaxLp): FP64
