@@ -8,7 +8,9 @@
 //      and columns c + 32 j, i, j < 4); each step forms the reflector from the
 //      column below the diagonal, p = tau A v (row sums over a half-wave),
 //      w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T.  The reflectors are
-//      kept in LDS.  Sums across lanes go through DPP permutes.
+//      kept in LDS.  Sums across lanes go through DPP permutes.  Register
+//      blocks whose rows or columns are all <= k (or >= n) drop out of the
+//      product and the update; the same holds for the rows of step 4.
 //   2. Eigenvalues of T by bisection on the Sturm count (the number of
 //      negative pivots of T - x I), four lanes per eigenvalue cutting the
 //      interval into five parts per round; 23 rounds take the Gershgorin
@@ -51,10 +53,6 @@ constexpr int kTeArrays = 6;                     // scratch arrays of the invers
 static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scratch layout");
 
 __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
-
-__device__ inline double te_sel(const double (&a)[kTeR], int c) {
-  return c == 0 ? a[0] : c == 1 ? a[1] : c == 2 ? a[2] : a[3];
-}
 
 // Cross-lane sums through DPP lane permutes (no LDS round trips); every lane
 // of a row (half-wave, wave) ends with the same bits, since each step adds
@@ -138,6 +136,176 @@ __device__ inline double te_start(int i, int j) {
   return (double)(h >> 8) * (2.0 / 16777216.0) - 1.0;
 }
 
+// Step k of the reduction, two barriers: every wave forms the reflector and
+// the scalar K itself (same bits in every wave); the column below the
+// diagonal alternates between two buffers so that the next step's owner
+// never overwrites one still being read.  Register blocks r < KB hold rows
+// (columns) <= k only and blocks r >= NB rows (columns) >= n only; there the
+// reflector v and the vector w are zero, the update leaves A as it is and
+// the product's terms are zeros, so those blocks are skipped.  (The values
+// are those of the full update up to which product each fused multiply-add
+// rounds first.)
+// KC = k / 32 is the block of column k (KB - 1 at the first step of a range
+// of k with the same KB, else KB).
+template <int KB, int NB, int KC>
+__device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeR], int k, int n,
+                                                double* xsb, double* ps, double* dS,
+                                                double* eS, double* tauS, double* vst) {
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, l64 = tid & 63;
+  double* xk = xsb + (k & 1) * kTeN;
+  if (tc == (k & 31)) {   // column k (its block may be below KB: read before the skip)
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int i = tr + 32 * r;
+      const double x = A[r][KC];
+      if (i > k && i < n) xk[i] = x;
+      if (i == k) dS[k] = x;
+    }
+  }
+  __syncthreads();
+  double sg = 0.0;
+  {
+    const int i0 = k + 2 + l64, i1 = i0 + 64;
+    if (i0 < n) sg += xk[i0] * xk[i0];
+    if (i1 < n) sg += xk[i1] * xk[i1];
+  }
+  sg = te_wave_sum(sg);
+  const double al = xk[k + 1];
+  double tau = 0.0, beta = al, sc = 0.0;
+  if (sg > 0.0) {
+    const double mu = sqrt(al * al + sg);
+    beta = al >= 0.0 ? -mu : mu;
+    sc = te_rcp(al - beta);   // al - beta and beta are nonzero here (sg > 0)
+    tau = (beta - al) * te_rcp(beta);
+  }
+  auto vof = [&](int i) -> double {
+    return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
+  };
+  double vi[kTeR], vj[kTeR], pr[kTeR] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = KB; r < NB; ++r) {
+    vi[r] = vof(tr + 32 * r);
+    vj[r] = vof(tc + 32 * r);
+  }
+#pragma unroll
+  for (int r = KB; r < NB; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = KB; c < NB; ++c) s += A[r][c] * vj[c];
+    pr[r] = te_half_sum(s);
+  }
+  if (tc == 0) {
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int i = tr + 32 * r;
+      if (i < n) ps[i] = (r >= KB && i > k) ? tau * pr[r] : 0.0;
+    }
+  }
+  __syncthreads();
+  double kk = 0.0;
+  if (l64 < n) kk += ps[l64] * vof(l64);
+  if (l64 + 64 < n) kk += ps[l64 + 64] * vof(l64 + 64);
+  const double K = 0.5 * tau * te_wave_sum(kk);
+  double wi[kTeR], wj[kTeR];
+#pragma unroll
+  for (int r = KB; r < NB; ++r) {
+    const int i = tr + 32 * r, j = tc + 32 * r;
+    wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
+    wj[r] = j < n ? ps[j] - K * vj[r] : 0.0;
+  }
+  // the reflector for the back-transformation (xk stays valid until step
+  // k + 2 writes it again), stored off the path to the second barrier
+  if (tid < 64) {
+    for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
+    if (tid == 0) {
+      tauS[k] = tau;
+      eS[k] = beta;
+    }
+  }
+#pragma unroll
+  for (int r = KB; r < NB; ++r)
+#pragma unroll
+    for (int c = KB; c < NB; ++c) A[r][c] -= vi[r] * wj[c] + wi[r] * vj[c];
+}
+
+// The steps k = 32 KB - 1 ... 32 KB + 30 (those with first active block KB),
+// from k on, while k + 2 < n.
+template <int KB, int NB>
+__device__ __forceinline__ void te_reduce_range(double (&A)[kTeR][kTeR], int& k, int n,
+                                                double* xsb, double* ps, double* dS,
+                                                double* eS, double* tauS, double* vst) {
+  if constexpr (KB > 0) {
+    if (k + 2 >= n) return;
+    te_reduce_step<KB, NB, KB - 1>(A, k, n, xsb, ps, dS, eS, tauS, vst);   // k = 32 KB - 1
+    ++k;
+  }
+  for (; k + 2 < n && k < 32 * KB + 31; ++k)
+    te_reduce_step<KB, NB, KB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+}
+
+// All steps of the reduction for n <= 32 NB.
+template <int NB>
+__device__ __forceinline__ void te_reduce(double (&A)[kTeR][kTeR], int n, double* xsb,
+                                          double* ps, double* dS, double* eS, double* tauS,
+                                          double* vst) {
+  int k = 0;
+  te_reduce_range<0, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+  if constexpr (NB > 1) te_reduce_range<1, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+  if constexpr (NB > 2) te_reduce_range<2, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+  if constexpr (NB > 3) te_reduce_range<3, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+}
+
+// Reflector k of the back-transformation Z -= v (tau v^T Z): the thread grid
+// writes partial column sums over its rows, one thread per column adds the
+// 32 partials (faster here than spreading the sum over lanes), and every
+// thread updates its entries.  Row blocks below KB (rows <= k, where v is
+// zero) and column blocks from NB on (columns >= n) are skipped.
+template <int KB, int NB>
+__device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeR], int k, int n,
+                                              const double* vst, const double* tauS,
+                                              double* red, double* ps) {
+  const double tau = tauS[k];
+  if (tau == 0.0) return;   // no reflection at this step (the same in every thread)
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  double vi[kTeR];
+#pragma unroll
+  for (int r = KB; r < NB; ++r) {
+    const int i = tr + 32 * r;
+    vi[r] = (i > k && i < n) ? vst[te_off(k) + i - k - 1] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = KB; r < NB; ++r) s += vi[r] * Z[r][c];
+    red[tr * kTeN + tc + 32 * c] = s;
+  }
+  __syncthreads();
+  if (tid < n) {
+    double s = 0.0;
+    for (int t = 0; t < 32; ++t) s += red[t * kTeN + tid];
+    ps[tid] = tau * s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = KB; r < NB; ++r)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Z[r][c] -= vi[r] * ps[tc + 32 * c];
+}
+
+template <int NB>
+__device__ __forceinline__ void te_back(double (&Z)[kTeR][kTeR], int n, const double* vst,
+                                        const double* tauS, double* red, double* ps) {
+  int k = n - 3;
+  if constexpr (NB > 3)
+    for (; k >= 95; --k) te_back_step<3, NB>(Z, k, n, vst, tauS, red, ps);
+  if constexpr (NB > 2)
+    for (; k >= 63; --k) te_back_step<2, NB>(Z, k, n, vst, tauS, red, ps);
+  if constexpr (NB > 1)
+    for (; k >= 31; --k) te_back_step<1, NB>(Z, k, n, vst, tauS, red, ps);
+  for (; k >= 0; --k) te_back_step<0, NB>(Z, k, n, vst, tauS, red, ps);
+}
+
 __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, int64_t lp, int n,
                                                   double* __restrict__ lam,
                                                   double* __restrict__ Ev,
@@ -148,7 +316,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   __shared__ double dS[kTeN], eS[kTeN], e2S[kTeN], tauS[kTeN], lamS[kTeN], znS[kTeN];
   __shared__ double shv[4];
   double* vst = big;
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, l64 = tid & 63;
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
   // scratch arrays: 0 multiplier, 1 reciprocal pivot, 2 and 3 the two super
   // diagonals of U, 4 interchange flag, 5 right-hand side / solution
   double* const sa[kTeArrays] = {scr, scr + kTeN * kTeN, scr + 2 * kTeN * kTeN,
@@ -171,87 +339,12 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   }
   __syncthreads();
 
-  // 1. tridiagonal reduction, two barriers a step: every wave forms the
-  // reflector and the scalar K itself (same bits in every wave); the column
-  // below the diagonal alternates between two buffers so that the next
-  // step's owner never overwrites one still being read
-  for (int k = 0; k + 2 < n; ++k) {
-    double* xk = xsb + (k & 1) * kTeN;
-    const int kc = k >> 5;
-    if (tc == (k & 31)) {
-#pragma unroll
-      for (int r = 0; r < kTeR; ++r) {
-        const int i = tr + 32 * r;
-        const double x = te_sel(A[r], kc);
-        if (i > k && i < n) xk[i] = x;
-        if (i == k) dS[k] = x;
-      }
-    }
-    __syncthreads();
-    double sg = 0.0;
-    {
-      const int i0 = k + 2 + l64, i1 = i0 + 64;
-      if (i0 < n) sg += xk[i0] * xk[i0];
-      if (i1 < n) sg += xk[i1] * xk[i1];
-    }
-    sg = te_wave_sum(sg);
-    const double al = xk[k + 1];
-    double tau = 0.0, beta = al, sc = 0.0;
-    if (sg > 0.0) {
-      const double mu = sqrt(al * al + sg);
-      beta = al >= 0.0 ? -mu : mu;
-      sc = te_rcp(al - beta);   // al - beta and beta are nonzero here (sg > 0)
-      tau = (beta - al) * te_rcp(beta);
-    }
-    auto vof = [&](int i) -> double {
-      return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
-    };
-    double vi[kTeR], vj[kTeR];
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r) {
-      vi[r] = vof(tr + 32 * r);
-      vj[r] = vof(tc + 32 * r);
-    }
-    double pr[kTeR];
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r) {
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < kTeR; ++c) s += A[r][c] * vj[c];
-      pr[r] = te_half_sum(s);
-    }
-    if (tc == 0) {
-#pragma unroll
-      for (int r = 0; r < kTeR; ++r) {
-        const int i = tr + 32 * r;
-        if (i < n) ps[i] = i > k ? tau * pr[r] : 0.0;
-      }
-    }
-    __syncthreads();
-    double kk = 0.0;
-    if (l64 < n) kk += ps[l64] * vof(l64);
-    if (l64 + 64 < n) kk += ps[l64 + 64] * vof(l64 + 64);
-    const double K = 0.5 * tau * te_wave_sum(kk);
-    double wi[kTeR], wj[kTeR];
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r) {
-      const int i = tr + 32 * r, j = tc + 32 * r;
-      wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
-      wj[r] = j < n ? ps[j] - K * vj[r] : 0.0;
-    }
-    // the reflector for the back-transformation (xk stays valid until step
-    // k + 2 writes it again), stored off the path to the second barrier
-    if (tid < 64) {
-      for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
-      if (tid == 0) {
-        tauS[k] = tau;
-        eS[k] = beta;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r)
-#pragma unroll
-      for (int c = 0; c < kTeR; ++c) A[r][c] -= vi[r] * wj[c] + wi[r] * vj[c];
+  // 1. tridiagonal reduction (the step is described at te_reduce_step)
+  switch ((n + 31) >> 5) {
+    case 1: te_reduce<1>(A, n, xsb, ps, dS, eS, tauS, vst); break;
+    case 2: te_reduce<2>(A, n, xsb, ps, dS, eS, tauS, vst); break;
+    case 3: te_reduce<3>(A, n, xsb, ps, dS, eS, tauS, vst); break;
+    default: te_reduce<4>(A, n, xsb, ps, dS, eS, tauS, vst); break;
   }
   // the last 2 x 2 block (or the single entry)
 #pragma unroll
@@ -416,10 +509,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   }
   __syncthreads();
 
-  // 4. W = Q Z, the reflectors in reverse order: per step the thread grid
-  // writes partial column sums over its rows, one thread per column adds
-  // the 32 partials (faster here than spreading the sum over lanes), and
-  // every thread updates its entries.
+  // 4. W = Q Z, the reflectors in reverse order (te_back_step)
   double* red = big + kTePacked;   // 32 x kTeN partial column sums
   double Z[kTeR][kTeR];
 #pragma unroll
@@ -429,33 +519,11 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
       const int i = tr + 32 * r, j = tc + 32 * c;
       Z[r][c] = (i < n && j < n) ? sa[5][i * kTeN + j] * znS[j] : 0.0;
     }
-  for (int k = n - 3; k >= 0; --k) {
-    const double tau = tauS[k];
-    if (tau == 0.0) continue;   // no reflection at this step (the same in every thread)
-    double vi[kTeR];
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r) {
-      const int i = tr + 32 * r;
-      vi[r] = (i > k && i < n) ? vst[te_off(k) + i - k - 1] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < kTeR; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int r = 0; r < kTeR; ++r) s += vi[r] * Z[r][c];
-      red[tr * kTeN + tc + 32 * c] = s;
-    }
-    __syncthreads();
-    if (tid < n) {
-      double s = 0.0;
-      for (int t = 0; t < 32; ++t) s += red[t * kTeN + tid];
-      ps[tid] = tau * s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kTeR; ++r)
-#pragma unroll
-      for (int c = 0; c < kTeR; ++c) Z[r][c] -= vi[r] * ps[tc + 32 * c];
+  switch ((n + 31) >> 5) {
+    case 1: te_back<1>(Z, n, vst, tauS, red, ps); break;
+    case 2: te_back<2>(Z, n, vst, tauS, red, ps); break;
+    case 3: te_back<3>(Z, n, vst, tauS, red, ps); break;
+    default: te_back<4>(Z, n, vst, tauS, red, ps); break;
   }
   __syncthreads();   // the reflector store is read for the last time above
 
