@@ -1,16 +1,18 @@
 // Small SVD of Section 2.1 step 6 through the symmetric eigenproblem of the
 // FP64 Gram C = B B^T (order n = l <= 128; its two triangles are averaged,
 // since a congruence Wp^T G Wp is symmetric only to rounding), in one
-// workgroup:
+// workgroup of 512 threads (eight waves: the steps below are bound by what
+// every wave repeats, so fewer waves issue less):
 //
 //   1. Householder reduction Q^T C Q = T (tridiagonal).  C is held in
-//      registers on a 32 x 32 thread grid (thread (r, c) owns rows r + 32 i
-//      and columns c + 32 j, i, j < 4); each step forms the reflector from the
-//      column below the diagonal, p = tau A v (row sums over a half-wave),
-//      w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T.  The reflectors are
-//      kept in LDS.  Sums across lanes go through DPP permutes.  Register
-//      blocks whose rows or columns are all <= k (or >= n) drop out of the
-//      product and the update; the same holds for the rows of step 4.
+//      registers on a 32 x 16 thread grid (thread (r, c) owns rows r + 32 i,
+//      i < 4, and columns c + 16 j, j < 8); each step forms the reflector
+//      from the column below the diagonal, p = tau A v (row sums over a
+//      16-lane DPP row), w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T.
+//      The reflectors are kept in LDS.  Sums across lanes go through DPP
+//      permutes.  Register blocks whose rows or columns are all <= k (or
+//      >= n) drop out of the product and the update; the same holds for the
+//      rows of step 4.
 //   2. Eigenvalues of T by bisection on the Sturm count (the number of
 //      negative pivots of T - x I), four lanes per eigenvalue cutting the
 //      interval into five parts per round; 23 rounds take the Gershgorin
@@ -44,9 +46,11 @@ namespace {
 
 constexpr int kTeN = (int)kTriMaxLp;             // largest order
 constexpr int kTeR = 4;                          // rows (columns) per thread
+constexpr int kTeT = 512;                        // threads: a 32 x 16 grid in phases 1, 4, 5
+constexpr int kTeC = 8;                          // columns per thread (blocks of 16)
 constexpr int kTeG = 4;                          // lanes per eigenvalue in the bisection
 constexpr int kTeRounds = 23;                    // (kTeG + 1)^23 = 5^23 > 2^52
-static_assert(kTeG * kTeN <= 1024, "one lane group per eigenvalue");
+static_assert(kTeG * kTeN == kTeT, "one lane group per eigenvalue");
 constexpr int kTePacked = kTeN * (kTeN - 1) / 2; // reflector store (doubles)
 constexpr double kTeTol = 1e-12;
 constexpr int kTeArrays = 6;                     // scratch arrays of the inverse iteration
@@ -78,12 +82,6 @@ __device__ inline double te_lane(double x, int l) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-__device__ inline double te_half_sum(double x) {   // over the 32 lanes of a half-wave
-  x = te_row_sum(x);
-  const double s0 = te_lane(x, 0) + te_lane(x, 16), s1 = te_lane(x, 32) + te_lane(x, 48);
-  return (threadIdx.x & 32) ? s1 : s0;
 }
 
 __device__ inline double te_wave_sum(double x) {
@@ -136,137 +134,143 @@ __device__ inline double te_start(int i, int j) {
   return (double)(h >> 8) * (2.0 / 16777216.0) - 1.0;
 }
 
-// Step k of the reduction, two barriers: every wave forms the reflector and
-// the scalar K itself (same bits in every wave); the column below the
-// diagonal alternates between two buffers so that the next step's owner
-// never overwrites one still being read.  Register blocks r < KB hold rows
-// (columns) <= k only and blocks r >= NB rows (columns) >= n only; there the
-// reflector v and the vector w are zero, the update leaves A as it is and
-// the product's terms are zeros, so those blocks are skipped.  (The values
-// are those of the full update up to which product each fused multiply-add
-// rounds first.)
-// KC = k / 32 is the block of column k (KB - 1 at the first step of a range
-// of k with the same KB, else KB).
-template <int KB, int NB, int KC>
-__device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeR], int k, int n,
+// Step k of the reduction, two barriers.  Thread (tr, tc) of the 32 x 16
+// grid holds rows tr + 32 r (r < 4) and columns tc + 16 c (c < 8) of A, so a
+// row of the grid is one 16-lane DPP row and its sums need no lane reads.
+// Every wave forms the reflector and the scalar K itself
+// (same bits in every wave); the column below the diagonal alternates
+// between two buffers so that the next step's owner never overwrites one
+// still being read.  Column blocks c < CKB (row blocks r < CKB / 2) hold
+// indices <= k only, and blocks from NB (2 NB) on indices >= n only; there
+// the reflector v and the vector w are zero, the update leaves A as it is
+// and the product's terms are zeros, so those blocks are skipped.  (The
+// values are those of the full update up to which product each fused
+// multiply-add rounds first.)
+template <int CKB, int NB>
+__device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeC], int k, int n,
                                                 double* xsb, double* ps, double* dS,
                                                 double* eS, double* tauS, double* vst) {
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31, l64 = tid & 63;
+  constexpr int RKB = CKB / 2, NC = 2 * NB;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, l64 = tid & 63;
   double* xk = xsb + (k & 1) * kTeN;
-  if (tc == (k & 31)) {   // column k (its block may be below KB: read before the skip)
+  if (tc == (k & 15)) {   // column k: block CKB, or CKB - 1 at the first step of the range
+    const bool at = (k >> 4) == CKB;
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
       const int i = tr + 32 * r;
-      const double x = A[r][KC];
+      const double x = at ? A[r][CKB] : A[r][CKB > 0 ? CKB - 1 : 0];
       if (i > k && i < n) xk[i] = x;
       if (i == k) dS[k] = x;
     }
   }
   __syncthreads();
-  double sg = 0.0;
-  {
-    const int i0 = k + 2 + l64, i1 = i0 + 64;
-    if (i0 < n) sg += xk[i0] * xk[i0];
-    if (i1 < n) sg += xk[i1] * xk[i1];
-  }
-  sg = te_wave_sum(sg);
-  const double al = xk[k + 1];
-  double tau = 0.0, beta = al, sc = 0.0;
-  if (sg > 0.0) {
-    const double mu = sqrt(al * al + sg);
-    beta = al >= 0.0 ? -mu : mu;
-    sc = te_rcp(al - beta);   // al - beta and beta are nonzero here (sg > 0)
-    tau = (beta - al) * te_rcp(beta);
-  }
+  double tau = 0.0, beta = 0.0, sc = 0.0;
   auto vof = [&](int i) -> double {
     return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
   };
-  double vi[kTeR], vj[kTeR], pr[kTeR] = {0.0, 0.0, 0.0, 0.0};
+  double vi[kTeR];
+  {
+    double sg = 0.0;
+    {
+      const int i0 = k + 2 + l64, i1 = i0 + 64;
+      if (i0 < n) sg += xk[i0] * xk[i0];
+      if (i1 < n) sg += xk[i1] * xk[i1];
+    }
+    sg = te_wave_sum(sg);
+    const double al = xk[k + 1];
+    beta = al;
+    if (sg > 0.0) {
+      const double mu = sqrt(al * al + sg);
+      beta = al >= 0.0 ? -mu : mu;
+      sc = te_rcp(al - beta);   // al - beta and beta are nonzero here (sg > 0)
+      tau = (beta - al) * te_rcp(beta);
+    }
 #pragma unroll
-  for (int r = KB; r < NB; ++r) {
-    vi[r] = vof(tr + 32 * r);
-    vj[r] = vof(tc + 32 * r);
-  }
+    for (int r = RKB; r < NB; ++r) vi[r] = vof(tr + 32 * r);
+    double pr[kTeR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int r = KB; r < NB; ++r) {
-    double s = 0.0;
+    for (int c = CKB; c < NC; ++c) {   // v over the thread's columns, read as needed
+      const double vc = vof(tc + 16 * c);
 #pragma unroll
-    for (int c = KB; c < NB; ++c) s += A[r][c] * vj[c];
-    pr[r] = te_half_sum(s);
-  }
-  if (tc == 0) {
+      for (int r = RKB; r < NB; ++r) pr[r] += A[r][c] * vc;
+    }
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      const int i = tr + 32 * r;
-      if (i < n) ps[i] = (r >= KB && i > k) ? tau * pr[r] : 0.0;
+    for (int r = RKB; r < NB; ++r) pr[r] = te_row_sum(pr[r]);
+    if (tc == 0) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int i = tr + 32 * r;
+        if (i < n) ps[i] = (r >= RKB && i > k) ? tau * pr[r] : 0.0;
+      }
     }
   }
   __syncthreads();
-  double kk = 0.0;
-  if (l64 < n) kk += ps[l64] * vof(l64);
-  if (l64 + 64 < n) kk += ps[l64 + 64] * vof(l64 + 64);
-  const double K = 0.5 * tau * te_wave_sum(kk);
-  double wi[kTeR], wj[kTeR];
+  {
+    double kk = 0.0;
+    if (l64 < n) kk += ps[l64] * vof(l64);
+    if (l64 + 64 < n) kk += ps[l64 + 64] * vof(l64 + 64);
+    const double K = 0.5 * tau * te_wave_sum(kk);
+    double wi[kTeR];
 #pragma unroll
-  for (int r = KB; r < NB; ++r) {
-    const int i = tr + 32 * r, j = tc + 32 * r;
-    wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
-    wj[r] = j < n ? ps[j] - K * vj[r] : 0.0;
-  }
-  // the reflector for the back-transformation (xk stays valid until step
-  // k + 2 writes it again), stored off the path to the second barrier
-  if (tid < 64) {
-    for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
-    if (tid == 0) {
-      tauS[k] = tau;
-      eS[k] = beta;
+    for (int r = RKB; r < NB; ++r) {
+      const int i = tr + 32 * r;
+      wi[r] = i < n ? ps[i] - K * vi[r] : 0.0;
+    }
+    // the reflector for the back-transformation (xk stays valid until step
+    // k + 2 writes it again), stored off the path to the second barrier
+    if (tid < 64) {
+      for (int i = k + 1 + tid; i < n; i += 64) vst[te_off(k) + i - k - 1] = vof(i);
+      if (tid == 0) {
+        tauS[k] = tau;
+        eS[k] = beta;
+      }
+    }
+#pragma unroll
+    for (int c = CKB; c < NC; ++c) {
+      const int j = tc + 16 * c;
+      const double vc = vof(j), wj = j < n ? ps[j] - K * vc : 0.0;
+#pragma unroll
+      for (int r = RKB; r < NB; ++r) A[r][c] -= vi[r] * wj + wi[r] * vc;
     }
   }
-#pragma unroll
-  for (int r = KB; r < NB; ++r)
-#pragma unroll
-    for (int c = KB; c < NB; ++c) A[r][c] -= vi[r] * wj[c] + wi[r] * vj[c];
 }
 
-// The steps k = 32 KB - 1 ... 32 KB + 30 (those with first active block KB),
-// from k on, while k + 2 < n.
-template <int KB, int NB>
-__device__ __forceinline__ void te_reduce_range(double (&A)[kTeR][kTeR], int& k, int n,
-                                                double* xsb, double* ps, double* dS,
-                                                double* eS, double* tauS, double* vst) {
-  if constexpr (KB > 0) {
-    if (k + 2 >= n) return;
-    te_reduce_step<KB, NB, KB - 1>(A, k, n, xsb, ps, dS, eS, tauS, vst);   // k = 32 KB - 1
-    ++k;
+// The steps with first active column block CKB (k = 16 CKB - 1 ...
+// 16 CKB + 14), from k on while k + 2 < n, then the next block's.
+template <int CKB, int NB>
+__device__ __forceinline__ void te_reduce(double (&A)[kTeR][kTeC], int& k, int n,
+                                          double* xsb, double* ps, double* dS, double* eS,
+                                          double* tauS, double* vst) {
+  for (; k + 2 < n && k < 16 * CKB + 15; ++k)
+    te_reduce_step<CKB, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+  if constexpr (CKB + 1 < 2 * NB) {
+    te_reduce<CKB + 1, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
+  } else {   // the last 2 x 2 block (or the single entry)
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+      for (int c = 0; c < 2 * NB; ++c) {
+        const int i = tr + 32 * r, j = tc + 16 * c;
+        if (i == j && i >= n - 2 && i < n) dS[i] = A[r][c];
+        if (n >= 2 && i == n - 1 && j == n - 2) eS[n - 2] = A[r][c];
+      }
   }
-  for (; k + 2 < n && k < 32 * KB + 31; ++k)
-    te_reduce_step<KB, NB, KB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
 }
 
-// All steps of the reduction for n <= 32 NB.
-template <int NB>
-__device__ __forceinline__ void te_reduce(double (&A)[kTeR][kTeR], int n, double* xsb,
-                                          double* ps, double* dS, double* eS, double* tauS,
-                                          double* vst) {
-  int k = 0;
-  te_reduce_range<0, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
-  if constexpr (NB > 1) te_reduce_range<1, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
-  if constexpr (NB > 2) te_reduce_range<2, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
-  if constexpr (NB > 3) te_reduce_range<3, NB>(A, k, n, xsb, ps, dS, eS, tauS, vst);
-}
-
-// Reflector k of the back-transformation Z -= v (tau v^T Z): the thread grid
-// writes partial column sums over its rows, one thread per column adds the
-// 32 partials (faster here than spreading the sum over lanes), and every
-// thread updates its entries.  Row blocks below KB (rows <= k, where v is
-// zero) and column blocks from NB on (columns >= n) are skipped.
+// Reflector k of the back-transformation Z -= v (tau v^T Z), Z on the 32 x 16
+// grid as A: the grid writes partial column sums over its rows, one thread
+// per column adds the 32 partials (faster here than spreading the sum over
+// lanes), and every thread updates its entries.  Row blocks below KB (rows
+// <= k, where v is zero) and column blocks from 2 NB on (columns >= n) are
+// skipped.
 template <int KB, int NB>
-__device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeR], int k, int n,
+__device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeC], int k, int n,
                                               const double* vst, const double* tauS,
                                               double* red, double* ps) {
   const double tau = tauS[k];
   if (tau == 0.0) return;   // no reflection at this step (the same in every thread)
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   double vi[kTeR];
 #pragma unroll
   for (int r = KB; r < NB; ++r) {
@@ -274,11 +278,11 @@ __device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeR], int k, int
     vi[r] = (i > k && i < n) ? vst[te_off(k) + i - k - 1] : 0.0;
   }
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
+  for (int c = 0; c < 2 * NB; ++c) {
     double s = 0.0;
 #pragma unroll
     for (int r = KB; r < NB; ++r) s += vi[r] * Z[r][c];
-    red[tr * kTeN + tc + 32 * c] = s;
+    red[tr * kTeN + tc + 16 * c] = s;
   }
   __syncthreads();
   if (tid < n) {
@@ -290,11 +294,11 @@ __device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeR], int k, int
 #pragma unroll
   for (int r = KB; r < NB; ++r)
 #pragma unroll
-    for (int c = 0; c < NB; ++c) Z[r][c] -= vi[r] * ps[tc + 32 * c];
+    for (int c = 0; c < 2 * NB; ++c) Z[r][c] -= vi[r] * ps[tc + 16 * c];
 }
 
 template <int NB>
-__device__ __forceinline__ void te_back(double (&Z)[kTeR][kTeR], int n, const double* vst,
+__device__ __forceinline__ void te_back(double (&Z)[kTeR][kTeC], int n, const double* vst,
                                         const double* tauS, double* red, double* ps) {
   int k = n - 3;
   if constexpr (NB > 3)
@@ -306,7 +310,7 @@ __device__ __forceinline__ void te_back(double (&Z)[kTeR][kTeR], int n, const do
   for (; k >= 0; --k) te_back_step<0, NB>(Z, k, n, vst, tauS, red, ps);
 }
 
-__global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, int64_t lp, int n,
+__global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, int64_t lp, int n,
                                                   double* __restrict__ lam,
                                                   double* __restrict__ Ev,
                                                   double* __restrict__ scr,
@@ -316,22 +320,23 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   __shared__ double dS[kTeN], eS[kTeN], e2S[kTeN], tauS[kTeN], lamS[kTeN], znS[kTeN];
   __shared__ double shv[4];
   double* vst = big;
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   // scratch arrays: 0 multiplier, 1 reciprocal pivot, 2 and 3 the two super
   // diagonals of U, 4 interchange flag, 5 right-hand side / solution
   double* const sa[kTeArrays] = {scr, scr + kTeN * kTeN, scr + 2 * kTeN * kTeN,
                                  scr + 3 * kTeN * kTeN, scr + 4 * kTeN * kTeN,
                                  scr + 5 * kTeN * kTeN};
 
-  double A[kTeR][kTeR];
+  // the thread's share of C: rows tr + 32 r, columns tc + 16 c
+  double A[kTeR][kTeC];
 #pragma unroll
   for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-    for (int c = 0; c < kTeR; ++c) {
-      const int i = tr + 32 * r, j = tc + 32 * c;
+    for (int c = 0; c < kTeC; ++c) {
+      const int i = tr + 32 * r, j = tc + 16 * c;
       A[r][c] = (i < n && j < n) ? 0.5 * (G[(int64_t)i * lp + j] + G[(int64_t)j * lp + i]) : 0.0;
     }
-  for (int i = tid; i < kTeN; i += 1024) {
+  for (int i = tid; i < kTeN; i += kTeT) {
     ps[i] = 0.0;
     eS[i] = 0.0;
     e2S[i] = 0.0;
@@ -340,23 +345,17 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   __syncthreads();
 
   // 1. tridiagonal reduction (the step is described at te_reduce_step)
-  switch ((n + 31) >> 5) {
-    case 1: te_reduce<1>(A, n, xsb, ps, dS, eS, tauS, vst); break;
-    case 2: te_reduce<2>(A, n, xsb, ps, dS, eS, tauS, vst); break;
-    case 3: te_reduce<3>(A, n, xsb, ps, dS, eS, tauS, vst); break;
-    default: te_reduce<4>(A, n, xsb, ps, dS, eS, tauS, vst); break;
-  }
-  // the last 2 x 2 block (or the single entry)
-#pragma unroll
-  for (int r = 0; r < kTeR; ++r)
-#pragma unroll
-    for (int c = 0; c < kTeR; ++c) {
-      const int i = tr + 32 * r, j = tc + 32 * c;
-      if (i == j && i >= n - 2 && i < n) dS[i] = A[r][c];
-      if (n >= 2 && i == n - 1 && j == n - 2) eS[n - 2] = A[r][c];
+  {
+    int k = 0;
+    switch ((n + 31) >> 5) {
+      case 1: te_reduce<0, 1>(A, k, n, xsb, ps, dS, eS, tauS, vst); break;
+      case 2: te_reduce<0, 2>(A, k, n, xsb, ps, dS, eS, tauS, vst); break;
+      case 3: te_reduce<0, 3>(A, k, n, xsb, ps, dS, eS, tauS, vst); break;
+      default: te_reduce<0, 4>(A, k, n, xsb, ps, dS, eS, tauS, vst); break;
     }
+  }
   __syncthreads();
-  for (int i = tid; i + 1 < n; i += 1024) e2S[i] = eS[i] * eS[i];
+  for (int i = tid; i + 1 < n; i += kTeT) e2S[i] = eS[i] * eS[i];
   if (tid < 64) {   // Gershgorin interval, |T| and the pivot floor
     double lo = __builtin_inf(), hi = -__builtin_inf(), em = 0.0;
     for (int i = tid; i < n; i += 64) {
@@ -511,12 +510,12 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
 
   // 4. W = Q Z, the reflectors in reverse order (te_back_step)
   double* red = big + kTePacked;   // 32 x kTeN partial column sums
-  double Z[kTeR][kTeR];
+  double Z[kTeR][kTeC];
 #pragma unroll
   for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-    for (int c = 0; c < kTeR; ++c) {
-      const int i = tr + 32 * r, j = tc + 32 * c;
+    for (int c = 0; c < kTeC; ++c) {
+      const int i = tr + 32 * r, j = tc + 16 * c;
       Z[r][c] = (i < n && j < n) ? sa[5][i * kTeN + j] * znS[j] : 0.0;
     }
   switch ((n + 31) >> 5) {
@@ -531,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
 #pragma unroll
   for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-    for (int c = 0; c < kTeR; ++c) big[(tr + 32 * r) * kTeN + tc + 32 * c] = Z[r][c];
+    for (int c = 0; c < kTeC; ++c) big[(tr + 32 * r) * kTeN + tc + 16 * c] = Z[r][c];
   __syncthreads();
   double lmax = 0.0;
   for (int j = 0; j < n; ++j) lmax = fmax(lmax, fabs(lamS[j]));
@@ -540,77 +539,87 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
   };
   bool bad = !(lmax < __builtin_inf());
   {   // W^T W = I
-    double g[kTeR][kTeR];
+    double g[kTeR][kTeC];
 #pragma unroll
     for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-      for (int c = 0; c < kTeR; ++c) g[r][c] = 0.0;
+      for (int c = 0; c < kTeC; ++c) g[r][c] = 0.0;
     for (int i = 0; i < n; ++i) {
-      double wa[kTeR], wb[kTeR];
+      double wa[kTeR], wb[kTeC];
 #pragma unroll
-      for (int r = 0; r < kTeR; ++r) {
-        wa[r] = big[i * kTeN + tr + 32 * r];
-        wb[r] = big[i * kTeN + tc + 32 * r];
-      }
+      for (int r = 0; r < kTeR; ++r) wa[r] = big[i * kTeN + tr + 32 * r];
+#pragma unroll
+      for (int c = 0; c < kTeC; ++c) wb[c] = big[i * kTeN + tc + 16 * c];
 #pragma unroll
       for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-        for (int c = 0; c < kTeR; ++c) g[r][c] += wa[r] * wb[c];
+        for (int c = 0; c < kTeC; ++c) g[r][c] += wa[r] * wb[c];
     }
 #pragma unroll
     for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-      for (int c = 0; c < kTeR; ++c) {
-        const int a = tr + 32 * r, b = tc + 32 * c;
+      for (int c = 0; c < kTeC; ++c) {
+        const int a = tr + 32 * r, b = tc + 16 * c;
         if (a < n && b < n && !(fabs(g[r][c] - (a == b ? 1.0 : 0.0)) <= kTeTol)) bad = true;
       }
   }
   {   // C (W y) = W (diag(lambda) y) for a fixed pseudo-random y: eight
-      // threads per row, sixteen entries each, then a sum over the eight
-    const int i = tid >> 3, s8 = tid & 7;
-    double u = 0.0, t = 0.0;
-    if (i < n)
+      // threads per row, sixteen entries each, then a sum over the eight;
+      // each group of eight takes rows i and i + 64
+    const int s8 = tid & 7;
+    double tv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = (tid >> 3) + 64 * h;
+      double u = 0.0, t = 0.0;
+      if (i < n)
 #pragma unroll 4
-      for (int q = 0; q < 16; ++q) {
-        const int j = 16 * s8 + q;
-        if (j < n) {
-          const double y = te_start(j, 4099), w = big[i * kTeN + j];
-          u += w * y;
-          t += w * (lamS[j] * y);
+        for (int q = 0; q < 16; ++q) {
+          const int j = 16 * s8 + q;
+          if (j < n) {
+            const double y = te_start(j, 4099), w = big[i * kTeN + j];
+            u += w * y;
+            t += w * (lamS[j] * y);
+          }
         }
-      }
-    u += te_dpp<0xB1>(u);
-    u += te_dpp<0x4E>(u);
-    u += te_dpp<0x141>(u);
-    t += te_dpp<0xB1>(t);
-    t += te_dpp<0x4E>(t);
-    t += te_dpp<0x141>(t);
-    if (s8 == 0 && i < kTeN) ps[i] = i < n ? u : 0.0;
-    __syncthreads();
-    double cu = 0.0;
-    if (i < n) {
-      double cv[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int m = 16 * s8 + q;
-        cv[q] = m < n ? cval(i, m) : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) cu += cv[q] * ps[16 * s8 + q];
+      u += te_dpp<0xB1>(u);
+      u += te_dpp<0x4E>(u);
+      u += te_dpp<0x141>(u);
+      t += te_dpp<0xB1>(t);
+      t += te_dpp<0x4E>(t);
+      t += te_dpp<0x141>(t);
+      if (s8 == 0) ps[i] = i < n ? u : 0.0;
+      tv[h] = t;
     }
-    cu += te_dpp<0xB1>(cu);
-    cu += te_dpp<0x4E>(cu);
-    cu += te_dpp<0x141>(cu);
+    __syncthreads();
     double ysum = 0.0;
     for (int j = 0; j < n; ++j) ysum += fabs(te_start(j, 4099));
-    if (i < n && s8 == 0 && !(fabs(cu - t) <= kTeTol * lmax * ysum)) bad = true;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = (tid >> 3) + 64 * h;
+      double cu = 0.0;
+      if (i < n) {
+        double cv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int m = 16 * s8 + q;
+          cv[q] = m < n ? cval(i, m) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cu += cv[q] * ps[16 * s8 + q];
+      }
+      cu += te_dpp<0xB1>(cu);
+      cu += te_dpp<0x4E>(cu);
+      cu += te_dpp<0x141>(cu);
+      if (i < n && s8 == 0 && !(fabs(cu - tv[h]) <= kTeTol * lmax * ysum)) bad = true;
+    }
   }
   const int any_bad = __syncthreads_or(bad ? 1 : 0);
-  for (int e = tid; e < lp * lp; e += 1024) {
+  for (int e = tid; e < lp * lp; e += kTeT) {
     const int i = e / (int)lp, j = e % (int)lp;
     Ev[e] = (i < n && j < n) ? big[i * kTeN + j] : 0.0;
   }
-  for (int j = tid; j < lp; j += 1024) lam[j] = j < n ? lamS[j] : 0.0;
+  for (int j = tid; j < lp; j += kTeT) lam[j] = j < n ? lamS[j] : 0.0;
   if (tid == 0) {
     status[kStTriOk] = any_bad ? 0 : 1;
     if (!any_bad) {
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const double* __restrict__ G, 
 hipError_t launch_tri_eig(const double* G, int64_t lp, int64_t l, double* lam, double* Ev,
                           double* scratch, int32_t* status, hipStream_t s) {
   if (lp > kTeN || l < 1 || l > lp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(1024), 0, s, G, lp, (int)l, lam, Ev, scratch,
+  hipLaunchKernelGGL(k_tri_eig, dim3(1), dim3(kTeT), 0, s, G, lp, (int)l, lam, Ev, scratch,
                      status);
   return hipGetLastError();
 }
