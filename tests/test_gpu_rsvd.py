@@ -139,6 +139,36 @@ def test_small_svd_tridiagonal_matches_jacobi():
     assert su <= 1e-4 and sv <= 1e-4
 
 
+@pytest.mark.parametrize("l", [33, 80, 97, 128])
+def test_small_svd_tridiagonal_widths(l):
+    """The tridiagonal small SVD keeps its register blocks of 32 rows and 16
+    columns only while they hold live entries: width 33 takes two row blocks,
+    80 three, 97 and 128 (the largest) four.  sigma_i = i^-1/2 with little
+    noise keeps the eigenvalues of C apart, so the result must pass the
+    kernel's own checks (no Jacobi sweeps), match the oracle, and give the
+    factors of the Cholesky + one-sided Jacobi path."""
+    dev = need_gpu()
+    m, n, k, p = 3000, 1200, l - 10, 10
+    A = workloads.dense_lowrank(m, n, np.arange(1, n + 1) ** -0.5, 1e-8, seed=21,
+                                out_dtype=torch.float32)
+    S1, _, info = run_and_compare(A.numpy(), k, p, 2, tile=(1024, 1024))
+    assert info["jacobi_sweeps"] == 0
+    plan = Plan(m, n, k, p, 2, tile=(1024, 1024), flags=L.FLAG_JACOBI_ONLY)
+    U2, S2, V2, info2 = plan.factor(A.to(dev))
+    torch.cuda.synchronize()
+    plan1 = Plan(m, n, k, p, 2, tile=(1024, 1024))
+    U1, _, V1, _ = plan1.factor(A.to(dev))
+    torch.cuda.synchronize()
+    S2 = S2.cpu().double().numpy()
+    su = metrics.sin_theta(U2.cpu().double().numpy(), U1.cpu().double().numpy())
+    sv = metrics.sin_theta(V2.cpu().double().numpy(), V1.cpu().double().numpy())
+    say(f"l={l}: tridiagonal vs Jacobi sigma diff {np.max(np.abs(S1 - S2)) / S2[0]:.2e}, "
+        f"sin U {su:.1e}, sin V {sv:.1e}, sweeps {info2['jacobi_sweeps']}")
+    assert info2["jacobi_sweeps"] > 0
+    assert np.max(np.abs(S1 - S2)) <= 1e-6 * S2[0]
+    assert su <= 1e-4 and sv <= 1e-4
+
+
 def test_small_svd_falls_back_to_jacobi_on_repeated_eigenvalues():
     """Rank 8 with l = 16: the dropped directions give C a repeated zero
     eigenvalue, independent inverse iterations are not orthogonal there, and
