@@ -59,7 +59,7 @@ static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scr
 __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
 
 // Cross-lane sums through DPP lane permutes (no LDS round trips); every lane
-// of a row (half-wave, wave) ends with the same bits, since each step adds
+// of a row (wave) ends with the same bits, since each step adds
 // the same two operands in every lane.
 template <int kCtrl>
 __device__ inline double te_dpp(double x) {
