@@ -159,16 +159,16 @@ __device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeC], int k, i
     for (int r = 0; r < NB; ++r) {
       const int i = tr + 32 * r;
       const double x = at ? A[r][CKB] : A[r][CKB > 0 ? CKB - 1 : 0];
-      if (i > k && i < n) xk[i] = x;
+      if (i < n) xk[i] = i > k ? x : 0.0;   // zeros at and above the diagonal
       if (i == k) dS[k] = x;
     }
   }
   __syncthreads();
   double tau = 0.0, beta = 0.0, sc = 0.0;
-  auto vof = [&](int i) -> double {
-    return (i <= k || i >= n) ? 0.0 : (i == k + 1 ? 1.0 : xk[i] * sc);
-  };
-  double vi[kTeR];
+  // v: zero at rows <= k (xk holds zeros there) and >= n (never written,
+  // zero from the start), 1 at k + 1, the scaled column below
+  auto vof = [&](int i) -> double { return i == k + 1 ? 1.0 : xk[i] * sc; };
+  double vi[kTeR], vj[kTeC];
   {
     double sg = 0.0;
     {
@@ -189,10 +189,10 @@ __device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeC], int k, i
     for (int r = RKB; r < NB; ++r) vi[r] = vof(tr + 32 * r);
     double pr[kTeR] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = CKB; c < NC; ++c) {   // v over the thread's columns, read as needed
-      const double vc = vof(tc + 16 * c);
+    for (int c = CKB; c < NC; ++c) {
+      vj[c] = vof(tc + 16 * c);
 #pragma unroll
-      for (int r = RKB; r < NB; ++r) pr[r] += A[r][c] * vc;
+      for (int r = RKB; r < NB; ++r) pr[r] += A[r][c] * vj[c];
     }
 #pragma unroll
     for (int r = RKB; r < NB; ++r) pr[r] = te_row_sum(pr[r]);
@@ -228,9 +228,9 @@ __device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeC], int k, i
 #pragma unroll
     for (int c = CKB; c < NC; ++c) {
       const int j = tc + 16 * c;
-      const double vc = vof(j), wj = j < n ? ps[j] - K * vc : 0.0;
+      const double wj = j < n ? ps[j] - K * vj[c] : 0.0;
 #pragma unroll
-      for (int r = RKB; r < NB; ++r) A[r][c] -= vi[r] * wj + wi[r] * vc;
+      for (int r = RKB; r < NB; ++r) A[r][c] -= vi[r] * wj + wi[r] * vj[c];
     }
   }
 }
@@ -337,6 +337,8 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
       A[r][c] = (i < n && j < n) ? 0.5 * (G[(int64_t)i * lp + j] + G[(int64_t)j * lp + i]) : 0.0;
     }
   for (int i = tid; i < kTeN; i += kTeT) {
+    xsb[i] = 0.0;
+    xsb[kTeN + i] = 0.0;
     ps[i] = 0.0;
     eS[i] = 0.0;
     e2S[i] = 0.0;
