@@ -45,7 +45,7 @@ namespace rsvd {
 namespace {
 
 constexpr int kTeN = (int)kTriMaxLp;             // largest order
-constexpr int kTeR = 4;                          // rows (columns) per thread
+constexpr int kTeR = 4;                          // rows per thread (blocks of 32)
 constexpr int kTeT = 512;                        // threads: a 32 x 16 grid in phases 1, 4, 5
 constexpr int kTeC = 8;                          // columns per thread (blocks of 16)
 constexpr int kTeG = 4;                          // lanes per eigenvalue in the bisection
@@ -59,8 +59,8 @@ static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scr
 __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
 
 // Cross-lane sums through DPP lane permutes (no LDS round trips); every lane
-// of a row (wave) ends with the same bits, since each step adds
-// the same two operands in every lane.
+// of the 16-lane row (of the wave) ends with the same bits, since each step
+// adds the same two operands in every lane.
 template <int kCtrl>
 __device__ inline double te_dpp(double x) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x);
@@ -137,10 +137,10 @@ __device__ inline double te_start(int i, int j) {
 // Step k of the reduction, two barriers.  Thread (tr, tc) of the 32 x 16
 // grid holds rows tr + 32 r (r < 4) and columns tc + 16 c (c < 8) of A, so a
 // row of the grid is one 16-lane DPP row and its sums need no lane reads.
-// Every wave forms the reflector and the scalar K itself
-// (same bits in every wave); the column below the diagonal alternates
-// between two buffers so that the next step's owner never overwrites one
-// still being read.  Column blocks c < CKB (row blocks r < CKB / 2) hold
+// Every wave forms the reflector and the scalar K itself (same bits in every
+// wave); the column below the diagonal alternates between two buffers so
+// that the next step's owner never overwrites one still being read.  Column
+// blocks c < CKB (row blocks r < CKB / 2) hold
 // indices <= k only, and blocks from NB (2 NB) on indices >= n only; there
 // the reflector v and the vector w are zero, the update leaves A as it is
 // and the product's terms are zeros, so those blocks are skipped.  (The
@@ -159,7 +159,7 @@ __device__ __forceinline__ void te_reduce_step(double (&A)[kTeR][kTeC], int k, i
     for (int r = 0; r < NB; ++r) {
       const int i = tr + 32 * r;
       const double x = at ? A[r][CKB] : A[r][CKB > 0 ? CKB - 1 : 0];
-      if (i < n) xk[i] = i > k ? x : 0.0;   // zeros at and above the diagonal
+      if (i < n) xk[i] = i > k ? x : 0.0;   // zeros at rows <= k
       if (i == k) dS[k] = x;
     }
   }
