@@ -52,6 +52,8 @@ constexpr int kTeG = 4;                          // lanes per eigenvalue in the 
 constexpr int kTeRounds = 23;                    // (kTeG + 1)^23 = 5^23 > 2^52
 static_assert(kTeG * kTeN == kTeT, "one lane group per eigenvalue");
 constexpr int kTePacked = kTeN * (kTeN - 1) / 2; // reflector store (doubles)
+constexpr int kTeRed = 33;                       // column stride of the partial sums
+static_assert(kTePacked + kTeN * kTeRed <= kTeN * kTeN, "reflectors and partial sums fit");
 constexpr double kTeTol = 1e-12;
 constexpr int kTeArrays = 6;                     // scratch arrays of the inverse iteration
 static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scratch layout");
@@ -259,11 +261,11 @@ __device__ __forceinline__ void te_reduce(double (&A)[kTeR][kTeC], int& k, int n
 }
 
 // Reflector k of the back-transformation Z -= v (tau v^T Z), Z on the 32 x 16
-// grid as A: the grid writes partial column sums over its rows, one thread
-// per column adds the 32 partials (faster here than spreading the sum over
-// lanes), and every thread updates its entries.  Row blocks below KB (rows
-// <= k, where v is zero) and column blocks from 2 NB on (columns >= n) are
-// skipped.
+// grid as A: the grid writes partial column sums over its rows (column-major,
+// stride kTeRed), four threads per column add eight partials each and then
+// the four through DPP, and every thread updates its entries.  Row blocks
+// below KB (rows <= k, where v is zero) and column blocks from 2 NB on
+// (columns >= n) are skipped.
 template <int KB, int NB>
 __device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeC], int k, int n,
                                               const double* vst, const double* tauS,
@@ -282,13 +284,18 @@ __device__ __forceinline__ void te_back_step(double (&Z)[kTeR][kTeC], int k, int
     double s = 0.0;
 #pragma unroll
     for (int r = KB; r < NB; ++r) s += vi[r] * Z[r][c];
-    red[tr * kTeN + tc + 16 * c] = s;
+    red[(tc + 16 * c) * kTeRed + tr] = s;
   }
   __syncthreads();
-  if (tid < n) {
+  {
+    const int col = tid >> 2, q = tid & 3;
     double s = 0.0;
-    for (int t = 0; t < 32; ++t) s += red[t * kTeN + tid];
-    ps[tid] = tau * s;
+    if (col < n)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s += red[col * kTeRed + 8 * q + t];
+    s += te_dpp<0xB1>(s);   // quad_perm [1, 0, 3, 2]
+    s += te_dpp<0x4E>(s);   // quad_perm [2, 3, 0, 1]
+    if (col < n && q == 0) ps[col] = tau * s;
   }
   __syncthreads();
 #pragma unroll
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
   __syncthreads();
 
   // 4. W = Q Z, the reflectors in reverse order (te_back_step)
-  double* red = big + kTePacked;   // 32 x kTeN partial column sums
+  double* red = big + kTePacked;   // kTeN columns of 32 partial sums
   double Z[kTeR][kTeC];
 #pragma unroll
   for (int r = 0; r < kTeR; ++r)
