@@ -540,6 +540,8 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
   for (int r = 0; r < kTeR; ++r)
 #pragma unroll
     for (int c = 0; c < kTeC; ++c) big[(tr + 32 * r) * kTeN + tc + 16 * c] = Z[r][c];
+  // y of the residual check, in the (now free) column buffer of the reduction
+  if (tid < kTeN) xsb[tid] = tid < n ? te_start(tid, 4099) : 0.0;
   __syncthreads();
   double lmax = 0.0;
   for (int j = 0; j < n; ++j) lmax = fmax(lmax, fabs(lamS[j]));
@@ -547,7 +549,8 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
     return row < n ? 0.5 * (G[(int64_t)row * lp + i] + G[(int64_t)i * lp + row]) : 0.0;
   };
   bool bad = !(lmax < __builtin_inf());
-  {   // W^T W = I
+  {   // W^T W = I; it is symmetric (the two products of a pair are the same
+      // bits), so register blocks wholly below the diagonal are left out
     double g[kTeR][kTeC];
 #pragma unroll
     for (int r = 0; r < kTeR; ++r)
@@ -562,12 +565,12 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
 #pragma unroll
       for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-        for (int c = 0; c < kTeC; ++c) g[r][c] += wa[r] * wb[c];
+        for (int c = 2 * r; c < kTeC; ++c) g[r][c] += wa[r] * wb[c];
     }
 #pragma unroll
     for (int r = 0; r < kTeR; ++r)
 #pragma unroll
-      for (int c = 0; c < kTeC; ++c) {
+      for (int c = 2 * r; c < kTeC; ++c) {
         const int a = tr + 32 * r, b = tc + 16 * c;
         if (a < n && b < n && !(fabs(g[r][c] - (a == b ? 1.0 : 0.0)) <= kTeTol)) bad = true;
       }
@@ -586,7 +589,7 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
         for (int q = 0; q < 16; ++q) {
           const int j = 16 * s8 + q;
           if (j < n) {
-            const double y = te_start(j, 4099), w = big[i * kTeN + j];
+            const double y = xsb[j], w = big[i * kTeN + j];
             u += w * y;
             t += w * (lamS[j] * y);
           }
@@ -601,8 +604,7 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
       tv[h] = t;
     }
     __syncthreads();
-    double ysum = 0.0;
-    for (int j = 0; j < n; ++j) ysum += fabs(te_start(j, 4099));
+    const double ysum = te_wave_sum(fabs(xsb[tid & 63]) + fabs(xsb[(tid & 63) + 64]));
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = (tid >> 3) + 64 * h;
