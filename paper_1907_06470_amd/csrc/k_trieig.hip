@@ -465,9 +465,33 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
     }
     double scale = 1.0;
     for (int it = 0; it < 2; ++it) {
-      if (it > 0) {   // forward pass on the normalised previous solution
+      if (it > 0) {   // forward pass on the normalised previous solution, four
+                      // rows at a time with their loads issued together (rows
+                      // i + 1 .. i + 4 are read before rows i .. i + 3 are written)
         double bi = X[0] * scale;
-        for (int i = 0; i + 1 < n; ++i) {
+        int i = 0;
+        for (; i + 4 < n; i += 4) {
+          double f[4], pf[4], bn[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int o = (i + u) * kTeN;
+            f[u] = dl[o];
+            pf[u] = pv[o];
+            bn[u] = X[o + kTeN] * scale;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int o = (i + u) * kTeN;
+            if (pf[u] != 0.0) {
+              X[o] = bn[u];
+              bi = bi - f[u] * bn[u];
+            } else {
+              X[o] = bi;
+              bi = bn[u] - f[u] * bi;
+            }
+          }
+        }
+        for (; i + 1 < n; ++i) {
           const int o = i * kTeN;
           const double f = dl[o], bn = X[o + kTeN] * scale;
           if (pv[o] != 0.0) {
