@@ -56,6 +56,7 @@ constexpr int kTeRed = 33;                       // column stride of the partial
 static_assert(kTePacked + kTeN * kTeRed <= kTeN * kTeN, "reflectors and partial sums fit");
 constexpr double kTeTol = 1e-12;
 constexpr int kTeArrays = 6;                     // scratch arrays of the inverse iteration
+constexpr int kTeIb = 8;                         // rows per batch of its loads
 static_assert(kTeN == 128 && kTeArrays * kTeN * kTeN == kTriScratchDoubles, "scratch layout");
 
 __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
@@ -465,22 +466,23 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
     }
     double scale = 1.0;
     for (int it = 0; it < 2; ++it) {
-      if (it > 0) {   // forward pass on the normalised previous solution, four
-                      // rows at a time with their loads issued together (rows
-                      // i + 1 .. i + 4 are read before rows i .. i + 3 are written)
+      if (it > 0) {   // forward pass on the normalised previous solution,
+                      // kTeIb rows at a time with their loads issued together
+                      // (rows i + 1 .. i + kTeIb are read before rows i ..
+                      // i + kTeIb - 1 are written)
         double bi = X[0] * scale;
         int i = 0;
-        for (; i + 4 < n; i += 4) {
-          double f[4], pf[4], bn[4];
+        for (; i + kTeIb < n; i += kTeIb) {
+          double f[kTeIb], pf[kTeIb], bn[kTeIb];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < kTeIb; ++u) {
             const int o = (i + u) * kTeN;
             f[u] = dl[o];
             pf[u] = pv[o];
             bn[u] = X[o + kTeN] * scale;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < kTeIb; ++u) {
             const int o = (i + u) * kTeN;
             if (pf[u] != 0.0) {
               X[o] = bn[u];
@@ -504,14 +506,14 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
         }
         X[(n - 1) * kTeN] = bi;
       }
-      // back substitution with U (reciprocal pivots, super diagonals), four
+      // back substitution with U (reciprocal pivots, super diagonals), kTeIb
       // rows at a time with their loads issued together
       double x1 = 0.0, x2 = 0.0, nrm = 0.0;
       int i = n - 1;
-      for (; i >= 3; i -= 4) {
-        double b[4], a1[4], a2[4], rr[4];
+      for (; i >= kTeIb - 1; i -= kTeIb) {
+        double b[kTeIb], a1[kTeIb], a2[kTeIb], rr[kTeIb];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kTeIb; ++u) {
           const int o = (i - u) * kTeN;
           b[u] = X[o];
           a1[u] = u1[o];
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(kTeT) void k_tri_eig(const double* __restrict__ G, 
           rr[u] = rp[o];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kTeIb; ++u) {
           const double x = (b[u] - a1[u] * x1 - a2[u] * x2) * rr[u];
           X[(i - u) * kTeN] = x;
           nrm += x * x;
