@@ -64,11 +64,12 @@ __device__ inline int te_off(int k) { return k * kTeN - k * (k + 1) / 2; }
 // Cross-lane sums through DPP lane permutes (no LDS round trips); every lane
 // of the 16-lane row (of the wave) ends with the same bits, since each step
 // adds the same two operands in every lane.
-template <int kCtrl>
+template <int kCtrl, int kRows = 0xF>   // rows outside kRows get 0
 __device__ inline double te_dpp(double x) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kCtrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kCtrl, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kCtrl, kRows, 0xF, false);
+  const int hi =
+      __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kCtrl, kRows, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
@@ -87,9 +88,12 @@ __device__ inline double te_lane(double x, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// the four row sums r0..r3 meet in lane 63 as (r3 + r2) + (r1 + r0)
 __device__ inline double te_wave_sum(double x) {
   x = te_row_sum(x);
-  return (te_lane(x, 0) + te_lane(x, 16)) + (te_lane(x, 32) + te_lane(x, 48));
+  x += te_dpp<0x142, 0xA>(x);   // row_bcast:15: lane 15 (47) into row 1 (3)
+  x += te_dpp<0x143, 0xC>(x);   // row_bcast:31: lane 31 into rows 2 and 3
+  return te_lane(x, 63);
 }
 
 // 1 / q: the hardware reciprocal and one Newton step
