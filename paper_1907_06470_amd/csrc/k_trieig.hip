@@ -23,7 +23,7 @@
 //      pattern) go to a global scratch laid out [array][row][lane], then two
 //      solves from a fixed pseudo-random start, normalising in between.
 //   4. Back-transformation W = Q Z, the reflectors applied in reverse order
-//      (column sums: partials over the thread grid in LDS, then one thread
+//      (column sums: partials over the thread grid in LDS, then four threads
 //      per column).
 //   5. Checks: |W^T W - I| <= 1e-12 (the accuracy the one-sided Jacobi path
 //      reaches) and, for a fixed pseudo-random y,
